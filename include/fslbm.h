@@ -1,0 +1,149 @@
+/*
+ * fslbm.h -- C ABI of the MI355X (gfx950) free surface lattice Boltzmann
+ * library libfslbm.so.
+ *
+ * The library advances the free surface lattice Boltzmann method (FSLBM) of
+ * Bogner, Ruede and Harting, "Curvature estimation from a volume of fluid
+ * indicator function for the simulation of surface tension and wetting with a
+ * free surface lattice Boltzmann method" (arXiv:1509.07691), Sec. II: D3Q19
+ * stream-collide (eqs. lbe1, lbe2), fill-level advection by mass exchange
+ * (eqs. advection1, advection2), free-surface reconstruction at gas links with
+ * the Laplace pressure jump (eq. reconstruct, rho_b = (p_g + p_s)/c_s^2,
+ * p_s = 2 sigma kappa), curvature by finite differences (Sec. II.A, eqs.
+ * curvature, normal) or by the least-squares fit of PLIC points with the
+ * wetting condition (Sec. II.C, eqs. LSQR-model, LSQR-error, anacurv,
+ * contactNormal, contactConstraint), and cell-type conversion.
+ *
+ * Conventions for every function:
+ *  - Return 0 (FSLBM_OK) or a negative FSLBM_E_* code; fslbm_last_error()
+ *    then holds a message (per thread). No exception crosses the ABI.
+ *  - An argument error leaves the handle unchanged.
+ *  - Arrays over the lattice have nx*ny*nz entries with linear index
+ *    i = x + nx*(y + ny*z) (x fastest); vector fields are component-major
+ *    (all x components, then all y, then all z). All axes wrap periodically;
+ *    walls are obstacle cells.
+ *  - Ownership: the caller owns every host and device buffer, including the
+ *    device workspace handed to fslbm_create; the library keeps raw pointers
+ *    into it and never frees them. The library owns only its handle.
+ *  - Work is enqueued on the HIP stream given at creation (or by
+ *    fslbm_set_stream). fslbm_step does not synchronise; every read function
+ *    synchronises that stream before it returns.
+ *  - Curvature is reported as K = -div(n) = 2 kappa (2/R for a sphere,
+ *    positive for a droplet); the pressure jump is p_s = sigma*K, i.e.
+ *    2 sigma kappa with kappa the mean curvature.
+ */
+#ifndef FSLBM_H
+#define FSLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fslbm_lattice *fslbm_t;
+
+enum fslbm_status {
+    FSLBM_OK = 0,
+    FSLBM_E_ARG = -1,      /* invalid argument value */
+    FSLBM_E_SHAPE = -2,    /* lattice or buffer size out of range */
+    FSLBM_E_HIP = -3,      /* a HIP runtime call failed */
+    FSLBM_E_STATE = -4,    /* handle not usable for this call */
+    FSLBM_E_NUMERIC = -5   /* non-finite or non-positive density found */
+};
+
+/* Storage and arithmetic precision of the distributions. F16/BF16 store
+ * (f_q - w_q) * S in 16 bits (S = 2^12 for F16, 1 for BF16) and compute in
+ * FP32; m, phi, rho and K are FP64 in F64 mode and FP32 otherwise. Normals,
+ * PLIC points and the least-squares solve are always FP64. */
+enum fslbm_precision { FSLBM_F64 = 0, FSLBM_F32 = 1, FSLBM_F16_STORE = 2, FSLBM_BF16_STORE = 3 };
+enum fslbm_curv_model { FSLBM_CURV_FD = 0, FSLBM_CURV_LSQR = 1 };
+enum fslbm_collision { FSLBM_SRT = 0, FSLBM_TRT = 1 };
+/* Cell types reported by fslbm_read_flags. */
+enum fslbm_cell { FSLBM_GAS = 0, FSLBM_LIQUID = 1, FSLBM_INTERFACE = 2, FSLBM_OBSTACLE = 3 };
+/* Keys of fslbm_set_option. */
+enum fslbm_option {
+    FSLBM_OPT_EPS_C = 0,      /* conversion offset eps: fill if m > (1+eps) rho,
+                                 empty if m < -eps rho (default 1e-3) */
+    FSLBM_OPT_COLLISION = 1,  /* FSLBM_SRT (default) or FSLBM_TRT */
+    FSLBM_OPT_TRT_MAGIC = 2   /* TRT Lambda = (tau-1/2)(tau_odd-1/2), default 3/16 */
+};
+
+/* Device workspace needed for a lattice (bytes, written to *bytes).
+ * FSLBM_E_SHAPE if any extent is < 3 or the cell count exceeds 2^31 - 1. */
+int fslbm_required_bytes(int nx, int ny, int nz, int precision, size_t *bytes);
+
+/*
+ * Create a lattice (Sec. II: fill level and cell types).
+ *  fill     host, n doubles: liquid volume fraction per cell. Cell types are
+ *           derived as obstacle where obstacle[i] != 0, else liquid for
+ *           fill >= 1, gas for fill <= 0, interface otherwise; a liquid cell
+ *           with a gas D3Q19 neighbour becomes an interface cell with fill 1.
+ *  obstacle host, n bytes, may be NULL (no walls).
+ *  workspace device memory of at least fslbm_required_bytes() bytes, 256-byte
+ *           aligned, owned by the caller and kept alive until fslbm_destroy.
+ *  hip_stream a hipStream_t (NULL = the null stream).
+ * The distributions start at equilibrium with rho = 1, u = 0, the interface
+ * mass at m = fill. Parameters start at sigma = 0, tau = 1, theta = pi/2,
+ * rho_gas = 1 until fslbm_set_params. Copies fill and obstacle; returns with
+ * the initialisation enqueued on the stream.
+ */
+int fslbm_create(int nx, int ny, int nz, int precision, int curv_model, const double *fill,
+                 const uint8_t *obstacle, void *workspace, size_t workspace_bytes,
+                 void *hip_stream, fslbm_t *out);
+
+/* sigma >= 0 (surface tension, lattice units), tau > 1/2 (relaxation time,
+ * nu = (tau - 1/2)/3), 0 < theta < pi (equilibrium contact angle, radians),
+ * rho_gas > 0 (gas pressure p_g = rho_gas/3). Recomputes the curvature field
+ * (it depends on theta at walls). */
+int fslbm_set_params(fslbm_t h, double sigma, double tau, double theta_rad, double rho_gas);
+int fslbm_set_option(fslbm_t h, int key, double value);
+int fslbm_set_stream(fslbm_t h, void *hip_stream);
+
+/* Overwrite the distributions of all fluid cells with feq(rho, u) (host
+ * arrays: rho n doubles, u 3n component-major); interface masses become
+ * m = fill * rho. Used to start flows with a prescribed velocity. */
+int fslbm_set_equilibrium(fslbm_t h, const double *rho, const double *u3);
+
+/* Advance nsteps >= 0 time steps; enqueued, no synchronisation. */
+int fslbm_step(fslbm_t h, int64_t nsteps);
+
+/* Read-outs (n doubles; 3n for velocity and normal). out_is_device = 1 if
+ * out is device memory, 0 for host memory. Synchronise the stream.
+ *  fill: phi (1 liquid, 0 gas, m/rho interface, reflected value at walls);
+ *  pressure: rho/3 at fluid cells, rho_gas/3 at gas cells, 0 at obstacles;
+ *  curvature: K at interface cells, 0 elsewhere;
+ *  velocity: u at fluid cells, 0 elsewhere;
+ *  normal / plic: unit normal of the raw fill level and PLIC plane offset
+ *  (point p = cell centre + a n) at interface cells, 0 elsewhere;
+ *  mass_field: interface mass m (0 at other cells). */
+int fslbm_read_fill(fslbm_t h, double *out, int out_is_device);
+int fslbm_read_pressure(fslbm_t h, double *out, int out_is_device);
+int fslbm_read_curvature(fslbm_t h, double *out, int out_is_device);
+int fslbm_read_velocity(fslbm_t h, double *out3, int out_is_device);
+int fslbm_read_normal(fslbm_t h, double *out3, int out_is_device);
+int fslbm_read_plic(fslbm_t h, double *out, int out_is_device);
+int fslbm_read_mass_field(fslbm_t h, double *out, int out_is_device);
+/* Cell types (enum fslbm_cell), n bytes. */
+int fslbm_read_flags(fslbm_t h, uint8_t *out, int out_is_device);
+/* Interface cells as ascending linear indices into host out[capacity];
+ * *count receives the number of interface cells (FSLBM_E_SHAPE if it
+ * exceeds capacity; out may be NULL to query the count). */
+int fslbm_read_interface_list(fslbm_t h, int32_t *out, int64_t capacity, int64_t *count);
+/* Total mass: sum of rho over liquid cells + sum of m over interface cells +
+ * excess mass that found no receiving cell; FP64, fixed summation order. */
+int fslbm_mass(fslbm_t h, double *total);
+/* FSLBM_E_NUMERIC if any fluid cell has a non-finite or non-positive
+ * density, else 0. Synchronises. */
+int fslbm_check_numeric(fslbm_t h);
+/* Number of time steps taken since creation. */
+int fslbm_steps_taken(fslbm_t h, int64_t *steps);
+
+void fslbm_destroy(fslbm_t h);
+const char *fslbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -717,17 +717,17 @@ static void one_step(orc_lattice *L)
             if (tn == ORC_OBSTACLE) { nw[0] += CX[q]; nw[1] += CY[q]; nw[2] += CZ[q]; }
         }
         /* corner-node rule (Fig. inhomo): at an interface cell with gas and
-         * wall links, a wall link whose outgoing direction points against the
-         * liquid-pointing normal projected into the wall takes the free
-         * surface rule. nt = n |nw|^2 - (n.nw) nw is that projection scaled by
-         * |nw|^2 > 0, enough for the sign test. */
-        double ntp[3] = {0, 0, 0};
+         * wall links, a wall link whose outgoing direction c_o points against
+         * the liquid-pointing normal n projected into the wall takes the free
+         * surface rule: c_o . P n < 0 with P the projection onto the wall
+         * plane. Since P is symmetric this is (P c_o) . n < 0, and
+         * P c_o |nw|^2 = c_o |nw|^2 - (c_o.nw) nw is an exact integer vector:
+         * the link normal to the wall projects to exactly zero and stays
+         * bounce-back, as in the figure. */
         int corner = (t == ORC_INTERFACE) && has_gas && dot3(nw, nw) > 0.0;
-        if (corner) {
-            const double *nn = L->nrm + 3 * i;
-            double ww = dot3(nw, nw), nd = dot3(nn, nw);
-            for (int k = 0; k < 3; ++k) ntp[k] = nn[k] * ww - nd * nw[k];
-        }
+        const double *nn = L->nrm + 3 * i;
+        int iw[3] = {(int)nw[0], (int)nw[1], (int)nw[2]};
+        int ww = iw[0] * iw[0] + iw[1] * iw[1] + iw[2] * iw[2];
         fin[0] = fo[0];
         for (int q = 1; q < NQ; ++q) {
             long j = nbr(L, i, -CX[q], -CY[q], -CZ[q]); /* upstream node x - c_q */
@@ -740,8 +740,11 @@ static void one_step(orc_lattice *L)
                 reconstruct = 1;
             } else { /* obstacle: half-way bounce-back unless the corner rule applies;
                       * outgoing direction towards the wall is c_o = -c_q */
-                double co_nt = -(CX[q] * ntp[0] + CY[q] * ntp[1] + CZ[q] * ntp[2]);
-                if (corner && co_nt < 0.0) reconstruct = 1;
+                int co[3] = {-CX[q], -CY[q], -CZ[q]};
+                int cw = co[0] * iw[0] + co[1] * iw[1] + co[2] * iw[2];
+                double s = 0.0;
+                for (int k = 0; k < 3; ++k) s += (double)(co[k] * ww - cw * iw[k]) * nn[k];
+                if (corner && s < 0.0) reconstruct = 1;
                 else fin[q] = fo[o];
             }
             if (reconstruct) /* eq. reconstruct with q and qbar renamed */

@@ -1,0 +1,756 @@
+// Host driver and C ABI of libfslbm (declared in include/fslbm.h).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "fslbm.h"
+#include "fslbm_convert.hpp"
+#include "fslbm_device.hpp"
+#include "fslbm_geometry.hpp"
+#include "fslbm_stream.hpp"
+
+using namespace fslbm;
+
+// ------------------------------------------------------------ errors
+static thread_local std::string g_err;
+
+static int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_OK(call)                                                                           \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess) return fail(FSLBM_E_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+// ------------------------------------------------------------ layout
+namespace {
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+size_t fbytes(int prec)
+{
+    switch (prec) {
+    case P_F64: return 8;
+    case P_F32: return 4;
+    default: return 2;
+    }
+}
+size_t rbytes(int prec) { return prec == P_F64 ? 8 : 4; }
+
+struct Layout {
+    size_t fA, fB, flags, conv, mark, m, rho, phi, K, nrm, plic, share, phis, nmol, ilist, olist, staging,
+        counts, part, sc, total;
+};
+
+constexpr int MASS_BLOCKS = 1024;
+
+Layout make_layout(long long N, int prec)
+{
+    Layout L;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    const size_t fb = fbytes(prec), rb = rbytes(prec);
+    const size_t nblk = (N + CMP_CELLS - 1) / CMP_CELLS;
+    L.fA = take(19 * N * fb);
+    L.fB = take(19 * N * fb);
+    L.flags = take(N);
+    L.conv = take(N);
+    L.mark = take(4 * N);
+    L.m = take(N * rb);
+    L.rho = take(N * rb);
+    L.phi = take(N * rb);
+    L.K = take(N * rb);
+    L.nrm = take(3 * N * rb);
+    L.plic = take(N * rb);
+    L.share = take(N * rb);
+    L.phis = take(N * rb);
+    L.nmol = take(3 * N * rb);
+    L.ilist = take(4 * N);
+    L.olist = take(4 * N);
+    L.staging = take(8 * N);
+    L.counts = take(4 * nblk);
+    L.part = take(8 * MASS_BLOCKS);
+    L.sc = take(sizeof(DevScalars));
+    L.total = off;
+    return L;
+}
+
+bool shape_ok(int nx, int ny, int nz)
+{
+    if (nx < 3 || ny < 3 || nz < 3) return false;
+    const long long N = (long long)nx * ny * nz;
+    return N <= 2147483647LL / 1;  // cell indices are 32-bit
+}
+
+}  // namespace
+
+struct fslbm_lattice {
+    int nx, ny, nz;
+    int N;
+    int prec, curv, coll;
+    double sigma, tau, theta, rho_gas, eps_c, trt_magic;
+    hipStream_t stream;
+    char *ws;
+    Layout L;
+    int cur;  // 0: current f' in fA, 1: in fB
+    long long steps;
+};
+
+namespace {
+
+Params make_params(const fslbm_lattice *h)
+{
+    Params p;
+    p.sigma = h->sigma;
+    p.tau = h->tau;
+    p.omega = 1.0 / h->tau;
+    p.omega_odd = 1.0 / (0.5 + h->trt_magic / (h->tau - 0.5));
+    p.cos_theta = cos(h->theta);
+    p.sin_theta = sin(h->theta);
+    p.rho_gas = h->rho_gas;
+    p.eps_c = h->eps_c;
+    return p;
+}
+
+template <class P>
+Fields<P> make_fields(const fslbm_lattice *h)
+{
+    using S = typename P::S;
+    using R = typename P::R;
+    Fields<P> F;
+    char *w = h->ws;
+    const Layout &L = h->L;
+    F.fsrc = (const S *)(w + (h->cur == 0 ? L.fA : L.fB));
+    F.fdst = (S *)(w + (h->cur == 0 ? L.fB : L.fA));
+    F.flags = (uint8_t *)(w + L.flags);
+    F.conv = (uint8_t *)(w + L.conv);
+    F.mark = (uint32_t *)(w + L.mark);
+    F.m = (R *)(w + L.m);
+    F.rho = (R *)(w + L.rho);
+    F.phi = (R *)(w + L.phi);
+    F.K = (R *)(w + L.K);
+    F.nrm = (R *)(w + L.nrm);
+    F.plic = (R *)(w + L.plic);
+    F.share = (R *)(w + L.share);
+    F.phis = (R *)(w + L.phis);
+    F.nmol = (R *)(w + L.nmol);
+    F.ilist = (int32_t *)(w + L.ilist);
+    F.olist = (int32_t *)(w + L.olist);
+    F.sc = (DevScalars *)(w + L.sc);
+    F.nx = h->nx;
+    F.ny = h->ny;
+    F.nz = h->nz;
+    F.N = h->N;
+    return F;
+}
+
+inline int cell_blocks(int N) { return (N + 255) / 256; }
+inline int list_blocks(int N) { return std::min(LIST_GRID, std::max(1, (N + 255) / 256)); }
+inline int cmp_blocks(int N) { return (N + CMP_CELLS - 1) / CMP_CELLS; }
+
+// ------------------------------------------------------ init kernels
+__global__ void k_fill_bytes(uint8_t *p, size_t n, uint8_t v)
+{
+    for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) p[i] = v;
+}
+
+__global__ void k_init_scalars(DevScalars *sc)
+{
+    sc->icount = 0;
+    sc->ocount = 0;
+    sc->nconv = 0;
+    sc->step = 1;
+    sc->reservoir = 0.0;
+    sc->mass = 0.0;
+    sc->bad = 0;
+    sc->pad = 0;
+}
+
+// Types from fill level and obstacle mask (obstacle input in `types` on entry).
+__global__ void k_init_types(const double *fill, uint8_t *types, int N)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= N) return;
+    const double f = fill[i];
+    types[i] = types[i] ? FL_OBST : (f >= 1.0 ? FL_LIQ : (f <= 0.0 ? FL_GAS : FL_IF));
+}
+
+// Final flags and fields: a liquid cell with a gas D3Q19 neighbour becomes
+// an interface cell with phi = 1; f' = feq(1, 0); m = phi; rho = 1.
+template <class P>
+__global__ void k_init_fields(Fields<P> F, const double *fill, const uint8_t *types, uint8_t *out_flags)
+{
+    using R = typename P::R;
+    using T = typename P::T;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= F.N) return;
+    const Nbr nb(i, F.nx, F.ny, F.nz);
+    uint8_t t = types[i];
+    bool gas_nb = false, obst_nb = false;
+#pragma unroll
+    for (int q = 1; q < NQ; ++q) {
+        const uint8_t u = types[nb.at(dir_x(q), dir_y(q), dir_z(q))];
+        gas_nb |= u == FL_GAS;
+        obst_nb |= u == FL_OBST;
+    }
+    if (t == FL_LIQ && gas_nb) t = FL_IF;
+    out_flags[i] = t | (obst_nb ? FL_NEAR_OBST : 0);
+    R phi = 0, m = 0, rho = 0;
+    if (t == FL_LIQ) phi = 1;
+    if (t == FL_IF) {
+        phi = R(fill[i] < 1.0 ? fill[i] : 1.0);
+        m = phi;
+        rho = 1;
+    }
+    F.phi[i] = phi;
+    F.m[i] = m;
+    F.rho[i] = rho;
+    F.K[i] = 0;
+    F.plic[i] = 0;
+    F.share[i] = 0;
+    F.phis[i] = 0;
+    const size_t N = F.N;
+    for (int c = 0; c < 3; ++c) {
+        F.nrm[c * N + i] = 0;
+        F.nmol[c * N + i] = 0;
+    }
+    F.mark[i] = 0;
+    typename P::S *dst = F.fdst;
+    typename P::S *src = const_cast<typename P::S *>(F.fsrc);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const T v = t == FL_OBST ? T(0) : weight<T>(q);
+        switch (q) {
+#define FSLBM_ST(QQ)                                 \
+    case QQ:                                         \
+        store_f<P, QQ>(plane<P, QQ>(src, F.N), i, v); \
+        store_f<P, QQ>(plane<P, QQ>(dst, F.N), i, v); \
+        break;
+            FSLBM_ST(0) FSLBM_ST(1) FSLBM_ST(2) FSLBM_ST(3) FSLBM_ST(4) FSLBM_ST(5) FSLBM_ST(6)
+            FSLBM_ST(7) FSLBM_ST(8) FSLBM_ST(9) FSLBM_ST(10) FSLBM_ST(11) FSLBM_ST(12) FSLBM_ST(13)
+            FSLBM_ST(14) FSLBM_ST(15) FSLBM_ST(16) FSLBM_ST(17) FSLBM_ST(18)
+#undef FSLBM_ST
+        }
+    }
+}
+
+__global__ void k_copy_bytes(const uint8_t *src, uint8_t *dst, int N)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < N) dst[i] = src[i];
+}
+
+// f' = feq(rho, u) at fluid cells; u read from three planes of doubles.
+template <class P>
+__global__ void k_set_equilibrium(Fields<P> F, const double *rho_in, const double *u_in)
+{
+    using T = typename P::T;
+    using R = typename P::R;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= F.N) return;
+    const uint8_t fl = F.flags[i];
+    if (!(fl & FL_FLUID)) return;
+    const size_t N = F.N;
+    const T r = T(rho_in[i]), ux = T(u_in[i]), uy = T(u_in[N + i]), uz = T(u_in[2 * N + i]);
+    const T usq = ux * ux + uy * uy + uz * uz;
+    typename P::S *dst = const_cast<typename P::S *>(F.fsrc);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const T v = feq<T>(q, r, ux, uy, uz, usq);
+        switch (q) {
+#define FSLBM_ST(QQ) case QQ: store_f<P, QQ>(plane<P, QQ>(dst, F.N), i, v); break;
+            FSLBM_ST(0) FSLBM_ST(1) FSLBM_ST(2) FSLBM_ST(3) FSLBM_ST(4) FSLBM_ST(5) FSLBM_ST(6)
+            FSLBM_ST(7) FSLBM_ST(8) FSLBM_ST(9) FSLBM_ST(10) FSLBM_ST(11) FSLBM_ST(12) FSLBM_ST(13)
+            FSLBM_ST(14) FSLBM_ST(15) FSLBM_ST(16) FSLBM_ST(17) FSLBM_ST(18)
+#undef FSLBM_ST
+        }
+    }
+    if (fl & FL_IF) {
+        F.rho[i] = R(r);
+        F.m[i] = F.phi[i] * R(r);
+    }
+}
+
+// ----------------------------------------------------------- read-outs
+template <class P>
+__device__ inline void load_all(const Fields<P> &F, int i, typename P::T (&f)[NQ])
+{
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        switch (q) {
+#define FSLBM_LD(QQ) case QQ: f[q] = load_f<P, QQ>(plane<P, QQ>(F.fsrc, F.N), i); break;
+            FSLBM_LD(0) FSLBM_LD(1) FSLBM_LD(2) FSLBM_LD(3) FSLBM_LD(4) FSLBM_LD(5) FSLBM_LD(6)
+            FSLBM_LD(7) FSLBM_LD(8) FSLBM_LD(9) FSLBM_LD(10) FSLBM_LD(11) FSLBM_LD(12) FSLBM_LD(13)
+            FSLBM_LD(14) FSLBM_LD(15) FSLBM_LD(16) FSLBM_LD(17) FSLBM_LD(18)
+#undef FSLBM_LD
+        }
+    }
+}
+
+enum ReadWhat { RD_FILL, RD_PRESSURE, RD_CURV, RD_VEL, RD_NORMAL, RD_PLIC, RD_MASS };
+
+template <class P>
+__global__ void k_read(Fields<P> F, double rho_gas, int what, int comp, double *out)
+{
+    using T = typename P::T;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= F.N) return;
+    const uint8_t fl = F.flags[i];
+    const bool fluid = fl & FL_FLUID, ifc = fl & FL_IF;
+    const size_t N = F.N;
+    double v = 0.0;
+    switch (what) {
+    case RD_FILL: v = double(F.phi[i]); break;
+    case RD_CURV: v = ifc ? double(F.K[i]) : 0.0; break;
+    case RD_NORMAL: v = ifc ? double(F.nrm[comp * N + i]) : 0.0; break;
+    case RD_PLIC: v = ifc ? double(F.plic[i]) : 0.0; break;
+    case RD_MASS: v = ifc ? double(F.m[i]) : 0.0; break;
+    case RD_PRESSURE:
+    case RD_VEL:
+        if (fluid) {
+            T f[NQ];
+            load_all(F, i, f);
+            T r, ux, uy, uz;
+            moments(f, r, ux, uy, uz);
+            if (what == RD_PRESSURE) v = double(r) / 3.0;
+            else v = double(comp == 0 ? ux : (comp == 1 ? uy : uz));
+        } else if (what == RD_PRESSURE) {
+            v = (fl & FL_GAS) ? rho_gas / 3.0 : 0.0;
+        }
+        break;
+    }
+    out[i] = v;
+}
+
+__global__ void k_read_flags(const uint8_t *flags, uint8_t *out, int N)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= N) return;
+    const uint8_t t = flags[i] & FL_TYPE;
+    out[i] = t == FL_GAS ? 0 : (t == FL_LIQ ? 1 : (t == FL_IF ? 2 : 3));
+}
+
+// Mass: fixed partition of the cells over MASS_BLOCKS blocks, fixed
+// per-thread order and fixed tree inside each block, then one block adds the
+// partial sums in a fixed tree. The result does not depend on scheduling.
+template <class P>
+__global__ __launch_bounds__(256) void k_mass_partial(Fields<P> F, double *part)
+{
+    using T = typename P::T;
+    __shared__ double s[256];
+    const int chunk = (F.N + MASS_BLOCKS - 1) / MASS_BLOCKS;
+    const int b0 = blockIdx.x * chunk, b1 = min(F.N, b0 + chunk);
+    double acc = 0.0;
+    for (int i = b0 + threadIdx.x; i < b1; i += 256) {
+        const uint8_t fl = F.flags[i];
+        if (fl & FL_LIQ) {
+            T f[NQ];
+            load_all(F, i, f);
+            T r = 0;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) r += f[q];
+            acc += double(r);
+        } else if (fl & FL_IF) {
+            acc += double(F.m[i]);
+        }
+    }
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
+__global__ __launch_bounds__(1024) void k_mass_final(const double *part, DevScalars *sc)
+{
+    __shared__ double s[1024];
+    s[threadIdx.x] = threadIdx.x < MASS_BLOCKS ? part[threadIdx.x] : 0.0;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if (threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) sc->mass = s[0] + sc->reservoir;
+}
+
+template <class P>
+__global__ void k_check_numeric(Fields<P> F)
+{
+    using T = typename P::T;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= F.N) return;
+    if (!(F.flags[i] & FL_FLUID)) return;
+    T f[NQ];
+    load_all(F, i, f);
+    T r = 0;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) r += f[q];
+    if (!(r > T(0)) || !isfinite(double(r))) atomicOr(&F.sc->bad, 1);
+}
+
+// ------------------------------------------------------ host sequences
+template <class P>
+int enqueue_compaction(fslbm_lattice *h, const uint8_t *flags, uint8_t want, int32_t *list, int *count, int force)
+{
+    const Fields<P> F = make_fields<P>(h);
+    int *counts = (int *)(h->ws + h->L.counts);
+    const int nb = cmp_blocks(h->N);
+    k_compact_count<<<nb, 256, 0, h->stream>>>(flags, h->N, want, counts, F.sc, force);
+    k_compact_scan<<<1, 1024, 0, h->stream>>>(counts, nb, count, F.sc, force);
+    k_compact_write<<<nb, 256, 0, h->stream>>>(flags, h->N, want, counts, list, F.sc, force);
+    HIP_OK(hipGetLastError());
+    return 0;
+}
+
+template <class P>
+int enqueue_geometry(fslbm_lattice *h)
+{
+    const Fields<P> F = make_fields<P>(h);
+    const Params prm = make_params(h);
+    const int lb = list_blocks(h->N);
+    k_normals_plic<P><<<lb, 256, 0, h->stream>>>(F);
+    if (h->curv == FSLBM_CURV_FD) {
+        k_fd_mollify<P><<<cell_blocks(h->N), 256, 0, h->stream>>>(F);
+        k_fd_normals<P><<<cell_blocks(h->N), 256, 0, h->stream>>>(F);
+        k_fd_curvature<P><<<lb, 256, 0, h->stream>>>(F);
+    } else {
+        k_curv_lsqr<P><<<lb, 256, 0, h->stream>>>(F, prm);
+    }
+    HIP_OK(hipGetLastError());
+    return 0;
+}
+
+template <class P>
+int enqueue_step(fslbm_lattice *h)
+{
+    const Fields<P> F = make_fields<P>(h);
+    const Params prm = make_params(h);
+    const int lb = list_blocks(h->N);
+    if (h->coll == FSLBM_SRT) k_stream_collide<P, 0><<<cell_blocks(h->N), 256, 0, h->stream>>>(F, prm);
+    else k_stream_collide<P, 1><<<cell_blocks(h->N), 256, 0, h->stream>>>(F, prm);
+    k_conv_prune<P><<<lb, 256, 0, h->stream>>>(F);
+    k_conv_mark_init<P><<<lb, 256, 0, h->stream>>>(F);
+    k_conv_share<P><<<lb, 256, 0, h->stream>>>(F);
+    k_conv_gather<P><<<lb, 256, 0, h->stream>>>(F);
+    k_conv_flags<P><<<lb, 256, 0, h->stream>>>(F);
+    HIP_OK(hipGetLastError());
+    int rc = enqueue_compaction<P>(h, F.flags, FL_IF, F.ilist, &F.sc->icount, 0);
+    if (rc) return rc;
+    k_obstacle_fill<P><<<lb, 256, 0, h->stream>>>(F, 1);
+    h->cur ^= 1;  // f'(t+1) is now current
+    rc = enqueue_geometry<P>(h);
+    if (rc) return rc;
+    h->steps += 1;
+    return 0;
+}
+
+template <class P>
+int enqueue_init(fslbm_lattice *h, const double *fill, const uint8_t *obstacle)
+{
+    Fields<P> F = make_fields<P>(h);
+    const int N = h->N;
+    double *staging = (double *)(h->ws + h->L.staging);
+    HIP_OK(hipMemcpyAsync(staging, fill, sizeof(double) * N, hipMemcpyHostToDevice, h->stream));
+    if (obstacle) {
+        HIP_OK(hipMemcpyAsync(F.conv, obstacle, N, hipMemcpyHostToDevice, h->stream));
+    } else {
+        k_fill_bytes<<<std::min(4096, cell_blocks(N)), 256, 0, h->stream>>>(F.conv, N, 0);
+    }
+    k_init_scalars<<<1, 1, 0, h->stream>>>(F.sc);
+    k_init_types<<<cell_blocks(N), 256, 0, h->stream>>>(staging, F.conv, N);
+    k_init_fields<P><<<cell_blocks(N), 256, 0, h->stream>>>(F, staging, F.conv, F.flags);
+    // static list of obstacle cells next to non-obstacle cells
+    k_mark_wall_cells<<<cell_blocks(N), 256, 0, h->stream>>>(F.flags, F.conv, h->nx, h->ny, h->nz, N);
+    int rc = enqueue_compaction<P>(h, F.conv, 1, F.olist, &F.sc->ocount, 1);
+    if (rc) return rc;
+    k_fill_bytes<<<std::min(4096, cell_blocks(N)), 256, 0, h->stream>>>(F.conv, N, 0);
+    rc = enqueue_compaction<P>(h, F.flags, FL_IF, F.ilist, &F.sc->icount, 1);
+    if (rc) return rc;
+    k_obstacle_fill<P><<<list_blocks(N), 256, 0, h->stream>>>(F, 0);
+    HIP_OK(hipGetLastError());
+    return enqueue_geometry<P>(h);
+}
+
+template <class P>
+int do_read(fslbm_lattice *h, int what, double *out, int out_is_device)
+{
+    const Fields<P> F = make_fields<P>(h);
+    const int N = h->N;
+    const int comps = (what == RD_VEL || what == RD_NORMAL) ? 3 : 1;
+    double *staging = (double *)(h->ws + h->L.staging);
+    for (int c = 0; c < comps; ++c) {
+        double *dst = out_is_device ? out + (size_t)c * N : staging;
+        k_read<P><<<cell_blocks(N), 256, 0, h->stream>>>(F, h->rho_gas, what, c, dst);
+        HIP_OK(hipGetLastError());
+        if (!out_is_device)
+            HIP_OK(hipMemcpyAsync(out + (size_t)c * N, staging, sizeof(double) * N, hipMemcpyDeviceToHost, h->stream));
+    }
+    HIP_OK(hipStreamSynchronize(h->stream));
+    return 0;
+}
+
+template <class P>
+int do_mass(fslbm_lattice *h, double *total)
+{
+    const Fields<P> F = make_fields<P>(h);
+    double *part = (double *)(h->ws + h->L.part);
+    k_mass_partial<P><<<MASS_BLOCKS, 256, 0, h->stream>>>(F, part);
+    k_mass_final<<<1, 1024, 0, h->stream>>>(part, F.sc);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipMemcpyAsync(total, &F.sc->mass, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIP_OK(hipStreamSynchronize(h->stream));
+    return 0;
+}
+
+template <class P>
+int do_check(fslbm_lattice *h)
+{
+    const Fields<P> F = make_fields<P>(h);
+    int zero = 0, bad = 0;
+    HIP_OK(hipMemcpyAsync(&F.sc->bad, &zero, sizeof(int), hipMemcpyHostToDevice, h->stream));
+    k_check_numeric<P><<<cell_blocks(h->N), 256, 0, h->stream>>>(F);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipMemcpyAsync(&bad, &F.sc->bad, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    HIP_OK(hipStreamSynchronize(h->stream));
+    return bad ? fail(FSLBM_E_NUMERIC, "non-finite or non-positive density in a fluid cell") : 0;
+}
+
+template <class P>
+int do_set_equilibrium(fslbm_lattice *h, const double *rho, const double *u3)
+{
+    const Fields<P> F = make_fields<P>(h);
+    const int N = h->N;
+    double *staging = (double *)(h->ws + h->L.staging);
+    // the velocity goes through the (scratch) destination PDF buffer, whose
+    // 19 planes hold at least 3 planes of doubles for every precision
+    double *ubuf = (double *)(h->ws + (h->cur == 0 ? h->L.fB : h->L.fA));
+    HIP_OK(hipMemcpyAsync(staging, rho, sizeof(double) * N, hipMemcpyHostToDevice, h->stream));
+    HIP_OK(hipMemcpyAsync(ubuf, u3, sizeof(double) * 3 * N, hipMemcpyHostToDevice, h->stream));
+    k_set_equilibrium<P><<<cell_blocks(N), 256, 0, h->stream>>>(F, staging, ubuf);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipStreamSynchronize(h->stream));
+    return 0;
+}
+
+// Dispatch on the precision of the handle.
+template <template <class> class Op, class... A>
+int dispatch(fslbm_lattice *h, A... a)
+{
+    switch (h->prec) {
+    case P_F64: return Op<Prec<P_F64>>::run(h, a...);
+    case P_F32: return Op<Prec<P_F32>>::run(h, a...);
+    case P_F16: return Op<Prec<P_F16>>::run(h, a...);
+    default: return Op<Prec<P_BF16>>::run(h, a...);
+    }
+}
+template <class P> struct OpInit { static int run(fslbm_lattice *h, const double *f, const uint8_t *o) { return enqueue_init<P>(h, f, o); } };
+template <class P> struct OpStep { static int run(fslbm_lattice *h) { return enqueue_step<P>(h); } };
+template <class P> struct OpGeom { static int run(fslbm_lattice *h) { return enqueue_geometry<P>(h); } };
+template <class P> struct OpRead { static int run(fslbm_lattice *h, int w, double *o, int d) { return do_read<P>(h, w, o, d); } };
+template <class P> struct OpMass { static int run(fslbm_lattice *h, double *t) { return do_mass<P>(h, t); } };
+template <class P> struct OpCheck { static int run(fslbm_lattice *h) { return do_check<P>(h); } };
+template <class P> struct OpEq { static int run(fslbm_lattice *h, const double *r, const double *u) { return do_set_equilibrium<P>(h, r, u); } };
+
+}  // namespace
+
+// ================================================================ C ABI
+extern "C" {
+
+const char *fslbm_last_error(void) { return g_err.c_str(); }
+
+int fslbm_required_bytes(int nx, int ny, int nz, int precision, size_t *bytes)
+{
+    if (!bytes) return fail(FSLBM_E_ARG, "bytes is NULL");
+    if (precision < 0 || precision > 3) return fail(FSLBM_E_ARG, "unknown precision %d", precision);
+    if (!shape_ok(nx, ny, nz)) return fail(FSLBM_E_SHAPE, "lattice %dx%dx%d out of range", nx, ny, nz);
+    *bytes = make_layout((long long)nx * ny * nz, precision).total;
+    return 0;
+}
+
+int fslbm_create(int nx, int ny, int nz, int precision, int curv_model, const double *fill,
+                 const uint8_t *obstacle, void *workspace, size_t workspace_bytes, void *hip_stream,
+                 fslbm_t *out)
+{
+    if (!out) return fail(FSLBM_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!fill) return fail(FSLBM_E_ARG, "fill is NULL");
+    if (!workspace) return fail(FSLBM_E_ARG, "workspace is NULL");
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return fail(FSLBM_E_ARG, "workspace not 256-byte aligned");
+    if (precision < 0 || precision > 3) return fail(FSLBM_E_ARG, "unknown precision %d", precision);
+    if (curv_model != FSLBM_CURV_FD && curv_model != FSLBM_CURV_LSQR)
+        return fail(FSLBM_E_ARG, "unknown curvature model %d", curv_model);
+    if (!shape_ok(nx, ny, nz)) return fail(FSLBM_E_SHAPE, "lattice %dx%dx%d out of range", nx, ny, nz);
+    const long long N = (long long)nx * ny * nz;
+    const Layout L = make_layout(N, precision);
+    if (workspace_bytes < L.total)
+        return fail(FSLBM_E_SHAPE, "workspace has %zu bytes, %zu needed", workspace_bytes, L.total);
+    fslbm_lattice *h = new (std::nothrow) fslbm_lattice();
+    if (!h) return fail(FSLBM_E_STATE, "out of host memory");
+    h->nx = nx; h->ny = ny; h->nz = nz;
+    h->N = (int)N;
+    h->prec = precision;
+    h->curv = curv_model;
+    h->coll = FSLBM_SRT;
+    h->sigma = 0.0; h->tau = 1.0; h->theta = M_PI / 2; h->rho_gas = 1.0;
+    h->eps_c = 1e-3; h->trt_magic = 3.0 / 16.0;
+    h->stream = (hipStream_t)hip_stream;
+    h->ws = (char *)workspace;
+    h->L = L;
+    h->cur = 0;
+    h->steps = 0;
+    const int rc = dispatch<OpInit>(h, fill, obstacle);
+    if (rc) {
+        delete h;
+        return rc;
+    }
+    *out = h;
+    return 0;
+}
+
+int fslbm_set_params(fslbm_t h, double sigma, double tau, double theta_rad, double rho_gas)
+{
+    if (!h) return fail(FSLBM_E_STATE, "null handle");
+    if (!(sigma >= 0.0) || !std::isfinite(sigma)) return fail(FSLBM_E_ARG, "sigma must be >= 0");
+    if (!(tau > 0.5) || !std::isfinite(tau)) return fail(FSLBM_E_ARG, "tau must be > 1/2");
+    if (!(theta_rad > 0.0 && theta_rad < M_PI)) return fail(FSLBM_E_ARG, "theta must lie in (0, pi)");
+    if (!(rho_gas > 0.0) || !std::isfinite(rho_gas)) return fail(FSLBM_E_ARG, "rho_gas must be > 0");
+    h->sigma = sigma; h->tau = tau; h->theta = theta_rad; h->rho_gas = rho_gas;
+    return dispatch<OpGeom>(h);
+}
+
+int fslbm_set_option(fslbm_t h, int key, double value)
+{
+    if (!h) return fail(FSLBM_E_STATE, "null handle");
+    switch (key) {
+    case FSLBM_OPT_EPS_C:
+        if (!(value >= 0.0 && value < 0.5)) return fail(FSLBM_E_ARG, "eps_c must lie in [0, 0.5)");
+        h->eps_c = value;
+        return 0;
+    case FSLBM_OPT_COLLISION:
+        if (value != FSLBM_SRT && value != FSLBM_TRT) return fail(FSLBM_E_ARG, "collision must be SRT or TRT");
+        h->coll = (int)value;
+        return 0;
+    case FSLBM_OPT_TRT_MAGIC:
+        if (!(value > 0.0) || !std::isfinite(value)) return fail(FSLBM_E_ARG, "TRT Lambda must be > 0");
+        h->trt_magic = value;
+        return 0;
+    default: return fail(FSLBM_E_ARG, "unknown option %d", key);
+    }
+}
+
+int fslbm_set_stream(fslbm_t h, void *hip_stream)
+{
+    if (!h) return fail(FSLBM_E_STATE, "null handle");
+    h->stream = (hipStream_t)hip_stream;
+    return 0;
+}
+
+int fslbm_set_equilibrium(fslbm_t h, const double *rho, const double *u3)
+{
+    if (!h) return fail(FSLBM_E_STATE, "null handle");
+    if (!rho || !u3) return fail(FSLBM_E_ARG, "rho and u must be given");
+    return dispatch<OpEq>(h, rho, u3);
+}
+
+int fslbm_step(fslbm_t h, int64_t nsteps)
+{
+    if (!h) return fail(FSLBM_E_STATE, "null handle");
+    if (nsteps < 0) return fail(FSLBM_E_ARG, "nsteps must be >= 0");
+    for (int64_t s = 0; s < nsteps; ++s) {
+        const int rc = dispatch<OpStep>(h);
+        if (rc) return rc;
+    }
+    return 0;
+}
+
+static int read_common(fslbm_t h, int what, double *out, int dev)
+{
+    if (!h) return fail(FSLBM_E_STATE, "null handle");
+    if (!out) return fail(FSLBM_E_ARG, "out is NULL");
+    return dispatch<OpRead>(h, what, out, dev);
+}
+
+int fslbm_read_fill(fslbm_t h, double *out, int d) { return read_common(h, RD_FILL, out, d); }
+int fslbm_read_pressure(fslbm_t h, double *out, int d) { return read_common(h, RD_PRESSURE, out, d); }
+int fslbm_read_curvature(fslbm_t h, double *out, int d) { return read_common(h, RD_CURV, out, d); }
+int fslbm_read_velocity(fslbm_t h, double *out3, int d) { return read_common(h, RD_VEL, out3, d); }
+int fslbm_read_normal(fslbm_t h, double *out3, int d) { return read_common(h, RD_NORMAL, out3, d); }
+int fslbm_read_plic(fslbm_t h, double *out, int d) { return read_common(h, RD_PLIC, out, d); }
+int fslbm_read_mass_field(fslbm_t h, double *out, int d) { return read_common(h, RD_MASS, out, d); }
+
+int fslbm_read_flags(fslbm_t h, uint8_t *out, int out_is_device)
+{
+    if (!h) return fail(FSLBM_E_STATE, "null handle");
+    if (!out) return fail(FSLBM_E_ARG, "out is NULL");
+    const int N = h->N;
+    uint8_t *flags = (uint8_t *)(h->ws + h->L.flags);
+    uint8_t *dst = out_is_device ? out : (uint8_t *)(h->ws + h->L.staging);
+    k_read_flags<<<cell_blocks(N), 256, 0, h->stream>>>(flags, dst, N);
+    HIP_OK(hipGetLastError());
+    if (!out_is_device) HIP_OK(hipMemcpyAsync(out, dst, N, hipMemcpyDeviceToHost, h->stream));
+    HIP_OK(hipStreamSynchronize(h->stream));
+    return 0;
+}
+
+int fslbm_read_interface_list(fslbm_t h, int32_t *out, int64_t capacity, int64_t *count)
+{
+    if (!h) return fail(FSLBM_E_STATE, "null handle");
+    if (!count) return fail(FSLBM_E_ARG, "count is NULL");
+    const DevScalars *sc = (const DevScalars *)(h->ws + h->L.sc);
+    int n = 0;
+    HIP_OK(hipMemcpyAsync(&n, &sc->icount, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    HIP_OK(hipStreamSynchronize(h->stream));
+    *count = n;
+    if (!out) return 0;
+    if (n > capacity) return fail(FSLBM_E_SHAPE, "interface list has %d entries, capacity %lld", n, (long long)capacity);
+    if (n > 0) {
+        HIP_OK(hipMemcpyAsync(out, h->ws + h->L.ilist, sizeof(int32_t) * n, hipMemcpyDeviceToHost, h->stream));
+        HIP_OK(hipStreamSynchronize(h->stream));
+    }
+    return 0;
+}
+
+int fslbm_mass(fslbm_t h, double *total)
+{
+    if (!h) return fail(FSLBM_E_STATE, "null handle");
+    if (!total) return fail(FSLBM_E_ARG, "total is NULL");
+    return dispatch<OpMass>(h, total);
+}
+
+int fslbm_check_numeric(fslbm_t h)
+{
+    if (!h) return fail(FSLBM_E_STATE, "null handle");
+    return dispatch<OpCheck>(h);
+}
+
+int fslbm_steps_taken(fslbm_t h, int64_t *steps)
+{
+    if (!h) return fail(FSLBM_E_STATE, "null handle");
+    if (!steps) return fail(FSLBM_E_ARG, "steps is NULL");
+    *steps = h->steps;
+    return 0;
+}
+
+void fslbm_destroy(fslbm_t h) { delete h; }
+
+}  // extern "C"

@@ -1,0 +1,397 @@
+// Cell-type conversion, interface-list compaction, obstacle fill reflection.
+//
+// The paper keeps the liquid / interface / gas classification of Sec. II
+// (an interface cell has liquid and gas D3Q19 neighbours, only interface
+// cells hold 0 < phi < 1) and defers the conversion rules to Koerner et al.
+// This library uses the following rules, per step:
+//   1  interface cells fill when m > (1 + eps) rho and empty when
+//      m < -eps rho (classified in the stream-collide kernel);
+//   2  filling wins: an emptying cell with a filling D3Q19 neighbour stays;
+//   3  gas neighbours of filling cells and liquid neighbours of emptying
+//      cells become interface cells; those from gas get
+//      f' = feq(mean rho, mean u) of their liquid/interface neighbours and
+//      m = 0, those from liquid keep f' and get m = rho;
+//   4  a filling cell hands on m - rho, an emptying cell m, split equally
+//      over its D3Q19 neighbours that are interface cells after the step;
+//      with no such neighbour the amount goes to a reservoir;
+//   5  filling cells become liquid, emptying cells gas.
+// Every kernel runs over the interface list of the step (grid-stride) and is
+// written as a gather: each output value has one writer, or several writers
+// storing the identical value (new cells reached from several converting
+// neighbours). New cells are tagged in `mark` with the step number, so no
+// clearing pass is needed. Kernels return at once when no cell converts.
+#pragma once
+
+#include "fslbm_device.hpp"
+#include "fslbm_stream.hpp"
+
+namespace fslbm {
+
+constexpr int LIST_GRID = 2048;  // blocks of the grid-stride list kernels
+
+__device__ inline int list_count(const DevScalars *sc) { return *(volatile const int *)&sc->icount; }
+
+template <class P>
+__device__ inline bool is_converter(const Fields<P> &F, int j)
+{
+    return (F.flags[j] & FL_IF) && F.conv[j] != CV_NONE;
+}
+
+// Rule 2: an emptying cell next to a filling cell does not empty. Readers of
+// conv only test for CV_FILL, which this kernel never writes or clears.
+template <class P>
+__global__ __launch_bounds__(256) void k_conv_prune(Fields<P> F)
+{
+    if (F.sc->nconv == 0) return;
+    const int n = list_count(F.sc);
+    for (int k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256) {
+        const int i = F.ilist[k];
+        if (F.conv[i] != CV_EMPTY) continue;
+        const Nbr nb(i, F.nx, F.ny, F.nz);
+        bool near_fill = false;
+#pragma unroll
+        for (int q = 1; q < NQ; ++q) {
+            const int j = nb.at(dir_x(q), dir_y(q), dir_z(q));
+            near_fill |= (F.flags[j] & FL_IF) && F.conv[j] == CV_FILL;
+        }
+        if (near_fill) F.conv[i] = CV_NONE;
+    }
+}
+
+// Rule 3: tag the new interface cells and initialise them. Cells reached
+// from several converting neighbours are written identically by each.
+template <class P>
+__global__ __launch_bounds__(256) void k_conv_mark_init(Fields<P> F)
+{
+    using T = typename P::T;
+    using R = typename P::R;
+    if (F.sc->nconv == 0) return;
+    const uint32_t tag = F.sc->step << 2;
+    const int n = list_count(F.sc);
+    const int N = F.N;
+    for (int k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256) {
+        const int i = F.ilist[k];
+        const uint8_t st = F.conv[i];
+        if (st == CV_NONE) continue;
+        const Nbr nb(i, F.nx, F.ny, F.nz);
+        for (int q = 1; q < NQ; ++q) {
+            const int j = nb.at(dir_x(q), dir_y(q), dir_z(q));
+            const uint8_t tj = F.flags[j] & FL_TYPE;
+            if (st == CV_FILL && tj == FL_GAS) {
+                F.mark[j] = tag | 1u;
+                // mean rho and u over the liquid / interface neighbours of j
+                const Nbr nj(j, F.nx, F.ny, F.nz);
+                T rs = 0, usx = 0, usy = 0, usz = 0;
+                int cnt = 0;
+                for (int p = 1; p < NQ; ++p) {
+                    const int w = nj.at(dir_x(p), dir_y(p), dir_z(p));
+                    if (!(F.flags[w] & FL_FLUID)) continue;
+                    T fw[NQ];
+#pragma unroll
+                    for (int s = 0; s < NQ; ++s) {
+                        switch (s) {
+#define FSLBM_LD(QQ) case QQ: fw[s] = load_f<P, QQ>(plane<P, QQ>((const typename P::S *)F.fdst, N), w); break;
+                            FSLBM_LD(0) FSLBM_LD(1) FSLBM_LD(2) FSLBM_LD(3) FSLBM_LD(4) FSLBM_LD(5)
+                            FSLBM_LD(6) FSLBM_LD(7) FSLBM_LD(8) FSLBM_LD(9) FSLBM_LD(10) FSLBM_LD(11)
+                            FSLBM_LD(12) FSLBM_LD(13) FSLBM_LD(14) FSLBM_LD(15) FSLBM_LD(16)
+                            FSLBM_LD(17) FSLBM_LD(18)
+#undef FSLBM_LD
+                        }
+                    }
+                    T r, ux, uy, uz;
+                    moments(fw, r, ux, uy, uz);
+                    rs += r; usx += ux; usy += uy; usz += uz;
+                    ++cnt;
+                }
+                const T rm = rs / T(cnt), ux = usx / T(cnt), uy = usy / T(cnt), uz = usz / T(cnt);
+                const T usq = ux * ux + uy * uy + uz * uz;
+#pragma unroll
+                for (int s = 0; s < NQ; ++s) {
+                    const T v = feq<T>(s, rm, ux, uy, uz, usq);
+                    switch (s) {
+#define FSLBM_ST(QQ) case QQ: store_f<P, QQ>(plane<P, QQ>(F.fdst, N), j, v); break;
+                        FSLBM_ST(0) FSLBM_ST(1) FSLBM_ST(2) FSLBM_ST(3) FSLBM_ST(4) FSLBM_ST(5)
+                        FSLBM_ST(6) FSLBM_ST(7) FSLBM_ST(8) FSLBM_ST(9) FSLBM_ST(10) FSLBM_ST(11)
+                        FSLBM_ST(12) FSLBM_ST(13) FSLBM_ST(14) FSLBM_ST(15) FSLBM_ST(16)
+                        FSLBM_ST(17) FSLBM_ST(18)
+#undef FSLBM_ST
+                    }
+                }
+                F.rho[j] = R(rm);
+                F.m[j] = R(0);
+            } else if (st == CV_EMPTY && tj == FL_LIQ) {
+                F.mark[j] = tag | 2u;
+                T fw[NQ];
+#pragma unroll
+                for (int s = 0; s < NQ; ++s) {
+                    switch (s) {
+#define FSLBM_LD(QQ) case QQ: fw[s] = load_f<P, QQ>(plane<P, QQ>((const typename P::S *)F.fdst, N), j); break;
+                        FSLBM_LD(0) FSLBM_LD(1) FSLBM_LD(2) FSLBM_LD(3) FSLBM_LD(4) FSLBM_LD(5)
+                        FSLBM_LD(6) FSLBM_LD(7) FSLBM_LD(8) FSLBM_LD(9) FSLBM_LD(10) FSLBM_LD(11)
+                        FSLBM_LD(12) FSLBM_LD(13) FSLBM_LD(14) FSLBM_LD(15) FSLBM_LD(16)
+                        FSLBM_LD(17) FSLBM_LD(18)
+#undef FSLBM_LD
+                    }
+                }
+                T r = 0;
+#pragma unroll
+                for (int s = 0; s < NQ; ++s) r += fw[s];
+                F.rho[j] = R(r);
+                F.m[j] = R(r);
+            }
+        }
+    }
+}
+
+template <class P>
+__device__ inline bool is_receiver(const Fields<P> &F, int j, uint32_t tag)
+{
+    const uint8_t f = F.flags[j];
+    return ((f & FL_IF) && F.conv[j] == CV_NONE) || (F.mark[j] & ~3u) == tag;
+}
+
+// Rule 4, first half: each converting cell computes its share.
+template <class P>
+__global__ __launch_bounds__(256) void k_conv_share(Fields<P> F)
+{
+    using R = typename P::R;
+    if (F.sc->nconv == 0) return;
+    const uint32_t tag = F.sc->step << 2;
+    const int n = list_count(F.sc);
+    for (int k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256) {
+        const int i = F.ilist[k];
+        const uint8_t st = F.conv[i];
+        if (st == CV_NONE) continue;
+        const R mex = st == CV_FILL ? F.m[i] - F.rho[i] : F.m[i];
+        const Nbr nb(i, F.nx, F.ny, F.nz);
+        int cnt = 0;
+#pragma unroll
+        for (int q = 1; q < NQ; ++q) cnt += is_receiver(F, nb.at(dir_x(q), dir_y(q), dir_z(q)), tag);
+        if (cnt > 0) {
+            F.share[i] = mex / R(cnt);
+        } else {
+            F.share[i] = R(0);
+            atomicAdd(&F.sc->reservoir, (double)mex);
+        }
+    }
+}
+
+template <class P>
+__device__ inline typename P::R gathered_excess(const Fields<P> &F, int j)
+{
+    using R = typename P::R;
+    const Nbr nb(j, F.nx, F.ny, F.nz);
+    R acc = 0;
+#pragma unroll
+    for (int q = 1; q < NQ; ++q) {
+        const int w = nb.at(dir_x(q), dir_y(q), dir_z(q));
+        if (is_converter(F, w)) acc += F.share[w];
+    }
+    return acc;
+}
+
+// Rule 4, second half: receivers gather their neighbours' shares in fixed
+// direction order. This kernel also sets phi = m / rho of every interface
+// cell for the new time level, so it runs in every step.
+template <class P>
+__global__ __launch_bounds__(256) void k_conv_gather(Fields<P> F)
+{
+    using R = typename P::R;
+    const bool any = F.sc->nconv != 0;
+    const uint32_t tag = F.sc->step << 2;
+    const int n = list_count(F.sc);
+    for (int k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256) {
+        const int i = F.ilist[k];
+        const uint8_t st = any ? F.conv[i] : CV_NONE;
+        if (st == CV_NONE) {
+            const R acc = any ? gathered_excess(F, i) : R(0);
+            const R mn = F.m[i] + acc;
+            F.m[i] = mn;
+            F.phi[i] = mn / F.rho[i];
+            continue;
+        }
+        F.phi[i] = st == CV_FILL ? R(1) : R(0);
+        const Nbr nb(i, F.nx, F.ny, F.nz);
+        for (int q = 1; q < NQ; ++q) {
+            const int j = nb.at(dir_x(q), dir_y(q), dir_z(q));
+            const uint32_t mk = F.mark[j];
+            if ((mk & ~3u) != tag) continue;
+            const R base = (mk & 3u) == 1u ? R(0) : F.rho[j];
+            const R mn = base + gathered_excess(F, j);
+            F.m[j] = mn;
+            F.phi[j] = mn / F.rho[j];
+        }
+    }
+}
+
+// Rule 5 and the new interface cells' types.
+template <class P>
+__global__ __launch_bounds__(256) void k_conv_flags(Fields<P> F)
+{
+    if (F.sc->nconv == 0) return;
+    const uint32_t tag = F.sc->step << 2;
+    const int n = list_count(F.sc);
+    for (int k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256) {
+        const int i = F.ilist[k];
+        const uint8_t st = F.conv[i];
+        if (st == CV_NONE) continue;
+        const uint8_t stat = F.flags[i] & FL_NEAR_OBST;
+        F.flags[i] = stat | (st == CV_FILL ? FL_LIQ : FL_GAS);
+        const Nbr nb(i, F.nx, F.ny, F.nz);
+        for (int q = 1; q < NQ; ++q) {
+            const int j = nb.at(dir_x(q), dir_y(q), dir_z(q));
+            if ((F.mark[j] & ~3u) == tag) F.flags[j] = (F.flags[j] & FL_NEAR_OBST) | FL_IF;
+        }
+    }
+}
+
+// ----------------------------------------------------------- compaction
+// Ascending list of the cells whose flags match `want`: each block covers
+// 1024 consecutive cells (4 per thread); per-block counts, one scan block,
+// then the write pass with a wavefront-ballot / shuffle prefix sum.
+constexpr int CMP_CELLS = 1024;
+
+__device__ inline int block_exclusive_scan(int v, int *lds_wave, int &total)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    if (lane == 63) lds_wave[wave] = x;
+    __syncthreads();
+    int off = 0, tot = 0;
+    const int nw = blockDim.x >> 6;
+    for (int w = 0; w < nw; ++w) {
+        if (w < wave) off += lds_wave[w];
+        tot += lds_wave[w];
+    }
+    total = tot;
+    __syncthreads();
+    return off + x - v;
+}
+
+__device__ inline int cells_matching(const uint8_t *flags, int base, int N, uint8_t want, bool (&hit)[4])
+{
+    int c = 0;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int i = base + s;
+        hit[s] = i < N && (flags[i] & want);
+        c += hit[s];
+    }
+    return c;
+}
+
+__global__ __launch_bounds__(256) void k_compact_count(const uint8_t *flags, int N, uint8_t want,
+                                                       int *counts, const DevScalars *sc, int force)
+{
+    if (!force && sc->nconv == 0) return;
+    __shared__ int lw[4];
+    bool hit[4];
+    const int base = blockIdx.x * CMP_CELLS + threadIdx.x * 4;
+    const int c = cells_matching(flags, base, N, want, hit);
+    int total;
+    block_exclusive_scan(c, lw, total);
+    if (threadIdx.x == 0) counts[blockIdx.x] = total;
+}
+
+// One block: exclusive scan of the block counts, list length to *out_count.
+__global__ __launch_bounds__(1024) void k_compact_scan(int *counts, int nblocks, int *out_count,
+                                                       const DevScalars *sc, int force)
+{
+    if (!force && sc->nconv == 0) return;
+    __shared__ int lw[16];
+    int carry = 0;
+    for (int b0 = 0; b0 < nblocks; b0 += 1024) {
+        const int b = b0 + threadIdx.x;
+        const int v = b < nblocks ? counts[b] : 0;
+        int total;
+        const int ex = block_exclusive_scan(v, lw, total);
+        if (b < nblocks) counts[b] = carry + ex;
+        carry += total;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out_count = carry;
+}
+
+__global__ __launch_bounds__(256) void k_compact_write(const uint8_t *flags, int N, uint8_t want,
+                                                       const int *offsets, int32_t *list,
+                                                       const DevScalars *sc, int force)
+{
+    if (!force && sc->nconv == 0) return;
+    __shared__ int lw[4];
+    bool hit[4];
+    const int base = blockIdx.x * CMP_CELLS + threadIdx.x * 4;
+    const int c = cells_matching(flags, base, N, want, hit);
+    int total;
+    int pos = offsets[blockIdx.x] + block_exclusive_scan(c, lw, total);
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+        if (hit[s]) list[pos++] = base + s;
+}
+
+// Static list of obstacle cells with at least one non-obstacle D3Q19
+// neighbour: mark them with FL_NEAR_OBST in a scratch byte array.
+__global__ __launch_bounds__(256) void k_mark_wall_cells(const uint8_t *flags, uint8_t *out, int nx, int ny,
+                                                         int nz, int N)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= N) return;
+    uint8_t v = 0;
+    if (flags[i] & FL_OBST) {
+        const Nbr nb(i, nx, ny, nz);
+#pragma unroll
+        for (int q = 1; q < NQ; ++q)
+            if (!(flags[nb.at(dir_x(q), dir_y(q), dir_z(q))] & FL_OBST)) v = 1;
+    }
+    out[i] = v;
+}
+
+// ------------------------------------------------ obstacle fill (Sec. II.A)
+// phi(x_o) = sum |nw.c^_q| phi(x_o + c_q) / sum |nw.c^_q| over fluid
+// neighbours with aperture |nw.c^_q| > sqrt(2)/2 (strict; the 45-degree
+// links are excluded), nw the normalised sum of the directions from x_o to
+// its non-obstacle neighbours. Block 0 also closes the step's bookkeeping.
+template <class P>
+__global__ __launch_bounds__(256) void k_obstacle_fill(Fields<P> F, int end_of_step)
+{
+    using R = typename P::R;
+    if (end_of_step && blockIdx.x == 0 && threadIdx.x == 0) {
+        F.sc->nconv = 0;
+        F.sc->step += 1;
+    }
+    const int n = F.sc->ocount;
+    const double alpha = 0.70710678118654752440 + 1e-12;
+    for (int k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256) {
+        const int i = F.olist[k];
+        const Nbr nb(i, F.nx, F.ny, F.nz);
+        int sx = 0, sy = 0, sz = 0;
+#pragma unroll
+        for (int q = 1; q < NQ; ++q)
+            if (!(F.flags[nb.at(dir_x(q), dir_y(q), dir_z(q))] & FL_OBST)) {
+                sx += dir_x(q); sy += dir_y(q); sz += dir_z(q);
+            }
+        const double len = sqrt(double(sx * sx + sy * sy + sz * sz));
+        double num = 0, den = 0;
+        if (len > 0) {
+            const double wx = sx / len, wy = sy / len, wz = sz / len;
+#pragma unroll
+            for (int q = 1; q < NQ; ++q) {
+                const int j = nb.at(dir_x(q), dir_y(q), dir_z(q));
+                if (!(F.flags[j] & FL_FLUID)) continue;
+                const double cl = sqrt(double(dir_len2(q)));
+                const double w = fabs((wx * dir_x(q) + wy * dir_y(q) + wz * dir_z(q)) / cl);
+                if (w > alpha) {
+                    num += w * double(F.phi[j]);
+                    den += w;
+                }
+            }
+        }
+        F.phi[i] = R(den > 0 ? num / den : 0.0);
+    }
+}
+
+}  // namespace fslbm

@@ -1,0 +1,173 @@
+// Device-side definitions shared by the FSLBM kernels: D3Q19 lattice,
+// precision traits, cell flags and the field bundle handed to every kernel.
+#pragma once
+
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fslbm {
+
+// ---------------------------------------------------------------- lattice
+// D3Q19 (Sec. II): rest, the 6 face and the 12 edge directions. Directions
+// 2k-1 and 2k are opposite. Weights 1/3, 1/18, 1/36 (Qian et al. 1992).
+constexpr int NQ = 19;
+// Components are encoded as bit masks over q (bit q set: component +1 or
+// -1), which folds to constants in unrolled loops and stays a few integer
+// operations for a run-time q.
+constexpr unsigned XP = (1u << 1) | (1u << 7) | (1u << 9) | (1u << 11) | (1u << 13);
+constexpr unsigned XM = (1u << 2) | (1u << 8) | (1u << 10) | (1u << 12) | (1u << 14);
+constexpr unsigned YP = (1u << 3) | (1u << 7) | (1u << 10) | (1u << 15) | (1u << 17);
+constexpr unsigned YM = (1u << 4) | (1u << 8) | (1u << 9) | (1u << 16) | (1u << 18);
+constexpr unsigned ZP = (1u << 5) | (1u << 11) | (1u << 14) | (1u << 15) | (1u << 18);
+constexpr unsigned ZM = (1u << 6) | (1u << 12) | (1u << 13) | (1u << 16) | (1u << 17);
+__host__ __device__ constexpr int dir_x(int q) { return int((XP >> q) & 1u) - int((XM >> q) & 1u); }
+__host__ __device__ constexpr int dir_y(int q) { return int((YP >> q) & 1u) - int((YM >> q) & 1u); }
+__host__ __device__ constexpr int dir_z(int q) { return int((ZP >> q) & 1u) - int((ZM >> q) & 1u); }
+__host__ __device__ constexpr int opp(int q) { return q == 0 ? 0 : ((q & 1) ? q + 1 : q - 1); }
+__host__ __device__ constexpr int dir_len2(int q)
+{
+    return dir_x(q) * dir_x(q) + dir_y(q) * dir_y(q) + dir_z(q) * dir_z(q);
+}
+template <class T>
+__host__ __device__ constexpr T weight(int q)
+{
+    return dir_len2(q) == 0 ? T(1) / T(3) : (dir_len2(q) == 1 ? T(1) / T(18) : T(1) / T(36));
+}
+
+// ------------------------------------------------------------- cell flags
+// Low nibble: cell type (exactly one bit). Bit 4 (static): the cell has an
+// obstacle among its D3Q19 neighbours.
+enum : uint8_t {
+    FL_GAS = 1,
+    FL_LIQ = 2,
+    FL_IF = 4,
+    FL_OBST = 8,
+    FL_TYPE = 15,
+    FL_FLUID = FL_LIQ | FL_IF,
+    FL_NEAR_OBST = 16,
+};
+// Conversion status of an interface cell within one step.
+enum : uint8_t { CV_NONE = 0, CV_FILL = 1, CV_EMPTY = 2 };
+
+// ------------------------------------------------------- precision traits
+// S: stored type of a distribution, T: arithmetic type of the collide,
+// R: type of the scalar fields m, rho, phi, K, normals and PLIC offsets.
+// Shifted storage keeps g_q = (f_q - w_q) * SCALE.
+enum Precision { P_F64 = 0, P_F32 = 1, P_F16 = 2, P_BF16 = 3 };
+
+template <int P> struct Prec;
+template <> struct Prec<P_F64> {
+    using S = double; using T = double; using R = double;
+    static constexpr bool SHIFT = false;
+    static constexpr double SCALE = 1.0;
+};
+template <> struct Prec<P_F32> {
+    using S = float; using T = float; using R = float;
+    static constexpr bool SHIFT = false;
+    static constexpr double SCALE = 1.0;
+};
+template <> struct Prec<P_F16> {
+    using S = __half; using T = float; using R = float;
+    static constexpr bool SHIFT = true;
+    static constexpr double SCALE = 4096.0;
+};
+template <> struct Prec<P_BF16> {
+    using S = __hip_bfloat16; using T = float; using R = float;
+    static constexpr bool SHIFT = true;
+    static constexpr double SCALE = 1.0;
+};
+
+__device__ inline float to_float(__half v) { return __half2float(v); }
+__device__ inline float to_float(__hip_bfloat16 v) { return __bfloat162float(v); }
+template <class S> __device__ inline S from_float(float v);
+// Round-to-nearest-even conversions (a truncating conversion would bias the
+// stored distributions and show up as mass drift).
+template <> __device__ inline __half from_float<__half>(float v) { return __float2half_rn(v); }
+template <> __device__ inline __hip_bfloat16 from_float<__hip_bfloat16>(float v) { return __float2bfloat16(v); }
+
+template <class P, int Q>
+__device__ inline typename P::T load_f(const typename P::S *__restrict__ plane, int i)
+{
+    using T = typename P::T;
+    if constexpr (P::SHIFT) {
+        return weight<T>(Q) + to_float(plane[i]) * T(1.0 / P::SCALE);
+    } else {
+        return plane[i];
+    }
+}
+template <class P, int Q>
+__device__ inline void store_f(typename P::S *__restrict__ plane, int i, typename P::T v)
+{
+    using S = typename P::S;
+    if constexpr (P::SHIFT) {
+        plane[i] = from_float<S>((v - weight<typename P::T>(Q)) * typename P::T(P::SCALE));
+    } else {
+        plane[i] = v;
+    }
+}
+
+// ------------------------------------------------------ per-step scalars
+struct DevScalars {
+    int icount;         // number of interface cells in ilist
+    int ocount;         // number of obstacle cells in olist (static)
+    int nconv;          // interface cells that fill or empty in this step
+    unsigned step;      // completed steps + 1 (conversion tag, never 0)
+    double reservoir;   // excess mass that found no receiving cell
+    double mass;        // result of the last mass reduction
+    int bad;            // numeric check result
+    int pad;
+};
+
+// Model parameters (Sec. II): rho_b = 3 (p_g + sigma K), p_g = rho_gas / 3.
+struct Params {
+    double sigma;
+    double tau;
+    double omega;      // 1/tau
+    double omega_odd;  // TRT odd rate
+    double cos_theta, sin_theta;
+    double rho_gas;
+    double eps_c;
+};
+
+template <class P> struct Fields {
+    using S = typename P::S;
+    using R = typename P::R;
+    const S *fsrc;     // f'(t), 19 planes of N
+    S *fdst;           // f'(t+1)
+    uint8_t *flags;
+    uint8_t *conv;
+    uint32_t *mark;
+    R *m, *rho, *phi, *K, *nrm, *plic, *share, *phis, *nmol;
+    int32_t *ilist, *olist;
+    DevScalars *sc;
+    int nx, ny, nz;
+    int N;
+};
+
+// Periodic neighbour offsets of one cell: index of (x+dx, y+dy, z+dz) is
+// ox[dx+1] + oy[dy+1] + oz[dz+1].
+struct Nbr {
+    int ox[3], oy[3], oz[3];
+    int x, y, z;
+    __device__ inline Nbr(int i, int nx, int ny, int nz)
+    {
+        const int yz = i / nx;
+        x = i - yz * nx;
+        z = yz / ny;
+        y = yz - z * ny;
+        const int nxy = nx * ny;
+        ox[0] = x == 0 ? nx - 1 : x - 1; ox[1] = x; ox[2] = x == nx - 1 ? 0 : x + 1;
+        oy[0] = (y == 0 ? ny - 1 : y - 1) * nx; oy[1] = y * nx;
+        oy[2] = (y == ny - 1 ? 0 : y + 1) * nx;
+        oz[0] = (z == 0 ? nz - 1 : z - 1) * nxy; oz[1] = z * nxy;
+        oz[2] = (z == nz - 1 ? 0 : z + 1) * nxy;
+    }
+    __device__ inline int at(int dx, int dy, int dz) const
+    {
+        return ox[dx + 1] + oy[dy + 1] + oz[dz + 1];
+    }
+};
+
+}  // namespace fslbm

@@ -1,0 +1,313 @@
+"""Python binding of libfslbm (C ABI in include/fslbm.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+of libfslbm.so. PyTorch provides the device workspace and the stream. The
+module raises ImportError-style errors when the library is missing; there is
+no CPU fallback.
+
+Module-level functions carry the names of the C entry points; `Lattice`
+bundles one handle with its workspace.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfslbm.so")
+
+FSLBM_F64, FSLBM_F32, FSLBM_F16_STORE, FSLBM_BF16_STORE = 0, 1, 2, 3
+FSLBM_CURV_FD, FSLBM_CURV_LSQR = 0, 1
+FSLBM_SRT, FSLBM_TRT = 0, 1
+FSLBM_GAS, FSLBM_LIQUID, FSLBM_INTERFACE, FSLBM_OBSTACLE = 0, 1, 2, 3
+FSLBM_OPT_EPS_C, FSLBM_OPT_COLLISION, FSLBM_OPT_TRT_MAGIC = 0, 1, 2
+
+PRECISIONS = {"f64": FSLBM_F64, "f32": FSLBM_F32, "f16": FSLBM_F16_STORE, "bf16": FSLBM_BF16_STORE}
+MODELS = {"fd": FSLBM_CURV_FD, "lsqr": FSLBM_CURV_LSQR}
+
+
+class FslbmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libfslbm error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libfslbm.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FileNotFoundError(
+            f"{path} is missing: build it with paper_1509_07691_amd/build_lib.py (no CPU fallback exists)")
+    L = ctypes.CDLL(path)
+    vp, dp, i32, i64 = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int, ctypes.c_int64
+    u8p = ctypes.POINTER(ctypes.c_uint8)
+    sig = {
+        "fslbm_required_bytes": [i32, i32, i32, i32, ctypes.POINTER(ctypes.c_size_t)],
+        "fslbm_create": [i32, i32, i32, i32, i32, dp, u8p, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)],
+        "fslbm_set_params": [vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double],
+        "fslbm_set_option": [vp, i32, ctypes.c_double],
+        "fslbm_set_stream": [vp, vp],
+        "fslbm_set_equilibrium": [vp, dp, dp],
+        "fslbm_step": [vp, i64],
+        "fslbm_read_fill": [vp, vp, i32],
+        "fslbm_read_pressure": [vp, vp, i32],
+        "fslbm_read_curvature": [vp, vp, i32],
+        "fslbm_read_velocity": [vp, vp, i32],
+        "fslbm_read_normal": [vp, vp, i32],
+        "fslbm_read_plic": [vp, vp, i32],
+        "fslbm_read_mass_field": [vp, vp, i32],
+        "fslbm_read_flags": [vp, vp, i32],
+        "fslbm_read_interface_list": [vp, ctypes.POINTER(ctypes.c_int32), i64, ctypes.POINTER(i64)],
+        "fslbm_mass": [vp, dp],
+        "fslbm_check_numeric": [vp],
+        "fslbm_steps_taken": [vp, ctypes.POINTER(i64)],
+    }
+    for name, args in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    L.fslbm_destroy.argtypes = [vp]
+    L.fslbm_destroy.restype = None
+    L.fslbm_last_error.argtypes = []
+    L.fslbm_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != 0:
+        raise FslbmError(rc, load_library().fslbm_last_error().decode())
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+# ---------------------------------------------- C entry points, same names
+def fslbm_required_bytes(nx, ny, nz, precision):
+    out = ctypes.c_size_t(0)
+    _check(load_library().fslbm_required_bytes(nx, ny, nz, precision, ctypes.byref(out)))
+    return out.value
+
+
+def fslbm_create(nx, ny, nz, precision, curv_model, fill, obstacle, workspace_ptr, workspace_bytes, stream_ptr):
+    fill = np.ascontiguousarray(fill, dtype=np.float64).reshape(-1)
+    if fill.size != nx * ny * nz:
+        raise ValueError("fill has the wrong size")
+    obs = None
+    if obstacle is not None:
+        obs = np.ascontiguousarray(obstacle, dtype=np.uint8).reshape(-1)
+        if obs.size != fill.size:
+            raise ValueError("obstacle has the wrong size")
+    h = ctypes.c_void_p()
+    _check(load_library().fslbm_create(
+        nx, ny, nz, precision, curv_model, _dptr(fill),
+        obs.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)) if obs is not None else None,
+        ctypes.c_void_p(workspace_ptr), workspace_bytes, ctypes.c_void_p(stream_ptr), ctypes.byref(h)))
+    return h
+
+
+def fslbm_set_params(h, sigma, tau, theta_rad, rho_gas):
+    _check(load_library().fslbm_set_params(h, sigma, tau, theta_rad, rho_gas))
+
+
+def fslbm_set_option(h, key, value):
+    _check(load_library().fslbm_set_option(h, key, float(value)))
+
+
+def fslbm_set_stream(h, stream_ptr):
+    _check(load_library().fslbm_set_stream(h, ctypes.c_void_p(stream_ptr)))
+
+
+def fslbm_set_equilibrium(h, rho, u3):
+    rho = np.ascontiguousarray(rho, dtype=np.float64).reshape(-1)
+    u3 = np.ascontiguousarray(u3, dtype=np.float64).reshape(-1)
+    _check(load_library().fslbm_set_equilibrium(h, _dptr(rho), _dptr(u3)))
+
+
+def fslbm_step(h, nsteps):
+    _check(load_library().fslbm_step(h, int(nsteps)))
+
+
+def _read(name, h, out, device):
+    ptr = out.data_ptr() if device else out.ctypes.data
+    _check(getattr(load_library(), name)(h, ctypes.c_void_p(ptr), 1 if device else 0))
+    return out
+
+
+def fslbm_read_fill(h, out, device=False):
+    return _read("fslbm_read_fill", h, out, device)
+
+
+def fslbm_read_pressure(h, out, device=False):
+    return _read("fslbm_read_pressure", h, out, device)
+
+
+def fslbm_read_curvature(h, out, device=False):
+    return _read("fslbm_read_curvature", h, out, device)
+
+
+def fslbm_read_velocity(h, out3, device=False):
+    return _read("fslbm_read_velocity", h, out3, device)
+
+
+def fslbm_read_normal(h, out3, device=False):
+    return _read("fslbm_read_normal", h, out3, device)
+
+
+def fslbm_read_plic(h, out, device=False):
+    return _read("fslbm_read_plic", h, out, device)
+
+
+def fslbm_read_mass_field(h, out, device=False):
+    return _read("fslbm_read_mass_field", h, out, device)
+
+
+def fslbm_read_flags(h, out, device=False):
+    return _read("fslbm_read_flags", h, out, device)
+
+
+def fslbm_read_interface_list(h):
+    L = load_library()
+    cnt = ctypes.c_int64(0)
+    _check(L.fslbm_read_interface_list(h, None, 0, ctypes.byref(cnt)))
+    out = np.zeros(max(cnt.value, 1), dtype=np.int32)
+    _check(L.fslbm_read_interface_list(h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                       out.size, ctypes.byref(cnt)))
+    return out[:cnt.value]
+
+
+def fslbm_mass(h):
+    out = ctypes.c_double(0.0)
+    _check(load_library().fslbm_mass(h, ctypes.byref(out)))
+    return out.value
+
+
+def fslbm_check_numeric(h):
+    _check(load_library().fslbm_check_numeric(h))
+
+
+def fslbm_steps_taken(h):
+    out = ctypes.c_int64(0)
+    _check(load_library().fslbm_steps_taken(h, ctypes.byref(out)))
+    return out.value
+
+
+def fslbm_destroy(h):
+    load_library().fslbm_destroy(h)
+
+
+# ---------------------------------------------------------------- wrapper
+class Lattice:
+    """One FSLBM lattice on a HIP device; arrays are (nz, ny, nx), x fastest.
+
+    The device workspace is a torch uint8 tensor owned by this object; work
+    runs on the torch stream that is current at construction unless a
+    stream is given.
+    """
+
+    def __init__(self, fill, obstacle=None, *, precision="f64", curv_model="fd", sigma=0.0, tau=1.0,
+                 theta=math.pi / 2, rho_gas=1.0, eps_c=None, collision="srt", trt_magic=None,
+                 device="cuda:0", stream=None):
+        import torch
+
+        fill = np.ascontiguousarray(fill, dtype=np.float64)
+        if fill.ndim != 3:
+            raise ValueError("fill must be 3-d (nz, ny, nx)")
+        self.shape = fill.shape
+        nz, ny, nx = fill.shape
+        self.n = fill.size
+        self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        self.curv_model = MODELS[curv_model] if isinstance(curv_model, str) else int(curv_model)
+        self.device = torch.device(device)
+        nbytes = fslbm_required_bytes(nx, ny, nz, self.precision)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._h = None
+        self._h = fslbm_create(nx, ny, nz, self.precision, self.curv_model, fill, obstacle,
+                               self.workspace.data_ptr(), nbytes, self.stream.cuda_stream)
+        if eps_c is not None:
+            fslbm_set_option(self._h, FSLBM_OPT_EPS_C, eps_c)
+        if trt_magic is not None:
+            fslbm_set_option(self._h, FSLBM_OPT_TRT_MAGIC, trt_magic)
+        fslbm_set_option(self._h, FSLBM_OPT_COLLISION, FSLBM_TRT if collision == "trt" else FSLBM_SRT)
+        fslbm_set_params(self._h, sigma, tau, theta, rho_gas)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h is not None:
+            fslbm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, sigma, tau, theta, rho_gas):
+        fslbm_set_params(self._h, sigma, tau, theta, rho_gas)
+
+    def set_equilibrium(self, rho, u):
+        rho = np.broadcast_to(np.asarray(rho, dtype=np.float64), self.shape)
+        fslbm_set_equilibrium(self._h, rho, u)
+
+    def step(self, nsteps=1):
+        fslbm_step(self._h, nsteps)
+
+    def _host(self, fn, comps=1):
+        out = np.zeros(comps * self.n, dtype=np.float64)
+        fn(self._h, out)
+        return out.reshape((comps,) + self.shape) if comps > 1 else out.reshape(self.shape)
+
+    def fill(self):
+        return self._host(fslbm_read_fill)
+
+    def pressure(self):
+        return self._host(fslbm_read_pressure)
+
+    def density(self):
+        return 3.0 * self.pressure()
+
+    def curvature(self):
+        return self._host(fslbm_read_curvature)
+
+    def velocity(self):
+        return self._host(fslbm_read_velocity, 3)
+
+    def normal(self):
+        return self._host(fslbm_read_normal, 3)
+
+    def plic(self):
+        return self._host(fslbm_read_plic)
+
+    def mass_field(self):
+        return self._host(fslbm_read_mass_field)
+
+    def flags(self):
+        out = np.zeros(self.n, dtype=np.uint8)
+        fslbm_read_flags(self._h, out)
+        return out.reshape(self.shape)
+
+    def interface_list(self):
+        return fslbm_read_interface_list(self._h)
+
+    def mass(self):
+        return fslbm_mass(self._h)
+
+    def check_numeric(self):
+        fslbm_check_numeric(self._h)
+
+    def steps_taken(self):
+        return fslbm_steps_taken(self._h)
