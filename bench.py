@@ -1,0 +1,231 @@
+"""Benchmark of the FSLBM hot path on one MI355X.
+
+Default workload: the static-droplet sweep of radius 32 in a periodic 128^3
+lattice, FP32 storage and arithmetic, eight runs (tau 0.6 / 1.0 x sigma 1e-4 /
+1e-3 x FD / LSQR curvature) advanced together; one step is one time step of
+all eight lattices (stream-collide with mass exchange, conversions, list
+compaction, obstacle fill, curvature). Inputs are synthetic: exact sphere
+volume fractions plus 1e-6 uniform noise on interface cells (seed 0).
+
+Prints one JSON line: MLUPS over all lattice cells (value), the roofline of the
+dominant kernel (stream-collide, timed with HIP events on each lattice's own
+stream inside the timed region) and the FP64 CPU reference timed on a bounded
+sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "D3Q19 FSLBM MLUPS + %HBM roofline (FP32 vs FP16 store); adjoint/forward cost"
+HBM_PEAK_GBS = 8000.0
+STREAM_SRC = os.path.join(ROOT, "paper_1509_07691_amd", "csrc", "fslbm_stream.hpp")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stream_collide_traffic.json")
+FBYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
+RBYTES = {"f64": 8, "f32": 4, "f16": 4, "bf16": 4}
+
+
+def workload_runs(name):
+    """List of (label, fill, obstacle, params) of one workload."""
+    from paper_1509_07691_amd import inputs as I
+
+    if name == "c1":
+        fill, obst = I.droplet(128, 32.0, noise=1e-6, seed=0)
+        runs = []
+        for model in ("fd", "lsqr"):
+            for tau in (0.6, 1.0):
+                for sigma in (1e-4, 1e-3):
+                    runs.append((f"{model}-tau{tau}-sigma{sigma}", fill, obst,
+                                 dict(curv_model=model, tau=tau, sigma=sigma)))
+        desc = ("static droplet R=32 in periodic 128^3, 8 runs (tau 0.6/1.0 x sigma 1e-4/1e-3 x FD/LSQR) "
+                "stepped together")
+        return runs, desc
+    if name == "c3":
+        fill, obst = I.ellipsoid_droplet(512, (96, 80, 80), noise=1e-6, seed=0)
+        return [("ellipsoid", fill, obst, dict(curv_model="lsqr", tau=0.55, sigma=1e-3))], \
+            "oscillating droplet, ellipsoid 96/80/80 in periodic 512^3, LSQR"
+    if name == "probe":
+        fill, obst = I.bubble_probe(512, 64.0)
+        return [("bubble", fill, obst, dict(curv_model="lsqr", tau=0.8, sigma=1e-3))], \
+            "gas bubble R=64 in liquid-filled periodic 512^3, LSQR"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def sc_bytes(flags, prec):
+    """Algorithmic bytes of one launch of the liquid stream-collide kernel:
+    19 reads + 19 writes of a distribution per liquid cell and 1 flag byte
+    per lattice cell; and of the interface kernel: the same 38 distribution
+    accesses per interface cell plus m (read, write), rho (write), K and phi
+    (read) and one status byte."""
+    nl = int((flags == 1).sum())
+    ni = int((flags == 2).sum())
+    n = flags.size
+    return 38 * FBYTES[prec] * nl + n, ni * (38 * FBYTES[prec] + 5 * RBYTES[prec] + 1), nl, ni
+
+
+def stored_traffic():
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    h = hashlib.sha256(open(STREAM_SRC, "rb").read()).hexdigest()
+    return rec if rec.get("source_sha256") == h else None
+
+
+def cpu_baseline(runs, budget_s):
+    """FP64 oracle (single thread) on the first run of the workload, timed
+    until budget_s of stepping has elapsed."""
+    import oracle as O
+
+    label, fill, obst, p = runs[0]
+    orc = O.Oracle(fill, obst, sigma=p["sigma"], tau=p["tau"],
+                   curv_model=O.CURV_FD if p["curv_model"] == "fd" else O.CURV_LSQR)
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        orc.step(1)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s:
+            break
+    return {"value": fill.size * steps / el / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} steps of one {'x'.join(map(str, fill.shape[::-1]))} lattice ({label}), "
+                      f"{el:.1f} s, FP64, single-threaded plain C"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="c1", choices=["c1", "c3", "probe"])
+    ap.add_argument("--precision", default="f32", choices=["f64", "f32", "f16", "bf16"])
+    ap.add_argument("--graph", type=int, default=1,
+                    help="also time a graph-replay pass after the timed region")
+    ap.add_argument("--split", type=int, default=0,
+                    help="1: interface cells in their own list kernel (same results)")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(use --gpus 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1509_07691_amd.fslbm import Batch, Lattice
+
+    dev = torch.device("cuda:0")
+    runs, desc = workload_runs(args.workload)
+    stream = torch.cuda.Stream(dev)
+    lats = []
+    with torch.cuda.stream(stream):
+        for label, fill, obst, p in runs:
+            lats.append(Lattice(fill, obst, precision=args.precision, device=dev, stream=stream, **p))
+    batch = Batch(lats)
+    if args.split:
+        batch.set_split_interface(True)
+    torch.cuda.synchronize()
+    print(f"# {len(lats)} lattice(s) created: {desc}", file=sys.stderr, flush=True)
+
+    batch.step(args.warmup)
+    torch.cuda.synchronize()
+    batch.set_timing(True)
+    batch.reset_timing()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.step(args.steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms_per_step = 1e3 * el / args.steps
+    phase, st = batch.timing()
+    assert st == args.steps
+    batch.set_timing(False)
+
+    bytes_liq = bytes_if = 0
+    nl_tot = ni_tot = ncell = 0
+    for lat in lats:
+        bl, bi, nl, ni = sc_bytes(lat.flags(), args.precision)
+        bytes_liq += bl
+        bytes_if += bi
+        nl_tot += nl
+        ni_tot += ni
+        ncell += lat.n
+        lat.check_numeric()
+    nf_tot = nl_tot + ni_tot
+    sc_ms = phase[0]
+    # merged mode: the bulk kernel also moves the interface cells' bytes
+    sc_bytes_launch = bytes_liq if args.split else bytes_liq + bytes_if
+    achieved = sc_bytes_launch * args.steps / (sc_ms * 1e-3) / 1e9
+    if_achieved = bytes_if * args.steps / (phase[1] * 1e-3) / 1e9 if args.split else None
+    mlups = ncell * args.steps / el / 1e6
+    traffic = stored_traffic()
+
+    # the same number of steps replayed from HIP graphs, untimed per kernel
+    graph_ms = None
+    if args.graph:
+        batch.set_graph(True)
+        batch.step(2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        batch.step(args.steps)
+        torch.cuda.synchronize()
+        graph_ms = 1e3 * (time.perf_counter() - t0) / args.steps
+        batch.set_graph(False)
+    res = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.precision,
+        "data": "synthetic",
+        "config": {"workload": desc, "lattice": list(runs[0][1].shape[::-1]), "lattices": len(lats),
+                   "storage": args.precision, "batched_launches": True, "split_interface": bool(args.split),
+                   "fluid_cells": nf_tot, "interface_cells": ni_tot},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": (traffic or {}).get("bytes_per_launch") if traffic else None,
+                     "kernel": "k_stream_collide" + (" (liquid cells)" if args.split else " (liquid and interface cells)")
+                               + ", all lattices in one launch",
+                     "avg_launch_us": round(1e3 * sc_ms / args.steps, 3),
+                     "algorithmic_bytes_per_launch": int(sc_bytes_launch)},
+        "phases_ms_per_step": {k: round(v / args.steps, 4) for k, v in
+                               zip(("stream_collide_liquid", "stream_collide_interface", "conversion",
+                                    "compaction", "geometry"), phase)},
+        "mflups": round(nf_tot * args.steps / el / 1e6, 1),
+    }
+    if args.split:
+        res["interface_kernel"] = {"kernel": "k_stream_collide_interface",
+                                   "avg_launch_us": round(1e3 * phase[1] / args.steps, 3),
+                                   "algorithmic_bytes_per_launch": int(bytes_if), "achieved_GBs": round(if_achieved, 1)}
+    if graph_ms is not None:
+        res["graph_replay"] = {"ms_per_step": round(graph_ms, 4),
+                               "mlups": round(ncell / graph_ms / 1e3, 1)}
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_baseline(runs, args.cpu_seconds)
+    batch.close()
+    for lat in lats:
+        lat.close()
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

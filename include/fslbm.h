@@ -43,6 +43,7 @@ extern "C" {
 #endif
 
 typedef struct fslbm_lattice *fslbm_t;
+typedef struct fslbm_batch *fslbm_batch_t;
 
 enum fslbm_status {
     FSLBM_OK = 0,
@@ -67,7 +68,16 @@ enum fslbm_option {
     FSLBM_OPT_EPS_C = 0,      /* conversion offset eps: fill if m > (1+eps) rho,
                                  empty if m < -eps rho (default 1e-3) */
     FSLBM_OPT_COLLISION = 1,  /* FSLBM_SRT (default) or FSLBM_TRT */
-    FSLBM_OPT_TRT_MAGIC = 2   /* TRT Lambda = (tau-1/2)(tau_odd-1/2), default 3/16 */
+    FSLBM_OPT_TRT_MAGIC = 2,  /* TRT Lambda = (tau-1/2)(tau_odd-1/2), default 3/16 */
+    FSLBM_OPT_TIMING = 3,     /* 1: record HIP events around the phases of every
+                                 step (read with fslbm_read_timing), 0: off */
+    FSLBM_OPT_GRAPH = 4,      /* 1: replay each step as a captured HIP graph
+                                 (ignored while timing is on or on the null
+                                 stream), 0: plain launches (default) */
+    FSLBM_OPT_SPLIT_INTERFACE = 5  /* 1: interface cells stream and collide in
+                                 their own kernel over the interface list;
+                                 0 (default): inside the bulk kernel. Results
+                                 are identical either way. */
 };
 
 /* Device workspace needed for a lattice (bytes, written to *bytes).
@@ -115,8 +125,9 @@ int fslbm_step(fslbm_t h, int64_t nsteps);
  *  pressure: rho/3 at fluid cells, rho_gas/3 at gas cells, 0 at obstacles;
  *  curvature: K at interface cells, 0 elsewhere;
  *  velocity: u at fluid cells, 0 elsewhere;
- *  normal / plic: unit normal of the raw fill level and PLIC plane offset
- *  (point p = cell centre + a n) at interface cells, 0 elsewhere;
+ *  normal / plic: unit normal of the raw fill level and (LSQR model only)
+ *  PLIC plane offset (point p = cell centre + a n) at interface cells,
+ *  0 elsewhere;
  *  mass_field: interface mass m (0 at other cells). */
 int fslbm_read_fill(fslbm_t h, double *out, int out_is_device);
 int fslbm_read_pressure(fslbm_t h, double *out, int out_is_device);
@@ -140,6 +151,31 @@ int fslbm_check_numeric(fslbm_t h);
 /* Number of time steps taken since creation. */
 int fslbm_steps_taken(fslbm_t h, int64_t *steps);
 
+/* Batches: 1..8 lattices of the same precision, on the same stream and at
+ * the same step count, advanced together; each kernel of a step is launched
+ * once for all of them (the lattice index is the second grid dimension), so
+ * small lattices fill the device and a step is one graph when
+ * FSLBM_OPT_GRAPH is set on the batch. The batch holds the handles (not
+ * their memory); destroy it before its handles. Stepping a batch advances
+ * each lattice exactly as fslbm_step would. Only FSLBM_OPT_TIMING,
+ * FSLBM_OPT_GRAPH and FSLBM_OPT_SPLIT_INTERFACE apply to a batch. */
+int fslbm_batch_create(const fslbm_t *handles, int count, fslbm_batch_t *out);
+int fslbm_batch_step(fslbm_batch_t b, int64_t nsteps);
+int fslbm_batch_set_option(fslbm_batch_t b, int key, double value);
+int fslbm_batch_read_timing(fslbm_batch_t b, double *phase_ms, int64_t *steps);
+int fslbm_batch_reset_timing(fslbm_batch_t b);
+void fslbm_batch_destroy(fslbm_batch_t b);
+
+/* Accumulated device time (ms) of the five phases of a step while
+ * FSLBM_OPT_TIMING is on, phase_ms[5]: [0] stream-collide of liquid cells,
+ * [1] stream-collide with mass exchange of interface cells, [2] cell
+ * conversion, [3] interface-list compaction, [4] obstacle fill and
+ * curvature; *steps receives the number of timed steps. Synchronises. */
+int fslbm_read_timing(fslbm_t h, double *phase_ms, int64_t *steps);
+int fslbm_reset_timing(fslbm_t h);
+
+/* Synchronises the handle's stream and frees the handle (not the caller's
+ * workspace). */
 void fslbm_destroy(fslbm_t h);
 const char *fslbm_last_error(void);
 

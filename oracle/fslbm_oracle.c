@@ -443,9 +443,10 @@ static void obstacle_fill(orc_lattice *L)
 }
 
 /* ---- curvature ---------------------------------------------------------- */
-/* Normals from raw phi and PLIC offsets at interface cells (Sec. II.B: the
- * PLIC normal uses no convolution). An interface cell whose gradient
- * vanishes gets a zero normal and no PLIC point. */
+/* Normals from raw phi at interface cells (the corner rule uses them with
+ * both models) and, for the LSQR model, PLIC offsets (Sec. II.B: the PLIC
+ * normal uses no convolution). An interface cell whose gradient vanishes
+ * gets a zero normal and no PLIC point. */
 static void normals_and_plic(orc_lattice *L)
 {
     for (long i = 0; i < L->n; ++i) {
@@ -460,7 +461,7 @@ static void normals_and_plic(orc_lattice *L)
         L->nrm[3 * i] = nh[0];
         L->nrm[3 * i + 1] = nh[1];
         L->nrm[3 * i + 2] = nh[2];
-        L->plic[i] = orc_plic_offset(nh, L->phi[i]);
+        if (L->p.curv_model == ORC_CURV_LSQR) L->plic[i] = orc_plic_offset(nh, L->phi[i]);
     }
 }
 

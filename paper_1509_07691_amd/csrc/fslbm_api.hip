@@ -7,6 +7,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "fslbm.h"
 #include "fslbm_convert.hpp"
@@ -68,7 +69,6 @@ Layout make_layout(long long N, int prec)
         return o;
     };
     const size_t fb = fbytes(prec), rb = rbytes(prec);
-    const size_t nblk = (N + CMP_CELLS - 1) / CMP_CELLS;
     L.fA = take(19 * N * fb);
     L.fB = take(19 * N * fb);
     L.flags = take(N);
@@ -86,7 +86,7 @@ Layout make_layout(long long N, int prec)
     L.ilist = take(4 * N);
     L.olist = take(4 * N);
     L.staging = take(8 * N);
-    L.counts = take(4 * nblk);
+    L.counts = take(4 * (size_t)CMP_GRID);  // one count per compaction block (fixed grid)
     L.part = take(8 * MASS_BLOCKS);
     L.sc = take(sizeof(DevScalars));
     L.total = off;
@@ -102,6 +102,29 @@ bool shape_ok(int nx, int ny, int nz)
 
 }  // namespace
 
+struct fslbm_lattice;
+
+// A set of lattices advanced together: each kernel of the step is launched
+// once for all of them (blockIdx.y selects the lattice). Every handle also
+// owns an implicit batch holding only itself.
+struct fslbm_batch {
+    std::vector<fslbm_lattice *> hs;
+    std::vector<unsigned> versions;  // handle versions the graphs were captured at
+    int prec;
+    // optional phase timing: events around stream-collide, conversion,
+    // compaction and obstacle fill + curvature of every step
+    int timing;
+    std::vector<hipEvent_t> ev;
+    int ev_used;  // steps recorded in ev since the last fold
+    double tacc[5];
+    long long tsteps;
+    // optional replay of one step as a HIP graph (one per buffer parity)
+    int use_graph;
+    hipGraphExec_t gexec[2];
+    // interface cells: 0 = in the bulk stream-collide kernel, 1 = own list kernel
+    int split_interface;
+};
+
 struct fslbm_lattice {
     int nx, ny, nz;
     int N;
@@ -112,7 +135,15 @@ struct fslbm_lattice {
     Layout L;
     int cur;  // 0: current f' in fA, 1: in fB
     long long steps;
+    unsigned version;  // bumped whenever launch arguments change
+    fslbm_batch self;
 };
+
+namespace {
+constexpr int TIMING_CAP = 512;  // steps held in the event pool before folding
+constexpr int TIMING_EV = 6;     // events per step
+constexpr int NPHASE = TIMING_EV - 1;
+}
 
 namespace {
 
@@ -127,6 +158,8 @@ Params make_params(const fslbm_lattice *h)
     p.sin_theta = sin(h->theta);
     p.rho_gas = h->rho_gas;
     p.eps_c = h->eps_c;
+    p.curv = h->curv;
+    p.coll = h->coll;
     return p;
 }
 
@@ -154,6 +187,7 @@ Fields<P> make_fields(const fslbm_lattice *h)
     F.nmol = (R *)(w + L.nmol);
     F.ilist = (int32_t *)(w + L.ilist);
     F.olist = (int32_t *)(w + L.olist);
+    F.counts = (int *)(w + L.counts);
     F.sc = (DevScalars *)(w + L.sc);
     F.nx = h->nx;
     F.ny = h->ny;
@@ -164,7 +198,9 @@ Fields<P> make_fields(const fslbm_lattice *h)
 
 inline int cell_blocks(int N) { return (N + 255) / 256; }
 inline int list_blocks(int N) { return std::min(LIST_GRID, std::max(1, (N + 255) / 256)); }
-inline int cmp_blocks(int N) { return (N + CMP_CELLS - 1) / CMP_CELLS; }
+inline int cmp_blocks(int N) { return std::min(CMP_GRID, (N + CMP_CELLS - 1) / CMP_CELLS); }
+constexpr int GEOM_GRID = 1024;  // blocks per lattice of the tiled geometry kernels
+constexpr int SC_GRID = 1024;  // blocks per lattice of the bulk stream-collide
 
 // ------------------------------------------------------ init kernels
 __global__ void k_fill_bytes(uint8_t *p, size_t n, uint8_t v)
@@ -182,6 +218,9 @@ __global__ void k_init_scalars(DevScalars *sc)
     sc->mass = 0.0;
     sc->bad = 0;
     sc->pad = 0;
+    for (int k = 0; k < 6; ++k) sc->bbox[k] = 0;
+    sc->fbox[0] = sc->fbox[1] = sc->fbox[2] = 1 << 30;
+    sc->fbox[3] = sc->fbox[4] = sc->fbox[5] = -1;
 }
 
 // Types from fill level and obstacle mask (obstacle input in `types` on entry).
@@ -250,6 +289,37 @@ __global__ void k_init_fields(Fields<P> F, const double *fill, const uint8_t *ty
 #undef FSLBM_ST
         }
     }
+}
+
+// Bounding box of the fluid cells (block min / max, then atomics).
+__global__ __launch_bounds__(256) void k_fluid_box(const uint8_t *flags, int nx, int ny, int N, DevScalars *sc)
+{
+    __shared__ int red[6][256];
+    int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {-1, -1, -1};
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < N; i += gridDim.x * 256) {
+        if (!(flags[i] & FL_FLUID)) continue;
+        const int yz = i / nx, x = i - yz * nx, z = yz / ny, y = yz - z * ny;
+        lo[0] = min(lo[0], x); lo[1] = min(lo[1], y); lo[2] = min(lo[2], z);
+        hi[0] = max(hi[0], x); hi[1] = max(hi[1], y); hi[2] = max(hi[2], z);
+    }
+    for (int k = 0; k < 3; ++k) {
+        red[k][threadIdx.x] = lo[k];
+        red[3 + k][threadIdx.x] = hi[k];
+    }
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w)
+            for (int k = 0; k < 3; ++k) {
+                red[k][threadIdx.x] = min(red[k][threadIdx.x], red[k][threadIdx.x + w]);
+                red[3 + k][threadIdx.x] = max(red[3 + k][threadIdx.x], red[3 + k][threadIdx.x + w]);
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && red[3][0] >= 0)
+        for (int k = 0; k < 3; ++k) {
+            atomicMin(&sc->fbox[k], red[k][0]);
+            atomicMax(&sc->fbox[3 + k], red[3 + k][0]);
+        }
 }
 
 __global__ void k_copy_bytes(const uint8_t *src, uint8_t *dst, int N)
@@ -410,57 +480,225 @@ __global__ void k_check_numeric(Fields<P> F)
 
 // ------------------------------------------------------ host sequences
 template <class P>
-int enqueue_compaction(fslbm_lattice *h, const uint8_t *flags, uint8_t want, int32_t *list, int *count, int force)
+Batch<P> make_batch(const fslbm_batch *b, int &maxN, bool &any_srt, bool &any_trt)
 {
-    const Fields<P> F = make_fields<P>(h);
-    int *counts = (int *)(h->ws + h->L.counts);
-    const int nb = cmp_blocks(h->N);
-    k_compact_count<<<nb, 256, 0, h->stream>>>(flags, h->N, want, counts, F.sc, force);
-    k_compact_scan<<<1, 1024, 0, h->stream>>>(counts, nb, count, F.sc, force);
-    k_compact_write<<<nb, 256, 0, h->stream>>>(flags, h->N, want, counts, list, F.sc, force);
+    Batch<P> A;
+    maxN = 0;
+    any_srt = any_trt = false;
+    const int n = (int)b->hs.size();
+    for (int i = 0; i < MAXB; ++i) {
+        const fslbm_lattice *h = b->hs[i < n ? i : 0];
+        A.f[i] = make_fields<P>(h);
+        A.p[i] = make_params(h);
+    }
+    for (int i = 0; i < n; ++i) {
+        maxN = std::max(maxN, b->hs[i]->N);
+        any_srt |= b->hs[i]->coll == FSLBM_SRT;
+        any_trt |= b->hs[i]->coll == FSLBM_TRT;
+    }
+    return A;
+}
+
+inline hipStream_t bstream(const fslbm_batch *b) { return b->hs[0]->stream; }
+
+template <class P>
+int enqueue_compaction(const fslbm_batch *b, const Batch<P> &A, int maxN, int which, int force)
+{
+    const unsigned n = (unsigned)b->hs.size();
+    const hipStream_t st = bstream(b);
+    k_compact_count<P><<<dim3(cmp_blocks(maxN), n), 256, 0, st>>>(A, which, force);
+    k_compact_scan<P><<<dim3(1, n), 1024, 0, st>>>(A, which, force, cmp_blocks(maxN));
+    k_compact_write<P><<<dim3(cmp_blocks(maxN), n), 256, 0, st>>>(A, which, force);
     HIP_OK(hipGetLastError());
     return 0;
 }
 
 template <class P>
-int enqueue_geometry(fslbm_lattice *h)
+int enqueue_geometry(const fslbm_batch *b, const Batch<P> &A, int maxN)
 {
-    const Fields<P> F = make_fields<P>(h);
-    const Params prm = make_params(h);
-    const int lb = list_blocks(h->N);
-    k_normals_plic<P><<<lb, 256, 0, h->stream>>>(F);
-    if (h->curv == FSLBM_CURV_FD) {
-        k_fd_mollify<P><<<cell_blocks(h->N), 256, 0, h->stream>>>(F);
-        k_fd_normals<P><<<cell_blocks(h->N), 256, 0, h->stream>>>(F);
-        k_fd_curvature<P><<<lb, 256, 0, h->stream>>>(F);
-    } else {
-        k_curv_lsqr<P><<<lb, 256, 0, h->stream>>>(F, prm);
+    const unsigned n = (unsigned)b->hs.size();
+    const hipStream_t st = bstream(b);
+    const dim3 tg(std::min(GEOM_GRID, std::max(1, maxN / 512)), n);
+    bool any_fd = false, any_lsqr = false;
+    for (auto *h : b->hs) {
+        any_fd |= h->curv == FSLBM_CURV_FD;
+        any_lsqr |= h->curv == FSLBM_CURV_LSQR;
+    }
+    if (any_fd) k_geometry_fd<P><<<tg, 256, 0, st>>>(A);
+    if (any_lsqr) {
+        const dim3 lg(list_blocks(maxN), n);
+        k_normals_plic<P><<<lg, 256, 0, st>>>(A);
+        k_curv_lsqr<P><<<lg, 256, 0, st>>>(A);
     }
     HIP_OK(hipGetLastError());
     return 0;
 }
 
 template <class P>
-int enqueue_step(fslbm_lattice *h)
+int enqueue_geometry_one(fslbm_lattice *h)
 {
-    const Fields<P> F = make_fields<P>(h);
-    const Params prm = make_params(h);
-    const int lb = list_blocks(h->N);
-    if (h->coll == FSLBM_SRT) k_stream_collide<P, 0><<<cell_blocks(h->N), 256, 0, h->stream>>>(F, prm);
-    else k_stream_collide<P, 1><<<cell_blocks(h->N), 256, 0, h->stream>>>(F, prm);
-    k_conv_prune<P><<<lb, 256, 0, h->stream>>>(F);
-    k_conv_mark_init<P><<<lb, 256, 0, h->stream>>>(F);
-    k_conv_share<P><<<lb, 256, 0, h->stream>>>(F);
-    k_conv_gather<P><<<lb, 256, 0, h->stream>>>(F);
-    k_conv_flags<P><<<lb, 256, 0, h->stream>>>(F);
+    int maxN;
+    bool s_, t_;
+    const Batch<P> A = make_batch<P>(&h->self, maxN, s_, t_);
+    return enqueue_geometry<P>(&h->self, A, maxN);
+}
+
+inline void mark(fslbm_batch *b, int k)
+{
+    if (b->timing) (void)hipEventRecord(b->ev[(size_t)b->ev_used * TIMING_EV + k], bstream(b));
+}
+
+// Kernels of one time step of every lattice of the batch.
+template <class P>
+int enqueue_step_kernels(fslbm_batch *b)
+{
+    int maxN;
+    bool any_srt, any_trt;
+    const Batch<P> A = make_batch<P>(b, maxN, any_srt, any_trt);
+    const unsigned n = (unsigned)b->hs.size();
+    const hipStream_t st = bstream(b);
+    const dim3 cg(std::min(SC_GRID, cell_blocks(maxN)), n), lg(list_blocks(maxN), n);
+    mark(b, 0);
+    if (b->split_interface) {
+        if (any_srt) k_stream_collide<P, 0, false><<<cg, 256, 0, st>>>(A);
+        if (any_trt) k_stream_collide<P, 1, false><<<cg, 256, 0, st>>>(A);
+        mark(b, 1);
+        if (any_srt) k_stream_collide_interface<P, 0><<<lg, 256, 0, st>>>(A);
+        if (any_trt) k_stream_collide_interface<P, 1><<<lg, 256, 0, st>>>(A);
+    } else {
+        if (any_srt) k_stream_collide<P, 0, true><<<cg, 256, 0, st>>>(A);
+        if (any_trt) k_stream_collide<P, 1, true><<<cg, 256, 0, st>>>(A);
+        mark(b, 1);
+    }
+    mark(b, 2);
+    k_conv_prune<P><<<lg, 256, 0, st>>>(A);
+    k_conv_mark_init<P><<<lg, 256, 0, st>>>(A);
+    k_conv_share<P><<<lg, 256, 0, st>>>(A);
+    k_conv_gather<P><<<lg, 256, 0, st>>>(A);
+    k_conv_flags<P><<<lg, 256, 0, st>>>(A);
+    mark(b, 3);
     HIP_OK(hipGetLastError());
-    int rc = enqueue_compaction<P>(h, F.flags, FL_IF, F.ilist, &F.sc->icount, 0);
+    int rc = enqueue_compaction<P>(b, A, maxN, 0, 0);
     if (rc) return rc;
-    k_obstacle_fill<P><<<lb, 256, 0, h->stream>>>(F, 1);
-    h->cur ^= 1;  // f'(t+1) is now current
-    rc = enqueue_geometry<P>(h);
+    mark(b, 4);
+    k_obstacle_fill<P><<<lg, 256, 0, st>>>(A, 1);
+    rc = enqueue_geometry<P>(b, A, maxN);
     if (rc) return rc;
-    h->steps += 1;
+    mark(b, 5);
+    return 0;
+}
+
+int fold_timing(fslbm_batch *b)
+{
+    if (!b->timing || b->ev_used == 0) return 0;
+    HIP_OK(hipEventSynchronize(b->ev[(size_t)(b->ev_used - 1) * TIMING_EV + TIMING_EV - 1]));
+    for (int s = 0; s < b->ev_used; ++s)
+        for (int k = 0; k < NPHASE; ++k) {
+            float ms = 0.f;
+            HIP_OK(hipEventElapsedTime(&ms, b->ev[(size_t)s * TIMING_EV + k], b->ev[(size_t)s * TIMING_EV + k + 1]));
+            b->tacc[k] += ms;
+        }
+    b->tsteps += b->ev_used;
+    b->ev_used = 0;
+    return 0;
+}
+
+void drop_graphs(fslbm_batch *b)
+{
+    for (int c = 0; c < 2; ++c)
+        if (b->gexec[c]) {
+            (void)hipGraphExecDestroy(b->gexec[c]);
+            b->gexec[c] = nullptr;
+        }
+}
+
+void batch_init(fslbm_batch *b)
+{
+    b->prec = 0;
+    b->timing = 0;
+    b->ev_used = 0;
+    b->tsteps = 0;
+    for (int k = 0; k < NPHASE; ++k) b->tacc[k] = 0.0;
+    b->use_graph = 0;
+    b->gexec[0] = b->gexec[1] = nullptr;
+    b->split_interface = 0;
+}
+
+void batch_release(fslbm_batch *b)
+{
+    drop_graphs(b);
+    for (auto &e : b->ev)
+        if (e) (void)hipEventDestroy(e);
+    b->ev.clear();
+}
+
+int batch_set_timing(fslbm_batch *b, int on)
+{
+    if (on && b->ev.empty()) {
+        b->ev.resize((size_t)TIMING_CAP * TIMING_EV, nullptr);
+        for (auto &e : b->ev) HIP_OK(hipEventCreate(&e));
+    }
+    if (!on) {
+        const int rc = fold_timing(b);
+        if (rc) return rc;
+    }
+    b->timing = on;
+    return 0;
+}
+
+bool graphs_stale(const fslbm_batch *b)
+{
+    if (b->versions.size() != b->hs.size()) return true;
+    for (size_t i = 0; i < b->hs.size(); ++i)
+        if (b->versions[i] != b->hs[i]->version) return true;
+    return false;
+}
+
+template <class P>
+int batch_step_once(fslbm_batch *b)
+{
+    const int cur = b->hs[0]->cur;
+    for (auto *h : b->hs)
+        if (h->cur != cur) return fail(FSLBM_E_STATE, "lattices of a batch must have taken the same number of steps");
+    const hipStream_t st = bstream(b);
+    if (b->use_graph && !b->timing && st != nullptr) {
+        if (graphs_stale(b)) {
+            drop_graphs(b);
+            b->versions.clear();
+            for (auto *h : b->hs) b->versions.push_back(h->version);
+        }
+        hipGraphExec_t &ge = b->gexec[cur];
+        if (!ge) {
+            hipGraph_t g = nullptr;
+            HIP_OK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+            const int rc = enqueue_step_kernels<P>(b);
+            const hipError_t e = hipStreamEndCapture(st, &g);
+            if (rc) {
+                if (g) (void)hipGraphDestroy(g);
+                return rc;
+            }
+            if (e != hipSuccess) return fail(FSLBM_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+            const hipError_t e2 = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e2 != hipSuccess) {
+                ge = nullptr;
+                return fail(FSLBM_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e2));
+            }
+        }
+        HIP_OK(hipGraphLaunch(ge, st));
+    } else {
+        if (b->timing && b->ev_used == TIMING_CAP) {
+            const int rc = fold_timing(b);
+            if (rc) return rc;
+        }
+        const int rc = enqueue_step_kernels<P>(b);
+        if (rc) return rc;
+        if (b->timing) b->ev_used += 1;
+    }
+    for (auto *h : b->hs) {
+        h->cur ^= 1;  // f'(t+1) is now current
+        h->steps += 1;
+    }
     return 0;
 }
 
@@ -479,16 +717,21 @@ int enqueue_init(fslbm_lattice *h, const double *fill, const uint8_t *obstacle)
     k_init_scalars<<<1, 1, 0, h->stream>>>(F.sc);
     k_init_types<<<cell_blocks(N), 256, 0, h->stream>>>(staging, F.conv, N);
     k_init_fields<P><<<cell_blocks(N), 256, 0, h->stream>>>(F, staging, F.conv, F.flags);
+    k_fluid_box<<<std::min(1024, cell_blocks(N)), 256, 0, h->stream>>>(F.flags, h->nx, h->ny, N, F.sc);
     // static list of obstacle cells next to non-obstacle cells
     k_mark_wall_cells<<<cell_blocks(N), 256, 0, h->stream>>>(F.flags, F.conv, h->nx, h->ny, h->nz, N);
-    int rc = enqueue_compaction<P>(h, F.conv, 1, F.olist, &F.sc->ocount, 1);
+    HIP_OK(hipGetLastError());
+    int maxN;
+    bool s_, t_;
+    const Batch<P> A = make_batch<P>(&h->self, maxN, s_, t_);
+    int rc = enqueue_compaction<P>(&h->self, A, maxN, 1, 1);
     if (rc) return rc;
     k_fill_bytes<<<std::min(4096, cell_blocks(N)), 256, 0, h->stream>>>(F.conv, N, 0);
-    rc = enqueue_compaction<P>(h, F.flags, FL_IF, F.ilist, &F.sc->icount, 1);
+    rc = enqueue_compaction<P>(&h->self, A, maxN, 0, 1);
     if (rc) return rc;
-    k_obstacle_fill<P><<<list_blocks(N), 256, 0, h->stream>>>(F, 0);
+    k_obstacle_fill<P><<<dim3(list_blocks(N), 1), 256, 0, h->stream>>>(A, 0);
     HIP_OK(hipGetLastError());
-    return enqueue_geometry<P>(h);
+    return enqueue_geometry<P>(&h->self, A, maxN);
 }
 
 template <class P>
@@ -564,8 +807,22 @@ int dispatch(fslbm_lattice *h, A... a)
     }
 }
 template <class P> struct OpInit { static int run(fslbm_lattice *h, const double *f, const uint8_t *o) { return enqueue_init<P>(h, f, o); } };
-template <class P> struct OpStep { static int run(fslbm_lattice *h) { return enqueue_step<P>(h); } };
-template <class P> struct OpGeom { static int run(fslbm_lattice *h) { return enqueue_geometry<P>(h); } };
+template <class P> struct OpGeom { static int run(fslbm_lattice *h) { return enqueue_geometry_one<P>(h); } };
+
+int batch_step(fslbm_batch *b, int64_t nsteps)
+{
+    for (int64_t s = 0; s < nsteps; ++s) {
+        int rc;
+        switch (b->prec) {
+        case P_F64: rc = batch_step_once<Prec<P_F64>>(b); break;
+        case P_F32: rc = batch_step_once<Prec<P_F32>>(b); break;
+        case P_F16: rc = batch_step_once<Prec<P_F16>>(b); break;
+        default: rc = batch_step_once<Prec<P_BF16>>(b); break;
+        }
+        if (rc) return rc;
+    }
+    return 0;
+}
 template <class P> struct OpRead { static int run(fslbm_lattice *h, int w, double *o, int d) { return do_read<P>(h, w, o, d); } };
 template <class P> struct OpMass { static int run(fslbm_lattice *h, double *t) { return do_mass<P>(h, t); } };
 template <class P> struct OpCheck { static int run(fslbm_lattice *h) { return do_check<P>(h); } };
@@ -618,6 +875,10 @@ int fslbm_create(int nx, int ny, int nz, int precision, int curv_model, const do
     h->L = L;
     h->cur = 0;
     h->steps = 0;
+    h->version = 0;
+    batch_init(&h->self);
+    h->self.hs.push_back(h);
+    h->self.prec = precision;
     const int rc = dispatch<OpInit>(h, fill, obstacle);
     if (rc) {
         delete h;
@@ -635,6 +896,7 @@ int fslbm_set_params(fslbm_t h, double sigma, double tau, double theta_rad, doub
     if (!(theta_rad > 0.0 && theta_rad < M_PI)) return fail(FSLBM_E_ARG, "theta must lie in (0, pi)");
     if (!(rho_gas > 0.0) || !std::isfinite(rho_gas)) return fail(FSLBM_E_ARG, "rho_gas must be > 0");
     h->sigma = sigma; h->tau = tau; h->theta = theta_rad; h->rho_gas = rho_gas;
+    h->version += 1;
     return dispatch<OpGeom>(h);
 }
 
@@ -645,15 +907,21 @@ int fslbm_set_option(fslbm_t h, int key, double value)
     case FSLBM_OPT_EPS_C:
         if (!(value >= 0.0 && value < 0.5)) return fail(FSLBM_E_ARG, "eps_c must lie in [0, 0.5)");
         h->eps_c = value;
+        h->version += 1;
         return 0;
     case FSLBM_OPT_COLLISION:
         if (value != FSLBM_SRT && value != FSLBM_TRT) return fail(FSLBM_E_ARG, "collision must be SRT or TRT");
         h->coll = (int)value;
+        h->version += 1;
         return 0;
     case FSLBM_OPT_TRT_MAGIC:
         if (!(value > 0.0) || !std::isfinite(value)) return fail(FSLBM_E_ARG, "TRT Lambda must be > 0");
         h->trt_magic = value;
+        h->version += 1;
         return 0;
+    case FSLBM_OPT_TIMING:
+    case FSLBM_OPT_GRAPH:
+    case FSLBM_OPT_SPLIT_INTERFACE: return fslbm_batch_set_option(&h->self, key, value);
     default: return fail(FSLBM_E_ARG, "unknown option %d", key);
     }
 }
@@ -661,6 +929,9 @@ int fslbm_set_option(fslbm_t h, int key, double value)
 int fslbm_set_stream(fslbm_t h, void *hip_stream)
 {
     if (!h) return fail(FSLBM_E_STATE, "null handle");
+    const int rc = fold_timing(&h->self);
+    if (rc) return rc;
+    h->version += 1;
     h->stream = (hipStream_t)hip_stream;
     return 0;
 }
@@ -676,11 +947,86 @@ int fslbm_step(fslbm_t h, int64_t nsteps)
 {
     if (!h) return fail(FSLBM_E_STATE, "null handle");
     if (nsteps < 0) return fail(FSLBM_E_ARG, "nsteps must be >= 0");
-    for (int64_t s = 0; s < nsteps; ++s) {
-        const int rc = dispatch<OpStep>(h);
-        if (rc) return rc;
+    return batch_step(&h->self, nsteps);
+}
+
+int fslbm_batch_create(const fslbm_t *handles, int count, fslbm_batch_t *out)
+{
+    if (!out) return fail(FSLBM_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!handles || count < 1 || count > MAXB) return fail(FSLBM_E_ARG, "a batch holds 1..%d lattices", MAXB);
+    for (int i = 0; i < count; ++i) {
+        if (!handles[i]) return fail(FSLBM_E_ARG, "handle %d is NULL", i);
+        if (handles[i]->prec != handles[0]->prec) return fail(FSLBM_E_ARG, "lattices of a batch share the precision");
+        if (handles[i]->stream != handles[0]->stream) return fail(FSLBM_E_ARG, "lattices of a batch share the stream");
+        if (handles[i]->cur != handles[0]->cur) return fail(FSLBM_E_STATE, "lattices of a batch must be at the same step parity");
+        for (int j = 0; j < i; ++j)
+            if (handles[j] == handles[i]) return fail(FSLBM_E_ARG, "handle %d appears twice", i);
     }
+    fslbm_batch *b = new (std::nothrow) fslbm_batch();
+    if (!b) return fail(FSLBM_E_STATE, "out of host memory");
+    batch_init(b);
+    b->prec = handles[0]->prec;
+    for (int i = 0; i < count; ++i) b->hs.push_back(handles[i]);
+    *out = b;
     return 0;
+}
+
+int fslbm_batch_step(fslbm_batch_t b, int64_t nsteps)
+{
+    if (!b) return fail(FSLBM_E_STATE, "null batch");
+    if (nsteps < 0) return fail(FSLBM_E_ARG, "nsteps must be >= 0");
+    for (auto *h : b->hs)
+        if (h->stream != b->hs[0]->stream) return fail(FSLBM_E_STATE, "lattices of a batch share the stream");
+    return batch_step(b, nsteps);
+}
+
+int fslbm_batch_set_option(fslbm_batch_t b, int key, double value)
+{
+    if (!b) return fail(FSLBM_E_STATE, "null batch");
+    switch (key) {
+    case FSLBM_OPT_TIMING: return batch_set_timing(b, value != 0.0);
+    case FSLBM_OPT_GRAPH:
+        b->use_graph = value != 0.0;
+        if (!b->use_graph) drop_graphs(b);
+        return 0;
+    case FSLBM_OPT_SPLIT_INTERFACE:
+        b->split_interface = value != 0.0;
+        drop_graphs(b);
+        return 0;
+    default: return fail(FSLBM_E_ARG, "option %d does not apply to a batch", key);
+    }
+}
+
+int fslbm_batch_read_timing(fslbm_batch_t b, double *phase_ms, int64_t *steps)
+{
+    if (!b) return fail(FSLBM_E_STATE, "null batch");
+    if (!phase_ms || !steps) return fail(FSLBM_E_ARG, "null output");
+    HIP_OK(hipStreamSynchronize(bstream(b)));
+    const int rc = fold_timing(b);
+    if (rc) return rc;
+    for (int k = 0; k < NPHASE; ++k) phase_ms[k] = b->tacc[k];
+    *steps = b->tsteps;
+    return 0;
+}
+
+int fslbm_batch_reset_timing(fslbm_batch_t b)
+{
+    if (!b) return fail(FSLBM_E_STATE, "null batch");
+    HIP_OK(hipStreamSynchronize(bstream(b)));
+    const int rc = fold_timing(b);
+    if (rc) return rc;
+    for (int k = 0; k < NPHASE; ++k) b->tacc[k] = 0.0;
+    b->tsteps = 0;
+    return 0;
+}
+
+void fslbm_batch_destroy(fslbm_batch_t b)
+{
+    if (!b) return;
+    (void)hipStreamSynchronize(bstream(b));
+    batch_release(b);
+    delete b;
 }
 
 static int read_common(fslbm_t h, int what, double *out, int dev)
@@ -751,6 +1097,24 @@ int fslbm_steps_taken(fslbm_t h, int64_t *steps)
     return 0;
 }
 
-void fslbm_destroy(fslbm_t h) { delete h; }
+int fslbm_read_timing(fslbm_t h, double *phase_ms, int64_t *steps)
+{
+    if (!h) return fail(FSLBM_E_STATE, "null handle");
+    return fslbm_batch_read_timing(&h->self, phase_ms, steps);
+}
+
+int fslbm_reset_timing(fslbm_t h)
+{
+    if (!h) return fail(FSLBM_E_STATE, "null handle");
+    return fslbm_batch_reset_timing(&h->self);
+}
+
+void fslbm_destroy(fslbm_t h)
+{
+    if (!h) return;
+    (void)hipStreamSynchronize(h->stream);
+    batch_release(&h->self);
+    delete h;
+}
 
 }  // extern "C"

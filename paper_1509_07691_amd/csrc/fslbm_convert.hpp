@@ -27,7 +27,7 @@
 
 namespace fslbm {
 
-constexpr int LIST_GRID = 2048;  // blocks of the grid-stride list kernels
+constexpr int LIST_GRID = 256;  // blocks per lattice of the grid-stride list kernels
 
 __device__ inline int list_count(const DevScalars *sc) { return *(volatile const int *)&sc->icount; }
 
@@ -40,8 +40,9 @@ __device__ inline bool is_converter(const Fields<P> &F, int j)
 // Rule 2: an emptying cell next to a filling cell does not empty. Readers of
 // conv only test for CV_FILL, which this kernel never writes or clears.
 template <class P>
-__global__ __launch_bounds__(256) void k_conv_prune(Fields<P> F)
+__global__ __launch_bounds__(256) void k_conv_prune(const Batch<P> B)
 {
+    const Fields<P> &F = B.f[blockIdx.y];
     if (F.sc->nconv == 0) return;
     const int n = list_count(F.sc);
     for (int k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256) {
@@ -61,8 +62,9 @@ __global__ __launch_bounds__(256) void k_conv_prune(Fields<P> F)
 // Rule 3: tag the new interface cells and initialise them. Cells reached
 // from several converting neighbours are written identically by each.
 template <class P>
-__global__ __launch_bounds__(256) void k_conv_mark_init(Fields<P> F)
+__global__ __launch_bounds__(256) void k_conv_mark_init(const Batch<P> B)
 {
+    const Fields<P> &F = B.f[blockIdx.y];
     using T = typename P::T;
     using R = typename P::R;
     if (F.sc->nconv == 0) return;
@@ -79,6 +81,11 @@ __global__ __launch_bounds__(256) void k_conv_mark_init(Fields<P> F)
             const uint8_t tj = F.flags[j] & FL_TYPE;
             if (st == CV_FILL && tj == FL_GAS) {
                 F.mark[j] = tag | 1u;
+                {  // the fluid region grows by this cell
+                    const int yz = j / F.nx, x = j - yz * F.nx, z = yz / F.ny, y = yz - z * F.ny;
+                    atomicMin(&F.sc->fbox[0], x); atomicMin(&F.sc->fbox[1], y); atomicMin(&F.sc->fbox[2], z);
+                    atomicMax(&F.sc->fbox[3], x); atomicMax(&F.sc->fbox[4], y); atomicMax(&F.sc->fbox[5], z);
+                }
                 // mean rho and u over the liquid / interface neighbours of j
                 const Nbr nj(j, F.nx, F.ny, F.nz);
                 T rs = 0, usx = 0, usy = 0, usz = 0;
@@ -152,8 +159,9 @@ __device__ inline bool is_receiver(const Fields<P> &F, int j, uint32_t tag)
 
 // Rule 4, first half: each converting cell computes its share.
 template <class P>
-__global__ __launch_bounds__(256) void k_conv_share(Fields<P> F)
+__global__ __launch_bounds__(256) void k_conv_share(const Batch<P> B)
 {
+    const Fields<P> &F = B.f[blockIdx.y];
     using R = typename P::R;
     if (F.sc->nconv == 0) return;
     const uint32_t tag = F.sc->step << 2;
@@ -194,8 +202,9 @@ __device__ inline typename P::R gathered_excess(const Fields<P> &F, int j)
 // direction order. This kernel also sets phi = m / rho of every interface
 // cell for the new time level, so it runs in every step.
 template <class P>
-__global__ __launch_bounds__(256) void k_conv_gather(Fields<P> F)
+__global__ __launch_bounds__(256) void k_conv_gather(const Batch<P> B)
 {
+    const Fields<P> &F = B.f[blockIdx.y];
     using R = typename P::R;
     const bool any = F.sc->nconv != 0;
     const uint32_t tag = F.sc->step << 2;
@@ -226,8 +235,9 @@ __global__ __launch_bounds__(256) void k_conv_gather(Fields<P> F)
 
 // Rule 5 and the new interface cells' types.
 template <class P>
-__global__ __launch_bounds__(256) void k_conv_flags(Fields<P> F)
+__global__ __launch_bounds__(256) void k_conv_flags(const Batch<P> B)
 {
+    const Fields<P> &F = B.f[blockIdx.y];
     if (F.sc->nconv == 0) return;
     const uint32_t tag = F.sc->step << 2;
     const int n = list_count(F.sc);
@@ -273,64 +283,134 @@ __device__ inline int block_exclusive_scan(int v, int *lds_wave, int &total)
     return off + x - v;
 }
 
-__device__ inline int cells_matching(const uint8_t *flags, int base, int N, uint8_t want, bool (&hit)[4])
+// Cells k = base .. base+3 of a range (x fastest): hit[s] and their indices.
+__device__ inline int cells_matching(const uint8_t *flags, const CellRange &r, int nx, int ny, int base,
+                                     uint8_t want, bool (&hit)[4], int (&idx)[4])
 {
+    const int n = r.size();
     int c = 0;
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-        const int i = base + s;
-        hit[s] = i < N && (flags[i] & want);
+        const int k = base + s;
+        idx[s] = k < n ? r.cell(k, nx, ny) : 0;
+        hit[s] = k < n && (flags[idx[s]] & want);
         c += hit[s];
     }
     return c;
 }
 
-__global__ __launch_bounds__(256) void k_compact_count(const uint8_t *flags, int N, uint8_t want,
-                                                       int *counts, const DevScalars *sc, int force)
+// which = 0: interface cells (flags & FL_IF) into ilist / icount, run only
+// in steps with conversions unless forced; which = 1: the static list of
+// obstacle cells next to non-obstacle cells (conv == 1) into olist / ocount.
+template <class P>
+__device__ inline void compact_source(const Fields<P> &F, int which, const uint8_t *&src, uint8_t &want,
+                                      int32_t *&list, int *&count, CellRange &range)
 {
-    if (!force && sc->nconv == 0) return;
-    __shared__ int lw[4];
-    bool hit[4];
-    const int base = blockIdx.x * CMP_CELLS + threadIdx.x * 4;
-    const int c = cells_matching(flags, base, N, want, hit);
-    int total;
-    block_exclusive_scan(c, lw, total);
-    if (threadIdx.x == 0) counts[blockIdx.x] = total;
+    range = which == 0 ? CellRange::from(F.sc->fbox) : CellRange::whole(F.nx, F.ny, F.nz);
+    src = which == 0 ? F.flags : F.conv;
+    want = which == 0 ? FL_IF : 1;
+    list = which == 0 ? F.ilist : F.olist;
+    count = which == 0 ? &F.sc->icount : &F.sc->ocount;
 }
 
-// One block: exclusive scan of the block counts, list length to *out_count.
-__global__ __launch_bounds__(1024) void k_compact_scan(int *counts, int nblocks, int *out_count,
-                                                       const DevScalars *sc, int force)
+// A fixed grid of CMP_GRID blocks per lattice; block b owns a contiguous run
+// of 1024-cell tiles, so the list stays in ascending order.
+constexpr int CMP_GRID = 256;
+
+__device__ inline void tile_range(int N, int &t0, int &t1)
 {
-    if (!force && sc->nconv == 0) return;
+    const int ntiles = (N + CMP_CELLS - 1) / CMP_CELLS;  // N: cells of the range
+    const int per = (ntiles + gridDim.x - 1) / gridDim.x;
+    t0 = min(ntiles, (int)blockIdx.x * per);
+    t1 = min(ntiles, t0 + per);
+}
+
+template <class P>
+__global__ __launch_bounds__(256) void k_compact_count(const Batch<P> B, int which, int force)
+{
+    const Fields<P> &F = B.f[blockIdx.y];
+    if (!force && F.sc->nconv == 0) return;
+    const uint8_t *src; uint8_t want; int32_t *list; int *count; CellRange range;
+    compact_source(F, which, src, want, list, count, range);
+    __shared__ int lw[4];
+    int t0, t1;
+    tile_range(range.size(), t0, t1);
+    int sum = 0;
+    for (int t = t0; t < t1; ++t) {
+        bool hit[4];
+        int idx[4];
+        const int c = cells_matching(src, range, F.nx, F.ny, t * CMP_CELLS + threadIdx.x * 4, want, hit, idx);
+        int total;
+        block_exclusive_scan(c, lw, total);
+        sum += total;
+    }
+    if (threadIdx.x == 0) F.counts[blockIdx.x] = sum;
+}
+
+// One block per lattice: exclusive scan of the block counts, list length;
+// the interface bounding box is reset for the write pass.
+template <class P>
+__global__ __launch_bounds__(1024) void k_compact_scan(const Batch<P> B, int which, int force, int nblocks)
+{
+    const Fields<P> &F = B.f[blockIdx.y];
+    if (!force && F.sc->nconv == 0) return;
+    const uint8_t *src; uint8_t want; int32_t *list; int *count; CellRange range;
+    compact_source(F, which, src, want, list, count, range);
     __shared__ int lw[16];
     int carry = 0;
     for (int b0 = 0; b0 < nblocks; b0 += 1024) {
         const int b = b0 + threadIdx.x;
-        const int v = b < nblocks ? counts[b] : 0;
+        const int v = b < nblocks ? F.counts[b] : 0;
         int total;
         const int ex = block_exclusive_scan(v, lw, total);
-        if (b < nblocks) counts[b] = carry + ex;
+        if (b < nblocks) F.counts[b] = carry + ex;
         carry += total;
         __syncthreads();
     }
-    if (threadIdx.x == 0) *out_count = carry;
+    if (threadIdx.x == 0) {
+        *count = carry;
+        if (which == 0) {
+            F.sc->bbox[0] = F.nx; F.sc->bbox[1] = F.ny; F.sc->bbox[2] = F.nz;
+            F.sc->bbox[3] = -1; F.sc->bbox[4] = -1; F.sc->bbox[5] = -1;
+        }
+    }
 }
 
-__global__ __launch_bounds__(256) void k_compact_write(const uint8_t *flags, int N, uint8_t want,
-                                                       const int *offsets, int32_t *list,
-                                                       const DevScalars *sc, int force)
+template <class P>
+__global__ __launch_bounds__(256) void k_compact_write(const Batch<P> B, int which, int force)
 {
-    if (!force && sc->nconv == 0) return;
+    const Fields<P> &F = B.f[blockIdx.y];
+    if (!force && F.sc->nconv == 0) return;
+    const uint8_t *src; uint8_t want; int32_t *list; int *count; CellRange range;
+    compact_source(F, which, src, want, list, count, range);
     __shared__ int lw[4];
-    bool hit[4];
-    const int base = blockIdx.x * CMP_CELLS + threadIdx.x * 4;
-    const int c = cells_matching(flags, base, N, want, hit);
-    int total;
-    int pos = offsets[blockIdx.x] + block_exclusive_scan(c, lw, total);
+    int t0, t1;
+    tile_range(range.size(), t0, t1);
+    int base = F.counts[blockIdx.x];
+    int lo[3] = {F.nx, F.ny, F.nz}, hi[3] = {-1, -1, -1};
+    for (int t = t0; t < t1; ++t) {
+        bool hit[4];
+        int idx[4];
+        const int c = cells_matching(src, range, F.nx, F.ny, t * CMP_CELLS + threadIdx.x * 4, want, hit, idx);
+        int total;
+        int pos = base + block_exclusive_scan(c, lw, total);
 #pragma unroll
-    for (int s = 0; s < 4; ++s)
-        if (hit[s]) list[pos++] = base + s;
+        for (int s = 0; s < 4; ++s)
+            if (hit[s]) {
+                const int i = idx[s];
+                list[pos++] = i;
+                const int yz = i / F.nx, x = i - yz * F.nx, z = yz / F.ny, y = yz - z * F.ny;
+                lo[0] = min(lo[0], x); lo[1] = min(lo[1], y); lo[2] = min(lo[2], z);
+                hi[0] = max(hi[0], x); hi[1] = max(hi[1], y); hi[2] = max(hi[2], z);
+            }
+        base += total;
+    }
+    if (which == 0 && hi[0] >= 0) {
+        for (int k = 0; k < 3; ++k) {
+            atomicMin(&F.sc->bbox[k], lo[k]);
+            atomicMax(&F.sc->bbox[3 + k], hi[k]);
+        }
+    }
 }
 
 // Static list of obstacle cells with at least one non-obstacle D3Q19
@@ -356,8 +436,9 @@ __global__ __launch_bounds__(256) void k_mark_wall_cells(const uint8_t *flags, u
 // links are excluded), nw the normalised sum of the directions from x_o to
 // its non-obstacle neighbours. Block 0 also closes the step's bookkeeping.
 template <class P>
-__global__ __launch_bounds__(256) void k_obstacle_fill(Fields<P> F, int end_of_step)
+__global__ __launch_bounds__(256) void k_obstacle_fill(const Batch<P> B, int end_of_step)
 {
+    const Fields<P> &F = B.f[blockIdx.y];
     using R = typename P::R;
     if (end_of_step && blockIdx.x == 0 && threadIdx.x == 0) {
         F.sc->nconv = 0;

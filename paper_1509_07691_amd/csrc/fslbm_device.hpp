@@ -53,28 +53,30 @@ enum : uint8_t { CV_NONE = 0, CV_FILL = 1, CV_EMPTY = 2 };
 
 // ------------------------------------------------------- precision traits
 // S: stored type of a distribution, T: arithmetic type of the collide,
-// R: type of the scalar fields m, rho, phi, K, normals and PLIC offsets.
-// Shifted storage keeps g_q = (f_q - w_q) * SCALE.
+// R: type of the scalar fields m, rho, phi, K, normals and PLIC offsets,
+// G: arithmetic type of normals, PLIC offsets and FD curvature (the LSQR
+// normal equations are always FP64). Shifted storage keeps
+// g_q = (f_q - w_q) * SCALE.
 enum Precision { P_F64 = 0, P_F32 = 1, P_F16 = 2, P_BF16 = 3 };
 
 template <int P> struct Prec;
 template <> struct Prec<P_F64> {
-    using S = double; using T = double; using R = double;
+    using S = double; using T = double; using R = double; using G = double;
     static constexpr bool SHIFT = false;
     static constexpr double SCALE = 1.0;
 };
 template <> struct Prec<P_F32> {
-    using S = float; using T = float; using R = float;
+    using S = float; using T = float; using R = float; using G = float;
     static constexpr bool SHIFT = false;
     static constexpr double SCALE = 1.0;
 };
 template <> struct Prec<P_F16> {
-    using S = __half; using T = float; using R = float;
+    using S = __half; using T = float; using R = float; using G = float;
     static constexpr bool SHIFT = true;
     static constexpr double SCALE = 4096.0;
 };
 template <> struct Prec<P_BF16> {
-    using S = __hip_bfloat16; using T = float; using R = float;
+    using S = __hip_bfloat16; using T = float; using R = float; using G = float;
     static constexpr bool SHIFT = true;
     static constexpr double SCALE = 1.0;
 };
@@ -118,7 +120,38 @@ struct DevScalars {
     double mass;        // result of the last mass reduction
     int bad;            // numeric check result
     int pad;
+    int bbox[6];        // min x, y, z and max x, y, z of the interface cells
+    int fbox[6];        // the same for the fluid cells; never shrinks
 };
+
+// A box of cells [x0, x0+ex) x [y0, y0+ey) x [z0, z0+ez) enumerated with x
+// fastest, so consecutive box cells are consecutive in memory along rows and
+// the enumeration follows ascending linear index.
+struct CellRange {
+    int x0, y0, z0, ex, ey, ez;
+    __device__ inline int size() const { return ex * ey * ez; }
+    __device__ inline int cell(int k, int nx, int ny) const
+    {
+        const int x = k % ex, r = k / ex, y = r % ey, z = r / ey;
+        return (x0 + x) + nx * ((y0 + y) + ny * (z0 + z));
+    }
+    __device__ static inline CellRange whole(int nx, int ny, int nz) { return {0, 0, 0, nx, ny, nz}; }
+    __device__ static inline CellRange from(const int *b)
+    {
+        if (b[3] < b[0] || b[4] < b[1] || b[5] < b[2]) return {0, 0, 0, 0, 0, 0};
+        return {b[0], b[1], b[2], b[3] - b[0] + 1, b[4] - b[1] + 1, b[5] - b[2] + 1};
+    }
+};
+
+// Contiguous share [k0, k1) of n items for block blockIdx.x of gridDim.x,
+// in whole 256-item strides.
+__device__ inline void block_share(int n, int &k0, int &k1)
+{
+    const int strides = (n + 255) / 256;
+    const int per = (strides + gridDim.x - 1) / gridDim.x;
+    k0 = min(n, (int)blockIdx.x * per * 256);
+    k1 = min(n, k0 + per * 256);
+}
 
 // Model parameters (Sec. II): rho_b = 3 (p_g + sigma K), p_g = rho_gas / 3.
 struct Params {
@@ -129,6 +162,8 @@ struct Params {
     double cos_theta, sin_theta;
     double rho_gas;
     double eps_c;
+    int curv;          // 0 FD, 1 LSQR
+    int coll;          // 0 SRT, 1 TRT
 };
 
 template <class P> struct Fields {
@@ -141,9 +176,19 @@ template <class P> struct Fields {
     uint32_t *mark;
     R *m, *rho, *phi, *K, *nrm, *plic, *share, *phis, *nmol;
     int32_t *ilist, *olist;
+    int *counts;       // per-block counts of the list compaction
     DevScalars *sc;
     int nx, ny, nz;
     int N;
+};
+
+// Up to MAXB lattices advanced by one launch per kernel: lattice b is
+// handled by the blocks with blockIdx.y == b. Passed by value as the kernel
+// argument (about 1.8 KB), so no device-side descriptor memory is needed.
+constexpr int MAXB = 8;
+template <class P> struct Batch {
+    Fields<P> f[MAXB];
+    Params p[MAXB];
 };
 
 // Periodic neighbour offsets of one cell: index of (x+dx, y+dy, z+dz) is

@@ -9,6 +9,10 @@
 //     3x3x3 block with J = 0, plus the wetting gradient condition at contact
 //     points (Sec. II.C, eqs. LSQR-model, LSQR-error, anacurv, contactNormal,
 //     contactConstraint), solved through FP64 normal equations by Cholesky.
+// Both models run tile by tile: one workgroup takes an 8^3 tile of the
+// interface bounding box, stages the fill level (and cell flags) of the tile
+// and its halo in LDS with coalesced loads, and computes every stencil of
+// the tile from LDS.
 #pragma once
 
 #include "fslbm_convert.hpp"
@@ -36,146 +40,86 @@ __device__ inline void py_grad(const R *__restrict__ g, const Nbr &nb, double &g
 }
 
 // --------------------------------------------------------------- PLIC
-// Volume of {y in [0,1]^3 : s.y <= t} for 0 <= s1 <= s2 <= s3, s1+s2+s3 = 1
-// (from the corner expansion [t^3 - sum (t-s_i)_+^3 + ...] / (6 s1 s2 s3),
-// with each case rearranged so that only s2*s3 >= 0 divides, and the
-// complement for t > 1/2).
-__device__ inline double cube_cut_below(double s1, double s2, double s3, double t)
-{
-    bool flip = false;
-    if (t > 0.5) { t = 1.0 - t; flip = true; }
-    double v;
-    if (t <= 0.0) {
-        v = 0.0;
-    } else if (t <= s1) {
-        v = t * t * (t / s1) / (6.0 * s2 * s3);
-    } else if (t <= s2) {
-        v = (3.0 * t * t - 3.0 * t * s1 + s1 * s1) / (6.0 * s2 * s3);
-    } else if (t <= s1 + s2) {
-        const double e2 = t - s2;
-        double num = 3.0 * t * t - 3.0 * t * s1 + s1 * s1 - e2 * e2 * (e2 / s1);
-        if (t > s3) {
-            const double e3 = t - s3;
-            num -= e3 * e3 * (e3 / s1);
-        }
-        v = num / (6.0 * s2 * s3);
-    } else {
-        v = (2.0 * t - s1 - s2) / (2.0 * s3);
+// Volume V(t) of {y in [0,1]^3 : s.y <= t} for 0 <= s1 <= s2 <= s3,
+// s1+s2+s3 = 1, and its slope, from the corner expansion
+// [t^3 - sum (t-s_i)_+^3 + ...] / (6 s1 s2 s3) with each case rearranged so
+// that no small s_i divides alone; t > 1/2 by the point reflection
+// V(t) = 1 - V(1-t), V'(t) = V'(1-t). Reciprocals are taken once per cell.
+template <class G> struct CubeCut {
+    G s1, s2, s3, r1, r23, r3;  // r1 = 1/s1, r23 = 1/(6 s2 s3), r3 = 1/(2 s3)
+    __host__ __device__ inline CubeCut(G a, G b, G c) : s1(a), s2(b), s3(c)
+    {
+        r1 = s1 > G(0) ? G(1) / s1 : G(0);
+        r23 = s2 > G(0) ? G(1) / (G(6) * s2 * s3) : G(0);
+        r3 = G(1) / (G(2) * s3);
     }
-    return flip ? 1.0 - v : v;
-}
+    __host__ __device__ inline void eval(G t, G &v, G &dv) const
+    {
+        const bool flip = t > G(0.5);
+        if (flip) t = G(1) - t;
+        if (t <= G(0)) {
+            v = G(0);
+            dv = G(0);
+        } else if (t <= s1) {  // corner tetrahedron
+            v = t * t * (t * r1) * r23;
+            dv = G(3) * t * t * r1 * r23;
+        } else if (t <= s2) {
+            v = (G(3) * t * t - G(3) * t * s1 + s1 * s1) * r23;
+            dv = (G(6) * t - G(3) * s1) * r23;
+        } else if (t <= s1 + s2) {
+            const G e2 = t - s2;
+            G num = G(3) * t * t - G(3) * t * s1 + s1 * s1 - e2 * e2 * (e2 * r1);
+            G den = G(6) * t - G(3) * s1 - G(3) * e2 * e2 * r1;
+            if (t > s3) {
+                const G e3 = t - s3;
+                num -= e3 * e3 * (e3 * r1);
+                den -= G(3) * e3 * e3 * r1;
+            }
+            v = num * r23;
+            dv = den * r23;
+        } else {  // the plane cuts all four edges along y3
+            v = (G(2) * t - s1 - s2) * r3;
+            dv = G(2) * r3;
+        }
+        if (flip) v = G(1) - v;
+    }
+};
 
 // Plane offset a (point p = centre + a n) whose liquid side n.(x - centre) >= a
-// cuts volume phi out of the unit cell: 42 bisection halvings of
-// [-|n|_1/2, |n|_1/2] (bracket below 4e-13, Sec. II.B).
-__device__ inline double plic_offset(double nx, double ny, double nz, double phi)
+// cuts volume phi out of the unit cell (Sec. II.B). The liquid volume at
+// offset a is V(1/2 - a/|n|_1); the root t of V(t) = phi is found by Newton
+// steps kept inside a bisection bracket, stopping when the step falls below
+// the type's resolution. This reaches the root to rounding, within the 4e-13
+// bound of the paper's 40-step bisection.
+template <class G>
+__host__ __device__ inline G plic_offset(G nx, G ny, G nz, G phi)
 {
-    double m0 = fabs(nx), m1 = fabs(ny), m2 = fabs(nz);
-    const double l1 = m0 + m1 + m2;
-    if (!(l1 > 0.0)) return 0.0;
-    phi = fmin(fmax(phi, 0.0), 1.0);
-    m0 /= l1; m1 /= l1; m2 /= l1;
-    // sort ascending
-    if (m0 > m1) { const double t = m0; m0 = m1; m1 = t; }
-    if (m1 > m2) { const double t = m1; m1 = m2; m2 = t; }
-    if (m0 > m1) { const double t = m0; m0 = m1; m1 = t; }
-    double lo = -0.5 * l1, hi = 0.5 * l1;
-    for (int it = 0; it < 42; ++it) {
-        const double mid = 0.5 * (lo + hi);
-        // liquid volume at offset mid equals V(1/2 - mid/l1)
-        if (cube_cut_below(m0, m1, m2, 0.5 - mid / l1) > phi) lo = mid;
-        else hi = mid;
+    G m0 = fabs(nx), m1 = fabs(ny), m2 = fabs(nz);
+    const G l1 = m0 + m1 + m2;
+    if (!(l1 > G(0))) return G(0);
+    phi = fmin(fmax(phi, G(0)), G(1));
+    const G il1 = G(1) / l1;
+    m0 *= il1; m1 *= il1; m2 *= il1;
+    if (m0 > m1) { const G t = m0; m0 = m1; m1 = t; }
+    if (m1 > m2) { const G t = m1; m1 = m2; m2 = t; }
+    if (m0 > m1) { const G t = m0; m0 = m1; m1 = t; }
+    const CubeCut<G> cut(m0, m1, m2);
+    const G tol = sizeof(G) == 8 ? G(1e-15) : G(2e-7);
+    G lo = 0, hi = 1, t = phi;
+    for (int it = 0; it < 64; ++it) {
+        G v, dv;
+        cut.eval(t, v, dv);
+        v -= phi;
+        if (v <= G(0)) lo = t;  // V(lo) <= phi
+        else hi = t;            // V(hi) > phi
+        if (v == G(0) || hi - lo <= tol) break;
+        G tn = dv > G(0) ? t - v / dv : G(-1);
+        if (!(tn > lo && tn < hi)) tn = G(0.5) * (lo + hi);
+        const G step = fabs(tn - t);
+        t = tn;
+        if (step <= tol) break;
     }
-    return 0.5 * (lo + hi);
-}
-
-template <class P>
-__global__ __launch_bounds__(256) void k_normals_plic(Fields<P> F)
-{
-    using R = typename P::R;
-    const int n = list_count(F.sc);
-    const size_t N = F.N;
-    for (int k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256) {
-        const int i = F.ilist[k];
-        const Nbr nb(i, F.nx, F.ny, F.nz);
-        double gx, gy, gz;
-        py_grad(F.phi, nb, gx, gy, gz);
-        const double len = sqrt(gx * gx + gy * gy + gz * gz);
-        double nx = 0, ny = 0, nz = 0, a = 0;
-        if (len > 1e-12) {
-            nx = gx / len; ny = gy / len; nz = gz / len;
-            a = plic_offset(nx, ny, nz, double(F.phi[i]));
-        }
-        F.nrm[i] = R(nx);
-        F.nrm[N + i] = R(ny);
-        F.nrm[2 * N + i] = R(nz);
-        F.plic[i] = R(a);
-    }
-}
-
-// ----------------------------------------------------------- FD model
-// K8 kernel of support 2 on the 27-point block: (1 - r^2/4)^4 gives
-// 256, 81, 16, 1 (times 1/256) for r^2 = 0, 1, 2, 3; normalised by 942.
-__device__ inline double k8w(int r2) { return r2 == 0 ? 256.0 : (r2 == 1 ? 81.0 : (r2 == 2 ? 16.0 : 1.0)); }
-
-template <class P>
-__global__ __launch_bounds__(256) void k_fd_mollify(Fields<P> F)
-{
-    using R = typename P::R;
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= F.N) return;
-    const Nbr nb(i, F.nx, F.ny, F.nz);
-    double s = 0.0;
-#pragma unroll
-    for (int c = -1; c <= 1; ++c)
-#pragma unroll
-        for (int b = -1; b <= 1; ++b)
-#pragma unroll
-            for (int a = -1; a <= 1; ++a) s += k8w(a * a + b * b + c * c) * double(F.phi[nb.at(a, b, c)]);
-    F.phis[i] = R(s / 942.0);
-}
-
-template <class P>
-__global__ __launch_bounds__(256) void k_fd_normals(Fields<P> F)
-{
-    using R = typename P::R;
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= F.N) return;
-    const Nbr nb(i, F.nx, F.ny, F.nz);
-    double gx, gy, gz;
-    py_grad(F.phis, nb, gx, gy, gz);
-    const double len = sqrt(gx * gx + gy * gy + gz * gz);
-    const size_t N = F.N;
-    const bool ok = len > 1e-12;
-    F.nmol[i] = R(ok ? gx / len : 0.0);
-    F.nmol[N + i] = R(ok ? gy / len : 0.0);
-    F.nmol[2 * N + i] = R(ok ? gz / len : 0.0);
-}
-
-// K = -div(n^) with the PY-weighted central difference scaled to a
-// derivative: 1/16 for the transverse weights, 1/2 for the difference.
-template <class P>
-__global__ __launch_bounds__(256) void k_fd_curvature(Fields<P> F)
-{
-    using R = typename P::R;
-    const int n = list_count(F.sc);
-    const size_t N = F.N;
-    for (int k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256) {
-        const int i = F.ilist[k];
-        const Nbr nb(i, F.nx, F.ny, F.nz);
-        const R *nxf = F.nmol, *nyf = F.nmol + N, *nzf = F.nmol + 2 * N;
-        double dxx = 0, dyy = 0, dzz = 0;
-#pragma unroll
-        for (int a = -1; a <= 1; ++a)
-#pragma unroll
-            for (int b = -1; b <= 1; ++b) {
-                const double w = pyw(a) * pyw(b);
-                dxx += w * (double(nxf[nb.at(1, a, b)]) - double(nxf[nb.at(-1, a, b)]));
-                dyy += w * (double(nyf[nb.at(a, 1, b)]) - double(nyf[nb.at(a, -1, b)]));
-                dzz += w * (double(nzf[nb.at(a, b, 1)]) - double(nzf[nb.at(a, b, -1)]));
-            }
-        F.K[i] = R(-((dxx + dyy + dzz) / 32.0));
-    }
+    return l1 * (G(0.5) - t);
 }
 
 // --------------------------------------------------------- LSQR model
@@ -244,33 +188,230 @@ template <int C> struct Gram {
     }
 };
 
+
 __device__ inline double dot(const double (&a)[3], const double (&b)[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
 
-template <class P>
-__device__ inline void load_normal(const Fields<P> &F, int j, double (&n)[3])
+constexpr int TILE = 8;
+
+// Tiles covering the interface bounding box; a tile cell is processed when
+// its unwrapped coordinates lie inside the box (a box spanning a whole
+// periodic axis would otherwise see wrapped cells twice).
+struct Tiles {
+    CellRange box;
+    int tx, ty, tz;
+    __device__ inline Tiles(const DevScalars *sc)
+    {
+        box = CellRange::from(sc->bbox);
+        tx = (box.ex + TILE - 1) / TILE;
+        ty = (box.ey + TILE - 1) / TILE;
+        tz = (box.ez + TILE - 1) / TILE;
+    }
+    __device__ inline int count() const { return tx * ty * tz; }
+    __device__ inline void origin(int t, int &ox, int &oy, int &oz) const
+    {
+        ox = box.x0 + TILE * (t % tx);
+        oy = box.y0 + TILE * ((t / tx) % ty);
+        oz = box.z0 + TILE * (t / (tx * ty));
+    }
+    __device__ inline bool inside(int ux, int uy, int uz) const
+    {
+        return ux < box.x0 + box.ex && uy < box.y0 + box.ey && uz < box.z0 + box.ez;
+    }
+};
+
+__device__ inline int wrapi(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+__device__ inline int gidx(int x, int y, int z, int nx, int ny, int nz)
 {
-    const size_t N = F.N;
-    n[0] = double(F.nrm[j]);
-    n[1] = double(F.nrm[N + j]);
-    n[2] = double(F.nrm[2 * N + j]);
+    return wrapi(x, nx) + nx * (wrapi(y, ny) + ny * wrapi(z, nz));
 }
 
-// Contact point and contact normal of contact-line cell j at offset d from
-// the centre (eqs. contactNormal, contactConstraint; Fig. contactPoint).
-// Returns false when the condition is skipped.
+// Does the tile hold an interface cell? (uniform across the workgroup)
 template <class P>
-__device__ inline bool contact_condition(const Fields<P> &F, int j, int dx, int dy, int dz, const double (&pc)[3],
+__device__ inline bool tile_has_interface(const Fields<P> &F, const Tiles &T, int ox, int oy, int oz)
+{
+    int has = 0;
+    for (int c = threadIdx.x; c < TILE * TILE * TILE; c += 256) {
+        const int lx = c % TILE, ly = (c / TILE) % TILE, lz = c / (TILE * TILE);
+        if (!T.inside(ox + lx, oy + ly, oz + lz)) continue;
+        has |= F.flags[gidx(ox + lx, oy + ly, oz + lz, F.nx, F.ny, F.nz)] & FL_IF;
+    }
+    return __syncthreads_or(has) != 0;
+}
+
+// Unscaled Parker-Youngs gradient of an LDS cube of edge E at (x, y, z).
+template <int E, class G, class A>
+__device__ inline void py_grad_lds(const A &g, int x, int y, int z, G &gx, G &gy, G &gz)
+{
+    auto at = [&](int dx, int dy, int dz) { return g[((z + dz) * E + (y + dy)) * E + (x + dx)]; };
+    gx = gy = gz = G(0);
+#pragma unroll
+    for (int a = -1; a <= 1; ++a)
+#pragma unroll
+        for (int b = -1; b <= 1; ++b) {
+            const G w = G(pyw(a) * pyw(b));
+            gx += w * (at(1, a, b) - at(-1, a, b));
+            gy += w * (at(a, 1, b) - at(a, -1, b));
+            gz += w * (at(a, b, 1) - at(a, b, -1));
+        }
+}
+
+// Unit normal (zero when the gradient vanishes) from a PY gradient.
+template <class G>
+__device__ inline void unit_normal(G gx, G gy, G gz, G (&n)[3])
+{
+    const G len = sqrt(gx * gx + gy * gy + gz * gz);
+    const bool ok = len > G(1e-12);
+    n[0] = ok ? gx / len : G(0);
+    n[1] = ok ? gy / len : G(0);
+    n[2] = ok ? gz / len : G(0);
+}
+
+template <class P, class G>
+__device__ inline void store_normal(const Fields<P> &F, int i, const G (&n)[3], G a)
+{
+    using R = typename P::R;
+    const size_t N = F.N;
+    F.nrm[i] = R(n[0]);
+    F.nrm[N + i] = R(n[1]);
+    F.nrm[2 * N + i] = R(n[2]);
+    F.plic[i] = R(a);
+}
+
+// K8 kernel of support 2 on the 27-point block: (1 - r^2/4)^4 gives
+// 256, 81, 16, 1 (times 1/256) for r^2 = 0, 1, 2, 3; normalised by 942.
+__device__ inline double k8w(int r2) { return r2 == 0 ? 256.0 : (r2 == 1 ? 81.0 : (r2 == 2 ? 16.0 : 1.0)); }
+
+
+// FD model, one 8^3 tile per iteration. LDS: the fill level on the tile
+// grown by 3 (14^3), the mollified fill level grown by 2 (12^3) and the
+// mollified unit normals grown by 1 (10^3, reusing the fill-level space).
+// The raw-fill normals of the tile's interface cells (for the corner rule)
+// come from the same LDS copy.
+template <class G> struct FdLds {
+    G buf[3000];  // phi 14^3 (origin -3), later normals 3 x 10^3 (origin -1)
+    G mol[1728];  // mollified phi 12^3 (origin -2)
+};
+
+template <class P>
+__global__ __launch_bounds__(256) void k_geometry_fd(const Batch<P> B)
+{
+    if (B.p[blockIdx.y].curv != 0) return;
+    const Fields<P> &F = B.f[blockIdx.y];
+    using R = typename P::R;
+    using G = typename P::G;
+    __shared__ FdLds<G> L;
+    const Tiles T(F.sc);
+    const int nt = T.count();
+    for (int t = blockIdx.x; t < nt; t += gridDim.x) {
+        int ox, oy, oz;
+        T.origin(t, ox, oy, oz);
+        __syncthreads();
+        if (!tile_has_interface(F, T, ox, oy, oz)) continue;
+        for (int c = threadIdx.x; c < 14 * 14 * 14; c += 256) {
+            const int x = c % 14, y = (c / 14) % 14, z = c / 196;
+            L.buf[c] = G(F.phi[gidx(ox - 3 + x, oy - 3 + y, oz - 3 + z, F.nx, F.ny, F.nz)]);
+        }
+        __syncthreads();
+        // raw-fill normals of the tile's interface cells
+        for (int c = threadIdx.x; c < 512; c += 256) {
+            const int lx = c % 8, ly = (c / 8) % 8, lz = c / 64;
+            if (!T.inside(ox + lx, oy + ly, oz + lz)) continue;
+            const int i = gidx(ox + lx, oy + ly, oz + lz, F.nx, F.ny, F.nz);
+            if (!(F.flags[i] & FL_IF)) continue;
+            G gx, gy, gz, n[3];
+            py_grad_lds<14>(L.buf, lx + 3, ly + 3, lz + 3, gx, gy, gz);
+            unit_normal(gx, gy, gz, n);
+            store_normal(F, i, n, G(0));
+        }
+        // K8 mollification on 12^3
+        for (int c = threadIdx.x; c < 1728; c += 256) {
+            const int x = c % 12, y = (c / 12) % 12, z = c / 144;
+            G s = G(0);
+#pragma unroll
+            for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+                for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+                    for (int dx = -1; dx <= 1; ++dx)
+                        s += G(k8w(dx * dx + dy * dy + dz * dz)) * L.buf[((z + 1 + dz) * 14 + y + 1 + dy) * 14 + x + 1 + dx];
+            L.mol[c] = s / G(942);
+        }
+        __syncthreads();
+        // unit normals of the mollified field on 10^3
+        for (int c = threadIdx.x; c < 1000; c += 256) {
+            const int x = c % 10, y = (c / 10) % 10, z = c / 100;
+            G gx, gy, gz, n[3];
+            py_grad_lds<12>(L.mol, x + 1, y + 1, z + 1, gx, gy, gz);
+            unit_normal(gx, gy, gz, n);
+            L.buf[c] = n[0];
+            L.buf[1000 + c] = n[1];
+            L.buf[2000 + c] = n[2];
+        }
+        __syncthreads();
+        // K = -div(n^), PY-weighted central differences scaled by 1/32
+        for (int c = threadIdx.x; c < 512; c += 256) {
+            const int lx = c % 8, ly = (c / 8) % 8, lz = c / 64;
+            if (!T.inside(ox + lx, oy + ly, oz + lz)) continue;
+            const int i = gidx(ox + lx, oy + ly, oz + lz, F.nx, F.ny, F.nz);
+            if (!(F.flags[i] & FL_IF)) continue;
+            G dxx = 0, dyy = 0, dzz = 0;
+            auto at = [&](int comp, int dx, int dy, int dz) {
+                return L.buf[comp * 1000 + ((lz + 1 + dz) * 10 + ly + 1 + dy) * 10 + lx + 1 + dx];
+            };
+#pragma unroll
+            for (int a = -1; a <= 1; ++a)
+#pragma unroll
+                for (int b = -1; b <= 1; ++b) {
+                    const G w = G(pyw(a) * pyw(b));
+                    dxx += w * (at(0, 1, a, b) - at(0, -1, a, b));
+                    dyy += w * (at(1, a, 1, b) - at(1, a, -1, b));
+                    dzz += w * (at(2, a, b, 1) - at(2, a, b, -1));
+                }
+            F.K[i] = R(-((dxx + dyy + dzz) / G(32)));
+        }
+    }
+}
+
+// LSQR model: one thread per interface cell over the interface list (the
+// fit is FP64 arithmetic with long dependency chains, so full wavefronts
+// matter more than load coalescing). Neighbour data are read through a view
+// centred on the cell; offsets reach 2 cells (a contact cell next to the
+// centre needs its own wall neighbours).
+template <class P> struct LsqrView {
+    const Fields<P> &F;
+    int x, y, z;  // centre
+    __device__ inline int at(int dx, int dy, int dz) const { return gidx(x + dx, y + dy, z + dz, F.nx, F.ny, F.nz); }
+    __device__ inline uint8_t flag(int dx, int dy, int dz) const { return F.flags[at(dx, dy, dz)]; }
+    __device__ inline void normal(int dx, int dy, int dz, double (&n)[3]) const
+    {
+        const int j = at(dx, dy, dz);
+        const size_t N = F.N;
+        n[0] = double(F.nrm[j]);
+        n[1] = double(F.nrm[N + j]);
+        n[2] = double(F.nrm[2 * N + j]);
+    }
+    __device__ inline double plic(int dx, int dy, int dz) const { return double(F.plic[at(dx, dy, dz)]); }
+};
+
+// Contact point and contact normal of the contact-line cell at offset d from
+// the centre (eqs. contactNormal, contactConstraint; Fig. contactPoint): the
+// point of (PLIC plane) ∩ (wall plane) nearest to the PLIC point, reached
+// along the wall normal projected onto the PLIC plane; the wall plane lies
+// half a cell from the cell centre along the wall normal (the bounce-back
+// wall is half-way between nodes). Returns false when the condition is
+// skipped.
+template <class View>
+__device__ inline bool contact_condition(const View &V, int dx, int dy, int dz, const double (&pc)[3],
                                          const double (&nc)[3], const double (&tu)[3], const double (&tv)[3],
                                          const Params &prm, double &uc, double &vc, double &ru, double &rv)
 {
     double nj[3];
-    load_normal(F, j, nj);
+    V.normal(dx, dy, dz, nj);
     if (nj[0] == 0.0 && nj[1] == 0.0 && nj[2] == 0.0) return false;
-    const Nbr nb(j, F.nx, F.ny, F.nz);
     int sx = 0, sy = 0, sz = 0;
 #pragma unroll
     for (int q = 1; q < NQ; ++q)
-        if (F.flags[nb.at(dir_x(q), dir_y(q), dir_z(q))] & FL_OBST) {
+        if (V.flag(dx + dir_x(q), dy + dir_y(q), dz + dir_z(q)) & FL_OBST) {
             sx += dir_x(q); sy += dir_y(q); sz += dir_z(q);
         }
     const double lw = sqrt(double(sx * sx + sy * sy + sz * sz));
@@ -286,7 +427,7 @@ __device__ inline bool contact_condition(const Fields<P> &F, int j, int dx, int 
     const double g[3] = {nw[0] - nn * nj[0], nw[1] - nn * nj[1], nw[2] - nn * nj[2]};
     const double gn = dot(g, nw);
     if (gn < 1e-12) return false;
-    const double aj = double(F.plic[j]);
+    const double aj = V.plic(dx, dy, dz);
     const double pj[3] = {aj * nj[0], aj * nj[1], aj * nj[2]};
     const double t = (0.5 - dot(pj, nw)) / gn;
     const double r[3] = {dx + pj[0] + t * g[0] - pc[0], dy + pj[1] + t * g[1] - pc[1], dz + pj[2] + t * g[2] - pc[2]};
@@ -299,131 +440,163 @@ __device__ inline bool contact_condition(const Fields<P> &F, int j, int dx, int 
     return true;
 }
 
-template <class P>
-__global__ __launch_bounds__(256) void k_curv_lsqr(Fields<P> F, Params prm)
+// K = 2 kappa of the least-squares quadric at the centre of view V.
+template <class View>
+__device__ inline double lsqr_curvature(const View &V, const Params &prm)
 {
-    using R = typename P::R;
-    const int n = list_count(F.sc);
-    for (int k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256) {
-        const int i = F.ilist[k];
-        double nc[3];
-        load_normal(F, i, nc);
-        if (nc[0] == 0.0 && nc[1] == 0.0 && nc[2] == 0.0) {
-            F.K[i] = R(0);
-            continue;
+    double nc[3];
+    V.normal(0, 0, 0, nc);
+    if (nc[0] == 0.0 && nc[1] == 0.0 && nc[2] == 0.0) return 0.0;
+    // frame: t_u from the axis with the smallest |n_k| (first on ties)
+    int ax = 0;
+    if (fabs(nc[1]) < fabs(nc[ax])) ax = 1;
+    if (fabs(nc[2]) < fabs(nc[ax])) ax = 2;
+    double tu[3] = {-nc[ax] * nc[0], -nc[ax] * nc[1], -nc[ax] * nc[2]};
+    tu[ax] += 1.0;
+    const double ltu = sqrt(dot(tu, tu));
+    tu[0] /= ltu; tu[1] /= ltu; tu[2] /= ltu;
+    const double tv[3] = {nc[1] * tu[2] - nc[2] * tu[1], nc[2] * tu[0] - nc[0] * tu[2], nc[0] * tu[1] - nc[1] * tu[0]};
+    const double ac = V.plic(0, 0, 0);
+    const double pc[3] = {ac * nc[0], ac * nc[1], ac * nc[2]};
+    bool has_obst = false;
+#pragma unroll
+    for (int c = -1; c <= 1; ++c)
+#pragma unroll
+        for (int b = -1; b <= 1; ++b)
+#pragma unroll
+            for (int a = -1; a <= 1; ++a) has_obst |= (V.flag(a, b, c) & FL_OBST) != 0;
+
+    // hard constraint of the centre: H = hu - 2 uc A - vc C, I = hv - 2 vc B - uc C
+    bool hard = false;
+    double huc = 0, hvc = 0, hu = 0, hv = 0;
+    if (has_obst && (V.flag(0, 0, 0) & FL_NEAR_OBST))
+        hard = contact_condition(V, 0, 0, 0, pc, nc, tu, tv, prm, huc, hvc, hu, hv);
+
+    Gram<5> g5;  // free model (A, B, C, H, I)
+    Gram<3> g3;  // free: isotropic (A, H, I); hard: (A, B, C)
+    Gram<1> g1;  // hard isotropic (A)
+    int rows = 0;
+    auto add_row = [&](double r0, double r1, double r2, double r3, double r4, double b) {
+        ++rows;
+        if (!hard) {
+            const double a5[5] = {r0, r1, r2, r3, r4};
+            g5.add(a5, b);
+            const double a3[3] = {r0 + r1, r3, r4};
+            g3.add(a3, b);
+        } else {
+            const double e0 = r0 - r3 * (2.0 * huc), e1 = r1 - r4 * (2.0 * hvc);
+            const double e2 = r2 - r3 * hvc - r4 * huc;
+            const double be = b - r3 * hu - r4 * hv;
+            const double a3[3] = {e0, e1, e2};
+            g3.add(a3, be);
+            const double a1[1] = {e0 + e1};
+            g1.add(a1, be);
         }
-        // frame: t_u from the axis with the smallest |n_k| (first on ties)
-        int ax = 0;
-        if (fabs(nc[1]) < fabs(nc[ax])) ax = 1;
-        if (fabs(nc[2]) < fabs(nc[ax])) ax = 2;
-        double tu[3] = {-nc[ax] * nc[0], -nc[ax] * nc[1], -nc[ax] * nc[2]};
-        tu[ax] += 1.0;
-        const double ltu = sqrt(dot(tu, tu));
-        tu[0] /= ltu; tu[1] /= ltu; tu[2] /= ltu;
-        const double tv[3] = {nc[1] * tu[2] - nc[2] * tu[1], nc[2] * tu[0] - nc[0] * tu[2], nc[0] * tu[1] - nc[1] * tu[0]};
-        const double ac = double(F.plic[i]);
-        const double pc[3] = {ac * nc[0], ac * nc[1], ac * nc[2]};
-        const Nbr nb(i, F.nx, F.ny, F.nz);
-        bool has_obst = false;
-#pragma unroll
-        for (int c = -1; c <= 1; ++c)
-#pragma unroll
-            for (int b = -1; b <= 1; ++b)
-#pragma unroll
-                for (int a = -1; a <= 1; ++a) has_obst |= (F.flags[nb.at(a, b, c)] & FL_OBST) != 0;
-
-        // hard constraint of the centre: H = hu - 2 uc A - vc C, I = hv - 2 vc B - uc C
-        bool hard = false;
-        double huc = 0, hvc = 0, hu = 0, hv = 0;
-        if (has_obst && (F.flags[i] & FL_NEAR_OBST))
-            hard = contact_condition(F, i, 0, 0, 0, pc, nc, tu, tv, prm, huc, hvc, hu, hv);
-
-        Gram<5> g5;  // free model (A, B, C, H, I)
-        Gram<3> g3;  // free: isotropic (A, H, I); hard: (A, B, C)
-        Gram<1> g1;  // hard isotropic (A)
-        int rows = 0;
-        auto add_row = [&](double r0, double r1, double r2, double r3, double r4, double b) {
-            ++rows;
-            if (!hard) {
-                const double a5[5] = {r0, r1, r2, r3, r4};
-                g5.add(a5, b);
-                const double a3[3] = {r0 + r1, r3, r4};
-                g3.add(a3, b);
-            } else {
-                const double e0 = r0 - r3 * (2.0 * huc), e1 = r1 - r4 * (2.0 * hvc);
-                const double e2 = r2 - r3 * hvc - r4 * huc;
-                const double be = b - r3 * hu - r4 * hv;
-                const double a3[3] = {e0, e1, e2};
-                g3.add(a3, be);
-                const double a1[1] = {e0 + e1};
-                g1.add(a1, be);
+    };
+    // data rows: PLIC points of the other interface cells of the block
+    for (int c = -1; c <= 1; ++c)
+        for (int b = -1; b <= 1; ++b)
+            for (int a = -1; a <= 1; ++a) {
+                if (a == 0 && b == 0 && c == 0) continue;
+                if (!(V.flag(a, b, c) & FL_IF)) continue;
+                double nj[3];
+                V.normal(a, b, c, nj);
+                if (nj[0] == 0.0 && nj[1] == 0.0 && nj[2] == 0.0) continue;
+                const double aj = V.plic(a, b, c);
+                const double r[3] = {a + aj * nj[0] - pc[0], b + aj * nj[1] - pc[1], c + aj * nj[2] - pc[2]};
+                const double u = dot(r, tu), v = dot(r, tv), w = dot(r, nc);
+                add_row(u * u, v * v, u * v, u, v, w);
             }
-        };
-        // data rows: PLIC points of the other interface cells of the block
+    // wetting rows of the other contact-line cells
+    if (has_obst) {
         for (int c = -1; c <= 1; ++c)
             for (int b = -1; b <= 1; ++b)
                 for (int a = -1; a <= 1; ++a) {
                     if (a == 0 && b == 0 && c == 0) continue;
-                    const int j = nb.at(a, b, c);
-                    if (!(F.flags[j] & FL_IF)) continue;
-                    double nj[3];
-                    load_normal(F, j, nj);
-                    if (nj[0] == 0.0 && nj[1] == 0.0 && nj[2] == 0.0) continue;
-                    const double aj = double(F.plic[j]);
-                    const double r[3] = {a + aj * nj[0] - pc[0], b + aj * nj[1] - pc[1], c + aj * nj[2] - pc[2]};
-                    const double u = dot(r, tu), v = dot(r, tv), w = dot(r, nc);
-                    add_row(u * u, v * v, u * v, u, v, w);
+                    const uint8_t fj = V.flag(a, b, c);
+                    if (!((fj & FL_IF) && (fj & FL_NEAR_OBST))) continue;
+                    double uc, vc, ru, rv;
+                    if (!contact_condition(V, a, b, c, pc, nc, tu, tv, prm, uc, vc, ru, rv)) continue;
+                    add_row(2.0 * uc, 0.0, vc, 1.0, 0.0, ru);
+                    add_row(0.0, 2.0 * vc, uc, 0.0, 1.0, rv);
                 }
-        // wetting rows of the other contact-line cells
-        if (has_obst) {
-            for (int c = -1; c <= 1; ++c)
-                for (int b = -1; b <= 1; ++b)
-                    for (int a = -1; a <= 1; ++a) {
-                        if (a == 0 && b == 0 && c == 0) continue;
-                        const int j = nb.at(a, b, c);
-                        const uint8_t fj = F.flags[j];
-                        if (!((fj & FL_IF) && (fj & FL_NEAR_OBST))) continue;
-                        double uc, vc, ru, rv;
-                        if (!contact_condition(F, j, a, b, c, pc, nc, tu, tv, prm, uc, vc, ru, rv)) continue;
-                        add_row(2.0 * uc, 0.0, vc, 1.0, 0.0, ru);
-                        add_row(0.0, 2.0 * vc, uc, 0.0, 1.0, rv);
-                    }
-        }
-        double A = 0, B = 0, C = 0, H = 0, I = 0;
-        bool ok = false;
-        if (!hard) {
-            double x5[5];
-            if (rows >= 5 && g5.solve(x5)) {
-                A = x5[0]; B = x5[1]; C = x5[2]; H = x5[3]; I = x5[4];
-                ok = true;
-            } else {
-                double x3[3];
-                if (rows >= 3 && g3.solve(x3)) {
-                    A = x3[0]; B = x3[0]; C = 0.0; H = x3[1]; I = x3[2];
-                    ok = true;
-                }
-            }
+    }
+    double A = 0, Bq = 0, C = 0, H = 0, I = 0;
+    bool ok = false;
+    if (!hard) {
+        double x5[5];
+        if (rows >= 5 && g5.solve(x5)) {
+            A = x5[0]; Bq = x5[1]; C = x5[2]; H = x5[3]; I = x5[4];
+            ok = true;
         } else {
             double x3[3];
             if (rows >= 3 && g3.solve(x3)) {
-                A = x3[0]; B = x3[1]; C = x3[2];
+                A = x3[0]; Bq = x3[0]; C = 0.0; H = x3[1]; I = x3[2];
                 ok = true;
-            } else {
-                double x1[1];
-                if (rows >= 1 && g1.solve(x1)) {
-                    A = x1[0]; B = x1[0]; C = 0.0;
-                    ok = true;
-                }
             }
-            H = hu - 2.0 * huc * A - hvc * C;
-            I = hv - 2.0 * hvc * B - huc * C;
         }
-        double K = 0.0;
-        if (ok) {
-            const double gg = 1.0 + H * H + I * I;
-            K = 2.0 * (A * (1.0 + I * I) + B * (1.0 + H * H) - C * H * I) / (gg * sqrt(gg));
+    } else {
+        double x3[3];
+        if (rows >= 3 && g3.solve(x3)) {
+            A = x3[0]; Bq = x3[1]; C = x3[2];
+            ok = true;
+        } else {
+            double x1[1];
+            if (rows >= 1 && g1.solve(x1)) {
+                A = x1[0]; Bq = x1[0]; C = 0.0;
+                ok = true;
+            }
         }
-        F.K[i] = R(K);
+        H = hu - 2.0 * huc * A - hvc * C;
+        I = hv - 2.0 * hvc * Bq - huc * C;
+    }
+    if (!ok) return 0.0;
+    const double gg = 1.0 + H * H + I * I;
+    return 2.0 * (A * (1.0 + I * I) + Bq * (1.0 + H * H) - C * H * I) / (gg * sqrt(gg));
+}
+
+// Normals and PLIC points of the interface cells (LSQR model).
+template <class P>
+__global__ __launch_bounds__(256) void k_normals_plic(const Batch<P> B)
+{
+    if (B.p[blockIdx.y].curv != 1) return;
+    const Fields<P> &F = B.f[blockIdx.y];
+    using G = typename P::G;
+    const int n = list_count(F.sc);
+    for (int k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256) {
+        const int i = F.ilist[k];
+        const Nbr nb(i, F.nx, F.ny, F.nz);
+        G gx = 0, gy = 0, gz = 0;
+#pragma unroll
+        for (int a = -1; a <= 1; ++a)
+#pragma unroll
+            for (int b = -1; b <= 1; ++b) {
+                const G w = G(pyw(a) * pyw(b));
+                gx += w * (G(F.phi[nb.at(1, a, b)]) - G(F.phi[nb.at(-1, a, b)]));
+                gy += w * (G(F.phi[nb.at(a, 1, b)]) - G(F.phi[nb.at(a, -1, b)]));
+                gz += w * (G(F.phi[nb.at(a, b, 1)]) - G(F.phi[nb.at(a, b, -1)]));
+            }
+        G nrm[3];
+        unit_normal(gx, gy, gz, nrm);
+        const bool ok = nrm[0] != G(0) || nrm[1] != G(0) || nrm[2] != G(0);
+        const G a = ok ? plic_offset<G>(nrm[0], nrm[1], nrm[2], G(F.phi[i])) : G(0);
+        store_normal(F, i, nrm, a);
+    }
+}
+
+template <class P>
+__global__ __launch_bounds__(256) void k_curv_lsqr(const Batch<P> B)
+{
+    const Params &prm = B.p[blockIdx.y];
+    if (prm.curv != 1) return;
+    const Fields<P> &F = B.f[blockIdx.y];
+    using R = typename P::R;
+    const int n = list_count(F.sc);
+    for (int k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256) {
+        const int i = F.ilist[k];
+        const int yz = i / F.nx, x = i - yz * F.nx, z = yz / F.ny, y = yz - z * F.ny;
+        const LsqrView<P> V{F, x, y, z};
+        F.K[i] = R(lsqr_curvature(V, prm));
     }
 }
 

@@ -80,136 +80,13 @@ __device__ inline typename P::S *plane(typename P::S *base, int N)
     return base + (size_t)Q * (size_t)N;
 }
 
-template <class P, int COLL>
-__global__ __launch_bounds__(256) void k_stream_collide(Fields<P> F, Params prm)
+template <class P>
+__device__ inline void store_all(const Fields<P> &F, int i, const typename P::T (&f)[NQ])
 {
-    using T = typename P::T;
-    using R = typename P::R;
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= F.N) return;
-    const uint8_t fl = F.flags[i];
-    if (!(fl & FL_FLUID)) return;
-    const int N = F.N;
-    const Nbr nb(i, F.nx, F.ny, F.nz);
-    T fin[NQ];
-
-    if (fl == FL_LIQ) {
-        // Liquid cell away from walls: all D3Q19 neighbours are fluid (a
-        // liquid cell never touches gas), plain pull.
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            const int j = nb.at(-dir_x(q), -dir_y(q), -dir_z(q));
-            switch (q) {
-#define FSLBM_PULL(QQ) case QQ: fin[q] = load_f<P, QQ>(plane<P, QQ>(F.fsrc, N), j); break;
-                FSLBM_PULL(0) FSLBM_PULL(1) FSLBM_PULL(2) FSLBM_PULL(3) FSLBM_PULL(4)
-                FSLBM_PULL(5) FSLBM_PULL(6) FSLBM_PULL(7) FSLBM_PULL(8) FSLBM_PULL(9)
-                FSLBM_PULL(10) FSLBM_PULL(11) FSLBM_PULL(12) FSLBM_PULL(13) FSLBM_PULL(14)
-                FSLBM_PULL(15) FSLBM_PULL(16) FSLBM_PULL(17) FSLBM_PULL(18)
-#undef FSLBM_PULL
-            }
-        }
-    } else {
-        const bool is_if = (fl & FL_IF) != 0;
-        T fo[NQ];
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            switch (q) {
-#define FSLBM_OWN(QQ) case QQ: fo[q] = load_f<P, QQ>(plane<P, QQ>(F.fsrc, N), i); break;
-                FSLBM_OWN(0) FSLBM_OWN(1) FSLBM_OWN(2) FSLBM_OWN(3) FSLBM_OWN(4)
-                FSLBM_OWN(5) FSLBM_OWN(6) FSLBM_OWN(7) FSLBM_OWN(8) FSLBM_OWN(9)
-                FSLBM_OWN(10) FSLBM_OWN(11) FSLBM_OWN(12) FSLBM_OWN(13) FSLBM_OWN(14)
-                FSLBM_OWN(15) FSLBM_OWN(16) FSLBM_OWN(17) FSLBM_OWN(18)
-#undef FSLBM_OWN
-            }
-        }
-        // types of the upstream neighbours x - c_q
-        uint8_t nt[NQ];
-        bool has_gas = false;
-        int nwx = 0, nwy = 0, nwz = 0;  // sum of c_q towards obstacle neighbours
-#pragma unroll
-        for (int q = 1; q < NQ; ++q) {
-            nt[q] = F.flags[nb.at(-dir_x(q), -dir_y(q), -dir_z(q))] & FL_TYPE;
-            has_gas |= nt[q] == FL_GAS;
-            if (nt[q] == FL_OBST) { nwx -= dir_x(q); nwy -= dir_y(q); nwz -= dir_z(q); }
-        }
-        // boundary values of eq. reconstruct
-        T rb0, ubx, uby, ubz;
-        moments(fo, rb0, ubx, uby, ubz);
-        const T ubsq = ubx * ubx + uby * uby + ubz * ubz;
-        const T Kc = is_if ? T(F.K[i]) : T(0);
-        const T rhob = T(3) * (T(prm.rho_gas) / T(3) + T(prm.sigma) * Kc);
-        // corner rule: the outgoing link c_o = -c_q takes the free-surface rule
-        // when c_o . (P n) < 0, P the projection onto the wall plane; evaluated
-        // as (P c_o) . n with P c_o |nw|^2 = c_o |nw|^2 - (c_o . nw) nw in exact
-        // integers, so the link normal to the wall tests exactly zero.
-        const bool corner = is_if && has_gas && (nwx | nwy | nwz) != 0;
-        const int ww = nwx * nwx + nwy * nwy + nwz * nwz;
-        T cnx = 0, cny = 0, cnz = 0;
-        if (corner) {
-            cnx = T(F.nrm[i]);
-            cny = T(F.nrm[(size_t)N + i]);
-            cnz = T(F.nrm[2 * (size_t)N + i]);
-        }
-        fin[0] = fo[0];
-#pragma unroll
-        for (int q = 1; q < NQ; ++q) {
-            const int o = opp(q);
-            const uint8_t t = nt[q];
-            bool rec = false;
-            if (t & FL_FLUID) {
-                const int j = nb.at(-dir_x(q), -dir_y(q), -dir_z(q));
-                switch (q) {
-#define FSLBM_PULL(QQ) case QQ: fin[q] = load_f<P, QQ>(plane<P, QQ>(F.fsrc, N), j); break;
-                    FSLBM_PULL(1) FSLBM_PULL(2) FSLBM_PULL(3) FSLBM_PULL(4)
-                    FSLBM_PULL(5) FSLBM_PULL(6) FSLBM_PULL(7) FSLBM_PULL(8) FSLBM_PULL(9)
-                    FSLBM_PULL(10) FSLBM_PULL(11) FSLBM_PULL(12) FSLBM_PULL(13) FSLBM_PULL(14)
-                    FSLBM_PULL(15) FSLBM_PULL(16) FSLBM_PULL(17) FSLBM_PULL(18)
-#undef FSLBM_PULL
-                }
-            } else if (t == FL_GAS) {
-                rec = true;
-            } else {
-                const int cox = -dir_x(q), coy = -dir_y(q), coz = -dir_z(q);
-                const int cw = cox * nwx + coy * nwy + coz * nwz;
-                const T s = T(cox * ww - cw * nwx) * cnx + T(coy * ww - cw * nwy) * cny + T(coz * ww - cw * nwz) * cnz;
-                if (corner && s < T(0)) rec = true;
-                else fin[q] = fo[o];
-            }
-            if (rec)
-                fin[q] = feq<T>(q, rhob, ubx, uby, ubz, ubsq) + feq<T>(o, rhob, ubx, uby, ubz, ubsq) - fo[o];
-        }
-        if (is_if) {
-            // mass exchange: the neighbour x + c_q is the upstream node of o = qbar
-            const T phx = T(F.phi[i]);
-            T dm = 0;
-#pragma unroll
-            for (int q = 1; q < NQ; ++q) {
-                const int o = opp(q);
-                const uint8_t tz = nt[o];
-                T k;
-                if (tz == FL_LIQ) k = T(1);
-                else if (tz == FL_IF) k = T(0.5) * (T(F.phi[nb.at(dir_x(q), dir_y(q), dir_z(q))]) + phx);
-                else k = T(0);
-                dm += k * (fin[o] - fo[q]);
-            }
-            T r = 0;
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) r += fin[q];
-            const T mn = T(F.m[i]) + dm;
-            uint8_t st = CV_NONE;
-            if (mn > (T(1) + T(prm.eps_c)) * r) st = CV_FILL;
-            else if (mn < -T(prm.eps_c) * r) st = CV_EMPTY;
-            F.m[i] = R(mn);
-            F.rho[i] = R(r);
-            F.conv[i] = st;
-            if (st != CV_NONE) atomicAdd(&F.sc->nconv, 1);
-        }
-    }
-    collide<T, COLL>(fin, prm);
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
         switch (q) {
-#define FSLBM_STORE(QQ) case QQ: store_f<P, QQ>(plane<P, QQ>(F.fdst, N), i, fin[q]); break;
+#define FSLBM_STORE(QQ) case QQ: store_f<P, QQ>(plane<P, QQ>(F.fdst, F.N), i, f[q]); break;
             FSLBM_STORE(0) FSLBM_STORE(1) FSLBM_STORE(2) FSLBM_STORE(3) FSLBM_STORE(4)
             FSLBM_STORE(5) FSLBM_STORE(6) FSLBM_STORE(7) FSLBM_STORE(8) FSLBM_STORE(9)
             FSLBM_STORE(10) FSLBM_STORE(11) FSLBM_STORE(12) FSLBM_STORE(13) FSLBM_STORE(14)
@@ -217,6 +94,167 @@ __global__ __launch_bounds__(256) void k_stream_collide(Fields<P> F, Params prm)
 #undef FSLBM_STORE
         }
     }
+}
+
+// Load the 19 distributions f'_q(j_q) with j_q given per direction.
+template <class P>
+__device__ inline void load_dirs(const Fields<P> &F, const int (&j)[NQ], typename P::T (&f)[NQ])
+{
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        switch (q) {
+#define FSLBM_LD(QQ) case QQ: f[q] = load_f<P, QQ>(plane<P, QQ>(F.fsrc, F.N), j[q]); break;
+            FSLBM_LD(0) FSLBM_LD(1) FSLBM_LD(2) FSLBM_LD(3) FSLBM_LD(4)
+            FSLBM_LD(5) FSLBM_LD(6) FSLBM_LD(7) FSLBM_LD(8) FSLBM_LD(9)
+            FSLBM_LD(10) FSLBM_LD(11) FSLBM_LD(12) FSLBM_LD(13) FSLBM_LD(14)
+            FSLBM_LD(15) FSLBM_LD(16) FSLBM_LD(17) FSLBM_LD(18)
+#undef FSLBM_LD
+        }
+    }
+}
+
+// Liquid cell away from walls: every D3Q19 neighbour is fluid (a liquid cell
+// never touches gas), so the pull needs no neighbour types.
+template <class P, int COLL>
+__device__ inline void liquid_cell(const Fields<P> &F, const Params &prm, int i)
+{
+    using T = typename P::T;
+    const Nbr nb(i, F.nx, F.ny, F.nz);
+    int up[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) up[q] = nb.at(-dir_x(q), -dir_y(q), -dir_z(q));
+    T fin[NQ];
+    load_dirs<P>(F, up, fin);
+    collide<T, COLL>(fin, prm);
+    store_all<P>(F, i, fin);
+}
+
+// Cell with wall links (IS_IF = false) or interface cell (IS_IF = true).
+// All loads are issued before any of them is used: the cell's own
+// distributions, the upstream neighbours' types and distributions (loaded
+// whatever the neighbour type; only fluid ones are used) and, at interface
+// cells, the neighbours' fill levels.
+template <class P, int COLL, bool IS_IF>
+__device__ inline void boundary_cell(const Fields<P> &F, const Params &prm, int i)
+{
+    using T = typename P::T;
+    using R = typename P::R;
+    const int N = F.N;
+    const Nbr nb(i, F.nx, F.ny, F.nz);
+    int up[NQ], own[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        up[q] = nb.at(-dir_x(q), -dir_y(q), -dir_z(q));
+        own[q] = i;
+    }
+    T fo[NQ], pl[NQ];
+    load_dirs<P>(F, own, fo);
+    load_dirs<P>(F, up, pl);
+    uint8_t nt[NQ];
+#pragma unroll
+    for (int q = 1; q < NQ; ++q) nt[q] = F.flags[up[q]] & FL_TYPE;
+    T phn[NQ];
+    T Kc = 0, mc = 0, phx = 0, cnx = 0, cny = 0, cnz = 0;
+    if constexpr (IS_IF) {
+        // phi of x + c_q, the upstream node of direction opp(q)
+#pragma unroll
+        for (int q = 1; q < NQ; ++q) phn[q] = T(F.phi[up[opp(q)]]);
+        Kc = T(F.K[i]);
+        mc = T(F.m[i]);
+        phx = T(F.phi[i]);
+        cnx = T(F.nrm[i]);
+        cny = T(F.nrm[(size_t)N + i]);
+        cnz = T(F.nrm[2 * (size_t)N + i]);
+    }
+    bool has_gas = false;
+    int nwx = 0, nwy = 0, nwz = 0;  // sum of the directions towards obstacle neighbours
+#pragma unroll
+    for (int q = 1; q < NQ; ++q) {
+        has_gas |= nt[q] == FL_GAS;
+        if (nt[q] == FL_OBST) { nwx -= dir_x(q); nwy -= dir_y(q); nwz -= dir_z(q); }
+    }
+    // boundary values of eq. reconstruct
+    T rb0, ubx, uby, ubz;
+    moments(fo, rb0, ubx, uby, ubz);
+    const T ubsq = ubx * ubx + uby * uby + ubz * ubz;
+    const T rhob = T(3) * (T(prm.rho_gas) / T(3) + T(prm.sigma) * Kc);
+    // corner rule: the outgoing link c_o = -c_q takes the free-surface rule
+    // when c_o . (P n) < 0, P the projection onto the wall plane; evaluated
+    // as (P c_o) . n with P c_o |nw|^2 = c_o |nw|^2 - (c_o . nw) nw in exact
+    // integers, so the link normal to the wall tests exactly zero.
+    const bool corner = IS_IF && has_gas && (nwx | nwy | nwz) != 0;
+    const int ww = nwx * nwx + nwy * nwy + nwz * nwz;
+    T fin[NQ];
+    fin[0] = fo[0];
+#pragma unroll
+    for (int q = 1; q < NQ; ++q) {
+        const int o = opp(q);
+        const uint8_t t = nt[q];
+        const int cox = -dir_x(q), coy = -dir_y(q), coz = -dir_z(q);
+        const int cw = cox * nwx + coy * nwy + coz * nwz;
+        const T s = T(cox * ww - cw * nwx) * cnx + T(coy * ww - cw * nwy) * cny + T(coz * ww - cw * nwz) * cnz;
+        const bool rec = (t == FL_GAS) || (t == FL_OBST && corner && s < T(0));
+        const T vrec = feq<T>(q, rhob, ubx, uby, ubz, ubsq) + feq<T>(o, rhob, ubx, uby, ubz, ubsq) - fo[o];
+        fin[q] = (t & FL_FLUID) ? pl[q] : (rec ? vrec : fo[o]);
+    }
+    if constexpr (IS_IF) {
+        // mass exchange: the neighbour x + c_q is the upstream node of o = qbar
+        T dm = 0;
+#pragma unroll
+        for (int q = 1; q < NQ; ++q) {
+            const int o = opp(q);
+            const uint8_t tz = nt[o];
+            const T k = tz == FL_LIQ ? T(1) : (tz == FL_IF ? T(0.5) * (phn[q] + phx) : T(0));
+            dm += k * (fin[o] - fo[q]);
+        }
+        T r = 0;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) r += fin[q];
+        const T mn = mc + dm;
+        uint8_t st = CV_NONE;
+        if (mn > (T(1) + T(prm.eps_c)) * r) st = CV_FILL;
+        else if (mn < -T(prm.eps_c) * r) st = CV_EMPTY;
+        F.m[i] = R(mn);
+        F.rho[i] = R(r);
+        F.conv[i] = st;
+        if (st != CV_NONE) atomicAdd(&F.sc->nconv, 1);
+    }
+    collide<T, COLL>(fin, prm);
+    store_all<P>(F, i, fin);
+}
+
+// Bulk kernel over the fluid bounding box: every liquid cell, and with
+// WITH_IF also the interface cells (else they run in the list kernel). Each
+// block takes one contiguous run of the box, so the rows it pulls from
+// stay in one XCD's L2.
+template <class P, int COLL, bool WITH_IF>
+__global__ __launch_bounds__(256) void k_stream_collide(const Batch<P> B)
+{
+    const Params &prm = B.p[blockIdx.y];
+    if (prm.coll != COLL) return;
+    const Fields<P> &F = B.f[blockIdx.y];
+    const CellRange box = CellRange::from(F.sc->fbox);
+    int k0, k1;
+    block_share(box.size(), k0, k1);
+    for (int k = k0 + threadIdx.x; k < k1; k += 256) {
+        const int i = box.cell(k, F.nx, F.ny);
+        const uint8_t fl = F.flags[i];
+        if (fl == FL_LIQ) liquid_cell<P, COLL>(F, prm, i);
+        else if (fl & FL_LIQ) boundary_cell<P, COLL, false>(F, prm, i);
+        else if (WITH_IF && (fl & FL_IF)) boundary_cell<P, COLL, true>(F, prm, i);
+    }
+}
+
+// Interface cells, over the interface list (grid-stride).
+template <class P, int COLL>
+__global__ __launch_bounds__(256) void k_stream_collide_interface(const Batch<P> B)
+{
+    const Params &prm = B.p[blockIdx.y];
+    if (prm.coll != COLL) return;
+    const Fields<P> &F = B.f[blockIdx.y];
+    const int n = *(volatile const int *)&F.sc->icount;
+    for (int k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256)
+        boundary_cell<P, COLL, true>(F, prm, F.ilist[k]);
 }
 
 }  // namespace fslbm

@@ -23,7 +23,8 @@ FSLBM_F64, FSLBM_F32, FSLBM_F16_STORE, FSLBM_BF16_STORE = 0, 1, 2, 3
 FSLBM_CURV_FD, FSLBM_CURV_LSQR = 0, 1
 FSLBM_SRT, FSLBM_TRT = 0, 1
 FSLBM_GAS, FSLBM_LIQUID, FSLBM_INTERFACE, FSLBM_OBSTACLE = 0, 1, 2, 3
-FSLBM_OPT_EPS_C, FSLBM_OPT_COLLISION, FSLBM_OPT_TRT_MAGIC = 0, 1, 2
+FSLBM_OPT_EPS_C, FSLBM_OPT_COLLISION, FSLBM_OPT_TRT_MAGIC, FSLBM_OPT_TIMING, FSLBM_OPT_GRAPH = 0, 1, 2, 3, 4
+FSLBM_OPT_SPLIT_INTERFACE = 5
 
 PRECISIONS = {"f64": FSLBM_F64, "f32": FSLBM_F32, "f16": FSLBM_F16_STORE, "bf16": FSLBM_BF16_STORE}
 MODELS = {"fd": FSLBM_CURV_FD, "lsqr": FSLBM_CURV_LSQR}
@@ -69,6 +70,13 @@ def load_library(path: str = LIB_PATH):
         "fslbm_mass": [vp, dp],
         "fslbm_check_numeric": [vp],
         "fslbm_steps_taken": [vp, ctypes.POINTER(i64)],
+        "fslbm_read_timing": [vp, dp, ctypes.POINTER(i64)],
+        "fslbm_reset_timing": [vp],
+        "fslbm_batch_create": [ctypes.POINTER(vp), i32, ctypes.POINTER(vp)],
+        "fslbm_batch_step": [vp, i64],
+        "fslbm_batch_set_option": [vp, i32, ctypes.c_double],
+        "fslbm_batch_read_timing": [vp, dp, ctypes.POINTER(i64)],
+        "fslbm_batch_reset_timing": [vp],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -76,6 +84,8 @@ def load_library(path: str = LIB_PATH):
         fn.restype = ctypes.c_int
     L.fslbm_destroy.argtypes = [vp]
     L.fslbm_destroy.restype = None
+    L.fslbm_batch_destroy.argtypes = [vp]
+    L.fslbm_batch_destroy.restype = None
     L.fslbm_last_error.argtypes = []
     L.fslbm_last_error.restype = ctypes.c_char_p
     _lib = L
@@ -201,8 +211,51 @@ def fslbm_steps_taken(h):
     return out.value
 
 
+def fslbm_read_timing(h):
+    """(phase milliseconds [liquid stream-collide, interface stream-collide,
+    conversion, compaction, geometry], steps)."""
+    out = np.zeros(5)
+    steps = ctypes.c_int64(0)
+    _check(load_library().fslbm_read_timing(h, _dptr(out), ctypes.byref(steps)))
+    return out, steps.value
+
+
+def fslbm_reset_timing(h):
+    _check(load_library().fslbm_reset_timing(h))
+
+
 def fslbm_destroy(h):
     load_library().fslbm_destroy(h)
+
+
+def fslbm_batch_create(handles):
+    arr = (ctypes.c_void_p * len(handles))(*[h.value if isinstance(h, ctypes.c_void_p) else h for h in handles])
+    b = ctypes.c_void_p()
+    _check(load_library().fslbm_batch_create(arr, len(handles), ctypes.byref(b)))
+    return b
+
+
+def fslbm_batch_step(b, nsteps):
+    _check(load_library().fslbm_batch_step(b, int(nsteps)))
+
+
+def fslbm_batch_set_option(b, key, value):
+    _check(load_library().fslbm_batch_set_option(b, key, float(value)))
+
+
+def fslbm_batch_read_timing(b):
+    out = np.zeros(5)
+    steps = ctypes.c_int64(0)
+    _check(load_library().fslbm_batch_read_timing(b, _dptr(out), ctypes.byref(steps)))
+    return out, steps.value
+
+
+def fslbm_batch_reset_timing(b):
+    _check(load_library().fslbm_batch_reset_timing(b))
+
+
+def fslbm_batch_destroy(b):
+    load_library().fslbm_batch_destroy(b)
 
 
 # ---------------------------------------------------------------- wrapper
@@ -311,3 +364,56 @@ class Lattice:
 
     def steps_taken(self):
         return fslbm_steps_taken(self._h)
+
+    def set_timing(self, on=True):
+        fslbm_set_option(self._h, FSLBM_OPT_TIMING, 1 if on else 0)
+
+    def set_graph(self, on=True):
+        fslbm_set_option(self._h, FSLBM_OPT_GRAPH, 1 if on else 0)
+
+    def set_split_interface(self, on=True):
+        fslbm_set_option(self._h, FSLBM_OPT_SPLIT_INTERFACE, 1 if on else 0)
+
+    def timing(self):
+        return fslbm_read_timing(self._h)
+
+    def reset_timing(self):
+        fslbm_reset_timing(self._h)
+
+
+class Batch:
+    """Lattices on one stream advanced by one launch per kernel and step."""
+
+    def __init__(self, lattices):
+        self.lattices = list(lattices)
+        self._b = None
+        self._b = fslbm_batch_create([lat.handle for lat in self.lattices])
+
+    def step(self, nsteps=1):
+        fslbm_batch_step(self._b, nsteps)
+
+    def set_timing(self, on=True):
+        fslbm_batch_set_option(self._b, FSLBM_OPT_TIMING, 1 if on else 0)
+
+    def set_graph(self, on=True):
+        fslbm_batch_set_option(self._b, FSLBM_OPT_GRAPH, 1 if on else 0)
+
+    def set_split_interface(self, on=True):
+        fslbm_batch_set_option(self._b, FSLBM_OPT_SPLIT_INTERFACE, 1 if on else 0)
+
+    def timing(self):
+        return fslbm_batch_read_timing(self._b)
+
+    def reset_timing(self):
+        fslbm_batch_reset_timing(self._b)
+
+    def close(self):
+        if self._b is not None:
+            fslbm_batch_destroy(self._b)
+            self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
