@@ -116,6 +116,11 @@ def main():
                     help="also time a graph-replay pass after the timed region")
     ap.add_argument("--split", type=int, default=0,
                     help="1: interface cells in their own list kernel (same results)")
+    ap.add_argument("--compare", default="f16",
+                    help="comma list of storage precisions also timed on the same workload ('' for none)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain copy of 2^28 floats (for scaling rocprofv3 byte counters)")
+    ap.add_argument("--no-copy", action="store_true", help="skip the copy-bandwidth reference")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
@@ -128,6 +133,32 @@ def main():
     from paper_1509_07691_amd.fslbm import Batch, Lattice
 
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        # a plain elementwise copy: 1 GiB read and 1 GiB written per launch
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": 4 << 28, "bytes_written": 4 << 28, "launches": 5}))
+        return
+    # achievable HBM bandwidth on this device: a plain elementwise copy of
+    # 2 x 1 GiB (read + write), timed with events
+    copy_gbs = None
+    if not args.no_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(10):
+            torch.mul(src, 1.0, out=dst)
+        ev1.record()
+        torch.cuda.synchronize()
+        copy_gbs = 10 * 2 * (4 << 28) / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
+        del src, dst
+        torch.cuda.empty_cache()
+
     runs, desc = workload_runs(args.workload)
     stream = torch.cuda.Stream(dev)
     lats = []
@@ -184,6 +215,47 @@ def main():
         torch.cuda.synchronize()
         graph_ms = 1e3 * (time.perf_counter() - t0) / args.steps
         batch.set_graph(False)
+    nlat = len(lats)
+    batch.close()
+    for lat in lats:
+        lat.close()
+    del batch, lats
+    torch.cuda.synchronize()
+
+    compare = {}
+    for prec in [p for p in args.compare.split(",") if p and p != args.precision]:
+        clats = []
+        with torch.cuda.stream(stream):
+            for label, fill, obst, p in runs:
+                clats.append(Lattice(fill, obst, precision=prec, device=dev, stream=stream, **p))
+        cb = Batch(clats)
+        cb.step(args.warmup)
+        torch.cuda.synchronize()
+        cb.set_timing(True)
+        cb.reset_timing()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cb.step(args.steps)
+        torch.cuda.synchronize()
+        cel = time.perf_counter() - t0
+        cph, _ = cb.timing()
+        cb_liq = cb_if = 0
+        for lat in clats:
+            bl, bi, _, _ = sc_bytes(lat.flags(), prec)
+            cb_liq += bl
+            cb_if += bi
+        cbytes = cb_liq + cb_if
+        compare[prec] = {"mlups": round(ncell * args.steps / cel / 1e6, 1),
+                         "ms_per_step": round(1e3 * cel / args.steps, 4),
+                         "speedup_vs_" + args.precision: round(el / cel, 3),
+                         "stream_collide_us": round(1e3 * cph[0] / args.steps, 3),
+                         "stream_collide_GBs": round(cbytes * args.steps / (cph[0] * 1e-3) / 1e9, 1)}
+        cb.close()
+        for lat in clats:
+            lat.close()
+        del cb, clats
+        torch.cuda.synchronize()
+
     res = {
         "metric": METRIC,
         "value": round(mlups, 1),
@@ -197,11 +269,12 @@ def main():
         "vs_baseline": None,
         "dtype": args.precision,
         "data": "synthetic",
-        "config": {"workload": desc, "lattice": list(runs[0][1].shape[::-1]), "lattices": len(lats),
+        "config": {"workload": desc, "lattice": list(runs[0][1].shape[::-1]), "lattices": nlat,
                    "storage": args.precision, "batched_launches": True, "split_interface": bool(args.split),
                    "fluid_cells": nf_tot, "interface_cells": ni_tot},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "copy_kernel_GBs": round(copy_gbs, 1) if copy_gbs else None,
                      "traffic": (traffic or {}).get("bytes_per_launch") if traffic else None,
                      "kernel": "k_stream_collide" + (" (liquid cells)" if args.split else " (liquid and interface cells)")
                                + ", all lattices in one launch",
@@ -221,9 +294,8 @@ def main():
                                "mlups": round(ncell / graph_ms / 1e3, 1)}
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(runs, args.cpu_seconds)
-    batch.close()
-    for lat in lats:
-        lat.close()
+    if compare:
+        res["storage_comparison"] = compare
     print(json.dumps(res), flush=True)
 
 

@@ -74,10 +74,11 @@ enum fslbm_option {
     FSLBM_OPT_GRAPH = 4,      /* 1: replay each step as a captured HIP graph
                                  (ignored while timing is on or on the null
                                  stream), 0: plain launches (default) */
-    FSLBM_OPT_SPLIT_INTERFACE = 5  /* 1: interface cells stream and collide in
-                                 their own kernel over the interface list;
-                                 0 (default): inside the bulk kernel. Results
-                                 are identical either way. */
+    FSLBM_OPT_SPLIT_INTERFACE = 5  /* 1: two stream-collide passes, a lean one
+                                 for liquid cells away from walls and one for
+                                 interface and wall-adjacent cells; 0
+                                 (default): one pass for all fluid cells.
+                                 Results are identical either way. */
 };
 
 /* Device workspace needed for a lattice (bytes, written to *bytes).

@@ -7,6 +7,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <algorithm>
 #include <vector>
 
 #include "fslbm.h"
@@ -53,7 +54,8 @@ size_t fbytes(int prec)
 size_t rbytes(int prec) { return prec == P_F64 ? 8 : 4; }
 
 struct Layout {
-    size_t fA, fB, flags, conv, mark, m, rho, phi, K, nrm, plic, share, phis, nmol, ilist, olist, staging,
+    size_t fA, fB, flags, conv, mark, m, rho, phi, K, nrm, plic, share, phis, nmol, ilist, olist, newlist, ilist_tmp,
+        staging,
         counts, part, sc, total;
 };
 
@@ -85,6 +87,8 @@ Layout make_layout(long long N, int prec)
     L.nmol = take(3 * N * rb);
     L.ilist = take(4 * N);
     L.olist = take(4 * N);
+    L.newlist = take(4 * N);
+    L.ilist_tmp = take(4 * N);
     L.staging = take(8 * N);
     L.counts = take(4 * (size_t)CMP_GRID);  // one count per compaction block (fixed grid)
     L.part = take(8 * MASS_BLOCKS);
@@ -187,6 +191,8 @@ Fields<P> make_fields(const fslbm_lattice *h)
     F.nmol = (R *)(w + L.nmol);
     F.ilist = (int32_t *)(w + L.ilist);
     F.olist = (int32_t *)(w + L.olist);
+    F.newlist = (int32_t *)(w + L.newlist);
+    F.ilist_tmp = (int32_t *)(w + L.ilist_tmp);
     F.counts = (int *)(w + L.counts);
     F.sc = (DevScalars *)(w + L.sc);
     F.nx = h->nx;
@@ -213,6 +219,8 @@ __global__ void k_init_scalars(DevScalars *sc)
     sc->icount = 0;
     sc->ocount = 0;
     sc->nconv = 0;
+    sc->nnew = 0;
+    sc->nkeep = 0;
     sc->step = 1;
     sc->reservoir = 0.0;
     sc->mass = 0.0;
@@ -560,14 +568,14 @@ int enqueue_step_kernels(fslbm_batch *b)
     const dim3 cg(std::min(SC_GRID, cell_blocks(maxN)), n), lg(list_blocks(maxN), n);
     mark(b, 0);
     if (b->split_interface) {
-        if (any_srt) k_stream_collide<P, 0, false><<<cg, 256, 0, st>>>(A);
-        if (any_trt) k_stream_collide<P, 1, false><<<cg, 256, 0, st>>>(A);
+        if (any_srt) k_stream_collide<P, 0, 1><<<cg, 256, 0, st>>>(A);
+        if (any_trt) k_stream_collide<P, 1, 1><<<cg, 256, 0, st>>>(A);
         mark(b, 1);
-        if (any_srt) k_stream_collide_interface<P, 0><<<lg, 256, 0, st>>>(A);
-        if (any_trt) k_stream_collide_interface<P, 1><<<lg, 256, 0, st>>>(A);
+        if (any_srt) k_stream_collide<P, 0, 2><<<cg, 256, 0, st>>>(A);
+        if (any_trt) k_stream_collide<P, 1, 2><<<cg, 256, 0, st>>>(A);
     } else {
-        if (any_srt) k_stream_collide<P, 0, true><<<cg, 256, 0, st>>>(A);
-        if (any_trt) k_stream_collide<P, 1, true><<<cg, 256, 0, st>>>(A);
+        if (any_srt) k_stream_collide<P, 0, 0><<<cg, 256, 0, st>>>(A);
+        if (any_trt) k_stream_collide<P, 1, 0><<<cg, 256, 0, st>>>(A);
         mark(b, 1);
     }
     mark(b, 2);
@@ -578,8 +586,11 @@ int enqueue_step_kernels(fslbm_batch *b)
     k_conv_flags<P><<<lg, 256, 0, st>>>(A);
     mark(b, 3);
     HIP_OK(hipGetLastError());
-    int rc = enqueue_compaction<P>(b, A, maxN, 0, 0);
-    if (rc) return rc;
+    k_list_begin<P><<<dim3(1, n), 64, 0, st>>>(A);
+    k_list_keep<P><<<lg, 256, 0, st>>>(A);
+    k_list_finish<P><<<lg, 256, 0, st>>>(A);
+    HIP_OK(hipGetLastError());
+    int rc = 0;
     mark(b, 4);
     k_obstacle_fill<P><<<lg, 256, 0, st>>>(A, 1);
     rc = enqueue_geometry<P>(b, A, maxN);
@@ -1072,6 +1083,7 @@ int fslbm_read_interface_list(fslbm_t h, int32_t *out, int64_t capacity, int64_t
     if (n > 0) {
         HIP_OK(hipMemcpyAsync(out, h->ws + h->L.ilist, sizeof(int32_t) * n, hipMemcpyDeviceToHost, h->stream));
         HIP_OK(hipStreamSynchronize(h->stream));
+        std::sort(out, out + n);  // the device list is kept unordered between compactions
     }
     return 0;
 }

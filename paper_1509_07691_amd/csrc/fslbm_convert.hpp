@@ -80,7 +80,8 @@ __global__ __launch_bounds__(256) void k_conv_mark_init(const Batch<P> B)
             const int j = nb.at(dir_x(q), dir_y(q), dir_z(q));
             const uint8_t tj = F.flags[j] & FL_TYPE;
             if (st == CV_FILL && tj == FL_GAS) {
-                F.mark[j] = tag | 1u;
+                // the first thread to tag j lists it as a new interface cell
+                if ((atomicExch(&F.mark[j], tag | 1u) & ~3u) != tag) F.newlist[atomicAdd(&F.sc->nnew, 1)] = j;
                 {  // the fluid region grows by this cell
                     const int yz = j / F.nx, x = j - yz * F.nx, z = yz / F.ny, y = yz - z * F.ny;
                     atomicMin(&F.sc->fbox[0], x); atomicMin(&F.sc->fbox[1], y); atomicMin(&F.sc->fbox[2], z);
@@ -127,7 +128,7 @@ __global__ __launch_bounds__(256) void k_conv_mark_init(const Batch<P> B)
                 F.rho[j] = R(rm);
                 F.m[j] = R(0);
             } else if (st == CV_EMPTY && tj == FL_LIQ) {
-                F.mark[j] = tag | 2u;
+                if ((atomicExch(&F.mark[j], tag | 2u) & ~3u) != tag) F.newlist[atomicAdd(&F.sc->nnew, 1)] = j;
                 T fw[NQ];
 #pragma unroll
                 for (int s = 0; s < NQ; ++s) {
@@ -253,6 +254,93 @@ __global__ __launch_bounds__(256) void k_conv_flags(const Batch<P> B)
             if ((F.mark[j] & ~3u) == tag) F.flags[j] = (F.flags[j] & FL_NEAR_OBST) | FL_IF;
         }
     }
+}
+
+// ------------------------------------------------ interface-list update
+// After a step with conversions the list becomes (cells that stay) + (new
+// cells). The order of the list does not enter any result (every per-cell
+// computation is independent), so kept cells are appended with an atomic
+// counter; the interface bounding box is recomputed on the way.
+template <class P>
+__global__ void k_list_begin(const Batch<P> B)
+{
+    const Fields<P> &F = B.f[blockIdx.y];
+    if (F.sc->nconv == 0 || threadIdx.x != 0) return;
+    F.sc->nkeep = 0;
+    F.sc->bbox[0] = F.nx; F.sc->bbox[1] = F.ny; F.sc->bbox[2] = F.nz;
+    F.sc->bbox[3] = -1; F.sc->bbox[4] = -1; F.sc->bbox[5] = -1;
+}
+
+// Wavefront-aggregated bounding-box update: lanes with valid = true
+// contribute their cell; one lane per wavefront issues the atomics.
+template <class P>
+__device__ inline void bbox_include_wave(const Fields<P> &F, int i, bool valid)
+{
+    int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {-1, -1, -1};
+    if (valid) {
+        const int yz = i / F.nx, z = yz / F.ny;
+        lo[0] = hi[0] = i - yz * F.nx;
+        lo[1] = hi[1] = yz - z * F.ny;
+        lo[2] = hi[2] = z;
+    }
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            lo[c] = min(lo[c], __shfl_xor(lo[c], d, 64));
+            hi[c] = max(hi[c], __shfl_xor(hi[c], d, 64));
+        }
+    if ((threadIdx.x & 63) == 0 && hi[0] >= 0)
+        for (int c = 0; c < 3; ++c) {
+            atomicMin(&F.sc->bbox[c], lo[c]);
+            atomicMax(&F.sc->bbox[3 + c], hi[c]);
+        }
+}
+
+// Append the lanes with `take` to list (one atomic per wavefront).
+__device__ inline void wave_append(int32_t *list, int *counter, int value, bool take)
+{
+    const unsigned long long m = __ballot(take);
+    if (!m) return;
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((long long)m) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(counter, __popcll(m));
+    base = __shfl(base, leader, 64);
+    if (take) list[base + __popcll(m & ((1ull << lane) - 1ull))] = value;
+}
+
+template <class P>
+__global__ __launch_bounds__(256) void k_list_keep(const Batch<P> B)
+{
+    const Fields<P> &F = B.f[blockIdx.y];
+    if (F.sc->nconv == 0) return;
+    const int n = list_count(F.sc);
+    // whole wavefronts iterate together (ballots need every lane)
+    const int n_round = (n + 255) / 256 * 256;
+    for (int k = blockIdx.x * 256 + threadIdx.x; k < n_round; k += gridDim.x * 256) {
+        const int i = k < n ? F.ilist[k] : 0;
+        const bool keep = k < n && (F.flags[i] & FL_IF);  // converters left the interface
+        wave_append(F.ilist_tmp, &F.sc->nkeep, i, keep);
+        bbox_include_wave(F, i, keep);
+    }
+}
+
+template <class P>
+__global__ __launch_bounds__(256) void k_list_finish(const Batch<P> B)
+{
+    const Fields<P> &F = B.f[blockIdx.y];
+    if (F.sc->nconv == 0) return;
+    const int nk = F.sc->nkeep, nn = F.sc->nnew;
+    const int n_round = (nk + nn + 255) / 256 * 256;
+    for (int k = blockIdx.x * 256 + threadIdx.x; k < n_round; k += gridDim.x * 256) {
+        const bool live = k < nk + nn;
+        const bool fresh = live && k >= nk;
+        const int i = !live ? 0 : (k < nk ? F.ilist_tmp[k] : F.newlist[k - nk]);
+        if (live) F.ilist[k] = i;
+        bbox_include_wave(F, i, fresh);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) F.sc->icount = nk + nn;
 }
 
 // ----------------------------------------------------------- compaction
@@ -442,6 +530,7 @@ __global__ __launch_bounds__(256) void k_obstacle_fill(const Batch<P> B, int end
     using R = typename P::R;
     if (end_of_step && blockIdx.x == 0 && threadIdx.x == 0) {
         F.sc->nconv = 0;
+        F.sc->nnew = 0;
         F.sc->step += 1;
     }
     const int n = F.sc->ocount;

@@ -106,7 +106,7 @@ __device__ inline void store_f(typename P::S *__restrict__ plane, int i, typenam
     if constexpr (P::SHIFT) {
         plane[i] = from_float<S>((v - weight<typename P::T>(Q)) * typename P::T(P::SCALE));
     } else {
-        plane[i] = v;
+        __builtin_nontemporal_store(v, plane + i);
     }
 }
 
@@ -115,6 +115,8 @@ struct DevScalars {
     int icount;         // number of interface cells in ilist
     int ocount;         // number of obstacle cells in olist (static)
     int nconv;          // interface cells that fill or empty in this step
+    int nnew;           // new interface cells of this step (in newlist)
+    int nkeep;          // interface cells that stay (rebuilding the list)
     unsigned step;      // completed steps + 1 (conversion tag, never 0)
     double reservoir;   // excess mass that found no receiving cell
     double mass;        // result of the last mass reduction
@@ -176,6 +178,7 @@ template <class P> struct Fields {
     uint32_t *mark;
     R *m, *rho, *phi, *K, *nrm, *plic, *share, *phis, *nmol;
     int32_t *ilist, *olist;
+    int32_t *newlist, *ilist_tmp;  // new interface cells; scratch for the list rebuild
     int *counts;       // per-block counts of the list compaction
     DevScalars *sc;
     int nx, ny, nz;
@@ -199,9 +202,15 @@ struct Nbr {
     __device__ inline Nbr(int i, int nx, int ny, int nz)
     {
         const int yz = i / nx;
-        x = i - yz * nx;
-        z = yz / ny;
-        y = yz - z * ny;
+        const int zz = yz / ny;
+        set(i - yz * nx, yz - zz * ny, zz, nx, ny, nz);
+    }
+    __device__ inline Nbr(int x_, int y_, int z_, int nx, int ny, int nz) { set(x_, y_, z_, nx, ny, nz); }
+    __device__ inline void set(int x_, int y_, int z_, int nx, int ny, int nz)
+    {
+        x = x_;
+        y = y_;
+        z = z_;
         const int nxy = nx * ny;
         ox[0] = x == 0 ? nx - 1 : x - 1; ox[1] = x; ox[2] = x == nx - 1 ? 0 : x + 1;
         oy[0] = (y == 0 ? ny - 1 : y - 1) * nx; oy[1] = y * nx;

@@ -116,10 +116,9 @@ __device__ inline void load_dirs(const Fields<P> &F, const int (&j)[NQ], typenam
 // Liquid cell away from walls: every D3Q19 neighbour is fluid (a liquid cell
 // never touches gas), so the pull needs no neighbour types.
 template <class P, int COLL>
-__device__ inline void liquid_cell(const Fields<P> &F, const Params &prm, int i)
+__device__ inline void liquid_cell(const Fields<P> &F, const Params &prm, int i, const Nbr &nb)
 {
     using T = typename P::T;
-    const Nbr nb(i, F.nx, F.ny, F.nz);
     int up[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) up[q] = nb.at(-dir_x(q), -dir_y(q), -dir_z(q));
@@ -135,12 +134,11 @@ __device__ inline void liquid_cell(const Fields<P> &F, const Params &prm, int i)
 // whatever the neighbour type; only fluid ones are used) and, at interface
 // cells, the neighbours' fill levels.
 template <class P, int COLL, bool IS_IF>
-__device__ inline void boundary_cell(const Fields<P> &F, const Params &prm, int i)
+__device__ inline void boundary_cell(const Fields<P> &F, const Params &prm, int i, const Nbr &nb)
 {
     using T = typename P::T;
     using R = typename P::R;
     const int N = F.N;
-    const Nbr nb(i, F.nx, F.ny, F.nz);
     int up[NQ], own[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
@@ -223,11 +221,12 @@ __device__ inline void boundary_cell(const Fields<P> &F, const Params &prm, int 
     store_all<P>(F, i, fin);
 }
 
-// Bulk kernel over the fluid bounding box: every liquid cell, and with
-// WITH_IF also the interface cells (else they run in the list kernel). Each
-// block takes one contiguous run of the box, so the rows it pulls from
-// stay in one XCD's L2.
-template <class P, int COLL, bool WITH_IF>
+// Stream-collide over the fluid bounding box. MODE 0: every fluid cell;
+// MODE 1: only liquid cells away from walls (the lean pull, few registers);
+// MODE 2: only the other fluid cells (interface cells and liquid cells with
+// wall links). Each block takes one contiguous run of the box, so the rows
+// it pulls from stay in one XCD's L2.
+template <class P, int COLL, int MODE>
 __global__ __launch_bounds__(256) void k_stream_collide(const Batch<P> B)
 {
     const Params &prm = B.p[blockIdx.y];
@@ -236,25 +235,30 @@ __global__ __launch_bounds__(256) void k_stream_collide(const Batch<P> B)
     const CellRange box = CellRange::from(F.sc->fbox);
     int k0, k1;
     block_share(box.size(), k0, k1);
-    for (int k = k0 + threadIdx.x; k < k1; k += 256) {
-        const int i = box.cell(k, F.nx, F.ny);
+    int k = k0 + threadIdx.x;
+    if (k >= k1) return;
+    // box coordinates of k, then advanced by 256 cells per iteration
+    int bx = k % box.ex, r = k / box.ex, by = r % box.ey, bz = r / box.ey;
+    const int nxy = F.nx * F.ny;
+    for (; k < k1; k += 256) {
+        const int x = box.x0 + bx, y = box.y0 + by, z = box.z0 + bz;
+        const int i = x + F.nx * y + nxy * z;
         const uint8_t fl = F.flags[i];
-        if (fl == FL_LIQ) liquid_cell<P, COLL>(F, prm, i);
-        else if (fl & FL_LIQ) boundary_cell<P, COLL, false>(F, prm, i);
-        else if (WITH_IF && (fl & FL_IF)) boundary_cell<P, COLL, true>(F, prm, i);
+        if (fl & FL_FLUID) {
+            const Nbr nb(x, y, z, F.nx, F.ny, F.nz);
+            if (MODE != 2 && fl == FL_LIQ) liquid_cell<P, COLL>(F, prm, i, nb);
+            else if (MODE != 1 && (fl & FL_LIQ) && fl != FL_LIQ) boundary_cell<P, COLL, false>(F, prm, i, nb);
+            else if (MODE != 1 && (fl & FL_IF)) boundary_cell<P, COLL, true>(F, prm, i, nb);
+        }
+        bx += 256;
+        while (bx >= box.ex) {
+            bx -= box.ex;
+            if (++by == box.ey) {
+                by = 0;
+                ++bz;
+            }
+        }
     }
-}
-
-// Interface cells, over the interface list (grid-stride).
-template <class P, int COLL>
-__global__ __launch_bounds__(256) void k_stream_collide_interface(const Batch<P> B)
-{
-    const Params &prm = B.p[blockIdx.y];
-    if (prm.coll != COLL) return;
-    const Fields<P> &F = B.f[blockIdx.y];
-    const int n = *(volatile const int *)&F.sc->icount;
-    for (int k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256)
-        boundary_cell<P, COLL, true>(F, prm, F.ilist[k]);
 }
 
 }  // namespace fslbm
