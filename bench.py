@@ -29,7 +29,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "D3Q19 FSLBM MLUPS + %HBM roofline (FP32 vs FP16 store); adjoint/forward cost"
 HBM_PEAK_GBS = 8000.0
-STREAM_SRC = os.path.join(ROOT, "paper_1509_07691_amd", "csrc", "fslbm_stream.hpp")
+STREAM_SRCS = [os.path.join(ROOT, "paper_1509_07691_amd", "csrc", f) for f in ("fslbm_stream.hpp", "fslbm_device.hpp")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stream_collide_traffic.json")
 FBYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
 RBYTES = {"f64": 8, "f32": 4, "f16": 4, "bf16": 4}
@@ -80,8 +80,37 @@ def stored_traffic():
         rec = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
-    h = hashlib.sha256(open(STREAM_SRC, "rb").read()).hexdigest()
-    return rec if rec.get("source_sha256") == h else None
+    return rec if rec.get("source_sha256") == stream_source_hash() else None
+
+
+def stream_source_hash():
+    h = hashlib.sha256()
+    for f in STREAM_SRCS:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
+
+
+def traffic_from_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, workload_note):
+    """HBM bytes per stream-collide launch from rocprofv3 FETCH_SIZE and
+    WRITE_SIZE (KiB per dispatch), each scaled by what the same counter reads
+    for a plain copy of 2^28 floats (1 GiB read, 1 GiB written)."""
+    import csv
+
+    def mean_kib(path, kernel_part):
+        vals = [float(r["Counter_Value"]) for r in csv.DictReader(open(path)) if kernel_part in r["Kernel_Name"]]
+        return sum(vals) / len(vals), len(vals)
+
+    f_kib, nf = mean_kib(fetch_csv, "k_stream_collide")
+    w_kib, nw = mean_kib(write_csv, "k_stream_collide")
+    cf_kib, _ = mean_kib(copy_fetch_csv, "AUnaryFunctor")
+    cw_kib, _ = mean_kib(copy_write_csv, "AUnaryFunctor")
+    gib_kib = (4 << 28) / 1024.0
+    f_scale, w_scale = gib_kib / cf_kib, gib_kib / cw_kib
+    rec = {"source_sha256": stream_source_hash(), "workload": workload_note,
+           "fetch_kib_per_launch": f_kib, "write_kib_per_launch": w_kib, "dispatches": [nf, nw],
+           "copy_fetch_kib": cf_kib, "copy_write_kib": cw_kib, "fetch_scale": f_scale, "write_scale": w_scale,
+           "bytes_per_launch": int(1024 * (f_kib * f_scale + w_kib * w_scale))}
+    return rec
 
 
 def cpu_baseline(runs, budget_s):
@@ -121,9 +150,17 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain copy of 2^28 floats (for scaling rocprofv3 byte counters)")
     ap.add_argument("--no-copy", action="store_true", help="skip the copy-bandwidth reference")
+    ap.add_argument("--traffic-from", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
+                    help="write profiles/stream_collide_traffic.json from rocprofv3 --pmc counter CSVs and exit")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
+    if args.traffic_from:
+        rec = traffic_from_counters(*args.traffic_from, workload_note=args.workload)
+        with open(TRAFFIC_FILE, "w") as fh:
+            json.dump(rec, fh, indent=1)
+        print(json.dumps(rec))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
               "(use --gpus 1).", file=sys.stderr)

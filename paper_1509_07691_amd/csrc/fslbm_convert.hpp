@@ -71,22 +71,19 @@ __global__ __launch_bounds__(256) void k_conv_mark_init(const Batch<P> B)
     const uint32_t tag = F.sc->step << 2;
     const int n = list_count(F.sc);
     const int N = F.N;
-    for (int k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256) {
-        const int i = F.ilist[k];
-        const uint8_t st = F.conv[i];
-        if (st == CV_NONE) continue;
+    const int n_round = (n + 255) / 256 * 256;  // whole wavefronts iterate together
+    for (int k = blockIdx.x * 256 + threadIdx.x; k < n_round; k += gridDim.x * 256) {
+        int fresh[NQ];
+        int nfresh = 0;
+        const int i = k < n ? F.ilist[k] : 0;
+        const uint8_t st = k < n ? F.conv[i] : CV_NONE;
         const Nbr nb(i, F.nx, F.ny, F.nz);
-        for (int q = 1; q < NQ; ++q) {
+        for (int q = 1; q < NQ && st != CV_NONE; ++q) {
             const int j = nb.at(dir_x(q), dir_y(q), dir_z(q));
             const uint8_t tj = F.flags[j] & FL_TYPE;
             if (st == CV_FILL && tj == FL_GAS) {
                 // the first thread to tag j lists it as a new interface cell
-                if ((atomicExch(&F.mark[j], tag | 1u) & ~3u) != tag) F.newlist[atomicAdd(&F.sc->nnew, 1)] = j;
-                {  // the fluid region grows by this cell
-                    const int yz = j / F.nx, x = j - yz * F.nx, z = yz / F.ny, y = yz - z * F.ny;
-                    atomicMin(&F.sc->fbox[0], x); atomicMin(&F.sc->fbox[1], y); atomicMin(&F.sc->fbox[2], z);
-                    atomicMax(&F.sc->fbox[3], x); atomicMax(&F.sc->fbox[4], y); atomicMax(&F.sc->fbox[5], z);
-                }
+                if ((atomicExch(&F.mark[j], tag | 1u) & ~3u) != tag) fresh[nfresh++] = j;
                 // mean rho and u over the liquid / interface neighbours of j
                 const Nbr nj(j, F.nx, F.ny, F.nz);
                 T rs = 0, usx = 0, usy = 0, usz = 0;
@@ -128,7 +125,7 @@ __global__ __launch_bounds__(256) void k_conv_mark_init(const Batch<P> B)
                 F.rho[j] = R(rm);
                 F.m[j] = R(0);
             } else if (st == CV_EMPTY && tj == FL_LIQ) {
-                if ((atomicExch(&F.mark[j], tag | 2u) & ~3u) != tag) F.newlist[atomicAdd(&F.sc->nnew, 1)] = j;
+                if ((atomicExch(&F.mark[j], tag | 2u) & ~3u) != tag) fresh[nfresh++] = j;
                 T fw[NQ];
 #pragma unroll
                 for (int s = 0; s < NQ; ++s) {
@@ -148,6 +145,19 @@ __global__ __launch_bounds__(256) void k_conv_mark_init(const Batch<P> B)
                 F.m[j] = R(r);
             }
         }
+        // one atomic per wavefront for the new cells found by its lanes
+        const int lane = threadIdx.x & 63;
+        int incl = nfresh;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int y = __shfl_up(incl, d, 64);
+            if (lane >= d) incl += y;
+        }
+        const int total = __shfl(incl, 63, 64);
+        int base = 0;
+        if (lane == 63 && total > 0) base = atomicAdd(&F.sc->nnew, total);
+        base = __shfl(base, 63, 64) + incl - nfresh;
+        for (int s = 0; s < nfresh; ++s) F.newlist[base + s] = fresh[s];
     }
 }
 
@@ -271,84 +281,6 @@ __global__ void k_list_begin(const Batch<P> B)
     F.sc->bbox[3] = -1; F.sc->bbox[4] = -1; F.sc->bbox[5] = -1;
 }
 
-// Wavefront-aggregated bounding-box update: lanes with valid = true
-// contribute their cell; one lane per wavefront issues the atomics.
-template <class P>
-__device__ inline void bbox_include_wave(const Fields<P> &F, int i, bool valid)
-{
-    int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {-1, -1, -1};
-    if (valid) {
-        const int yz = i / F.nx, z = yz / F.ny;
-        lo[0] = hi[0] = i - yz * F.nx;
-        lo[1] = hi[1] = yz - z * F.ny;
-        lo[2] = hi[2] = z;
-    }
-#pragma unroll
-    for (int d = 32; d > 0; d >>= 1)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            lo[c] = min(lo[c], __shfl_xor(lo[c], d, 64));
-            hi[c] = max(hi[c], __shfl_xor(hi[c], d, 64));
-        }
-    if ((threadIdx.x & 63) == 0 && hi[0] >= 0)
-        for (int c = 0; c < 3; ++c) {
-            atomicMin(&F.sc->bbox[c], lo[c]);
-            atomicMax(&F.sc->bbox[3 + c], hi[c]);
-        }
-}
-
-// Append the lanes with `take` to list (one atomic per wavefront).
-__device__ inline void wave_append(int32_t *list, int *counter, int value, bool take)
-{
-    const unsigned long long m = __ballot(take);
-    if (!m) return;
-    const int lane = threadIdx.x & 63;
-    const int leader = __ffsll((long long)m) - 1;
-    int base = 0;
-    if (lane == leader) base = atomicAdd(counter, __popcll(m));
-    base = __shfl(base, leader, 64);
-    if (take) list[base + __popcll(m & ((1ull << lane) - 1ull))] = value;
-}
-
-template <class P>
-__global__ __launch_bounds__(256) void k_list_keep(const Batch<P> B)
-{
-    const Fields<P> &F = B.f[blockIdx.y];
-    if (F.sc->nconv == 0) return;
-    const int n = list_count(F.sc);
-    // whole wavefronts iterate together (ballots need every lane)
-    const int n_round = (n + 255) / 256 * 256;
-    for (int k = blockIdx.x * 256 + threadIdx.x; k < n_round; k += gridDim.x * 256) {
-        const int i = k < n ? F.ilist[k] : 0;
-        const bool keep = k < n && (F.flags[i] & FL_IF);  // converters left the interface
-        wave_append(F.ilist_tmp, &F.sc->nkeep, i, keep);
-        bbox_include_wave(F, i, keep);
-    }
-}
-
-template <class P>
-__global__ __launch_bounds__(256) void k_list_finish(const Batch<P> B)
-{
-    const Fields<P> &F = B.f[blockIdx.y];
-    if (F.sc->nconv == 0) return;
-    const int nk = F.sc->nkeep, nn = F.sc->nnew;
-    const int n_round = (nk + nn + 255) / 256 * 256;
-    for (int k = blockIdx.x * 256 + threadIdx.x; k < n_round; k += gridDim.x * 256) {
-        const bool live = k < nk + nn;
-        const bool fresh = live && k >= nk;
-        const int i = !live ? 0 : (k < nk ? F.ilist_tmp[k] : F.newlist[k - nk]);
-        if (live) F.ilist[k] = i;
-        bbox_include_wave(F, i, fresh);
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) F.sc->icount = nk + nn;
-}
-
-// ----------------------------------------------------------- compaction
-// Ascending list of the cells whose flags match `want`: each block covers
-// 1024 consecutive cells (4 per thread); per-block counts, one scan block,
-// then the write pass with a wavefront-ballot / shuffle prefix sum.
-constexpr int CMP_CELLS = 1024;
-
 __device__ inline int block_exclusive_scan(int v, int *lds_wave, int &total)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -370,6 +302,113 @@ __device__ inline int block_exclusive_scan(int v, int *lds_wave, int &total)
     __syncthreads();
     return off + x - v;
 }
+
+// Block-wide min / max of a box contribution; thread 0 issues the atomics.
+__device__ inline void block_box_update(int (&lo)[3], int (&hi)[3], int *box)
+{
+    __shared__ int red[6][4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            lo[c] = min(lo[c], __shfl_xor(lo[c], d, 64));
+            hi[c] = max(hi[c], __shfl_xor(hi[c], d, 64));
+        }
+    if (lane == 0)
+        for (int c = 0; c < 3; ++c) {
+            red[c][wave] = lo[c];
+            red[3 + c][wave] = hi[c];
+        }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 4; ++w)
+            for (int c = 0; c < 3; ++c) {
+                red[c][0] = min(red[c][0], red[c][w]);
+                red[3 + c][0] = max(red[3 + c][0], red[3 + c][w]);
+            }
+        if (red[3][0] >= 0)
+            for (int c = 0; c < 3; ++c) {
+                atomicMin(&box[c], red[c][0]);
+                atomicMax(&box[3 + c], red[3 + c][0]);
+            }
+    }
+    __syncthreads();
+}
+
+template <class P>
+__device__ inline void box_add(const Fields<P> &F, int i, int (&lo)[3], int (&hi)[3])
+{
+    const int yz = i / F.nx, z = yz / F.ny, y = yz - z * F.ny, x = i - yz * F.nx;
+    lo[0] = min(lo[0], x); lo[1] = min(lo[1], y); lo[2] = min(lo[2], z);
+    hi[0] = max(hi[0], x); hi[1] = max(hi[1], y); hi[2] = max(hi[2], z);
+}
+
+// Cells of the old list that are still interface cells, written in list
+// order within each block: a counting pass, one atomic for the block's
+// base, then the ordered write with a block prefix sum.
+template <class P>
+__global__ __launch_bounds__(256) void k_list_keep(const Batch<P> B)
+{
+    const Fields<P> &F = B.f[blockIdx.y];
+    if (F.sc->nconv == 0) return;
+    const int n = list_count(F.sc);
+    int k0, k1;
+    block_share(n, k0, k1);
+    __shared__ int lw[4];
+    __shared__ int base_s;
+    int cnt = 0;
+    for (int k = k0 + threadIdx.x; k < k1; k += 256) cnt += (F.flags[F.ilist[k]] & FL_IF) != 0;
+    int total;
+    block_exclusive_scan(cnt, lw, total);
+    if (threadIdx.x == 0) base_s = total > 0 ? atomicAdd(&F.sc->nkeep, total) : 0;
+    __syncthreads();
+    int pos = base_s;
+    int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {-1, -1, -1};
+    for (int kk = k0; kk < k1; kk += 256) {
+        const int k = kk + threadIdx.x;
+        const int i = k < k1 ? F.ilist[k] : 0;
+        const bool keep = k < k1 && (F.flags[i] & FL_IF);
+        int tot;
+        const int ex = block_exclusive_scan(keep ? 1 : 0, lw, tot);
+        if (keep) {
+            F.ilist_tmp[pos + ex] = i;
+            box_add(F, i, lo, hi);
+        }
+        pos += tot;
+    }
+    block_box_update(lo, hi, F.sc->bbox);
+}
+
+// New list = kept cells + new cells; the new cells extend both boxes.
+template <class P>
+__global__ __launch_bounds__(256) void k_list_finish(const Batch<P> B)
+{
+    const Fields<P> &F = B.f[blockIdx.y];
+    if (F.sc->nconv == 0) return;
+    const int nk = F.sc->nkeep, nn = F.sc->nnew;
+    int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {-1, -1, -1};
+    for (int k = blockIdx.x * 256 + threadIdx.x; k < nk + nn; k += gridDim.x * 256) {
+        if (k < nk) {
+            F.ilist[k] = F.ilist_tmp[k];
+        } else {
+            const int i = F.newlist[k - nk];
+            F.ilist[k] = i;
+            box_add(F, i, lo, hi);
+        }
+    }
+    int lo2[3] = {lo[0], lo[1], lo[2]}, hi2[3] = {hi[0], hi[1], hi[2]};
+    block_box_update(lo, hi, F.sc->bbox);
+    block_box_update(lo2, hi2, F.sc->fbox);  // the fluid region grows by the new cells
+    if (blockIdx.x == 0 && threadIdx.x == 0) F.sc->icount = nk + nn;
+}
+
+// ----------------------------------------------------------- compaction
+// Ascending list of the cells whose flags match `want`: each block covers
+// 1024 consecutive cells (4 per thread); per-block counts, one scan block,
+// then the write pass with a wavefront-ballot / shuffle prefix sum.
+constexpr int CMP_CELLS = 1024;
+
 
 // Cells k = base .. base+3 of a range (x fastest): hit[s] and their indices.
 __device__ inline int cells_matching(const uint8_t *flags, const CellRange &r, int nx, int ny, int base,
