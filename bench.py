@@ -134,6 +134,63 @@ def cpu_baseline(runs, budget_s):
                       f"{el:.1f} s, FP64, single-threaded plain C"}
 
 
+def adjoint_cost(dev, stream, steps, K, precision):
+    """Cost of the differentiation window (frozen cell types, checkpoints
+    every K steps, hand-written adjoint) on a sessile drop: hemisphere R=24
+    on the wall k=0 of a 128^3 lattice (walls k=0 and k=127, periodic x, y),
+    LSQR curvature with the wetting condition, sigma 1e-3, tau 0.8, theta
+    90 deg. Loss: squared distance of phi_T to the window's result at theta
+    70 deg, sigma 8e-4. Times T plain steps, the checkpointed window and the
+    reverse sweep (recompute + adjoint) on the same stream."""
+    import torch
+    from paper_1509_07691_amd import inputs as I
+    from paper_1509_07691_amd.fslbm import Lattice
+
+    fill, obst = I.sessile_droplet(128, 128, 128, 24.0, noise=1e-6, seed=1)
+    prm = dict(curv_model="lsqr", sigma=1e-3, tau=0.8, theta=math.pi / 2)
+    with torch.cuda.stream(stream):
+        lat = Lattice(fill, obst, precision=precision, device=dev, stream=stream, **prm)
+    start = lat.save_state()
+    keep = torch.tensor((obst == 0).astype(np.float64), device=dev)
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, out
+
+    lat.step(20)  # warm-up of the plain step
+    lat.load_state(start)
+    t_plain, _ = timed(lambda: lat.step(steps))
+    lat.load_state(start)
+    lat.set_params(sigma=8e-4, theta=math.radians(70.0))
+    lat.adjoint_forward(steps, K)
+    target = lat.fill_tensor()
+    lat.load_state(start)
+    lat.set_params(sigma=1e-3, theta=math.pi / 2)
+    t_fwd, _ = timed(lambda: lat.adjoint_forward(steps, K))
+    phi = lat.fill_tensor()
+    dphi = 2.0 * (phi - target) * keep
+    loss = float((((phi - target) * keep) ** 2).sum())
+    t_bwd, (d0, ds, dt) = timed(lambda: lat.adjoint_backward(dphi))
+    ws_gb = lat._adj_ws.numel() / 1e9
+    lat.close()
+    del lat, start
+    torch.cuda.empty_cache()
+    return {"workload": "sessile drop R=24 on the wall of a 128^3 lattice, LSQR + wetting, frozen-topology "
+                        f"window of {steps} steps, checkpoints every {K}",
+            "precision": precision, "steps": steps, "K": K,
+            "plain_ms_per_step": round(1e3 * t_plain / steps, 4),
+            "window_forward_ms_per_step": round(1e3 * t_fwd / steps, 4),
+            "backward_ms_per_step": round(1e3 * t_bwd / steps, 4),
+            "backward_over_forward": round(t_bwd / t_plain, 3),
+            "cost_ratio": round((t_fwd + t_bwd) / t_plain, 3),
+            "loss": loss, "dL_dsigma": ds, "dL_dtheta": dt,
+            "dL_dphi0_norm": float(torch.linalg.vector_norm(d0)),
+            "workspace_GB": round(ws_gb, 2)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -152,6 +209,9 @@ def main():
     ap.add_argument("--no-copy", action="store_true", help="skip the copy-bandwidth reference")
     ap.add_argument("--traffic-from", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
                     help="write profiles/stream_collide_traffic.json from rocprofv3 --pmc counter CSVs and exit")
+    ap.add_argument("--adjoint-steps", type=int, default=2000,
+                    help="steps of the differentiation window timed for the adjoint cost (0: skip)")
+    ap.add_argument("--adjoint-k", type=int, default=100, help="checkpoint interval of that window")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
@@ -293,6 +353,11 @@ def main():
         del cb, clats
         torch.cuda.synchronize()
 
+    adjoint = None
+    if args.adjoint_steps > 0:
+        adjoint = adjoint_cost(dev, stream, args.adjoint_steps, args.adjoint_k, args.precision)
+        print(f"# adjoint window done: {adjoint['cost_ratio']}x forward", file=sys.stderr, flush=True)
+
     res = {
         "metric": METRIC,
         "value": round(mlups, 1),
@@ -333,6 +398,8 @@ def main():
         res["cpu_baseline"] = cpu_baseline(runs, args.cpu_seconds)
     if compare:
         res["storage_comparison"] = compare
+    if adjoint:
+        res["adjoint"] = adjoint
     print(json.dumps(res), flush=True)
 
 

@@ -175,6 +175,58 @@ void fslbm_batch_destroy(fslbm_batch_t b);
 int fslbm_read_timing(fslbm_t h, double *phase_ms, int64_t *steps);
 int fslbm_reset_timing(fslbm_t h);
 
+/* Set the fill level of the interface cells (cell types unchanged): phi =
+ * fill[i] and m = fill[i] * rho at every interface cell i, where rho is the
+ * cell's current density; the obstacle fill reflection and the curvature
+ * are recomputed (Sec. II.A, II.C). fill holds n doubles (host, or device
+ * memory when in_is_device = 1); entries at other cells are ignored. This
+ * is the input phi_0 of the differentiation window below. */
+int fslbm_set_interface_fill(fslbm_t h, const double *fill, int in_is_device);
+
+/* Checkpoint and resume: the whole lattice state (distributions, cell
+ * flags, m, rho, phi, K, normals, PLIC offsets, lists, step count) as an
+ * opaque device buffer of fslbm_state_bytes() bytes owned by the caller.
+ * fslbm_load_state checks that the buffer was saved from a lattice of the
+ * same shape, precision and curvature model (FSLBM_E_ARG otherwise).
+ * Both synchronise the stream. */
+int fslbm_state_bytes(fslbm_t h, size_t *bytes);
+int fslbm_save_state(fslbm_t h, void *dst, size_t bytes);
+int fslbm_load_state(fslbm_t h, const void *src, size_t bytes);
+
+/*
+ * Differentiation window with frozen cell types (discrete adjoint).
+ *
+ * fslbm_adjoint_forward advances nsteps >= 1 steps from the current state
+ * with the cell types, the interface list and the obstacle list held fixed
+ * (no fill / empty conversion), so that the step is a smooth map of
+ * (f', m, phi) for given sigma and theta. It stores the state at t = 0, K,
+ * 2K, ... and at t = nsteps in `workspace` (device memory of at least
+ * fslbm_adjoint_required_bytes() bytes, 256-byte aligned, owned by the
+ * caller and kept unchanged until the last backward call; its size depends
+ * on the number of interface cells, so query it in the state the window
+ * starts from). The lattice ends at the state of step nsteps.
+ *
+ * fslbm_adjoint_backward takes dL/dphi_T (n doubles, host or device; only
+ * interface cells are used: the fill level of liquid and gas cells is
+ * constant and the value at obstacle cells is derived) and returns
+ *   *dL_dsigma  dL/dsigma (through rho_b = rho_gas + 3 sigma K, Sec. II),
+ *   *dL_dtheta  dL/dtheta (radians; through the contact condition of the
+ *               LSQR model, eqs. contactNormal, contactConstraint; 0 for FD),
+ *   dL_dfill_0  n doubles (host or device): dL/dphi_0 at interface cells for
+ *               phi_0 as set by fslbm_set_interface_fill (m_0 = phi_0 rho_0
+ *               with the distributions of the window start held fixed),
+ *               0 elsewhere.
+ * It recomputes each K-step segment from its checkpoint into a ring of
+ * K-1 states, runs the transposed steps in reverse order, and leaves the
+ * lattice at the state of step nsteps, so it may be called again with
+ * another dL/dphi_T. FSLBM_E_STATE if no window was recorded or the
+ * lattice has been stepped or modified since. Synchronises the stream.
+ */
+int fslbm_adjoint_required_bytes(fslbm_t h, int64_t nsteps, int K, size_t *bytes);
+int fslbm_adjoint_forward(fslbm_t h, int64_t nsteps, int K, void *workspace, size_t workspace_bytes);
+int fslbm_adjoint_backward(fslbm_t h, const double *dL_dfill_T, int in_is_device, double *dL_dsigma,
+                           double *dL_dtheta, double *dL_dfill_0, int out_is_device);
+
 /* Synchronises the handle's stream and frees the handle (not the caller's
  * workspace). */
 void fslbm_destroy(fslbm_t h);

@@ -775,9 +775,10 @@ static void one_step(orc_lattice *L)
         }
     }
 
-    /* Phase 2: classification of interface cells. */
+    /* Phase 2: classification of interface cells (none with frozen types,
+     * the setting of the differentiated window). */
     unsigned char *st = (unsigned char *)calloc(n, 1);
-    for (long i = 0; i < n; ++i) {
+    for (long i = 0; i < n && !p->frozen; ++i) {
         if (L->type[i] != ORC_INTERFACE) continue;
         if (mnew[i] > (1.0 + p->eps_c) * rnew[i]) st[i] = ST_FILL;
         else if (mnew[i] < -p->eps_c * rnew[i]) st[i] = ST_EMPTY;

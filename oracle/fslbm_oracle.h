@@ -31,6 +31,7 @@ typedef struct {
     double trt_magic;  /* TRT Lambda = (tau_e - 1/2)(tau_o - 1/2) */
     int curv_model;    /* ORC_CURV_FD or ORC_CURV_LSQR */
     int collision;     /* ORC_SRT or ORC_TRT */
+    int frozen;        /* 1: cell types stay fixed (no fill/empty conversion) */
 } orc_params;
 
 typedef struct orc_lattice orc_lattice;

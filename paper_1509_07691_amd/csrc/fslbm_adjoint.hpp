@@ -1,0 +1,1093 @@
+// Discrete adjoint of the FSLBM time step with frozen cell types.
+//
+// Over a window of T steps the flags, the interface list and the obstacle
+// list stay fixed (no fill / empty conversion), so one step is a smooth map
+// of the state s_t = (f'_t, m_t, phi_t) given the parameters sigma (through
+// rho_b = rho_gas + 3 sigma K, Sec. II) and theta (through the contact
+// condition of the LSQR model, eqs. contactNormal, contactConstraint):
+//   K_t      = curvature(phi_t)                      (Sec. II.A or II.C)
+//   f_in     = pull(f'_t; rho_b(K_t), u_b(f'_t))     (eqs. lbe1, reconstruct)
+//   m_{t+1}  = m_t + sum_q k_q(phi_t) (f_in,qbar - f'_q)   (eqs. advection1/2)
+//   phi_{t+1}= m_{t+1} / sum_q f_in,q
+//   f'_{t+1} = collide(f_in)                          (eq. lbe2)
+// The reverse step maps the adjoints (lam = dL/df', mbar, phib) at t+1 to
+// those at t. Every kernel is written as a gather (one writer per value) so
+// the results do not depend on scheduling:
+//   k_adj_prepass      phi_{t+1} = m_{t+1}/rho_{t+1} -> mbar, rhob
+//   k_adj_stream       per fluid cell: transposed collision, mass exchange
+//                      and boundary rules; the adjoint of each pulled value
+//                      is left at the receiving cell (gin), the adjoint of
+//                      the cell's own outgoing values in own, dL/dK in kbar
+//   k_adj_gather       lam_q(x) = own_q(x) + gin_q(x + c_q)
+//   FD:   k_adj_fd_*   transposed stencils of K = -div(n^), n^ from the
+//                      K8-mollified fill level
+//   LSQR: k_adj_lsqr_* reverse of the least-squares fit per interface cell
+//                      (normal equations: y = G^-1 xbar, bbar = M y,
+//                      Mbar = r y^T - M y x^T), the PLIC offsets by the
+//                      implicit function theorem (da/dphi = -1/A, da/dn =
+//                      centroid of the plane section, A its area) and the
+//                      Parker-Youngs normals
+//   k_adj_reflect      transposed obstacle fill reflection (Sec. II.A)
+// All adjoint arithmetic is FP64 whatever the storage precision.
+#pragma once
+
+#include "fslbm_geometry.hpp"
+#include "fslbm_stream.hpp"
+
+namespace fslbm {
+
+struct Adj {
+    double *lam;    // 19 planes: dL/df'(t)
+    double *gin;    // 19 planes: dL/df_in,q(x), kept at the receiving cell x
+    double *own;    // 19 planes: the cell's own share of dL/df'_q(x)
+    double *mbar;   // dL/dm
+    double *phib;   // dL/dphi (at obstacle cells: scratch of the reflection)
+    double *rhob;   // dL/drho(t+1) at interface cells
+    double *kbar;   // dL/dK at interface cells
+    double *sacc;   // per-cell accumulation of dL/dsigma
+    double *tacc;   // per-cell accumulation of dL/dtheta
+    double *ms;     // FD: mollified fill level
+    double *msb;    // FD: its adjoint
+    double *gb;     // 3 planes: adjoint of the Parker-Youngs gradient
+    double *contrib;  // LSQR: 27 x 4 partials (dK/dn_j, dK/da_j) per list entry
+    int *pos;       // list position of each interface cell
+};
+
+constexpr int CONTRIB = 27 * 4;
+
+__host__ __device__ constexpr int slot27(int a, int b, int c) { return (c + 1) * 9 + (b + 1) * 3 + (a + 1); }
+
+// ------------------------------------------------------- state snapshots
+// The state of a step in the frozen window: f' (19 planes, stored apart)
+// and, per interface-list entry, m, rho, phi, K, n (3) and the PLIC offset,
+// followed by phi of the obstacle-list cells. Everything else is constant
+// while the cell types are frozen.
+constexpr int SNAP = 8;
+
+template <class P>
+__global__ __launch_bounds__(256) void k_snap(Fields<P> F, typename P::R *snap, int save)
+{
+    using R = typename P::R;
+    const int n = F.sc->icount, no = F.sc->ocount;
+    const size_t N = F.N;
+    for (int k = blockIdx.x * 256 + threadIdx.x; k < n + no; k += gridDim.x * 256) {
+        if (k < n) {
+            const int i = F.ilist[k];
+            R *s = snap + (size_t)SNAP * k;
+            if (save) {
+                s[0] = F.m[i]; s[1] = F.rho[i]; s[2] = F.phi[i]; s[3] = F.K[i];
+                s[4] = F.nrm[i]; s[5] = F.nrm[N + i]; s[6] = F.nrm[2 * N + i]; s[7] = F.plic[i];
+            } else {
+                F.m[i] = s[0]; F.rho[i] = s[1]; F.phi[i] = s[2]; F.K[i] = s[3];
+                F.nrm[i] = s[4]; F.nrm[N + i] = s[5]; F.nrm[2 * N + i] = s[6]; F.plic[i] = s[7];
+            }
+        } else {
+            const int o = F.olist[k - n];
+            R *s = snap + (size_t)SNAP * n + (k - n);
+            if (save) *s = F.phi[o];
+            else F.phi[o] = *s;
+        }
+    }
+}
+
+// ------------------------------------------------------- set-up kernels
+__global__ void k_adj_zero(double *p, size_t n)
+{
+    for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) p[i] = 0.0;
+}
+
+// pos[] of the interface cells and phib = dL/dphi_T there.
+template <class P>
+__global__ void k_adj_begin(Fields<P> F, Adj A, const double *dphi)
+{
+    const int n = F.sc->icount;
+    for (int k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256) {
+        const int i = F.ilist[k];
+        A.pos[i] = k;
+        A.phib[i] = dphi[i];
+    }
+}
+
+// dL/dphi_0 = phib + mbar rho_0 at interface cells (m_0 = phi_0 rho_0 with
+// the distributions of the window start held fixed).
+template <class P>
+__global__ void k_adj_finish(Fields<P> F, Adj A, const typename P::R *snap0, double *out)
+{
+    const int n = F.sc->icount;
+    for (int k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256) {
+        const int i = F.ilist[k];
+        out[i] = A.phib[i] + A.mbar[i] * double(snap0[(size_t)SNAP * k + 1]);
+    }
+}
+
+// ------------------------------------------------ phi = m / rho (reverse)
+template <class P>
+__global__ void k_adj_prepass(Fields<P> F, Adj A, const typename P::R *snap_next)
+{
+    const int n = F.sc->icount;
+    for (int k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256) {
+        const int i = F.ilist[k];
+        const double m = double(snap_next[(size_t)SNAP * k]), r = double(snap_next[(size_t)SNAP * k + 1]);
+        const double pb = A.phib[i];
+        A.mbar[i] += pb / r;
+        A.rhob[i] = -pb * m / (r * r);
+        A.phib[i] = 0.0;
+    }
+}
+
+// ------------------------------------------- transposed collision (eq. lbe2)
+// fb = (d collide / d f)^T yb at the pre-collision values f.
+template <int COLL>
+__device__ inline void collide_adj(const double (&f)[NQ], const double (&yb)[NQ], const Params &p, double (&fb)[NQ])
+{
+    double rho, ux, uy, uz;
+    moments(f, rho, ux, uy, uz);
+    const double usq = ux * ux + uy * uy + uz * uz;
+    const double we = p.omega;
+    double eb[NQ];  // adjoint of feq_q
+    if constexpr (COLL == 0) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            fb[q] = (1.0 - we) * yb[q];
+            eb[q] = we * yb[q];
+        }
+    } else {
+        const double wo = p.omega_odd;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) fb[q] = eb[q] = 0.0;
+        // g_q = f_q - we (f+_q - e+_q) - wo (f-_q - e-_q), f+- = (f_q +- f_qbar)/2
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int o = opp(q);
+            const double y = yb[q];
+            fb[q] += y * (1.0 - 0.5 * we - 0.5 * wo);
+            fb[o] += y * (0.5 * wo - 0.5 * we);
+            eb[q] += y * (0.5 * we + 0.5 * wo);
+            eb[o] += y * (0.5 * we - 0.5 * wo);
+        }
+    }
+    // feq_q = w_q rho (1 + 3 c.u + 4.5 (c.u)^2 - 1.5 u.u)
+    double rb = 0.0, uxb = 0.0, uyb = 0.0, uzb = 0.0;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const double cx = dir_x(q), cy = dir_y(q), cz = dir_z(q);
+        const double cu = cx * ux + cy * uy + cz * uz;
+        const double w = weight<double>(q) * eb[q];
+        rb += w * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
+        const double s = w * rho * (3.0 + 9.0 * cu), t = w * rho * 3.0;
+        uxb += s * cx - t * ux;
+        uyb += s * cy - t * uy;
+        uzb += s * cz - t * uz;
+    }
+    // u = j / rho
+    const double jxb = uxb / rho, jyb = uyb / rho, jzb = uzb / rho;
+    rb -= (uxb * ux + uyb * uy + uzb * uz) / rho;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) fb[q] += rb + dir_x(q) * jxb + dir_y(q) * jyb + dir_z(q) * jzb;
+}
+
+template <class P>
+__device__ inline void load_dirs_d(const Fields<P> &F, const int (&j)[NQ], double (&f)[NQ])
+{
+    typename P::T t[NQ];
+    load_dirs<P>(F, j, t);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) f[q] = double(t[q]);
+}
+
+// ------------------------------------ reverse stream-collide, one fluid cell
+// Recomputes the forward pull of boundary_cell (same rules, in FP64) and
+// applies the transposed step. Writes gin and own of the cell; at interface
+// cells also kbar, phib (the part from the mass-exchange weights) and the
+// sigma accumulator.
+template <class P, int COLL>
+__device__ inline void cell_adj(const Fields<P> &F, const Adj &A, const Params &prm, int i, const Nbr &nb, uint8_t fl)
+{
+    const size_t N = F.N;
+    int up[NQ], own[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        up[q] = nb.at(-dir_x(q), -dir_y(q), -dir_z(q));
+        own[q] = i;
+    }
+    double yb[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) yb[q] = A.lam[q * N + i];
+    double pl[NQ];
+    load_dirs_d<P>(F, up, pl);
+    if (fl == FL_LIQ) {  // every upstream node is fluid: plain pull
+        double fb[NQ];
+        collide_adj<COLL>(pl, yb, prm, fb);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) A.gin[q * N + i] = fb[q];
+        return;
+    }
+    const bool is_if = (fl & FL_IF) != 0;
+    double fo[NQ];
+    load_dirs_d<P>(F, own, fo);
+    uint8_t nt[NQ];
+    nt[0] = FL_LIQ;
+#pragma unroll
+    for (int q = 1; q < NQ; ++q) nt[q] = F.flags[up[q]] & FL_TYPE;
+    double Kc = 0, phx = 0, cnx = 0, cny = 0, cnz = 0;
+    if (is_if) {
+        Kc = double(F.K[i]);
+        phx = double(F.phi[i]);
+        cnx = double(F.nrm[i]);
+        cny = double(F.nrm[N + i]);
+        cnz = double(F.nrm[2 * N + i]);
+    }
+    bool has_gas = false;
+    int nwx = 0, nwy = 0, nwz = 0;
+#pragma unroll
+    for (int q = 1; q < NQ; ++q) {
+        has_gas |= nt[q] == FL_GAS;
+        if (nt[q] == FL_OBST) { nwx -= dir_x(q); nwy -= dir_y(q); nwz -= dir_z(q); }
+    }
+    double rb0, ubx, uby, ubz;
+    moments(fo, rb0, ubx, uby, ubz);
+    const double ubsq = ubx * ubx + uby * uby + ubz * ubz;
+    const double rhob = 3.0 * (prm.rho_gas / 3.0 + prm.sigma * Kc);
+    const bool corner = is_if && has_gas && (nwx | nwy | nwz) != 0;
+    const int ww = nwx * nwx + nwy * nwy + nwz * nwz;
+    double fin[NQ];
+    bool rec[NQ];
+    fin[0] = fo[0];
+    rec[0] = false;
+#pragma unroll
+    for (int q = 1; q < NQ; ++q) {
+        const int o = opp(q);
+        const uint8_t t = nt[q];
+        const int cox = -dir_x(q), coy = -dir_y(q), coz = -dir_z(q);
+        const int cw = cox * nwx + coy * nwy + coz * nwz;
+        const double s = double(cox * ww - cw * nwx) * cnx + double(coy * ww - cw * nwy) * cny +
+                         double(coz * ww - cw * nwz) * cnz;
+        rec[q] = (t == FL_GAS) || (t == FL_OBST && corner && s < 0.0);
+        const double vrec = feq<double>(q, rhob, ubx, uby, ubz, ubsq) + feq<double>(o, rhob, ubx, uby, ubz, ubsq) - fo[o];
+        fin[q] = (t & FL_FLUID) ? pl[q] : (rec[q] ? vrec : fo[o]);
+    }
+    double fb[NQ], fob[NQ];
+    collide_adj<COLL>(fin, yb, prm, fb);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) fob[q] = 0.0;
+    if (is_if) {
+        // rho(t+1) = sum_q f_in,q
+        const double rb = A.rhob[i];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) fb[q] += rb;
+        // m(t+1) = m(t) + sum_q k_q (f_in,qbar - f'_q)
+        const double Mb = A.mbar[i];
+        double phb = 0.0;
+#pragma unroll
+        for (int q = 1; q < NQ; ++q) {
+            const int o = opp(q);
+            const uint8_t tz = nt[o];  // type of x + c_q
+            if (tz == FL_LIQ) {
+                fb[o] += Mb;
+                fob[q] -= Mb;
+            } else if (tz == FL_IF) {
+                const int z = up[o];
+                const double k = 0.5 * (double(F.phi[z]) + phx);
+                fb[o] += k * Mb;
+                fob[q] -= k * Mb;
+                // both ends of the link carry the weight (phi_x + phi_z)/2
+                phb += 0.5 * (fin[o] - fo[q]) * (Mb - A.mbar[z]);
+            }
+        }
+        A.phib[i] = phb;
+    }
+    // transposed pull and boundary rules
+    double rbb = 0.0, uxb = 0.0, uyb = 0.0, uzb = 0.0;
+    A.gin[i] = fb[0];
+#pragma unroll
+    for (int q = 1; q < NQ; ++q) {
+        const int o = opp(q);
+        if (nt[q] & FL_FLUID) {
+            A.gin[q * N + i] = fb[q];
+            continue;
+        }
+        A.gin[q * N + i] = 0.0;
+        if (rec[q]) {
+            // feq_q + feq_qbar = 2 w rho_b (1 + 4.5 (c.u_b)^2 - 1.5 u_b.u_b)
+            fob[o] -= fb[q];
+            const double cx = dir_x(q), cy = dir_y(q), cz = dir_z(q);
+            const double cu = cx * ubx + cy * uby + cz * ubz;
+            const double w2 = 2.0 * weight<double>(q) * fb[q];
+            rbb += w2 * (1.0 + 4.5 * cu * cu - 1.5 * ubsq);
+            const double s = w2 * rhob * 9.0 * cu, t = w2 * rhob * 3.0;
+            uxb += s * cx - t * ubx;
+            uyb += s * cy - t * uby;
+            uzb += s * cz - t * ubz;
+        } else {
+            fob[o] += fb[q];
+        }
+    }
+    if (uxb != 0.0 || uyb != 0.0 || uzb != 0.0) {
+        // u_b = j(f'_t(x)) / rho(f'_t(x))
+        const double jxb = uxb / rb0, jyb = uyb / rb0, jzb = uzb / rb0;
+        const double r0b = -(uxb * ubx + uyb * uby + uzb * ubz) / rb0;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) fob[q] += r0b + dir_x(q) * jxb + dir_y(q) * jyb + dir_z(q) * jzb;
+    }
+    if (is_if) {
+        // rho_b = rho_gas + 3 sigma K
+        A.kbar[i] = 3.0 * prm.sigma * rbb;
+        A.sacc[i] += 3.0 * Kc * rbb;
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) A.own[q * N + i] = fob[q];
+}
+
+// Reverse stream-collide over the fluid bounding box (same traversal as the
+// forward kernel).
+template <class P, int COLL>
+__global__ __launch_bounds__(256) void k_adj_stream(const Fields<P> F, const Adj A, const Params prm)
+{
+    const CellRange box = CellRange::from(F.sc->fbox);
+    const int n = box.size();
+    const int nxy = F.nx * F.ny;
+    for (int k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256) {
+        const int bx = k % box.ex, r = k / box.ex, by = r % box.ey, bz = r / box.ey;
+        const int x = box.x0 + bx, y = box.y0 + by, z = box.z0 + bz;
+        const int i = x + F.nx * y + nxy * z;
+        const uint8_t fl = F.flags[i];
+        if (!(fl & FL_FLUID)) continue;
+        const Nbr nb(x, y, z, F.nx, F.ny, F.nz);
+        cell_adj<P, COLL>(F, A, prm, i, nb, fl);
+    }
+}
+
+// lam_q(x) = own_q(x) + gin_q(x + c_q) (the downstream cell pulled f'_q(x)).
+template <class P>
+__global__ __launch_bounds__(256) void k_adj_gather(const Fields<P> F, const Adj A)
+{
+    const CellRange box = CellRange::from(F.sc->fbox);
+    const int n = box.size();
+    const int nxy = F.nx * F.ny;
+    const size_t N = F.N;
+    for (int k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256) {
+        const int bx = k % box.ex, r = k / box.ex, by = r % box.ey, bz = r / box.ey;
+        const int x = box.x0 + bx, y = box.y0 + by, z = box.z0 + bz;
+        const int i = x + F.nx * y + nxy * z;
+        const uint8_t fl = F.flags[i];
+        if (!(fl & FL_FLUID)) continue;
+        const Nbr nb(x, y, z, F.nx, F.ny, F.nz);
+        const bool has_own = fl != FL_LIQ;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int d = nb.at(dir_x(q), dir_y(q), dir_z(q));
+            double v = has_own ? A.own[q * N + i] : 0.0;
+            if (F.flags[d] & FL_FLUID) v += A.gin[q * N + d];
+            A.lam[q * N + i] = v;
+        }
+    }
+}
+
+// ------------------------------------------------ FD curvature (reverse)
+// Forward (Sec. II.A): ms = K8 * phi / 942, g = PY(ms), n = g/|g|,
+// K = -(PY_x n_x + PY_y n_y + PY_z n_z)/32 at interface cells. Each PY
+// difference is antisymmetric and its transverse weights symmetric, so the
+// transpose of PY_k is -PY_k.
+template <class P>
+__global__ __launch_bounds__(256) void k_adj_fd_mol(const Fields<P> F, const Adj A)
+{
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < F.N; i += gridDim.x * 256) {
+        const Nbr nb(i, F.nx, F.ny, F.nz);
+        double s = 0.0;
+#pragma unroll
+        for (int c = -1; c <= 1; ++c)
+#pragma unroll
+            for (int b = -1; b <= 1; ++b)
+#pragma unroll
+                for (int a = -1; a <= 1; ++a) s += k8w(a * a + b * b + c * c) * double(F.phi[nb.at(a, b, c)]);
+        A.ms[i] = s / 942.0;
+    }
+}
+
+// gb = (I - n n^T) nbar / |g| with nbar = PY(kbar)/32.
+template <class P>
+__global__ __launch_bounds__(256) void k_adj_fd_nbar(const Fields<P> F, const Adj A)
+{
+    const size_t N = F.N;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < F.N; i += gridDim.x * 256) {
+        const Nbr nb(i, F.nx, F.ny, F.nz);
+        double bx, by, bz;
+        py_grad(A.kbar, nb, bx, by, bz);
+        double o0 = 0.0, o1 = 0.0, o2 = 0.0;
+        if (bx != 0.0 || by != 0.0 || bz != 0.0) {
+            bx /= 32.0; by /= 32.0; bz /= 32.0;
+            double gx, gy, gz;
+            py_grad(A.ms, nb, gx, gy, gz);
+            const double len = sqrt(gx * gx + gy * gy + gz * gz);
+            if (len > 1e-12) {
+                const double nx = gx / len, ny = gy / len, nz = gz / len;
+                const double d = bx * nx + by * ny + bz * nz;
+                o0 = (bx - d * nx) / len;
+                o1 = (by - d * ny) / len;
+                o2 = (bz - d * nz) / len;
+            }
+        }
+        A.gb[i] = o0;
+        A.gb[N + i] = o1;
+        A.gb[2 * N + i] = o2;
+    }
+}
+
+// Transposed PY gradient of the three planes of gb: -(PY_x gb_x + PY_y gb_y + PY_z gb_z).
+__device__ inline double py_div_t(const double *gb, size_t N, const Nbr &nb)
+{
+    double s = 0.0;
+#pragma unroll
+    for (int a = -1; a <= 1; ++a)
+#pragma unroll
+        for (int b = -1; b <= 1; ++b) {
+            const double w = pyw(a) * pyw(b);
+            s += w * (gb[nb.at(1, a, b)] - gb[nb.at(-1, a, b)]);
+            s += w * (gb[N + nb.at(a, 1, b)] - gb[N + nb.at(a, -1, b)]);
+            s += w * (gb[2 * N + nb.at(a, b, 1)] - gb[2 * N + nb.at(a, b, -1)]);
+        }
+    return -s;
+}
+
+template <class P>
+__global__ __launch_bounds__(256) void k_adj_fd_msb(const Fields<P> F, const Adj A)
+{
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < F.N; i += gridDim.x * 256) {
+        const Nbr nb(i, F.nx, F.ny, F.nz);
+        A.msb[i] = py_div_t(A.gb, F.N, nb);
+    }
+}
+
+// phib += K8 * msb / 942 at interface cells; at obstacle cells the value is
+// kept in phib for the transposed reflection.
+template <class P>
+__global__ __launch_bounds__(256) void k_adj_fd_phib(const Fields<P> F, const Adj A)
+{
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < F.N; i += gridDim.x * 256) {
+        const uint8_t fl = F.flags[i];
+        if (!(fl & (FL_IF | FL_OBST))) continue;
+        const Nbr nb(i, F.nx, F.ny, F.nz);
+        double s = 0.0;
+#pragma unroll
+        for (int c = -1; c <= 1; ++c)
+#pragma unroll
+            for (int b = -1; b <= 1; ++b)
+#pragma unroll
+                for (int a = -1; a <= 1; ++a) s += k8w(a * a + b * b + c * c) * A.msb[nb.at(a, b, c)];
+        s /= 942.0;
+        if (fl & FL_IF) A.phib[i] += s;
+        else A.phib[i] = s;
+    }
+}
+
+// --------------------------------------- obstacle fill reflection (reverse)
+// phi(o) = sum_j w_oj phi(j) / sum_j w_oj over fluid neighbours j with
+// aperture w_oj > sqrt(2)/2; interface cell i gathers phib(o) w_oi / den_o
+// from each obstacle neighbour o.
+template <class P>
+__global__ __launch_bounds__(256) void k_adj_reflect(const Fields<P> F, const Adj A)
+{
+    const int n = F.sc->icount;
+    const double alpha = 0.70710678118654752440 + 1e-12;
+    for (int k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256) {
+        const int i = F.ilist[k];
+        if (!(F.flags[i] & FL_NEAR_OBST)) continue;
+        const Nbr ni(i, F.nx, F.ny, F.nz);
+        double acc = 0.0;
+        for (int q = 1; q < NQ; ++q) {
+            const int o = ni.at(dir_x(q), dir_y(q), dir_z(q));
+            if (!(F.flags[o] & FL_OBST)) continue;
+            const Nbr no(o, F.nx, F.ny, F.nz);
+            int sx = 0, sy = 0, sz = 0;
+            for (int p = 1; p < NQ; ++p)
+                if (!(F.flags[no.at(dir_x(p), dir_y(p), dir_z(p))] & FL_OBST)) {
+                    sx += dir_x(p); sy += dir_y(p); sz += dir_z(p);
+                }
+            const double len = sqrt(double(sx * sx + sy * sy + sz * sz));
+            if (!(len > 0)) continue;
+            const double wx = sx / len, wy = sy / len, wz = sz / len;
+            double den = 0.0, wi = 0.0;
+            for (int p = 1; p < NQ; ++p) {
+                const int j = no.at(dir_x(p), dir_y(p), dir_z(p));
+                if (!(F.flags[j] & FL_FLUID)) continue;
+                const double cl = sqrt(double(dir_len2(p)));
+                const double w = fabs((wx * dir_x(p) + wy * dir_y(p) + wz * dir_z(p)) / cl);
+                if (w > alpha) {
+                    den += w;
+                    if (p == opp(q)) wi = w;  // o + c_p = i
+                }
+            }
+            if (den > 0.0 && wi > 0.0) acc += A.phib[o] * wi / den;
+        }
+        A.phib[i] += acc;
+    }
+}
+
+// ------------------------------------------------ PLIC offset derivatives
+// For the plane n.y = a (|n| = 1) through the cell [-1/2, 1/2]^3, the cut
+// volume V(a, n) = |{y : n.y >= a}| has dV/da = -A and dV/dn = A c, A the
+// area of the plane section and c its centroid. With V(a, n) = phi the
+// implicit function theorem gives da/dphi = -1/A and da/dn = c.
+__host__ __device__ inline bool plic_section(const double (&n)[3], double a, double &area, double (&cen)[3])
+{
+    double pts[12][3];
+    int np = 0;
+    for (int e = 0; e < 3; ++e) {
+        if (n[e] == 0.0) continue;
+        const int e1 = (e + 1) % 3, e2 = (e + 2) % 3;
+        for (int s = 0; s < 4; ++s) {
+            const double y1 = (s & 1) ? 0.5 : -0.5, y2 = (s & 2) ? 0.5 : -0.5;
+            const double t = (a - n[e1] * y1 - n[e2] * y2) / n[e];
+            if (!(t >= -0.5 && t <= 0.5)) continue;
+            pts[np][e] = t;
+            pts[np][e1] = y1;
+            pts[np][e2] = y2;
+            ++np;
+        }
+    }
+    if (np < 3) return false;
+    double m[3] = {0, 0, 0};
+    for (int k = 0; k < np; ++k)
+        for (int d = 0; d < 3; ++d) m[d] += pts[k][d] / np;
+    // orthonormal basis (b1, b2) of the plane
+    int ax = 0;
+    if (fabs(n[1]) < fabs(n[ax])) ax = 1;
+    if (fabs(n[2]) < fabs(n[ax])) ax = 2;
+    double b1[3] = {-n[ax] * n[0], -n[ax] * n[1], -n[ax] * n[2]};
+    b1[ax] += 1.0;
+    const double l1 = sqrt(dot(b1, b1));
+    for (int d = 0; d < 3; ++d) b1[d] /= l1;
+    const double b2[3] = {n[1] * b1[2] - n[2] * b1[1], n[2] * b1[0] - n[0] * b1[2], n[0] * b1[1] - n[1] * b1[0]};
+    double u[12], v[12], ang[12];
+    int idx[12];
+    for (int k = 0; k < np; ++k) {
+        const double r[3] = {pts[k][0] - m[0], pts[k][1] - m[1], pts[k][2] - m[2]};
+        u[k] = dot(r, b1);
+        v[k] = dot(r, b2);
+        ang[k] = atan2(v[k], u[k]);
+        idx[k] = k;
+    }
+    for (int k = 1; k < np; ++k) {  // insertion sort by angle
+        const int c = idx[k];
+        int j = k - 1;
+        while (j >= 0 && ang[idx[j]] > ang[c]) {
+            idx[j + 1] = idx[j];
+            --j;
+        }
+        idx[j + 1] = c;
+    }
+    double A = 0.0, cu = 0.0, cv = 0.0;
+    for (int k = 0; k < np; ++k) {
+        const int p = idx[k], q = idx[(k + 1) % np];
+        const double t = 0.5 * (u[p] * v[q] - u[q] * v[p]);
+        A += t;
+        cu += t * (u[p] + u[q]) / 3.0;
+        cv += t * (v[p] + v[q]) / 3.0;
+    }
+    if (!(A > 1e-14)) return false;
+    cu /= A;
+    cv /= A;
+    for (int d = 0; d < 3; ++d) cen[d] = m[d] + cu * b1[d] + cv * b2[d];
+    area = A;
+    return true;
+}
+
+// da/dphi and da/dn of the PLIC offset a(n, phi) of a unit normal; phi is
+// clamped to [0, 1] by the offset solver, where a = -+|n|_1/2 and
+// da/dn = -+sign(n)/2.
+__host__ __device__ inline void plic_derivs(const double (&n)[3], double phi, double a, double &dphi, double (&dn)[3])
+{
+    dphi = 0.0;
+    dn[0] = dn[1] = dn[2] = 0.0;
+    if (phi <= 0.0 || phi >= 1.0) {
+        const double s = phi <= 0.0 ? 0.5 : -0.5;
+        for (int d = 0; d < 3; ++d) dn[d] = n[d] > 0.0 ? s : (n[d] < 0.0 ? -s : 0.0);
+        return;
+    }
+    double A, c[3];
+    if (!plic_section(n, a, A, c)) return;
+    dphi = -1.0 / A;
+    for (int d = 0; d < 3; ++d) dn[d] = c[d];
+}
+
+// ------------------------------------------------ LSQR curvature (reverse)
+// Reverse of contact_condition: given the adjoints of (u_c, v_c, -m_u/m_n,
+// -m_v/m_n), accumulates those of p_c, n_c, t_u, t_v, of the contact cell's
+// normal and PLIC offset (into its slot of cb) and of theta.
+template <class View>
+__host__ __device__ inline void contact_condition_adj(const View &V, int dx, int dy, int dz, const double (&pc)[3],
+                                                      const double (&nc)[3], const double (&tu)[3],
+                                                      const double (&tv)[3], const Params &prm, double ucb,
+                                                      double vcb, double rub, double rvb, double (&pcb)[3],
+                                                      double (&ncb)[3], double (&tub)[3], double (&tvb)[3],
+                                                      double *cb, double &thb)
+{
+    double nj[3];
+    V.normal(dx, dy, dz, nj);
+    if (nj[0] == 0.0 && nj[1] == 0.0 && nj[2] == 0.0) return;
+    int sx = 0, sy = 0, sz = 0;
+    for (int q = 1; q < NQ; ++q)
+        if (V.flag(dx + dir_x(q), dy + dir_y(q), dz + dir_z(q)) & FL_OBST) {
+            sx += dir_x(q); sy += dir_y(q); sz += dir_z(q);
+        }
+    const double lw = sqrt(double(sx * sx + sy * sy + sz * sz));
+    if (!(lw > 0.0)) return;
+    const double nw[3] = {sx / lw, sy / lw, sz / lw};
+    const double nn = dot(nj, nw);
+    const double ntr[3] = {nj[0] - nn * nw[0], nj[1] - nn * nw[1], nj[2] - nn * nw[2]};
+    const double lt = sqrt(dot(ntr, ntr));
+    if (lt < 1e-12) return;
+    const double nt[3] = {ntr[0] / lt, ntr[1] / lt, ntr[2] / lt};
+    const double ct = prm.cos_theta, st = prm.sin_theta;
+    const double mh[3] = {nw[0] * ct + nt[0] * st, nw[1] * ct + nt[1] * st, nw[2] * ct + nt[2] * st};
+    const double g[3] = {nw[0] - nn * nj[0], nw[1] - nn * nj[1], nw[2] - nn * nj[2]};
+    const double gn = dot(g, nw);
+    if (gn < 1e-12) return;
+    const double aj = V.plic(dx, dy, dz);
+    const double pj[3] = {aj * nj[0], aj * nj[1], aj * nj[2]};
+    const double t = (0.5 - dot(pj, nw)) / gn;
+    const double r[3] = {dx + pj[0] + t * g[0] - pc[0], dy + pj[1] + t * g[1] - pc[1], dz + pj[2] + t * g[2] - pc[2]};
+    const double mu = dot(mh, tu), mv = dot(mh, tv), mn = dot(mh, nc);
+    if (fabs(mn) < 1e-6) return;
+    // reverse
+    const double mub = -rub / mn, mvb = -rvb / mn, mnb = (rub * mu + rvb * mv) / (mn * mn);
+    double mhb[3], rb[3], pjb[3], gb[3], njb[3];
+    for (int k = 0; k < 3; ++k) {
+        mhb[k] = mub * tu[k] + mvb * tv[k] + mnb * nc[k];
+        tub[k] += mub * mh[k] + ucb * r[k];
+        tvb[k] += mvb * mh[k] + vcb * r[k];
+        ncb[k] += mnb * mh[k];
+        rb[k] = ucb * tu[k] + vcb * tv[k];
+        pcb[k] -= rb[k];
+        pjb[k] = rb[k];
+    }
+    const double tb = dot(rb, g);
+    for (int k = 0; k < 3; ++k) gb[k] = t * rb[k];
+    // t = (1/2 - pj.nw) / gn
+    const double gnb = -tb * t / gn;
+    for (int k = 0; k < 3; ++k) {
+        pjb[k] -= (tb / gn) * nw[k];
+        gb[k] += gnb * nw[k];
+    }
+    // g = nw - nn nj
+    double nnb = -dot(gb, nj);
+    for (int k = 0; k < 3; ++k) njb[k] = -nn * gb[k] + aj * pjb[k];
+    const double ajb = dot(pjb, nj);
+    // m = nw cos(theta) + nt sin(theta)
+    thb += -st * dot(mhb, nw) + ct * dot(mhb, nt);
+    double ntb[3] = {st * mhb[0], st * mhb[1], st * mhb[2]};
+    const double dn = dot(ntb, nt);
+    for (int k = 0; k < 3; ++k) {
+        const double ntrb = (ntb[k] - dn * nt[k]) / lt;
+        njb[k] += ntrb;
+        nnb -= ntrb * nw[k];
+    }
+    for (int k = 0; k < 3; ++k) njb[k] += nnb * nw[k];
+    double *c = cb + 4 * slot27(dx, dy, dz);
+    c[0] += njb[0];
+    c[1] += njb[1];
+    c[2] += njb[2];
+    c[3] += ajb;
+}
+
+// Reverse of lsqr_curvature for dL/dK = Kb: accumulates dL/dn_j and dL/da_j
+// of the 27 cells of the block (cb[4 s + 0..2], cb[4 s + 3], s = slot27)
+// and dL/dtheta. Recomputes the forward fit first (same rows, same order,
+// same model choice).
+template <class View>
+__host__ __device__ inline void lsqr_curvature_adj(const View &V, const Params &prm, double Kb, double *cb, double &thb)
+{
+    double nc[3];
+    V.normal(0, 0, 0, nc);
+    if (nc[0] == 0.0 && nc[1] == 0.0 && nc[2] == 0.0) return;
+    int ax = 0;
+    if (fabs(nc[1]) < fabs(nc[ax])) ax = 1;
+    if (fabs(nc[2]) < fabs(nc[ax])) ax = 2;
+    double tu[3] = {-nc[ax] * nc[0], -nc[ax] * nc[1], -nc[ax] * nc[2]};
+    tu[ax] += 1.0;
+    const double ltu = sqrt(dot(tu, tu));
+    tu[0] /= ltu; tu[1] /= ltu; tu[2] /= ltu;
+    const double tv[3] = {nc[1] * tu[2] - nc[2] * tu[1], nc[2] * tu[0] - nc[0] * tu[2], nc[0] * tu[1] - nc[1] * tu[0]};
+    const double ac = V.plic(0, 0, 0);
+    const double pc[3] = {ac * nc[0], ac * nc[1], ac * nc[2]};
+    bool has_obst = false;
+    for (int c = -1; c <= 1; ++c)
+        for (int b = -1; b <= 1; ++b)
+            for (int a = -1; a <= 1; ++a) has_obst |= (V.flag(a, b, c) & FL_OBST) != 0;
+    bool hard = false;
+    double huc = 0, hvc = 0, hu = 0, hv = 0;
+    if (has_obst && (V.flag(0, 0, 0) & FL_NEAR_OBST))
+        hard = contact_condition(V, 0, 0, 0, pc, nc, tu, tv, prm, huc, hvc, hu, hv);
+
+    // ---- forward fit
+    Gram<5> g5;
+    Gram<3> g3;
+    Gram<1> g1;
+    int rows = 0;
+    auto add_row = [&](double r0, double r1, double r2, double r3, double r4, double b) {
+        ++rows;
+        if (!hard) {
+            const double a5[5] = {r0, r1, r2, r3, r4};
+            g5.add(a5, b);
+            const double a3[3] = {r0 + r1, r3, r4};
+            g3.add(a3, b);
+        } else {
+            const double e0 = r0 - r3 * (2.0 * huc), e1 = r1 - r4 * (2.0 * hvc);
+            const double e2 = r2 - r3 * hvc - r4 * huc;
+            const double be = b - r3 * hu - r4 * hv;
+            const double a3[3] = {e0, e1, e2};
+            g3.add(a3, be);
+            const double a1[1] = {e0 + e1};
+            g1.add(a1, be);
+        }
+    };
+    for (int c = -1; c <= 1; ++c)
+        for (int b = -1; b <= 1; ++b)
+            for (int a = -1; a <= 1; ++a) {
+                if (a == 0 && b == 0 && c == 0) continue;
+                if (!(V.flag(a, b, c) & FL_IF)) continue;
+                double nj[3];
+                V.normal(a, b, c, nj);
+                if (nj[0] == 0.0 && nj[1] == 0.0 && nj[2] == 0.0) continue;
+                const double aj = V.plic(a, b, c);
+                const double r[3] = {a + aj * nj[0] - pc[0], b + aj * nj[1] - pc[1], c + aj * nj[2] - pc[2]};
+                const double u = dot(r, tu), v = dot(r, tv), w = dot(r, nc);
+                add_row(u * u, v * v, u * v, u, v, w);
+            }
+    if (has_obst) {
+        for (int c = -1; c <= 1; ++c)
+            for (int b = -1; b <= 1; ++b)
+                for (int a = -1; a <= 1; ++a) {
+                    if (a == 0 && b == 0 && c == 0) continue;
+                    const uint8_t fj = V.flag(a, b, c);
+                    if (!((fj & FL_IF) && (fj & FL_NEAR_OBST))) continue;
+                    double uc, vc, ru, rv;
+                    if (!contact_condition(V, a, b, c, pc, nc, tu, tv, prm, uc, vc, ru, rv)) continue;
+                    add_row(2.0 * uc, 0.0, vc, 1.0, 0.0, ru);
+                    add_row(0.0, 2.0 * vc, uc, 0.0, 1.0, rv);
+                }
+    }
+    // model: 0 none, 1 free 5, 2 free isotropic 3, 3 hard 3, 4 hard isotropic 1
+    int model = 0;
+    double x[5] = {0, 0, 0, 0, 0};
+    double A = 0, Bq = 0, C = 0, H = 0, I = 0;
+    if (!hard) {
+        double x5[5];
+        if (rows >= 5 && g5.solve(x5)) {
+            model = 1;
+            for (int k = 0; k < 5; ++k) x[k] = x5[k];
+            A = x5[0]; Bq = x5[1]; C = x5[2]; H = x5[3]; I = x5[4];
+        } else {
+            double x3[3];
+            if (rows >= 3 && g3.solve(x3)) {
+                model = 2;
+                x[0] = x3[0]; x[1] = x3[1]; x[2] = x3[2];
+                A = x3[0]; Bq = x3[0]; C = 0.0; H = x3[1]; I = x3[2];
+            }
+        }
+    } else {
+        double x3[3];
+        if (rows >= 3 && g3.solve(x3)) {
+            model = 3;
+            x[0] = x3[0]; x[1] = x3[1]; x[2] = x3[2];
+            A = x3[0]; Bq = x3[1]; C = x3[2];
+        } else {
+            double x1[1];
+            if (rows >= 1 && g1.solve(x1)) {
+                model = 4;
+                x[0] = x1[0];
+                A = x1[0]; Bq = x1[0]; C = 0.0;
+            }
+        }
+        H = hu - 2.0 * huc * A - hvc * C;
+        I = hv - 2.0 * hvc * Bq - huc * C;
+    }
+    if (model == 0) return;
+
+    // ---- K = 2 (A (1 + I^2) + B (1 + H^2) - C H I) / (1 + H^2 + I^2)^(3/2)
+    const double gg = 1.0 + H * H + I * I;
+    const double Nn = A * (1.0 + I * I) + Bq * (1.0 + H * H) - C * H * I;
+    const double Nb = 2.0 * Kb / (gg * sqrt(gg));
+    const double ggb = -3.0 * Nn * Kb / (gg * gg * sqrt(gg));
+    double Ab = Nb * (1.0 + I * I), Bb = Nb * (1.0 + H * H), Cb = -Nb * H * I;
+    double Hb = Nb * (2.0 * Bq * H - C * I) + 2.0 * H * ggb;
+    double Ib = Nb * (2.0 * A * I - C * H) + 2.0 * I * ggb;
+    double hucb = 0, hvcb = 0, hub = 0, hvb = 0;
+    if (hard) {
+        // H = hu - 2 huc A - hvc C, I = hv - 2 hvc B - huc C
+        hub += Hb;
+        hvb += Ib;
+        hucb += -2.0 * A * Hb - C * Ib;
+        hvcb += -C * Hb - 2.0 * Bq * Ib;
+        Ab += -2.0 * huc * Hb;
+        Bb += -2.0 * hvc * Ib;
+        Cb += -hvc * Hb - huc * Ib;
+    }
+    // adjoint of the solved vector and y = G^-1 xbar
+    double y[5] = {0, 0, 0, 0, 0};
+    if (model == 1) {
+        Gram<5> gy = g5;
+        const double xb[5] = {Ab, Bb, Cb, Hb, Ib};
+        for (int k = 0; k < 5; ++k) gy.g[k] = xb[k];
+        double yy[5];
+        gy.solve(yy);
+        for (int k = 0; k < 5; ++k) y[k] = yy[k];
+    } else if (model == 2 || model == 3) {
+        Gram<3> gy = g3;
+        if (model == 2) {
+            gy.g[0] = Ab + Bb; gy.g[1] = Hb; gy.g[2] = Ib;
+        } else {
+            gy.g[0] = Ab; gy.g[1] = Bb; gy.g[2] = Cb;
+        }
+        double yy[3];
+        gy.solve(yy);
+        for (int k = 0; k < 3; ++k) y[k] = yy[k];
+    } else {
+        Gram<1> gy = g1;
+        gy.g[0] = Ab + Bb;
+        double yy[1];
+        gy.solve(yy);
+        y[0] = yy[0];
+    }
+    // adjoint of one row (r0..r4 | b) of the model: rb[0..4], bb
+    auto row_adj = [&](const double (&r)[5], double b, double (&rb)[5], double &bb) {
+        for (int k = 0; k < 5; ++k) rb[k] = 0.0;
+        bb = 0.0;
+        if (model == 1) {
+            double ax5 = 0, ay = 0;
+            for (int k = 0; k < 5; ++k) { ax5 += r[k] * x[k]; ay += r[k] * y[k]; }
+            const double res = b - ax5;
+            bb = ay;
+            for (int k = 0; k < 5; ++k) rb[k] = res * y[k] - ay * x[k];
+        } else if (model == 2) {
+            const double a3[3] = {r[0] + r[1], r[3], r[4]};
+            double ax3 = 0, ay = 0;
+            for (int k = 0; k < 3; ++k) { ax3 += a3[k] * x[k]; ay += a3[k] * y[k]; }
+            const double res = b - ax3;
+            bb = ay;
+            const double a0b = res * y[0] - ay * x[0];
+            rb[0] = a0b;
+            rb[1] = a0b;
+            rb[3] = res * y[1] - ay * x[1];
+            rb[4] = res * y[2] - ay * x[2];
+        } else {
+            const double e0 = r[0] - r[3] * (2.0 * huc), e1 = r[1] - r[4] * (2.0 * hvc);
+            const double e2 = r[2] - r[3] * hvc - r[4] * huc;
+            const double be = b - r[3] * hu - r[4] * hv;
+            double eb0, eb1, eb2, beb;
+            if (model == 3) {
+                const double e[3] = {e0, e1, e2};
+                double ex = 0, ey = 0;
+                for (int k = 0; k < 3; ++k) { ex += e[k] * x[k]; ey += e[k] * y[k]; }
+                const double res = be - ex;
+                beb = ey;
+                eb0 = res * y[0] - ey * x[0];
+                eb1 = res * y[1] - ey * x[1];
+                eb2 = res * y[2] - ey * x[2];
+            } else {
+                const double e = e0 + e1;
+                const double res = be - e * x[0];
+                beb = e * y[0];
+                eb0 = eb1 = res * y[0] - e * y[0] * x[0];
+                eb2 = 0.0;
+            }
+            rb[0] = eb0;
+            rb[1] = eb1;
+            rb[2] = eb2;
+            rb[3] = -2.0 * huc * eb0 - hvc * eb2 - hu * beb;
+            rb[4] = -2.0 * hvc * eb1 - huc * eb2 - hv * beb;
+            bb = beb;
+            hucb += -2.0 * r[3] * eb0 - r[4] * eb2;
+            hvcb += -2.0 * r[4] * eb1 - r[3] * eb2;
+            hub += -r[3] * beb;
+            hvb += -r[4] * beb;
+        }
+    };
+    double pcb[3] = {0, 0, 0}, ncb[3] = {0, 0, 0}, tub[3] = {0, 0, 0}, tvb[3] = {0, 0, 0};
+    // ---- data rows (same order as the forward)
+    for (int c = -1; c <= 1; ++c)
+        for (int b = -1; b <= 1; ++b)
+            for (int a = -1; a <= 1; ++a) {
+                if (a == 0 && b == 0 && c == 0) continue;
+                if (!(V.flag(a, b, c) & FL_IF)) continue;
+                double nj[3];
+                V.normal(a, b, c, nj);
+                if (nj[0] == 0.0 && nj[1] == 0.0 && nj[2] == 0.0) continue;
+                const double aj = V.plic(a, b, c);
+                const double r[3] = {a + aj * nj[0] - pc[0], b + aj * nj[1] - pc[1], c + aj * nj[2] - pc[2]};
+                const double u = dot(r, tu), v = dot(r, tv), w = dot(r, nc);
+                const double row[5] = {u * u, v * v, u * v, u, v};
+                double rb5[5], bb;
+                row_adj(row, w, rb5, bb);
+                const double ub = 2.0 * u * rb5[0] + v * rb5[2] + rb5[3];
+                const double vb = 2.0 * v * rb5[1] + u * rb5[2] + rb5[4];
+                double rr[3];
+                for (int k = 0; k < 3; ++k) {
+                    rr[k] = ub * tu[k] + vb * tv[k] + bb * nc[k];
+                    tub[k] += ub * r[k];
+                    tvb[k] += vb * r[k];
+                    ncb[k] += bb * r[k];
+                    pcb[k] -= rr[k];
+                }
+                double *cs = cb + 4 * slot27(a, b, c);
+                cs[0] += aj * rr[0];
+                cs[1] += aj * rr[1];
+                cs[2] += aj * rr[2];
+                cs[3] += dot(nj, rr);
+            }
+    // ---- contact rows of the other contact-line cells
+    if (has_obst) {
+        for (int c = -1; c <= 1; ++c)
+            for (int b = -1; b <= 1; ++b)
+                for (int a = -1; a <= 1; ++a) {
+                    if (a == 0 && b == 0 && c == 0) continue;
+                    const uint8_t fj = V.flag(a, b, c);
+                    if (!((fj & FL_IF) && (fj & FL_NEAR_OBST))) continue;
+                    double uc, vc, ru, rv;
+                    if (!contact_condition(V, a, b, c, pc, nc, tu, tv, prm, uc, vc, ru, rv)) continue;
+                    const double row1[5] = {2.0 * uc, 0.0, vc, 1.0, 0.0};
+                    const double row2[5] = {0.0, 2.0 * vc, uc, 0.0, 1.0};
+                    double p5[5], q5[5], pb, qb;
+                    row_adj(row1, ru, p5, pb);
+                    row_adj(row2, rv, q5, qb);
+                    const double ucb = 2.0 * p5[0] + q5[2];
+                    const double vcb = p5[2] + 2.0 * q5[1];
+                    contact_condition_adj(V, a, b, c, pc, nc, tu, tv, prm, ucb, vcb, pb, qb, pcb, ncb, tub, tvb, cb, thb);
+                }
+    }
+    // ---- hard constraint of the centre
+    if (hard) contact_condition_adj(V, 0, 0, 0, pc, nc, tu, tv, prm, hucb, hvcb, hub, hvb, pcb, ncb, tub, tvb, cb, thb);
+    // ---- frame: t_v = n x t_u, t_u = w/|w|, w = e_ax - n_ax n; p_c = a_c n
+    ncb[0] += tu[1] * tvb[2] - tu[2] * tvb[1];
+    ncb[1] += tu[2] * tvb[0] - tu[0] * tvb[2];
+    ncb[2] += tu[0] * tvb[1] - tu[1] * tvb[0];
+    tub[0] += tvb[1] * nc[2] - tvb[2] * nc[1];
+    tub[1] += tvb[2] * nc[0] - tvb[0] * nc[2];
+    tub[2] += tvb[0] * nc[1] - tvb[1] * nc[0];
+    const double tt = dot(tub, tu);
+    double wb[3];
+    for (int k = 0; k < 3; ++k) wb[k] = (tub[k] - tt * tu[k]) / ltu;
+    const double wn = dot(wb, nc);
+    for (int k = 0; k < 3; ++k) ncb[k] += -nc[ax] * wb[k];
+    ncb[ax] += -wn;
+    const double acb = dot(pcb, nc);
+    for (int k = 0; k < 3; ++k) ncb[k] += ac * pcb[k];
+    double *c0 = cb + 4 * slot27(0, 0, 0);
+    c0[0] += ncb[0];
+    c0[1] += ncb[1];
+    c0[2] += ncb[2];
+    c0[3] += acb;
+}
+
+// Per interface cell: partials of K w.r.t. the normals and PLIC offsets of
+// its block, scaled by dL/dK, into contrib; dL/dtheta into tacc.
+template <class P>
+__global__ __launch_bounds__(256) void k_adj_lsqr_cell(const Fields<P> F, const Adj A, const Params prm)
+{
+    const int n = F.sc->icount;
+    for (int k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256) {
+        const int i = F.ilist[k];
+        double *cb = A.contrib + (size_t)CONTRIB * k;
+        for (int s = 0; s < CONTRIB; ++s) cb[s] = 0.0;
+        const double kb = A.kbar[i];
+        if (kb == 0.0) continue;
+        const int yz = i / F.nx, x = i - yz * F.nx, z = yz / F.ny, y = yz - z * F.ny;
+        const LsqrView<P> V{F, x, y, z};
+        double thb = 0.0;
+        lsqr_curvature_adj(V, prm, kb, cb, thb);
+        A.tacc[i] += thb;
+    }
+}
+
+// Per interface cell j: gather dL/dn_j, dL/da_j over the blocks containing
+// j, pass dL/da_j through the PLIC offset (into phib and dL/dn_j) and dL/dn_j
+// through n = g/|g| into gb.
+template <class P>
+__global__ __launch_bounds__(256) void k_adj_lsqr_plic(const Fields<P> F, const Adj A)
+{
+    const int n = F.sc->icount;
+    const size_t N = F.N;
+    for (int k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256) {
+        const int j = F.ilist[k];
+        const Nbr nb(j, F.nx, F.ny, F.nz);
+        double nbar[3] = {0, 0, 0}, abar = 0;
+        for (int c = -1; c <= 1; ++c)
+            for (int b = -1; b <= 1; ++b)
+                for (int a = -1; a <= 1; ++a) {
+                    const int i = nb.at(-a, -b, -c);  // j = i + (a, b, c)
+                    if (!(F.flags[i] & FL_IF)) continue;
+                    const double *cs = A.contrib + (size_t)CONTRIB * A.pos[i] + 4 * slot27(a, b, c);
+                    nbar[0] += cs[0];
+                    nbar[1] += cs[1];
+                    nbar[2] += cs[2];
+                    abar += cs[3];
+                }
+        const double nj[3] = {double(F.nrm[j]), double(F.nrm[N + j]), double(F.nrm[2 * N + j])};
+        double o[3] = {0, 0, 0};
+        if (nj[0] != 0.0 || nj[1] != 0.0 || nj[2] != 0.0) {
+            double dphi, dn[3];
+            plic_derivs(nj, double(F.phi[j]), double(F.plic[j]), dphi, dn);
+            A.phib[j] += abar * dphi;
+            for (int d = 0; d < 3; ++d) nbar[d] += abar * dn[d];
+            double gx, gy, gz;
+            py_grad(F.phi, nb, gx, gy, gz);
+            const double len = sqrt(gx * gx + gy * gy + gz * gz);
+            if (len > 1e-12) {
+                const double u[3] = {gx / len, gy / len, gz / len};
+                const double d = dot(nbar, u);
+                for (int e = 0; e < 3; ++e) o[e] = (nbar[e] - d * u[e]) / len;
+            }
+        }
+        A.gb[j] = o[0];
+        A.gb[N + j] = o[1];
+        A.gb[2 * N + j] = o[2];
+    }
+}
+
+// phib += -div_PY(gb) at interface cells; the value at obstacle-list cells
+// goes to their phib scratch for the reflection.
+template <class P>
+__global__ __launch_bounds__(256) void k_adj_lsqr_phib(const Fields<P> F, const Adj A)
+{
+    const int n = F.sc->icount, no = F.sc->ocount;
+    for (int k = blockIdx.x * 256 + threadIdx.x; k < n + no; k += gridDim.x * 256) {
+        const int i = k < n ? F.ilist[k] : F.olist[k - n];
+        const Nbr nb(i, F.nx, F.ny, F.nz);
+        const double v = py_div_t(A.gb, F.N, nb);
+        if (k < n) A.phib[i] += v;
+        else A.phib[i] = v;
+    }
+}
+
+// ------------------------------------------------------ reductions
+// Fixed-order sum of n values: per-block partial sums over a fixed
+// partition, then one block adds the partials (same scheme as the mass).
+__global__ __launch_bounds__(256) void k_adj_sum_partial(const double *v, int n, double *part, int nblocks)
+{
+    __shared__ double s[256];
+    const int chunk = (n + nblocks - 1) / nblocks;
+    const int b0 = blockIdx.x * chunk, b1 = min(n, b0 + chunk);
+    double acc = 0.0;
+    for (int i = b0 + threadIdx.x; i < b1; i += 256) acc += v[i];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
+__global__ __launch_bounds__(1024) void k_adj_sum_final(const double *part, int nblocks, double *out)
+{
+    __shared__ double s[1024];
+    s[threadIdx.x] = (int)threadIdx.x < nblocks ? part[threadIdx.x] : 0.0;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if (threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = s[0];
+}
+
+}  // namespace fslbm

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "fslbm.h"
+#include "fslbm_adjoint.hpp"
 #include "fslbm_convert.hpp"
 #include "fslbm_device.hpp"
 #include "fslbm_geometry.hpp"
@@ -108,6 +109,26 @@ bool shape_ok(int nx, int ny, int nz)
 
 struct fslbm_lattice;
 
+// A recorded frozen-topology window: checkpoints of the state every K steps
+// (and at the end) in a caller-owned device workspace, plus the adjoint
+// fields and a ring of K-1 states recomputed per segment in the reverse
+// sweep.
+struct AdjWindow {
+    int recorded = 0;
+    long long T = 0;
+    int K = 0;
+    int icount = 0, ocount = 0;
+    long long t_end = 0;     // steps taken at the end of the window
+    unsigned long long epoch = 0;  // state epoch at the end of the window
+    char *ws = nullptr;
+    size_t bytes = 0;
+    std::vector<long long> ck;  // checkpoint times 0, K, 2K, ..., T
+    size_t f_bytes = 0, snap_bytes = 0, slot_bytes = 0;
+    size_t off_ck = 0, off_ring = 0;
+    size_t off_lam = 0, off_gin = 0, off_own = 0, off_scal = 0, off_gb = 0, off_contrib = 0, off_pos = 0,
+           off_part = 0, total = 0;
+};
+
 // A set of lattices advanced together: each kernel of the step is launched
 // once for all of them (blockIdx.y selects the lattice). Every handle also
 // owns an implicit batch holding only itself.
@@ -140,7 +161,10 @@ struct fslbm_lattice {
     int cur;  // 0: current f' in fA, 1: in fB
     long long steps;
     unsigned version;  // bumped whenever launch arguments change
+    unsigned long long epoch;  // bumped whenever the state changes other than by stepping
+    int frozen;        // 1 inside a frozen-topology window
     fslbm_batch self;
+    AdjWindow adj;
 };
 
 namespace {
@@ -164,6 +188,7 @@ Params make_params(const fslbm_lattice *h)
     p.eps_c = h->eps_c;
     p.curv = h->curv;
     p.coll = h->coll;
+    p.frozen = h->frozen;
     return p;
 }
 
@@ -551,18 +576,24 @@ int enqueue_geometry_one(fslbm_lattice *h)
     return enqueue_geometry<P>(&h->self, A, maxN);
 }
 
-inline void mark(fslbm_batch *b, int k)
-{
-    if (b->timing) (void)hipEventRecord(b->ev[(size_t)b->ev_used * TIMING_EV + k], bstream(b));
-}
-
 // Kernels of one time step of every lattice of the batch.
+// With fsrc / fdst given (a single lattice), the step reads and writes those
+// distribution buffers instead of the lattice's pair, and records no timing.
 template <class P>
-int enqueue_step_kernels(fslbm_batch *b)
+int enqueue_step_kernels(fslbm_batch *b, const void *fsrc = nullptr, void *fdst = nullptr)
 {
     int maxN;
     bool any_srt, any_trt;
-    const Batch<P> A = make_batch<P>(b, maxN, any_srt, any_trt);
+    Batch<P> A = make_batch<P>(b, maxN, any_srt, any_trt);
+    const bool over = fsrc != nullptr;
+    if (over)
+        for (int k = 0; k < MAXB; ++k) {
+            A.f[k].fsrc = (const typename P::S *)fsrc;
+            A.f[k].fdst = (typename P::S *)fdst;
+        }
+    auto mark = [&](fslbm_batch *bb, int k) {
+        if (!over && bb->timing) (void)hipEventRecord(bb->ev[(size_t)bb->ev_used * TIMING_EV + k], bstream(bb));
+    };
     const unsigned n = (unsigned)b->hs.size();
     const hipStream_t st = bstream(b);
     const dim3 cg(std::min(SC_GRID, cell_blocks(maxN)), n), lg(list_blocks(maxN), n);
@@ -806,6 +837,323 @@ int do_set_equilibrium(fslbm_lattice *h, const double *rho, const double *u3)
     return 0;
 }
 
+// ------------------------------------------- interface fill, state copies
+template <class P>
+__global__ void k_set_interface_fill(Fields<P> F, const double *fill)
+{
+    using R = typename P::R;
+    const int n = F.sc->icount;
+    for (int k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256) {
+        const int i = F.ilist[k];
+        const R phi = R(fill[i]);
+        F.phi[i] = phi;
+        F.m[i] = phi * F.rho[i];
+    }
+}
+
+template <class P>
+int do_set_interface_fill(fslbm_lattice *h, const double *fill, int is_device)
+{
+    const Fields<P> F = make_fields<P>(h);
+    const int N = h->N;
+    const double *src = fill;
+    if (!is_device) {
+        double *staging = (double *)(h->ws + h->L.staging);
+        HIP_OK(hipMemcpyAsync(staging, fill, sizeof(double) * N, hipMemcpyHostToDevice, h->stream));
+        src = staging;
+    }
+    k_set_interface_fill<P><<<list_blocks(N), 256, 0, h->stream>>>(F, src);
+    HIP_OK(hipGetLastError());
+    int maxN;
+    bool s_, t_;
+    const Batch<P> A = make_batch<P>(&h->self, maxN, s_, t_);
+    k_obstacle_fill<P><<<dim3(list_blocks(N), 1), 256, 0, h->stream>>>(A, 0);
+    HIP_OK(hipGetLastError());
+    const int rc = enqueue_geometry<P>(&h->self, A, maxN);
+    if (rc) return rc;
+    if (!is_device) HIP_OK(hipStreamSynchronize(h->stream));
+    return 0;
+}
+
+// Parts of the workspace that make up the state (offset, bytes); the first
+// entry is the current distribution buffer.
+std::vector<std::pair<size_t, size_t>> state_regions(const fslbm_lattice *h)
+{
+    const Layout &L = h->L;
+    const size_t N = h->N, fb = fbytes(h->prec), rb = rbytes(h->prec);
+    return {{h->cur == 0 ? L.fA : L.fB, 19 * N * fb},
+            {L.flags, N},
+            {L.mark, 4 * N},
+            {L.m, N * rb},
+            {L.rho, N * rb},
+            {L.phi, N * rb},
+            {L.K, N * rb},
+            {L.nrm, 3 * N * rb},
+            {L.plic, N * rb},
+            {L.ilist, 4 * N},
+            {L.olist, 4 * N},
+            {L.sc, sizeof(DevScalars)}};
+}
+
+struct StateHeader {
+    uint64_t magic;
+    int32_t nx, ny, nz, prec, curv, pad;
+    int64_t steps;
+};
+constexpr uint64_t STATE_MAGIC = 0x31564d42534c5346ull;
+
+size_t state_bytes(const fslbm_lattice *h)
+{
+    size_t b = 256;
+    for (auto &r : state_regions(h)) b += align256(r.second);
+    return b;
+}
+
+// ------------------------------------------------ frozen-topology window
+size_t adj_layout(AdjWindow &w, const fslbm_lattice *h)
+{
+    const size_t N = h->N;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    w.off_lam = take(19 * N * 8);
+    w.off_gin = take(19 * N * 8);
+    w.off_own = take(19 * N * 8);
+    w.off_scal = take(8 * N * 8);  // mbar phib rhob kbar sacc tacc ms msb
+    w.off_gb = take(3 * N * 8);
+    w.off_contrib = take((size_t)CONTRIB * std::max(1, w.icount) * 8);
+    w.off_pos = take(4 * N);
+    w.off_part = take(8 * (MASS_BLOCKS + 4));
+    w.f_bytes = align256(19 * N * fbytes(h->prec));
+    w.snap_bytes = align256(((size_t)SNAP * w.icount + w.ocount) * rbytes(h->prec));
+    w.slot_bytes = w.f_bytes + w.snap_bytes;
+    w.ck.clear();
+    for (long long t = 0; t < w.T; t += w.K) w.ck.push_back(t);
+    w.ck.push_back(w.T);
+    w.off_ck = take(w.ck.size() * w.slot_bytes);
+    const long long ring = std::max(0LL, std::min<long long>(w.K, w.T) - 1);
+    w.off_ring = take((size_t)ring * w.slot_bytes);
+    w.total = off;
+    return off;
+}
+
+Adj adj_fields(const AdjWindow &w, const fslbm_lattice *h)
+{
+    const size_t N = h->N;
+    char *b = w.ws;
+    Adj A;
+    A.lam = (double *)(b + w.off_lam);
+    A.gin = (double *)(b + w.off_gin);
+    A.own = (double *)(b + w.off_own);
+    double *s = (double *)(b + w.off_scal);
+    A.mbar = s;
+    A.phib = s + N;
+    A.rhob = s + 2 * N;
+    A.kbar = s + 3 * N;
+    A.sacc = s + 4 * N;
+    A.tacc = s + 5 * N;
+    A.ms = s + 6 * N;
+    A.msb = s + 7 * N;
+    A.gb = (double *)(b + w.off_gb);
+    A.contrib = (double *)(b + w.off_contrib);
+    A.pos = (int *)(b + w.off_pos);
+    return A;
+}
+
+int read_counts(fslbm_lattice *h, int &icount, int &ocount)
+{
+    const DevScalars *sc = (const DevScalars *)(h->ws + h->L.sc);
+    int v[2] = {0, 0};
+    HIP_OK(hipMemcpyAsync(v, &sc->icount, 2 * sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    HIP_OK(hipStreamSynchronize(h->stream));
+    icount = v[0];
+    ocount = v[1];
+    return 0;
+}
+
+// Slot (distributions, snapshot) of the state at time t of the segment
+// [t0, t1] with checkpoint index s at t0.
+struct Slot {
+    char *f;
+    char *snap;
+};
+inline Slot ck_slot(const AdjWindow &w, size_t s)
+{
+    char *b = w.ws + w.off_ck + s * w.slot_bytes;
+    return {b, b + w.f_bytes};
+}
+inline Slot seg_slot(const AdjWindow &w, size_t s, long long t)
+{
+    const long long t0 = w.ck[s], t1 = w.ck[s + 1];
+    if (t == t0) return ck_slot(w, s);
+    if (t == t1) return ck_slot(w, s + 1);
+    char *b = w.ws + w.off_ring + (size_t)(t - t0 - 1) * w.slot_bytes;
+    return {b, b + w.f_bytes};
+}
+
+template <class P>
+int save_slot(fslbm_lattice *h, const Slot &sl, bool with_f)
+{
+    const Fields<P> F = make_fields<P>(h);
+    if (with_f)
+        HIP_OK(hipMemcpyAsync(sl.f, F.fsrc, 19 * (size_t)h->N * fbytes(h->prec), hipMemcpyDeviceToDevice, h->stream));
+    k_snap<P><<<list_blocks(h->N), 256, 0, h->stream>>>(F, (typename P::R *)sl.snap, 1);
+    HIP_OK(hipGetLastError());
+    return 0;
+}
+
+template <class P>
+int load_snap(fslbm_lattice *h, const char *snap)
+{
+    const Fields<P> F = make_fields<P>(h);
+    k_snap<P><<<list_blocks(h->N), 256, 0, h->stream>>>(F, (typename P::R *)snap, 0);
+    HIP_OK(hipGetLastError());
+    return 0;
+}
+
+template <class P>
+int do_adj_forward(fslbm_lattice *h, long long T, int K, void *ws, size_t bytes)
+{
+    AdjWindow &w = h->adj;
+    w.recorded = 0;
+    int rc = read_counts(h, w.icount, w.ocount);
+    if (rc) return rc;
+    w.T = T;
+    w.K = K;
+    adj_layout(w, h);
+    if (bytes < w.total) return fail(FSLBM_E_SHAPE, "adjoint workspace has %zu bytes, %zu needed", bytes, w.total);
+    w.ws = (char *)ws;
+    w.bytes = bytes;
+    h->frozen = 1;
+    h->version += 1;
+    rc = save_slot<P>(h, ck_slot(w, 0), true);
+    size_t next = 1;
+    for (long long t = 1; t <= T && !rc; ++t) {
+        rc = batch_step_once<P>(&h->self);
+        if (!rc && t == w.ck[next]) rc = save_slot<P>(h, ck_slot(w, next++), true);
+    }
+    h->frozen = 0;
+    h->version += 1;
+    if (rc) return rc;
+    w.t_end = h->steps;
+    w.epoch = h->epoch;
+    w.recorded = 1;
+    return 0;
+}
+
+template <class P>
+int enqueue_geometry_adjoint(fslbm_lattice *h, const Fields<P> &F, const Adj &A, const Params &prm)
+{
+    const hipStream_t st = h->stream;
+    const int N = h->N;
+    const int cg = std::min(4096, cell_blocks(N)), lg = list_blocks(N);
+    if (h->curv == FSLBM_CURV_FD) {
+        k_adj_fd_mol<P><<<cg, 256, 0, st>>>(F, A);
+        k_adj_fd_nbar<P><<<cg, 256, 0, st>>>(F, A);
+        k_adj_fd_msb<P><<<cg, 256, 0, st>>>(F, A);
+        k_adj_fd_phib<P><<<cg, 256, 0, st>>>(F, A);
+    } else {
+        k_adj_lsqr_cell<P><<<lg, 256, 0, st>>>(F, A, prm);
+        k_adj_lsqr_plic<P><<<lg, 256, 0, st>>>(F, A);
+        k_adj_lsqr_phib<P><<<lg, 256, 0, st>>>(F, A);
+    }
+    k_adj_reflect<P><<<lg, 256, 0, st>>>(F, A);
+    HIP_OK(hipGetLastError());
+    return 0;
+}
+
+template <class P>
+int do_adj_backward(fslbm_lattice *h, const double *dphi, int in_dev, double *dsig, double *dth, double *dfill0,
+                    int out_dev)
+{
+    AdjWindow &w = h->adj;
+    const hipStream_t st = h->stream;
+    const int N = h->N;
+    const int cg = std::min(4096, cell_blocks(N)), lg = list_blocks(N);
+    const Adj A = adj_fields(w, h);
+    // adjoint state at T: lam = 0, mbar = 0, phib = dL/dphi_T
+    k_adj_zero<<<4096, 256, 0, st>>>(A.lam, 19 * (size_t)N);
+    k_adj_zero<<<4096, 256, 0, st>>>((double *)(w.ws + w.off_scal), 8 * (size_t)N);
+    k_adj_zero<<<4096, 256, 0, st>>>(A.gb, 3 * (size_t)N);
+    HIP_OK(hipGetLastError());
+    double *staging = (double *)(h->ws + h->L.staging);
+    const double *src = dphi;
+    if (!in_dev) {
+        HIP_OK(hipMemcpyAsync(staging, dphi, sizeof(double) * N, hipMemcpyHostToDevice, st));
+        src = staging;
+    }
+    {
+        const Fields<P> F = make_fields<P>(h);
+        k_adj_begin<P><<<lg, 256, 0, st>>>(F, A, src);
+        HIP_OK(hipGetLastError());
+    }
+    h->frozen = 1;
+    const Params prm = make_params(h);
+    const size_t nseg = w.ck.size() - 1;
+    int rc = 0;
+    for (size_t s = nseg; s-- > 0 && !rc;) {
+        const long long t0 = w.ck[s], t1 = w.ck[s + 1];
+        // recompute the states t0+1 .. t1-1 of the segment into the ring
+        rc = load_snap<P>(h, ck_slot(w, s).snap);
+        for (long long t = t0; t + 1 < t1 && !rc; ++t) {
+            const Slot a = seg_slot(w, s, t), b = seg_slot(w, s, t + 1);
+            rc = enqueue_step_kernels<P>(&h->self, a.f, b.f);
+            if (!rc) {
+                const Fields<P> F = make_fields<P>(h);
+                k_snap<P><<<lg, 256, 0, st>>>(F, (typename P::R *)b.snap, 1);
+                HIP_OK(hipGetLastError());
+            }
+        }
+        // reverse steps t1-1 .. t0
+        for (long long t = t1 - 1; t >= t0 && !rc; --t) {
+            const Slot cur = seg_slot(w, s, t), nxt = seg_slot(w, s, t + 1);
+            Fields<P> F = make_fields<P>(h);
+            k_adj_prepass<P><<<lg, 256, 0, st>>>(F, A, (const typename P::R *)nxt.snap);
+            k_snap<P><<<lg, 256, 0, st>>>(F, (typename P::R *)cur.snap, 0);
+            F.fsrc = (const typename P::S *)cur.f;
+            if (h->coll == FSLBM_SRT) k_adj_stream<P, 0><<<cg, 256, 0, st>>>(F, A, prm);
+            else k_adj_stream<P, 1><<<cg, 256, 0, st>>>(F, A, prm);
+            k_adj_gather<P><<<cg, 256, 0, st>>>(F, A);
+            HIP_OK(hipGetLastError());
+            rc = enqueue_geometry_adjoint<P>(h, F, A, prm);
+        }
+    }
+    h->frozen = 0;
+    if (rc) return rc;
+    // dL/dphi_0, dL/dsigma, dL/dtheta
+    double *out = out_dev ? dfill0 : staging;
+    k_adj_zero<<<cg, 256, 0, st>>>(out, (size_t)N);
+    {
+        const Fields<P> F = make_fields<P>(h);
+        k_adj_finish<P><<<lg, 256, 0, st>>>(F, A, (const typename P::R *)ck_slot(w, 0).snap, out);
+    }
+    double *part = (double *)(w.ws + w.off_part);
+    double *res = part + MASS_BLOCKS;
+    k_adj_sum_partial<<<MASS_BLOCKS, 256, 0, st>>>(A.sacc, N, part, MASS_BLOCKS);
+    k_adj_sum_final<<<1, 1024, 0, st>>>(part, MASS_BLOCKS, res);
+    k_adj_sum_partial<<<MASS_BLOCKS, 256, 0, st>>>(A.tacc, N, part, MASS_BLOCKS);
+    k_adj_sum_final<<<1, 1024, 0, st>>>(part, MASS_BLOCKS, res + 1);
+    HIP_OK(hipGetLastError());
+    if (!out_dev) HIP_OK(hipMemcpyAsync(dfill0, staging, sizeof(double) * N, hipMemcpyDeviceToHost, st));
+    double g[2] = {0, 0};
+    HIP_OK(hipMemcpyAsync(g, res, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    // back to the state at the end of the window
+    {
+        const Slot last = ck_slot(w, nseg);
+        rc = load_snap<P>(h, last.snap);
+        if (rc) return rc;
+        const Fields<P> F = make_fields<P>(h);
+        HIP_OK(hipMemcpyAsync((void *)F.fsrc, last.f, 19 * (size_t)N * fbytes(h->prec), hipMemcpyDeviceToDevice, st));
+    }
+    HIP_OK(hipStreamSynchronize(st));
+    if (dsig) *dsig = g[0];
+    if (dth) *dth = g[1];
+    return 0;
+}
+
 // Dispatch on the precision of the handle.
 template <template <class> class Op, class... A>
 int dispatch(fslbm_lattice *h, A... a)
@@ -838,6 +1186,15 @@ template <class P> struct OpRead { static int run(fslbm_lattice *h, int w, doubl
 template <class P> struct OpMass { static int run(fslbm_lattice *h, double *t) { return do_mass<P>(h, t); } };
 template <class P> struct OpCheck { static int run(fslbm_lattice *h) { return do_check<P>(h); } };
 template <class P> struct OpEq { static int run(fslbm_lattice *h, const double *r, const double *u) { return do_set_equilibrium<P>(h, r, u); } };
+
+template <class P> struct OpFill { static int run(fslbm_lattice *h, const double *f, int d) { return do_set_interface_fill<P>(h, f, d); } };
+template <class P> struct OpAdjF { static int run(fslbm_lattice *h, long long T, int K, void *w, size_t b) { return do_adj_forward<P>(h, T, K, w, b); } };
+template <class P> struct OpAdjB {
+    static int run(fslbm_lattice *h, const double *g, int gd, double *ds, double *dt, double *d0, int od)
+    {
+        return do_adj_backward<P>(h, g, gd, ds, dt, d0, od);
+    }
+};
 
 }  // namespace
 
@@ -887,6 +1244,8 @@ int fslbm_create(int nx, int ny, int nz, int precision, int curv_model, const do
     h->cur = 0;
     h->steps = 0;
     h->version = 0;
+    h->epoch = 0;
+    h->frozen = 0;
     batch_init(&h->self);
     h->self.hs.push_back(h);
     h->self.prec = precision;
@@ -908,6 +1267,7 @@ int fslbm_set_params(fslbm_t h, double sigma, double tau, double theta_rad, doub
     if (!(rho_gas > 0.0) || !std::isfinite(rho_gas)) return fail(FSLBM_E_ARG, "rho_gas must be > 0");
     h->sigma = sigma; h->tau = tau; h->theta = theta_rad; h->rho_gas = rho_gas;
     h->version += 1;
+    h->epoch += 1;
     return dispatch<OpGeom>(h);
 }
 
@@ -919,16 +1279,19 @@ int fslbm_set_option(fslbm_t h, int key, double value)
         if (!(value >= 0.0 && value < 0.5)) return fail(FSLBM_E_ARG, "eps_c must lie in [0, 0.5)");
         h->eps_c = value;
         h->version += 1;
+        h->epoch += 1;
         return 0;
     case FSLBM_OPT_COLLISION:
         if (value != FSLBM_SRT && value != FSLBM_TRT) return fail(FSLBM_E_ARG, "collision must be SRT or TRT");
         h->coll = (int)value;
         h->version += 1;
+        h->epoch += 1;
         return 0;
     case FSLBM_OPT_TRT_MAGIC:
         if (!(value > 0.0) || !std::isfinite(value)) return fail(FSLBM_E_ARG, "TRT Lambda must be > 0");
         h->trt_magic = value;
         h->version += 1;
+        h->epoch += 1;
         return 0;
     case FSLBM_OPT_TIMING:
     case FSLBM_OPT_GRAPH:
@@ -951,6 +1314,7 @@ int fslbm_set_equilibrium(fslbm_t h, const double *rho, const double *u3)
 {
     if (!h) return fail(FSLBM_E_STATE, "null handle");
     if (!rho || !u3) return fail(FSLBM_E_ARG, "rho and u must be given");
+    h->epoch += 1;
     return dispatch<OpEq>(h, rho, u3);
 }
 
@@ -1119,6 +1483,98 @@ int fslbm_reset_timing(fslbm_t h)
 {
     if (!h) return fail(FSLBM_E_STATE, "null handle");
     return fslbm_batch_reset_timing(&h->self);
+}
+
+int fslbm_set_interface_fill(fslbm_t h, const double *fill, int in_is_device)
+{
+    if (!h) return fail(FSLBM_E_STATE, "null handle");
+    if (!fill) return fail(FSLBM_E_ARG, "fill is NULL");
+    h->epoch += 1;
+    return dispatch<OpFill>(h, fill, in_is_device);
+}
+
+int fslbm_state_bytes(fslbm_t h, size_t *bytes)
+{
+    if (!h) return fail(FSLBM_E_STATE, "null handle");
+    if (!bytes) return fail(FSLBM_E_ARG, "bytes is NULL");
+    *bytes = state_bytes(h);
+    return 0;
+}
+
+int fslbm_save_state(fslbm_t h, void *dst, size_t bytes)
+{
+    if (!h) return fail(FSLBM_E_STATE, "null handle");
+    if (!dst) return fail(FSLBM_E_ARG, "dst is NULL");
+    if (bytes < state_bytes(h)) return fail(FSLBM_E_SHAPE, "state buffer has %zu bytes, %zu needed", bytes, state_bytes(h));
+    StateHeader hd{STATE_MAGIC, h->nx, h->ny, h->nz, h->prec, h->curv, 0, h->steps};
+    char *d = (char *)dst;
+    HIP_OK(hipMemcpyAsync(d, &hd, sizeof hd, hipMemcpyHostToDevice, h->stream));
+    size_t off = 256;
+    for (auto &r : state_regions(h)) {
+        HIP_OK(hipMemcpyAsync(d + off, h->ws + r.first, r.second, hipMemcpyDeviceToDevice, h->stream));
+        off += align256(r.second);
+    }
+    HIP_OK(hipStreamSynchronize(h->stream));
+    return 0;
+}
+
+int fslbm_load_state(fslbm_t h, const void *src, size_t bytes)
+{
+    if (!h) return fail(FSLBM_E_STATE, "null handle");
+    if (!src) return fail(FSLBM_E_ARG, "src is NULL");
+    if (bytes < state_bytes(h)) return fail(FSLBM_E_SHAPE, "state buffer has %zu bytes, %zu needed", bytes, state_bytes(h));
+    StateHeader hd;
+    const char *s = (const char *)src;
+    HIP_OK(hipMemcpyAsync(&hd, s, sizeof hd, hipMemcpyDeviceToHost, h->stream));
+    HIP_OK(hipStreamSynchronize(h->stream));
+    if (hd.magic != STATE_MAGIC || hd.nx != h->nx || hd.ny != h->ny || hd.nz != h->nz || hd.prec != h->prec ||
+        hd.curv != h->curv)
+        return fail(FSLBM_E_ARG, "state buffer does not belong to a lattice of this shape, precision and model");
+    size_t off = 256;
+    for (auto &r : state_regions(h)) {
+        HIP_OK(hipMemcpyAsync(h->ws + r.first, s + off, r.second, hipMemcpyDeviceToDevice, h->stream));
+        off += align256(r.second);
+    }
+    h->steps = hd.steps;
+    h->epoch += 1;
+    h->version += 1;
+    HIP_OK(hipStreamSynchronize(h->stream));
+    return 0;
+}
+
+int fslbm_adjoint_required_bytes(fslbm_t h, int64_t nsteps, int K, size_t *bytes)
+{
+    if (!h) return fail(FSLBM_E_STATE, "null handle");
+    if (!bytes) return fail(FSLBM_E_ARG, "bytes is NULL");
+    if (nsteps < 1 || K < 1) return fail(FSLBM_E_ARG, "nsteps and K must be >= 1");
+    AdjWindow w;
+    const int rc = read_counts(h, w.icount, w.ocount);
+    if (rc) return rc;
+    w.T = nsteps;
+    w.K = K;
+    *bytes = adj_layout(w, h);
+    return 0;
+}
+
+int fslbm_adjoint_forward(fslbm_t h, int64_t nsteps, int K, void *workspace, size_t workspace_bytes)
+{
+    if (!h) return fail(FSLBM_E_STATE, "null handle");
+    if (nsteps < 1 || K < 1) return fail(FSLBM_E_ARG, "nsteps and K must be >= 1");
+    if (!workspace) return fail(FSLBM_E_ARG, "workspace is NULL");
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return fail(FSLBM_E_ARG, "workspace not 256-byte aligned");
+    return dispatch<OpAdjF>(h, (long long)nsteps, K, workspace, workspace_bytes);
+}
+
+int fslbm_adjoint_backward(fslbm_t h, const double *dL_dfill_T, int in_is_device, double *dL_dsigma,
+                           double *dL_dtheta, double *dL_dfill_0, int out_is_device)
+{
+    if (!h) return fail(FSLBM_E_STATE, "null handle");
+    if (!dL_dfill_T || !dL_dfill_0) return fail(FSLBM_E_ARG, "dL_dfill_T and dL_dfill_0 must be given");
+    const AdjWindow &w = h->adj;
+    if (!w.recorded) return fail(FSLBM_E_STATE, "no window recorded (call fslbm_adjoint_forward first)");
+    if (h->steps != w.t_end || h->epoch != w.epoch)
+        return fail(FSLBM_E_STATE, "the lattice changed since the window was recorded");
+    return dispatch<OpAdjB>(h, dL_dfill_T, in_is_device, dL_dsigma, dL_dtheta, dL_dfill_0, out_is_device);
 }
 
 void fslbm_destroy(fslbm_t h)

@@ -166,6 +166,7 @@ struct Params {
     double eps_c;
     int curv;          // 0 FD, 1 LSQR
     int coll;          // 0 SRT, 1 TRT
+    int frozen;        // 1: cell types stay fixed (no fill / empty conversion)
 };
 
 template <class P> struct Fields {

@@ -21,7 +21,7 @@
 namespace fslbm {
 
 // Parker-Youngs weights (1, 2, 1) across the two transverse directions.
-__device__ inline double pyw(int d) { return d == 0 ? 2.0 : 1.0; }
+__host__ __device__ inline double pyw(int d) { return d == 0 ? 2.0 : 1.0; }
 
 // Unscaled PY gradient of a scalar field g (type R) at cell i.
 template <class R>
@@ -127,7 +127,7 @@ __host__ __device__ inline G plic_offset(G nx, G ny, G nz, G phi)
 template <int C> struct Gram {
     double G[C][C];
     double g[C];
-    __device__ inline Gram()
+    __host__ __device__ inline Gram()
     {
 #pragma unroll
         for (int r = 0; r < C; ++r) {
@@ -136,7 +136,7 @@ template <int C> struct Gram {
             for (int c = 0; c < C; ++c) G[r][c] = 0.0;
         }
     }
-    __device__ inline void add(const double (&a)[C], double b)
+    __host__ __device__ inline void add(const double (&a)[C], double b)
     {
 #pragma unroll
         for (int r = 0; r < C; ++r) {
@@ -147,7 +147,7 @@ template <int C> struct Gram {
     }
     // Cholesky solve; fails when a pivot falls below 1e-12 * trace(G)
     // (rank deficiency of the row matrix).
-    __device__ inline bool solve(double (&x)[C]) const
+    __host__ __device__ inline bool solve(double (&x)[C]) const
     {
         double tr = 0.0;
 #pragma unroll
@@ -189,7 +189,7 @@ template <int C> struct Gram {
 };
 
 
-__device__ inline double dot(const double (&a)[3], const double (&b)[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+__host__ __device__ inline double dot(const double (&a)[3], const double (&b)[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
 
 constexpr int TILE = 8;
 
@@ -257,7 +257,7 @@ __device__ inline void py_grad_lds(const A &g, int x, int y, int z, G &gx, G &gy
 
 // Unit normal (zero when the gradient vanishes) from a PY gradient.
 template <class G>
-__device__ inline void unit_normal(G gx, G gy, G gz, G (&n)[3])
+__host__ __device__ inline void unit_normal(G gx, G gy, G gz, G (&n)[3])
 {
     const G len = sqrt(gx * gx + gy * gy + gz * gz);
     const bool ok = len > G(1e-12);
@@ -401,7 +401,7 @@ template <class P> struct LsqrView {
 // wall is half-way between nodes). Returns false when the condition is
 // skipped.
 template <class View>
-__device__ inline bool contact_condition(const View &V, int dx, int dy, int dz, const double (&pc)[3],
+__host__ __device__ inline bool contact_condition(const View &V, int dx, int dy, int dz, const double (&pc)[3],
                                          const double (&nc)[3], const double (&tu)[3], const double (&tv)[3],
                                          const Params &prm, double &uc, double &vc, double &ru, double &rv)
 {
@@ -442,7 +442,7 @@ __device__ inline bool contact_condition(const View &V, int dx, int dy, int dz, 
 
 // K = 2 kappa of the least-squares quadric at the centre of view V.
 template <class View>
-__device__ inline double lsqr_curvature(const View &V, const Params &prm)
+__host__ __device__ inline double lsqr_curvature(const View &V, const Params &prm)
 {
     double nc[3];
     V.normal(0, 0, 0, nc);

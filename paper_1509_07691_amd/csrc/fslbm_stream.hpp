@@ -10,7 +10,8 @@
 //   - eq. advection1/2 in mass form at interface cells (the incoming
 //     distribution f'_qbar(x + c_q) is exactly the pulled value),
 //   - moments and the SRT or TRT collision (eq. lbe2),
-//   - fill / empty classification of interface cells.
+//   - fill / empty classification of interface cells (counted only when
+//     cell types are not frozen, so that no conversion follows).
 #pragma once
 
 #include "fslbm_device.hpp"
@@ -215,7 +216,7 @@ __device__ inline void boundary_cell(const Fields<P> &F, const Params &prm, int 
         F.m[i] = R(mn);
         F.rho[i] = R(r);
         F.conv[i] = st;
-        if (st != CV_NONE) atomicAdd(&F.sc->nconv, 1);
+        if (st != CV_NONE && !prm.frozen) atomicAdd(&F.sc->nconv, 1);
     }
     collide<T, COLL>(fin, prm);
     store_all<P>(F, i, fin);

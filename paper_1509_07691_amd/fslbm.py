@@ -77,6 +77,13 @@ def load_library(path: str = LIB_PATH):
         "fslbm_batch_set_option": [vp, i32, ctypes.c_double],
         "fslbm_batch_read_timing": [vp, dp, ctypes.POINTER(i64)],
         "fslbm_batch_reset_timing": [vp],
+        "fslbm_set_interface_fill": [vp, vp, i32],
+        "fslbm_state_bytes": [vp, ctypes.POINTER(ctypes.c_size_t)],
+        "fslbm_save_state": [vp, vp, ctypes.c_size_t],
+        "fslbm_load_state": [vp, vp, ctypes.c_size_t],
+        "fslbm_adjoint_required_bytes": [vp, i64, i32, ctypes.POINTER(ctypes.c_size_t)],
+        "fslbm_adjoint_forward": [vp, i64, i32, vp, ctypes.c_size_t],
+        "fslbm_adjoint_backward": [vp, vp, i32, dp, dp, vp, i32],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -228,6 +235,53 @@ def fslbm_destroy(h):
     load_library().fslbm_destroy(h)
 
 
+def _ptr_dev(a):
+    """(pointer, is_device) of a contiguous float64 numpy array or torch tensor."""
+    if isinstance(a, np.ndarray):
+        return ctypes.c_void_p(a.ctypes.data), 0
+    return ctypes.c_void_p(a.data_ptr()), 1 if a.is_cuda else 0
+
+
+def fslbm_set_interface_fill(h, fill):
+    ptr, dev = _ptr_dev(fill)
+    _check(load_library().fslbm_set_interface_fill(h, ptr, dev))
+
+
+def fslbm_state_bytes(h):
+    out = ctypes.c_size_t(0)
+    _check(load_library().fslbm_state_bytes(h, ctypes.byref(out)))
+    return out.value
+
+
+def fslbm_save_state(h, dst_ptr, nbytes):
+    _check(load_library().fslbm_save_state(h, ctypes.c_void_p(dst_ptr), nbytes))
+
+
+def fslbm_load_state(h, src_ptr, nbytes):
+    _check(load_library().fslbm_load_state(h, ctypes.c_void_p(src_ptr), nbytes))
+
+
+def fslbm_adjoint_required_bytes(h, nsteps, K):
+    out = ctypes.c_size_t(0)
+    _check(load_library().fslbm_adjoint_required_bytes(h, int(nsteps), int(K), ctypes.byref(out)))
+    return out.value
+
+
+def fslbm_adjoint_forward(h, nsteps, K, workspace_ptr, workspace_bytes):
+    _check(load_library().fslbm_adjoint_forward(h, int(nsteps), int(K), ctypes.c_void_p(workspace_ptr),
+                                                workspace_bytes))
+
+
+def fslbm_adjoint_backward(h, dfill_T, dfill_0):
+    """dfill_T, dfill_0: float64 arrays of n entries (numpy or torch, host or
+    device, each on its own). Returns (dL/dsigma, dL/dtheta)."""
+    gp, gd = _ptr_dev(dfill_T)
+    op, od = _ptr_dev(dfill_0)
+    ds, dt = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    _check(load_library().fslbm_adjoint_backward(h, gp, gd, ctypes.byref(ds), ctypes.byref(dt), op, od))
+    return ds.value, dt.value
+
+
 def fslbm_batch_create(handles):
     arr = (ctypes.c_void_p * len(handles))(*[h.value if isinstance(h, ctypes.c_void_p) else h for h in handles])
     b = ctypes.c_void_p()
@@ -292,7 +346,9 @@ class Lattice:
         if trt_magic is not None:
             fslbm_set_option(self._h, FSLBM_OPT_TRT_MAGIC, trt_magic)
         fslbm_set_option(self._h, FSLBM_OPT_COLLISION, FSLBM_TRT if collision == "trt" else FSLBM_SRT)
+        self.sigma, self.tau, self.theta, self.rho_gas = sigma, tau, theta, rho_gas
         fslbm_set_params(self._h, sigma, tau, theta, rho_gas)
+        self._adj_ws = None
 
     @property
     def handle(self):
@@ -309,8 +365,12 @@ class Lattice:
         except Exception:
             pass
 
-    def set_params(self, sigma, tau, theta, rho_gas):
-        fslbm_set_params(self._h, sigma, tau, theta, rho_gas)
+    def set_params(self, sigma=None, tau=None, theta=None, rho_gas=None):
+        self.sigma = self.sigma if sigma is None else float(sigma)
+        self.tau = self.tau if tau is None else float(tau)
+        self.theta = self.theta if theta is None else float(theta)
+        self.rho_gas = self.rho_gas if rho_gas is None else float(rho_gas)
+        fslbm_set_params(self._h, self.sigma, self.tau, self.theta, self.rho_gas)
 
     def set_equilibrium(self, rho, u):
         rho = np.broadcast_to(np.asarray(rho, dtype=np.float64), self.shape)
@@ -379,6 +439,60 @@ class Lattice:
 
     def reset_timing(self):
         fslbm_reset_timing(self._h)
+
+    # ------------------------------------------ checkpoints, adjoint window
+    def set_interface_fill(self, fill):
+        """phi (and m = phi rho) of the interface cells from an (nz, ny, nx)
+        float64 numpy array or torch tensor."""
+        if isinstance(fill, np.ndarray):
+            fill = np.ascontiguousarray(fill, dtype=np.float64)
+        else:
+            fill = fill.detach().to(dtype=self._torch.float64).contiguous()
+        size = fill.size if isinstance(fill, np.ndarray) else fill.numel()
+        if size != self.n:
+            raise ValueError("fill has the wrong size")
+        fslbm_set_interface_fill(self._h, fill)
+
+    @property
+    def _torch(self):
+        import torch
+        return torch
+
+    def save_state(self):
+        """The whole state as a device uint8 tensor (for load_state)."""
+        nbytes = fslbm_state_bytes(self._h)
+        buf = self._torch.empty(nbytes, dtype=self._torch.uint8, device=self.device)
+        fslbm_save_state(self._h, buf.data_ptr(), nbytes)
+        return buf
+
+    def load_state(self, buf):
+        fslbm_load_state(self._h, buf.data_ptr(), buf.numel())
+
+    def adjoint_forward(self, nsteps, K):
+        """Advance nsteps steps with frozen cell types, checkpointing every K
+        steps into a device workspace held by this object."""
+        nbytes = fslbm_adjoint_required_bytes(self._h, nsteps, K)
+        if self._adj_ws is None or self._adj_ws.numel() < nbytes:
+            self._adj_ws = None
+            self._adj_ws = self._torch.empty(nbytes, dtype=self._torch.uint8, device=self.device)
+        fslbm_adjoint_forward(self._h, nsteps, K, self._adj_ws.data_ptr(), self._adj_ws.numel())
+
+    def adjoint_backward(self, dfill_T):
+        """(dL/dphi_0 as a device float64 tensor (nz, ny, nx), dL/dsigma,
+        dL/dtheta) for dL/dphi_T given as an array of the lattice shape."""
+        torch = self._torch
+        g = torch.as_tensor(dfill_T, dtype=torch.float64, device=self.device).contiguous()
+        if g.numel() != self.n:
+            raise ValueError("dL/dphi_T has the wrong size")
+        out = torch.zeros(self.shape, dtype=torch.float64, device=self.device)
+        ds, dt = fslbm_adjoint_backward(self._h, g, out)
+        return out, ds, dt
+
+    def fill_tensor(self):
+        """phi as a device float64 tensor (nz, ny, nx)."""
+        out = self._torch.empty(self.shape, dtype=self._torch.float64, device=self.device)
+        fslbm_read_fill(self._h, out, device=True)
+        return out
 
 
 class Batch:

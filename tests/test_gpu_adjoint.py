@@ -1,0 +1,201 @@
+"""Discrete adjoint of the frozen-topology window (HIP path, through the C
+ABI) against central differences of the FP64 oracle run with frozen cell
+types.
+
+Loss L = sum over non-obstacle cells of (phi_T - phi*)^2 (the fill level of
+liquid and gas cells is constant, so only interface cells contribute), with
+phi* = phi_T of the oracle at other parameters plus 0.01 v, v a seeded
+field on the interface cells. Gradients: dL/dsigma (relative step 1e-4),
+dL/dtheta (step 1e-4 rad, LSQR with walls), dL/dphi_0 at 12 seeded
+interface cells (step 1e-5) and the directional derivative <dL/dphi_0, v>
+(step 1e-5), each a central difference Richardson-extrapolated over the
+step and twice the step. The window has T = 24 steps with checkpoints
+every K = 5, so the reverse sweep crosses five segments, the last one short.
+Bars: FP64 1e-6 relative (the extrapolated differences are accurate to
+about 1e-8 at these steps); FP32 storage 2e-3 relative.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1509_07691_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+T_STEPS, K_CK = 24, 5
+MODELS = {"fd": O.CURV_FD, "lsqr": O.CURV_LSQR}
+
+
+@pytest.fixture(scope="module")
+def Lattice():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1509_07691_amd.fslbm import Lattice as L
+
+    return L
+
+
+def case(name):
+    """(fill, obstacle, model, params, initial velocity or None)."""
+    if name == "fd_droplet_moving":
+        fill, obst = I.droplet(20, 5.0, noise=1e-6, seed=3)
+        u = np.zeros((3,) + fill.shape)
+        u[0], u[1] = 0.02, -0.01
+        return fill, obst, "fd", dict(sigma=5e-3, tau=0.8, theta=math.pi / 2), u
+    if name == "fd_droplet_trt":
+        fill, obst = I.droplet(20, 5.0, noise=1e-6, seed=4)
+        return fill, obst, "fd", dict(sigma=5e-3, tau=0.7, theta=math.pi / 2, collision="trt"), None
+    if name == "lsqr_sessile":
+        fill, obst = I.sessile_droplet(22, 22, 12, 6.0, noise=1e-6, seed=5)
+        return fill, obst, "lsqr", dict(sigma=5e-3, tau=0.8, theta=math.radians(70.0)), None
+    if name == "lsqr_droplet":
+        fill, obst = I.droplet(20, 5.0, noise=1e-6, seed=6)
+        return fill, obst, "lsqr", dict(sigma=5e-3, tau=0.8, theta=math.pi / 2), None
+    raise KeyError(name)
+
+
+def oracle_phi(fill, obst, model, prm, u, steps=T_STEPS):
+    kw = dict(prm)
+    coll = kw.pop("collision", "srt")
+    o = O.Oracle(fill, obst, curv_model=MODELS[model], collision=O.TRT if coll == "trt" else O.SRT,
+                 frozen=True, **kw)
+    if u is not None:
+        o.set_equilibrium(np.ones(fill.shape), u)
+    o.step(steps)
+    return o.fill(), o.flags()
+
+
+def loss(phi, target, keep):
+    return float((((phi - target) * keep) ** 2).sum())
+
+
+def setup(name):
+    fill, obst, model, prm, u = case(name)
+    phi_ref, flags = oracle_phi(fill, obst, model, prm, u)
+    ifc0 = O.Oracle(fill, obst, frozen=True).flags() == O.INTERFACE
+    keep = (flags != O.OBSTACLE).astype(float)
+    rng = np.random.default_rng(11)
+    v = rng.uniform(-1.0, 1.0, fill.shape) * ifc0
+    # target: the window at other parameters, moved by 0.01 v
+    prm_t = dict(prm)
+    prm_t["sigma"] = 0.8 * prm["sigma"]
+    prm_t["theta"] = prm["theta"] + 0.1 if model == "lsqr" else prm["theta"]
+    target = oracle_phi(fill, obst, model, prm_t, u)[0] + 0.01 * v
+    # interface cells strictly inside (0, 1), where a small change of phi_0
+    # keeps the cell types
+    inner = ifc0 & (fill > 1e-3) & (fill < 1 - 1e-3)
+    return fill, obst, model, prm, u, target, keep, v * inner, inner
+
+
+def richardson(f, x, e):
+    """Central difference of f at x with step e, Richardson-extrapolated
+    over e and 2e, so the error is O(e^4): nearly empty or full interface
+    cells have a small PLIC section and large higher derivatives."""
+    d1 = (f(x + e) - f(x - e)) / (2 * e)
+    d2 = (f(x + 2 * e) - f(x - 2 * e)) / (4 * e)
+    return (4 * d1 - d2) / 3
+
+
+def fd_gradients(fill, obst, model, prm, u, target, keep, v, inner, with_theta):
+    def L(fill_=fill, **over):
+        p = dict(prm)
+        p.update(over)
+        return loss(oracle_phi(fill_, obst, model, p, u)[0], target, keep)
+
+    s = prm["sigma"]
+    g = {"sigma": richardson(lambda x: L(sigma=x), s, 1e-4 * s)}
+    if with_theta:
+        g["theta"] = richardson(lambda x: L(theta=x), prm["theta"], 1e-4)
+    e = 1e-5
+    cells = np.flatnonzero(inner)
+    pick = np.random.default_rng(7).choice(cells, size=min(12, cells.size), replace=False)
+    gc = []
+    for c in pick:
+        def Lc(x, c=c):
+            f = fill.copy()
+            f.flat[c] = x
+            return L(fill_=f)
+        gc.append(richardson(Lc, fill.flat[c], e))
+    g["cells"] = (pick, np.array(gc))
+    g["dir"] = richardson(lambda x: L(fill_=fill + x * v), 0.0, e)
+    return g
+
+
+def gpu_gradients(Lattice, fill, obst, model, prm, u, target, keep, precision):
+    kw = dict(prm)
+    g = Lattice(fill, obst, precision=precision, curv_model=model, **kw)
+    if u is not None:
+        g.set_equilibrium(1.0, u)
+    g.adjoint_forward(T_STEPS, K_CK)
+    phi = g.fill()
+    dphi = 2.0 * (phi - target) * keep
+    d0, ds, dt = g.adjoint_backward(dphi)
+    return phi, d0.cpu().numpy(), ds, dt, g
+
+
+def check(name, Lattice, precision, tol):
+    fill, obst, model, prm, u, target, keep, v, inner = setup(name)
+    with_theta = model == "lsqr" and obst is not None and obst.any()
+    fd = fd_gradients(fill, obst, model, prm, u, target, keep, v, inner, with_theta)
+    phi, d0, ds, dt, g = gpu_gradients(Lattice, fill, obst, model, prm, u, target, keep, precision)
+    phi_o, _ = oracle_phi(fill, obst, model, prm, u)
+    fluid = keep > 0
+    assert np.abs(phi - phi_o)[fluid].max() < (1e-12 if precision == "f64" else 1e-4)
+    errs = {"sigma": abs(ds - fd["sigma"]) / abs(fd["sigma"])}
+    if with_theta:
+        errs["theta"] = abs(dt - fd["theta"]) / abs(fd["theta"])
+    pick, gc = fd["cells"]
+    scale = np.abs(gc).max()
+    errs["cells"] = np.abs(d0.flat[pick] - gc).max() / scale
+    errs["dir"] = abs((d0 * v).sum() - fd["dir"]) / abs(fd["dir"])
+    print(name, precision, {k: f"{e:.2e}" for k, e in errs.items()},
+          f"dL/dsigma={ds:.6e} fd={fd['sigma']:.6e}", f"dL/dtheta={dt:.6e}")
+    for k, e in errs.items():
+        assert e < tol, f"{name} {precision}: {k} relative error {e:.3e}"
+    # the lattice is back at the end of the window: a second backward call
+    # gives the same gradients
+    phi2 = g.fill()
+    d0b, ds2, dt2 = g.adjoint_backward(2.0 * (phi2 - target) * keep)
+    assert ds2 == ds and dt2 == dt and np.array_equal(d0b.cpu().numpy(), d0)
+
+
+@pytest.mark.parametrize("name", ["fd_droplet_moving", "fd_droplet_trt", "lsqr_droplet", "lsqr_sessile"])
+def test_adjoint_fp64_vs_oracle_fd(Lattice, name):
+    check(name, Lattice, "f64", 1e-6)
+
+
+@pytest.mark.parametrize("name", ["fd_droplet_moving", "lsqr_sessile"])
+def test_adjoint_fp32_vs_oracle_fd(Lattice, name):
+    check(name, Lattice, "f32", 2e-3)
+
+
+def test_autograd_function_matches_abi(Lattice):
+    import torch
+
+    from paper_1509_07691_amd.adjoint import frozen_window
+
+    fill, obst, model, prm, u, target, keep, v, inner = setup("lsqr_sessile")
+    lat = Lattice(fill, obst, precision="f64", curv_model=model, **prm)
+    start = lat.save_state()
+    dev = lat.device
+    fill0 = torch.tensor(fill, dtype=torch.float64, device=dev, requires_grad=True)
+    sigma = torch.tensor(prm["sigma"], dtype=torch.float64, device=dev, requires_grad=True)
+    theta = torch.tensor(prm["theta"], dtype=torch.float64, device=dev, requires_grad=True)
+    tgt = torch.tensor(target, device=dev)
+    kp = torch.tensor(keep, device=dev)
+    grads = []
+    for _ in range(2):
+        phi = frozen_window(lat, fill0, sigma, theta, T_STEPS, K_CK, start_state=start)
+        L = (((phi - tgt) * kp) ** 2).sum()
+        grads.append([t.detach().cpu().numpy() for t in torch.autograd.grad(L, (fill0, sigma, theta))])
+    for a, b in zip(*grads):
+        assert np.array_equal(a, b)
+    # the same window through the C ABI directly
+    _, d0, ds, dt, _ = gpu_gradients(Lattice, fill, obst, model, prm, u, target, keep, "f64")
+    np.testing.assert_allclose(grads[0][0], d0, rtol=1e-12, atol=1e-14)
+    assert abs(float(grads[0][1]) - ds) <= 1e-12 * abs(ds)
+    assert abs(float(grads[0][2]) - dt) <= 1e-12 * abs(dt)
