@@ -173,6 +173,8 @@ def adjoint_cost(dev, stream, steps, K, precision):
     phi = lat.fill_tensor()
     dphi = 2.0 * (phi - target) * keep
     loss = float((((phi - target) * keep) ** 2).sum())
+    ifc = torch.tensor(lat.flags() == 2, device=dev)
+    phi_range = [float(phi[ifc].min()), float(phi[ifc].max())]
     t_bwd, (d0, ds, dt) = timed(lambda: lat.adjoint_backward(dphi))
     ws_gb = lat._adj_ws.numel() / 1e9
     lat.close()
@@ -188,6 +190,7 @@ def adjoint_cost(dev, stream, steps, K, precision):
             "cost_ratio": round((t_fwd + t_bwd) / t_plain, 3),
             "loss": loss, "dL_dsigma": ds, "dL_dtheta": dt,
             "dL_dphi0_norm": float(torch.linalg.vector_norm(d0)),
+            "interface_fill_range_T": phi_range,
             "workspace_GB": round(ws_gb, 2)}
 
 
