@@ -55,7 +55,7 @@ size_t fbytes(int prec)
 size_t rbytes(int prec) { return prec == P_F64 ? 8 : 4; }
 
 struct Layout {
-    size_t fA, fB, flags, conv, mark, m, rho, phi, K, nrm, plic, share, phis, nmol, ilist, olist, newlist, ilist_tmp,
+    size_t fA, fB, flags, conv, mark, m, rho, phi, K, nrm, plic, share, phis, nmol, ilist, olist, wlist, newlist, ilist_tmp,
         staging,
         counts, part, sc, total;
 };
@@ -88,6 +88,7 @@ Layout make_layout(long long N, int prec)
     L.nmol = take(3 * N * rb);
     L.ilist = take(4 * N);
     L.olist = take(4 * N);
+    L.wlist = take(4 * N);
     L.newlist = take(4 * N);
     L.ilist_tmp = take(4 * N);
     L.staging = take(8 * N);
@@ -216,6 +217,7 @@ Fields<P> make_fields(const fslbm_lattice *h)
     F.nmol = (R *)(w + L.nmol);
     F.ilist = (int32_t *)(w + L.ilist);
     F.olist = (int32_t *)(w + L.olist);
+    F.wlist = (int32_t *)(w + L.wlist);
     F.newlist = (int32_t *)(w + L.newlist);
     F.ilist_tmp = (int32_t *)(w + L.ilist_tmp);
     F.counts = (int *)(w + L.counts);
@@ -250,7 +252,7 @@ __global__ void k_init_scalars(DevScalars *sc)
     sc->reservoir = 0.0;
     sc->mass = 0.0;
     sc->bad = 0;
-    sc->pad = 0;
+    sc->wcount = 0;
     for (int k = 0; k < 6; ++k) sc->bbox[k] = 0;
     sc->fbox[0] = sc->fbox[1] = sc->fbox[2] = 1 << 30;
     sc->fbox[3] = sc->fbox[4] = sc->fbox[5] = -1;
@@ -602,8 +604,8 @@ int enqueue_step_kernels(fslbm_batch *b, const void *fsrc = nullptr, void *fdst 
         if (any_srt) k_stream_collide<P, 0, 1><<<cg, 256, 0, st>>>(A);
         if (any_trt) k_stream_collide<P, 1, 1><<<cg, 256, 0, st>>>(A);
         mark(b, 1);
-        if (any_srt) k_stream_collide<P, 0, 2><<<cg, 256, 0, st>>>(A);
-        if (any_trt) k_stream_collide<P, 1, 2><<<cg, 256, 0, st>>>(A);
+        if (any_srt) k_stream_collide_list<P, 0><<<cg, 256, 0, st>>>(A);
+        if (any_trt) k_stream_collide_list<P, 1><<<cg, 256, 0, st>>>(A);
     } else {
         if (any_srt) k_stream_collide<P, 0, 0><<<cg, 256, 0, st>>>(A);
         if (any_trt) k_stream_collide<P, 1, 0><<<cg, 256, 0, st>>>(A);
@@ -767,6 +769,7 @@ int enqueue_init(fslbm_lattice *h, const double *fill, const uint8_t *obstacle)
     bool s_, t_;
     const Batch<P> A = make_batch<P>(&h->self, maxN, s_, t_);
     int rc = enqueue_compaction<P>(&h->self, A, maxN, 1, 1);
+    if (!rc) rc = enqueue_compaction<P>(&h->self, A, maxN, 2, 1);
     if (rc) return rc;
     k_fill_bytes<<<std::min(4096, cell_blocks(N)), 256, 0, h->stream>>>(F.conv, N, 0);
     rc = enqueue_compaction<P>(&h->self, A, maxN, 0, 1);
@@ -892,6 +895,7 @@ std::vector<std::pair<size_t, size_t>> state_regions(const fslbm_lattice *h)
             {L.plic, N * rb},
             {L.ilist, 4 * N},
             {L.olist, 4 * N},
+            {L.wlist, 4 * N},
             {L.sc, sizeof(DevScalars)}};
 }
 

@@ -426,18 +426,20 @@ __device__ inline int cells_matching(const uint8_t *flags, const CellRange &r, i
     return c;
 }
 
-// which = 0: interface cells (flags & FL_IF) into ilist / icount, run only
-// in steps with conversions unless forced; which = 1: the static list of
-// obstacle cells next to non-obstacle cells (conv == 1) into olist / ocount.
+// which = 0: interface cells (flags & FL_IF) into ilist / icount (at
+// creation); which = 1: the static list of obstacle cells next to
+// non-obstacle cells (conv bit 0) into olist / ocount; which = 2: the static
+// list of non-obstacle cells next to obstacle cells (conv bit 1) into
+// wlist / wcount.
 template <class P>
 __device__ inline void compact_source(const Fields<P> &F, int which, const uint8_t *&src, uint8_t &want,
                                       int32_t *&list, int *&count, CellRange &range)
 {
     range = which == 0 ? CellRange::from(F.sc->fbox) : CellRange::whole(F.nx, F.ny, F.nz);
     src = which == 0 ? F.flags : F.conv;
-    want = which == 0 ? FL_IF : 1;
-    list = which == 0 ? F.ilist : F.olist;
-    count = which == 0 ? &F.sc->icount : &F.sc->ocount;
+    want = which == 0 ? FL_IF : (which == 1 ? 1 : 2);
+    list = which == 0 ? F.ilist : (which == 1 ? F.olist : F.wlist);
+    count = which == 0 ? &F.sc->icount : (which == 1 ? &F.sc->ocount : &F.sc->wcount);
 }
 
 // A fixed grid of CMP_GRID blocks per lattice; block b owns a contiguous run
@@ -540,21 +542,19 @@ __global__ __launch_bounds__(256) void k_compact_write(const Batch<P> B, int whi
     }
 }
 
-// Static list of obstacle cells with at least one non-obstacle D3Q19
-// neighbour: mark them with FL_NEAR_OBST in a scratch byte array.
+// Static wall lists: bit 0 marks obstacle cells with a non-obstacle D3Q19
+// neighbour, bit 1 non-obstacle cells with an obstacle D3Q19 neighbour.
 __global__ __launch_bounds__(256) void k_mark_wall_cells(const uint8_t *flags, uint8_t *out, int nx, int ny,
                                                          int nz, int N)
 {
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= N) return;
-    uint8_t v = 0;
-    if (flags[i] & FL_OBST) {
-        const Nbr nb(i, nx, ny, nz);
+    const bool obst = flags[i] & FL_OBST;
+    const Nbr nb(i, nx, ny, nz);
+    bool other = false;
 #pragma unroll
-        for (int q = 1; q < NQ; ++q)
-            if (!(flags[nb.at(dir_x(q), dir_y(q), dir_z(q))] & FL_OBST)) v = 1;
-    }
-    out[i] = v;
+    for (int q = 1; q < NQ; ++q) other |= ((flags[nb.at(dir_x(q), dir_y(q), dir_z(q))] & FL_OBST) != 0) != obst;
+    out[i] = other ? (obst ? 1 : 2) : 0;
 }
 
 // ------------------------------------------------ obstacle fill (Sec. II.A)

@@ -121,7 +121,7 @@ struct DevScalars {
     double reservoir;   // excess mass that found no receiving cell
     double mass;        // result of the last mass reduction
     int bad;            // numeric check result
-    int pad;
+    int wcount;         // number of cells in wlist (static)
     int bbox[6];        // min x, y, z and max x, y, z of the interface cells
     int fbox[6];        // the same for the fluid cells; never shrinks
 };
@@ -179,6 +179,7 @@ template <class P> struct Fields {
     uint32_t *mark;
     R *m, *rho, *phi, *K, *nrm, *plic, *share, *phis, *nmol;
     int32_t *ilist, *olist;
+    int32_t *wlist;    // static: non-obstacle cells with an obstacle D3Q19 neighbour
     int32_t *newlist, *ilist_tmp;  // new interface cells; scratch for the list rebuild
     int *counts;       // per-block counts of the list compaction
     DevScalars *sc;

@@ -401,7 +401,7 @@ template <class P> struct LsqrView {
 // wall is half-way between nodes). Returns false when the condition is
 // skipped.
 template <class View>
-__host__ __device__ inline bool contact_condition(const View &V, int dx, int dy, int dz, const double (&pc)[3],
+__host__ __device__ __forceinline__ bool contact_condition(const View &V, int dx, int dy, int dz, const double (&pc)[3],
                                          const double (&nc)[3], const double (&tu)[3], const double (&tv)[3],
                                          const Params &prm, double &uc, double &vc, double &ru, double &rv)
 {
@@ -440,119 +440,226 @@ __host__ __device__ inline bool contact_condition(const View &V, int dx, int dy,
     return true;
 }
 
-// K = 2 kappa of the least-squares quadric at the centre of view V.
+// Frame, PLIC point and wetting state of the centre of view V (Sec. II.C):
+// t_u from the axis with the smallest |n_k| (first on ties), t_v = n x t_u,
+// and, when the centre is a contact-line cell, its hard constraint
+// H = hu - 2 huc A - hvc C, I = hv - 2 hvc B - huc C.
+struct LsqrFrame {
+    double nc[3], tu[3], tv[3], pc[3];
+    bool ok, has_obst, hard;
+    double huc, hvc, hu, hv;
+};
+
 template <class View>
-__host__ __device__ inline double lsqr_curvature(const View &V, const Params &prm)
+__host__ __device__ __forceinline__ LsqrFrame lsqr_frame(const View &V, const Params &prm)
 {
-    double nc[3];
-    V.normal(0, 0, 0, nc);
-    if (nc[0] == 0.0 && nc[1] == 0.0 && nc[2] == 0.0) return 0.0;
-    // frame: t_u from the axis with the smallest |n_k| (first on ties)
+    LsqrFrame f;
+    V.normal(0, 0, 0, f.nc);
+    f.ok = !(f.nc[0] == 0.0 && f.nc[1] == 0.0 && f.nc[2] == 0.0);
+    f.has_obst = f.hard = false;
+    f.huc = f.hvc = f.hu = f.hv = 0.0;
+    if (!f.ok) return f;
+    const double(&nc)[3] = f.nc;
     int ax = 0;
     if (fabs(nc[1]) < fabs(nc[ax])) ax = 1;
     if (fabs(nc[2]) < fabs(nc[ax])) ax = 2;
-    double tu[3] = {-nc[ax] * nc[0], -nc[ax] * nc[1], -nc[ax] * nc[2]};
-    tu[ax] += 1.0;
+    // selects rather than a run-time index keep the frame in registers
+    const double nax = ax == 0 ? nc[0] : (ax == 1 ? nc[1] : nc[2]);
+    double tu[3] = {-nax * nc[0] + (ax == 0 ? 1.0 : 0.0), -nax * nc[1] + (ax == 1 ? 1.0 : 0.0),
+                    -nax * nc[2] + (ax == 2 ? 1.0 : 0.0)};
     const double ltu = sqrt(dot(tu, tu));
-    tu[0] /= ltu; tu[1] /= ltu; tu[2] /= ltu;
-    const double tv[3] = {nc[1] * tu[2] - nc[2] * tu[1], nc[2] * tu[0] - nc[0] * tu[2], nc[0] * tu[1] - nc[1] * tu[0]};
+    f.tu[0] = tu[0] / ltu; f.tu[1] = tu[1] / ltu; f.tu[2] = tu[2] / ltu;
+    f.tv[0] = nc[1] * f.tu[2] - nc[2] * f.tu[1];
+    f.tv[1] = nc[2] * f.tu[0] - nc[0] * f.tu[2];
+    f.tv[2] = nc[0] * f.tu[1] - nc[1] * f.tu[0];
     const double ac = V.plic(0, 0, 0);
-    const double pc[3] = {ac * nc[0], ac * nc[1], ac * nc[2]};
-    bool has_obst = false;
+    f.pc[0] = ac * nc[0]; f.pc[1] = ac * nc[1]; f.pc[2] = ac * nc[2];
 #pragma unroll
     for (int c = -1; c <= 1; ++c)
 #pragma unroll
         for (int b = -1; b <= 1; ++b)
 #pragma unroll
-            for (int a = -1; a <= 1; ++a) has_obst |= (V.flag(a, b, c) & FL_OBST) != 0;
+            for (int a = -1; a <= 1; ++a) f.has_obst |= (V.flag(a, b, c) & FL_OBST) != 0;
+    if (f.has_obst && (V.flag(0, 0, 0) & FL_NEAR_OBST))
+        f.hard = contact_condition(V, 0, 0, 0, f.pc, f.nc, f.tu, f.tv, prm, f.huc, f.hvc, f.hu, f.hv);
+    return f;
+}
 
-    // hard constraint of the centre: H = hu - 2 uc A - vc C, I = hv - 2 vc B - uc C
-    bool hard = false;
-    double huc = 0, hvc = 0, hu = 0, hv = 0;
-    if (has_obst && (V.flag(0, 0, 0) & FL_NEAR_OBST))
-        hard = contact_condition(V, 0, 0, 0, pc, nc, tu, tv, prm, huc, hvc, hu, hv);
-
-    Gram<5> g5;  // free model (A, B, C, H, I)
-    Gram<3> g3;  // free: isotropic (A, H, I); hard: (A, B, C)
-    Gram<1> g1;  // hard isotropic (A)
-    int rows = 0;
-    auto add_row = [&](double r0, double r1, double r2, double r3, double r4, double b) {
-        ++rows;
-        if (!hard) {
-            const double a5[5] = {r0, r1, r2, r3, r4};
-            g5.add(a5, b);
-            const double a3[3] = {r0 + r1, r3, r4};
-            g3.add(a3, b);
-        } else {
-            const double e0 = r0 - r3 * (2.0 * huc), e1 = r1 - r4 * (2.0 * hvc);
-            const double e2 = r2 - r3 * hvc - r4 * huc;
-            const double be = b - r3 * hu - r4 * hv;
-            const double a3[3] = {e0, e1, e2};
-            g3.add(a3, be);
-            const double a1[1] = {e0 + e1};
-            g1.add(a1, be);
+// Cholesky solve of a C x C system held as a packed lower triangle
+// (entry (r, c), c <= r, at r (r + 1) / 2 + c); fails when a pivot falls
+// below 1e-12 * trace (rank deficiency of the row matrix).
+template <int C>
+__host__ __device__ __forceinline__ bool packed_solve(const double *G, const double *g, double (&x)[C])
+{
+    double tr = 0.0;
+#pragma unroll
+    for (int r = 0; r < C; ++r) tr += G[r * (r + 1) / 2 + r];
+    if (!(tr > 0.0)) return false;
+    double L[C * (C + 1) / 2];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        double d = G[c * (c + 1) / 2 + c];
+#pragma unroll
+        for (int j = 0; j < c; ++j) d -= L[c * (c + 1) / 2 + j] * L[c * (c + 1) / 2 + j];
+        if (!(d >= 1e-12 * tr)) return false;
+        L[c * (c + 1) / 2 + c] = sqrt(d);
+#pragma unroll
+        for (int r = c + 1; r < C; ++r) {
+            double s = G[r * (r + 1) / 2 + c];
+#pragma unroll
+            for (int j = 0; j < c; ++j) s -= L[r * (r + 1) / 2 + j] * L[c * (c + 1) / 2 + j];
+            L[r * (r + 1) / 2 + c] = s / L[c * (c + 1) / 2 + c];
         }
-    };
-    // data rows: PLIC points of the other interface cells of the block
-    for (int c = -1; c <= 1; ++c)
-        for (int b = -1; b <= 1; ++b)
-            for (int a = -1; a <= 1; ++a) {
-                if (a == 0 && b == 0 && c == 0) continue;
-                if (!(V.flag(a, b, c) & FL_IF)) continue;
-                double nj[3];
-                V.normal(a, b, c, nj);
-                if (nj[0] == 0.0 && nj[1] == 0.0 && nj[2] == 0.0) continue;
-                const double aj = V.plic(a, b, c);
-                const double r[3] = {a + aj * nj[0] - pc[0], b + aj * nj[1] - pc[1], c + aj * nj[2] - pc[2]};
-                const double u = dot(r, tu), v = dot(r, tv), w = dot(r, nc);
-                add_row(u * u, v * v, u * v, u, v, w);
-            }
-    // wetting rows of the other contact-line cells
-    if (has_obst) {
-        for (int c = -1; c <= 1; ++c)
-            for (int b = -1; b <= 1; ++b)
-                for (int a = -1; a <= 1; ++a) {
-                    if (a == 0 && b == 0 && c == 0) continue;
-                    const uint8_t fj = V.flag(a, b, c);
-                    if (!((fj & FL_IF) && (fj & FL_NEAR_OBST))) continue;
-                    double uc, vc, ru, rv;
-                    if (!contact_condition(V, a, b, c, pc, nc, tu, tv, prm, uc, vc, ru, rv)) continue;
-                    add_row(2.0 * uc, 0.0, vc, 1.0, 0.0, ru);
-                    add_row(0.0, 2.0 * vc, uc, 0.0, 1.0, rv);
-                }
     }
+    double y[C];
+#pragma unroll
+    for (int r = 0; r < C; ++r) {
+        double s = g[r];
+#pragma unroll
+        for (int j = 0; j < r; ++j) s -= L[r * (r + 1) / 2 + j] * y[j];
+        y[r] = s / L[r * (r + 1) / 2 + r];
+    }
+#pragma unroll
+    for (int r = C - 1; r >= 0; --r) {
+        double s = y[r];
+#pragma unroll
+        for (int j = r + 1; j < C; ++j) s -= L[j * (j + 1) / 2 + r] * x[j];
+        x[r] = s / L[r * (r + 1) / 2 + r];
+    }
+    return true;
+}
+
+// Normal equations of the fit in one packed accumulator: the free model
+// (A, B, C, H, I), or under the hard constraint the model (A, B, C) in the
+// leading 3 x 3 part. The isotropic fallbacks (A = B, C = 0) are contracted
+// from these sums when needed.
+struct LsqrSums {
+    double G[15], g[5];
+    int rows = 0;
+    __host__ __device__ inline LsqrSums()
+    {
+#pragma unroll
+        for (int k = 0; k < 15; ++k) G[k] = 0.0;
+#pragma unroll
+        for (int k = 0; k < 5; ++k) g[k] = 0.0;
+    }
+    template <int C>
+    __host__ __device__ __forceinline__ void acc(const double (&a)[C], double b)
+    {
+#pragma unroll
+        for (int r = 0; r < C; ++r) {
+            g[r] += a[r] * b;
+#pragma unroll
+            for (int c = 0; c <= r; ++c) G[r * (r + 1) / 2 + c] += a[r] * a[c];
+        }
+    }
+    __host__ __device__ __forceinline__ void add(const LsqrFrame &f, double r0, double r1, double r2, double r3, double r4,
+                                        double b)
+    {
+        ++rows;
+        // a hard-constraint row (e0, e1, e2 | be) goes in as (e0, e1, e2, 0, 0):
+        // one code path with fixed indices, the 3 x 3 system is the leading block
+        const bool h = f.hard;
+        const double e0 = r0 - r3 * (2.0 * f.huc), e1 = r1 - r4 * (2.0 * f.hvc);
+        const double e2 = r2 - r3 * f.hvc - r4 * f.huc;
+        const double be = b - r3 * f.hu - r4 * f.hv;
+        const double a5[5] = {h ? e0 : r0, h ? e1 : r1, h ? e2 : r2, h ? 0.0 : r3, h ? 0.0 : r4};
+        acc(a5, h ? be : b);
+    }
+};
+
+// Rows contributed by the block cell at offset (a, b, c): its PLIC point
+// (interface cells other than the centre) and, for contact-line cells other
+// than the centre, the two rows of the gradient condition.
+template <class View>
+__host__ __device__ __forceinline__ void lsqr_cell_rows(const View &V, const Params &prm, const LsqrFrame &f, int a, int b,
+                                               int c, LsqrSums &S)
+{
+    if (a == 0 && b == 0 && c == 0) return;
+    const uint8_t fj = V.flag(a, b, c);
+    if (!(fj & FL_IF)) return;
+    double nj[3];
+    V.normal(a, b, c, nj);
+    if (nj[0] == 0.0 && nj[1] == 0.0 && nj[2] == 0.0) return;
+    const double aj = V.plic(a, b, c);
+    const double r[3] = {a + aj * nj[0] - f.pc[0], b + aj * nj[1] - f.pc[1], c + aj * nj[2] - f.pc[2]};
+    const double u = dot(r, f.tu), v = dot(r, f.tv), w = dot(r, f.nc);
+    S.add(f, u * u, v * v, u * v, u, v, w);
+}
+
+template <class View>
+__host__ __device__ __forceinline__ void lsqr_contact_rows(const View &V, const Params &prm, const LsqrFrame &f, int a, int b,
+                                                  int c, LsqrSums &S)
+{
+    if (a == 0 && b == 0 && c == 0) return;
+    const uint8_t fj = V.flag(a, b, c);
+    if (!((fj & FL_IF) && (fj & FL_NEAR_OBST))) return;
+    double uc, vc, ru, rv;
+    if (!contact_condition(V, a, b, c, f.pc, f.nc, f.tu, f.tv, prm, uc, vc, ru, rv)) return;
+    S.add(f, 2.0 * uc, 0.0, vc, 1.0, 0.0, ru);
+    S.add(f, 0.0, 2.0 * vc, uc, 0.0, 1.0, rv);
+}
+
+// Solve the normal equations (model choice as described above) and return
+// K = 2 kappa (eq. anacurv, cross term C H I), 0 when no model is solvable.
+__host__ __device__ __forceinline__ double lsqr_solve_curvature(const LsqrFrame &f, const LsqrSums &S)
+{
+    const double *G = S.G, *g = S.g;
     double A = 0, Bq = 0, C = 0, H = 0, I = 0;
     bool ok = false;
-    if (!hard) {
+    if (!f.hard) {
         double x5[5];
-        if (rows >= 5 && g5.solve(x5)) {
+        if (S.rows >= 5 && packed_solve<5>(G, g, x5)) {
             A = x5[0]; Bq = x5[1]; C = x5[2]; H = x5[3]; I = x5[4];
             ok = true;
-        } else {
+        } else if (S.rows >= 3) {
+            // rows (u^2 + v^2, u, v): contract columns 0 and 1
+            const double G3[6] = {G[0] + 2.0 * G[1] + G[2], G[6] + G[7], G[9], G[10] + G[11], G[13], G[14]};
+            const double g3[3] = {g[0] + g[1], g[3], g[4]};
             double x3[3];
-            if (rows >= 3 && g3.solve(x3)) {
+            if (packed_solve<3>(G3, g3, x3)) {
                 A = x3[0]; Bq = x3[0]; C = 0.0; H = x3[1]; I = x3[2];
                 ok = true;
             }
         }
     } else {
         double x3[3];
-        if (rows >= 3 && g3.solve(x3)) {
+        if (S.rows >= 3 && packed_solve<3>(G, g, x3)) {
             A = x3[0]; Bq = x3[1]; C = x3[2];
             ok = true;
-        } else {
+        } else if (S.rows >= 1) {
+            const double G1[1] = {G[0] + 2.0 * G[1] + G[2]};
+            const double g1[1] = {g[0] + g[1]};
             double x1[1];
-            if (rows >= 1 && g1.solve(x1)) {
+            if (packed_solve<1>(G1, g1, x1)) {
                 A = x1[0]; Bq = x1[0]; C = 0.0;
                 ok = true;
             }
         }
-        H = hu - 2.0 * huc * A - hvc * C;
-        I = hv - 2.0 * hvc * Bq - huc * C;
+        H = f.hu - 2.0 * f.huc * A - f.hvc * C;
+        I = f.hv - 2.0 * f.hvc * Bq - f.huc * C;
     }
     if (!ok) return 0.0;
     const double gg = 1.0 + H * H + I * I;
     return 2.0 * (A * (1.0 + I * I) + Bq * (1.0 + H * H) - C * H * I) / (gg * sqrt(gg));
+}
+
+// K = 2 kappa of the least-squares quadric at the centre of view V, rows
+// accumulated in block order (data rows, then contact rows).
+template <class View>
+__host__ __device__ inline double lsqr_curvature(const View &V, const Params &prm)
+{
+    const LsqrFrame f = lsqr_frame(V, prm);
+    if (!f.ok) return 0.0;
+    LsqrSums S;
+    for (int c = -1; c <= 1; ++c)
+        for (int b = -1; b <= 1; ++b)
+            for (int a = -1; a <= 1; ++a) lsqr_cell_rows(V, prm, f, a, b, c, S);
+    if (f.has_obst)
+        for (int c = -1; c <= 1; ++c)
+            for (int b = -1; b <= 1; ++b)
+                for (int a = -1; a <= 1; ++a) lsqr_contact_rows(V, prm, f, a, b, c, S);
+    return lsqr_solve_curvature(f, S);
 }
 
 // Normals and PLIC points of the interface cells (LSQR model).

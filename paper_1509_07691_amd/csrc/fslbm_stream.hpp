@@ -222,11 +222,98 @@ __device__ inline void boundary_cell(const Fields<P> &F, const Params &prm, int 
     store_all<P>(F, i, fin);
 }
 
+// Any fluid cell, written so that the lanes of a wavefront share the pull,
+// the collision and the stores: only the boundary rules (own distributions,
+// neighbour types, reconstruction, corner rule, mass exchange) diverge.
+// Same arithmetic as liquid_cell / boundary_cell.
+template <class P, int COLL>
+__device__ inline void fluid_cell(const Fields<P> &F, const Params &prm, int i, const Nbr &nb, uint8_t fl)
+{
+    using T = typename P::T;
+    using R = typename P::R;
+    const int N = F.N;
+    int up[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) up[q] = nb.at(-dir_x(q), -dir_y(q), -dir_z(q));
+    T fin[NQ];
+    load_dirs<P>(F, up, fin);  // the pull; final wherever the upstream node is fluid
+    if (fl != FL_LIQ) {
+        const bool is_if = (fl & FL_IF) != 0;
+        int own[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) own[q] = i;
+        T fo[NQ];
+        load_dirs<P>(F, own, fo);
+        uint8_t nt[NQ];
+#pragma unroll
+        for (int q = 1; q < NQ; ++q) nt[q] = F.flags[up[q]] & FL_TYPE;
+        T phn[NQ];
+        T Kc = 0, mc = 0, phx = 0, cnx = 0, cny = 0, cnz = 0;
+        if (is_if) {
+#pragma unroll
+            for (int q = 1; q < NQ; ++q) phn[q] = T(F.phi[up[opp(q)]]);
+            Kc = T(F.K[i]);
+            mc = T(F.m[i]);
+            phx = T(F.phi[i]);
+            cnx = T(F.nrm[i]);
+            cny = T(F.nrm[(size_t)N + i]);
+            cnz = T(F.nrm[2 * (size_t)N + i]);
+        }
+        bool has_gas = false;
+        int nwx = 0, nwy = 0, nwz = 0;
+#pragma unroll
+        for (int q = 1; q < NQ; ++q) {
+            has_gas |= nt[q] == FL_GAS;
+            if (nt[q] == FL_OBST) { nwx -= dir_x(q); nwy -= dir_y(q); nwz -= dir_z(q); }
+        }
+        T rb0, ubx, uby, ubz;
+        moments(fo, rb0, ubx, uby, ubz);
+        const T ubsq = ubx * ubx + uby * uby + ubz * ubz;
+        const T rhob = T(3) * (T(prm.rho_gas) / T(3) + T(prm.sigma) * Kc);
+        const bool corner = is_if && has_gas && (nwx | nwy | nwz) != 0;
+        const int ww = nwx * nwx + nwy * nwy + nwz * nwz;
+#pragma unroll
+        for (int q = 1; q < NQ; ++q) {
+            const int o = opp(q);
+            const uint8_t t = nt[q];
+            const int cox = -dir_x(q), coy = -dir_y(q), coz = -dir_z(q);
+            const int cw = cox * nwx + coy * nwy + coz * nwz;
+            const T s = T(cox * ww - cw * nwx) * cnx + T(coy * ww - cw * nwy) * cny + T(coz * ww - cw * nwz) * cnz;
+            const bool rec = (t == FL_GAS) || (t == FL_OBST && corner && s < T(0));
+            const T vrec = feq<T>(q, rhob, ubx, uby, ubz, ubsq) + feq<T>(o, rhob, ubx, uby, ubz, ubsq) - fo[o];
+            fin[q] = (t & FL_FLUID) ? fin[q] : (rec ? vrec : fo[o]);
+        }
+        if (is_if) {
+            T dm = 0;
+#pragma unroll
+            for (int q = 1; q < NQ; ++q) {
+                const int o = opp(q);
+                const uint8_t tz = nt[o];
+                const T k = tz == FL_LIQ ? T(1) : (tz == FL_IF ? T(0.5) * (phn[q] + phx) : T(0));
+                dm += k * (fin[o] - fo[q]);
+            }
+            T r = 0;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) r += fin[q];
+            const T mn = mc + dm;
+            uint8_t st = CV_NONE;
+            if (mn > (T(1) + T(prm.eps_c)) * r) st = CV_FILL;
+            else if (mn < -T(prm.eps_c) * r) st = CV_EMPTY;
+            F.m[i] = R(mn);
+            F.rho[i] = R(r);
+            F.conv[i] = st;
+            if (st != CV_NONE && !prm.frozen) atomicAdd(&F.sc->nconv, 1);
+        }
+    }
+    collide<T, COLL>(fin, prm);
+    store_all<P>(F, i, fin);
+}
+
 // Stream-collide over the fluid bounding box. MODE 0: every fluid cell;
-// MODE 1: only liquid cells away from walls (the lean pull, few registers);
-// MODE 2: only the other fluid cells (interface cells and liquid cells with
-// wall links). Each block takes one contiguous run of the box, so the rows
-// it pulls from stay in one XCD's L2.
+// MODE 1: only liquid cells away from walls (the lean pull, few registers;
+// the other fluid cells then go through k_stream_collide_list). Each block
+// takes one contiguous run of the box, so the rows it pulls from stay in
+// one XCD's L2.
 template <class P, int COLL, int MODE>
 __global__ __launch_bounds__(256) void k_stream_collide(const Batch<P> B)
 {
@@ -247,9 +334,11 @@ __global__ __launch_bounds__(256) void k_stream_collide(const Batch<P> B)
         const uint8_t fl = F.flags[i];
         if (fl & FL_FLUID) {
             const Nbr nb(x, y, z, F.nx, F.ny, F.nz);
-            if (MODE != 2 && fl == FL_LIQ) liquid_cell<P, COLL>(F, prm, i, nb);
-            else if (MODE != 1 && (fl & FL_LIQ) && fl != FL_LIQ) boundary_cell<P, COLL, false>(F, prm, i, nb);
-            else if (MODE != 1 && (fl & FL_IF)) boundary_cell<P, COLL, true>(F, prm, i, nb);
+            if (MODE == 1) {
+                if (fl == FL_LIQ) liquid_cell<P, COLL>(F, prm, i, nb);
+            } else {
+                fluid_cell<P, COLL>(F, prm, i, nb, fl);
+            }
         }
         bx += 256;
         while (bx >= box.ex) {
@@ -259,6 +348,27 @@ __global__ __launch_bounds__(256) void k_stream_collide(const Batch<P> B)
                 ++bz;
             }
         }
+    }
+}
+
+// The fluid cells that the lean box pass (MODE 1) leaves out, one thread
+// per cell: the interface cells from the interface list, then the liquid
+// cells of the static wall list (interface cells on that list are skipped
+// there, gas cells have no update). Wavefronts hold cells of one kind, so
+// the long boundary path does not stall liquid cells.
+template <class P, int COLL>
+__global__ __launch_bounds__(256) void k_stream_collide_list(const Batch<P> B)
+{
+    const Params &prm = B.p[blockIdx.y];
+    if (prm.coll != COLL) return;
+    const Fields<P> &F = B.f[blockIdx.y];
+    const int ni = *(volatile const int *)&F.sc->icount;
+    const int n = ni + F.sc->wcount;
+    for (int k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256) {
+        const int i = k < ni ? F.ilist[k] : F.wlist[k - ni];
+        const Nbr nb(i, F.nx, F.ny, F.nz);
+        if (k < ni) boundary_cell<P, COLL, true>(F, prm, i, nb);
+        else if ((F.flags[i] & FL_TYPE) == FL_LIQ) boundary_cell<P, COLL, false>(F, prm, i, nb);
     }
 }
 
