@@ -559,11 +559,15 @@ int enqueue_geometry(const fslbm_batch *b, const Batch<P> &A, int maxN)
         any_fd |= h->curv == FSLBM_CURV_FD;
         any_lsqr |= h->curv == FSLBM_CURV_LSQR;
     }
-    if (any_fd) k_geometry_fd<P><<<tg, 256, 0, st>>>(A);
-    if (any_lsqr) {
-        const dim3 lg(list_blocks(maxN), n);
-        k_normals_plic<P><<<lg, 256, 0, st>>>(A);
-        k_curv_lsqr<P><<<lg, 256, 0, st>>>(A);
+    const dim3 cg4(std::min(GEOM_GRID, std::max(1, maxN / 256)), n);
+    if (any_fd && any_lsqr) {
+        k_geometry_mixed<P><<<tg, 256, 0, st>>>(A);
+        k_curv_lsqr4<P><<<cg4, 256, 0, st>>>(A);
+    } else if (any_fd) {
+        k_geometry_fd<P><<<tg, 256, 0, st>>>(A);
+    } else if (any_lsqr) {
+        k_normals_plic<P><<<dim3(list_blocks(maxN), n), 256, 0, st>>>(A);
+        k_curv_lsqr4<P><<<cg4, 256, 0, st>>>(A);
     }
     HIP_OK(hipGetLastError());
     return 0;
@@ -612,14 +616,12 @@ int enqueue_step_kernels(fslbm_batch *b, const void *fsrc = nullptr, void *fdst 
         mark(b, 1);
     }
     mark(b, 2);
-    k_conv_prune<P><<<lg, 256, 0, st>>>(A);
     k_conv_mark_init<P><<<lg, 256, 0, st>>>(A);
     k_conv_share<P><<<lg, 256, 0, st>>>(A);
     k_conv_gather<P><<<lg, 256, 0, st>>>(A);
     k_conv_flags<P><<<lg, 256, 0, st>>>(A);
     mark(b, 3);
     HIP_OK(hipGetLastError());
-    k_list_begin<P><<<dim3(1, n), 64, 0, st>>>(A);
     k_list_keep<P><<<lg, 256, 0, st>>>(A);
     k_list_finish<P><<<lg, 256, 0, st>>>(A);
     HIP_OK(hipGetLastError());

@@ -37,30 +37,32 @@ __device__ inline bool is_converter(const Fields<P> &F, int j)
     return (F.flags[j] & FL_IF) && F.conv[j] != CV_NONE;
 }
 
-// Rule 2: an emptying cell next to a filling cell does not empty. Readers of
-// conv only test for CV_FILL, which this kernel never writes or clears.
+// Rule 2 for cell i: an emptying cell next to a filling cell does not
+// empty. Returns the cell's status after it. Readers of other cells' status
+// only test for CV_FILL, which this never writes or clears.
 template <class P>
-__global__ __launch_bounds__(256) void k_conv_prune(const Batch<P> B)
+__device__ inline uint8_t prune_own(const Fields<P> &F, int i)
 {
-    const Fields<P> &F = B.f[blockIdx.y];
-    if (F.sc->nconv == 0) return;
-    const int n = list_count(F.sc);
-    for (int k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256) {
-        const int i = F.ilist[k];
-        if (F.conv[i] != CV_EMPTY) continue;
-        const Nbr nb(i, F.nx, F.ny, F.nz);
-        bool near_fill = false;
+    uint8_t st = F.conv[i];
+    if (st != CV_EMPTY) return st;
+    const Nbr nb(i, F.nx, F.ny, F.nz);
+    bool near_fill = false;
 #pragma unroll
-        for (int q = 1; q < NQ; ++q) {
-            const int j = nb.at(dir_x(q), dir_y(q), dir_z(q));
-            near_fill |= (F.flags[j] & FL_IF) && F.conv[j] == CV_FILL;
-        }
-        if (near_fill) F.conv[i] = CV_NONE;
+    for (int q = 1; q < NQ; ++q) {
+        const int j = nb.at(dir_x(q), dir_y(q), dir_z(q));
+        near_fill |= (F.flags[j] & FL_IF) && F.conv[j] == CV_FILL;
     }
+    if (near_fill) {
+        F.conv[i] = CV_NONE;
+        st = CV_NONE;
+    }
+    return st;
 }
 
-// Rule 3: tag the new interface cells and initialise them. Cells reached
-// from several converting neighbours are written identically by each.
+// Rules 2 and 3: prune the cell's own emptying (it reads only its
+// neighbours' filling, which pruning never changes), then tag the new
+// interface cells and initialise them. Cells reached from several
+// converting neighbours are written identically by each.
 template <class P>
 __global__ __launch_bounds__(256) void k_conv_mark_init(const Batch<P> B)
 {
@@ -76,7 +78,7 @@ __global__ __launch_bounds__(256) void k_conv_mark_init(const Batch<P> B)
         int fresh[NQ];
         int nfresh = 0;
         const int i = k < n ? F.ilist[k] : 0;
-        const uint8_t st = k < n ? F.conv[i] : CV_NONE;
+        const uint8_t st = k < n ? prune_own(F, i) : CV_NONE;
         const Nbr nb(i, F.nx, F.ny, F.nz);
         for (int q = 1; q < NQ && st != CV_NONE; ++q) {
             const int j = nb.at(dir_x(q), dir_y(q), dir_z(q));
@@ -244,12 +246,18 @@ __global__ __launch_bounds__(256) void k_conv_gather(const Batch<P> B)
     }
 }
 
-// Rule 5 and the new interface cells' types.
+// Rule 5 and the new interface cells' types; block 0 also resets the list
+// rebuild counters for k_list_keep.
 template <class P>
 __global__ __launch_bounds__(256) void k_conv_flags(const Batch<P> B)
 {
     const Fields<P> &F = B.f[blockIdx.y];
     if (F.sc->nconv == 0) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        F.sc->nkeep = 0;
+        F.sc->bbox[0] = F.nx; F.sc->bbox[1] = F.ny; F.sc->bbox[2] = F.nz;
+        F.sc->bbox[3] = -1; F.sc->bbox[4] = -1; F.sc->bbox[5] = -1;
+    }
     const uint32_t tag = F.sc->step << 2;
     const int n = list_count(F.sc);
     for (int k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256) {
@@ -271,16 +279,6 @@ __global__ __launch_bounds__(256) void k_conv_flags(const Batch<P> B)
 // cells). The order of the list does not enter any result (every per-cell
 // computation is independent), so kept cells are appended with an atomic
 // counter; the interface bounding box is recomputed on the way.
-template <class P>
-__global__ void k_list_begin(const Batch<P> B)
-{
-    const Fields<P> &F = B.f[blockIdx.y];
-    if (F.sc->nconv == 0 || threadIdx.x != 0) return;
-    F.sc->nkeep = 0;
-    F.sc->bbox[0] = F.nx; F.sc->bbox[1] = F.ny; F.sc->bbox[2] = F.nz;
-    F.sc->bbox[3] = -1; F.sc->bbox[4] = -1; F.sc->bbox[5] = -1;
-}
-
 __device__ inline int block_exclusive_scan(int v, int *lds_wave, int &total)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;

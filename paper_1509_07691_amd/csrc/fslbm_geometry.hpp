@@ -293,10 +293,8 @@ template <class G> struct FdLds {
 };
 
 template <class P>
-__global__ __launch_bounds__(256) void k_geometry_fd(const Batch<P> B)
+__device__ inline void geometry_fd_tiles(const Fields<P> &F)
 {
-    if (B.p[blockIdx.y].curv != 0) return;
-    const Fields<P> &F = B.f[blockIdx.y];
     using R = typename P::R;
     using G = typename P::G;
     __shared__ FdLds<G> L;
@@ -370,6 +368,13 @@ __global__ __launch_bounds__(256) void k_geometry_fd(const Batch<P> B)
             F.K[i] = R(-((dxx + dyy + dzz) / G(32)));
         }
     }
+}
+
+template <class P>
+__global__ __launch_bounds__(256) void k_geometry_fd(const Batch<P> B)
+{
+    if (B.p[blockIdx.y].curv != 0) return;
+    geometry_fd_tiles(B.f[blockIdx.y]);
 }
 
 // LSQR model: one thread per interface cell over the interface list (the
@@ -450,15 +455,16 @@ struct LsqrFrame {
     double huc, hvc, hu, hv;
 };
 
+// Completes a frame whose centre normal f.nc and validity f.ok are set,
+// given whether the block holds an obstacle cell.
 template <class View>
-__host__ __device__ __forceinline__ LsqrFrame lsqr_frame(const View &V, const Params &prm)
+__host__ __device__ __forceinline__ void lsqr_frame_finish(const View &V, const Params &prm, LsqrFrame &f,
+                                                           bool has_obst)
 {
-    LsqrFrame f;
-    V.normal(0, 0, 0, f.nc);
-    f.ok = !(f.nc[0] == 0.0 && f.nc[1] == 0.0 && f.nc[2] == 0.0);
-    f.has_obst = f.hard = false;
+    f.has_obst = has_obst;
+    f.hard = false;
     f.huc = f.hvc = f.hu = f.hv = 0.0;
-    if (!f.ok) return f;
+    if (!f.ok) return;
     const double(&nc)[3] = f.nc;
     int ax = 0;
     if (fabs(nc[1]) < fabs(nc[ax])) ax = 1;
@@ -474,14 +480,24 @@ __host__ __device__ __forceinline__ LsqrFrame lsqr_frame(const View &V, const Pa
     f.tv[2] = nc[0] * f.tu[1] - nc[1] * f.tu[0];
     const double ac = V.plic(0, 0, 0);
     f.pc[0] = ac * nc[0]; f.pc[1] = ac * nc[1]; f.pc[2] = ac * nc[2];
+    if (f.has_obst && (V.flag(0, 0, 0) & FL_NEAR_OBST))
+        f.hard = contact_condition(V, 0, 0, 0, f.pc, f.nc, f.tu, f.tv, prm, f.huc, f.hvc, f.hu, f.hv);
+}
+
+template <class View>
+__host__ __device__ __forceinline__ LsqrFrame lsqr_frame(const View &V, const Params &prm)
+{
+    LsqrFrame f;
+    V.normal(0, 0, 0, f.nc);
+    f.ok = !(f.nc[0] == 0.0 && f.nc[1] == 0.0 && f.nc[2] == 0.0);
+    bool has_obst = false;
 #pragma unroll
     for (int c = -1; c <= 1; ++c)
 #pragma unroll
         for (int b = -1; b <= 1; ++b)
 #pragma unroll
-            for (int a = -1; a <= 1; ++a) f.has_obst |= (V.flag(a, b, c) & FL_OBST) != 0;
-    if (f.has_obst && (V.flag(0, 0, 0) & FL_NEAR_OBST))
-        f.hard = contact_condition(V, 0, 0, 0, f.pc, f.nc, f.tu, f.tv, prm, f.huc, f.hvc, f.hu, f.hv);
+            for (int a = -1; a <= 1; ++a) has_obst |= (V.flag(a, b, c) & FL_OBST) != 0;
+    lsqr_frame_finish(V, prm, f, has_obst);
     return f;
 }
 
@@ -664,10 +680,8 @@ __host__ __device__ inline double lsqr_curvature(const View &V, const Params &pr
 
 // Normals and PLIC points of the interface cells (LSQR model).
 template <class P>
-__global__ __launch_bounds__(256) void k_normals_plic(const Batch<P> B)
+__device__ inline void normals_plic_list(const Fields<P> &F)
 {
-    if (B.p[blockIdx.y].curv != 1) return;
-    const Fields<P> &F = B.f[blockIdx.y];
     using G = typename P::G;
     const int n = list_count(F.sc);
     for (int k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256) {
@@ -692,6 +706,23 @@ __global__ __launch_bounds__(256) void k_normals_plic(const Batch<P> B)
 }
 
 template <class P>
+__global__ __launch_bounds__(256) void k_normals_plic(const Batch<P> B)
+{
+    if (B.p[blockIdx.y].curv != 1) return;
+    normals_plic_list(B.f[blockIdx.y]);
+}
+
+// First geometry launch of a batch that mixes the models: FD lattices run
+// their whole tiled curvature, LSQR lattices their normals and PLIC points
+// (the LSQR fit follows in k_curv_lsqr4), so the two overlap on the device.
+template <class P>
+__global__ __launch_bounds__(256) void k_geometry_mixed(const Batch<P> B)
+{
+    if (B.p[blockIdx.y].curv == 0) geometry_fd_tiles(B.f[blockIdx.y]);
+    else normals_plic_list(B.f[blockIdx.y]);
+}
+
+template <class P>
 __global__ __launch_bounds__(256) void k_curv_lsqr(const Batch<P> B)
 {
     const Params &prm = B.p[blockIdx.y];
@@ -704,6 +735,63 @@ __global__ __launch_bounds__(256) void k_curv_lsqr(const Batch<P> B)
         const int yz = i / F.nx, x = i - yz * F.nx, z = yz / F.ny, y = yz - z * F.ny;
         const LsqrView<P> V{F, x, y, z};
         F.K[i] = R(lsqr_curvature(V, prm));
+    }
+}
+
+// LSQR curvature with 4 lanes per interface cell (64 cells per workgroup):
+// lane l of a group scans the block cells s = l, l + 4, ... (s = 0..26,
+// x fastest) for obstacles and adds their data and contact rows; the sums
+// are reduced over the 4 lanes by an xor butterfly (a fixed order, the same
+// result on every lane) and every lane solves the same system.
+template <class P>
+__global__ __launch_bounds__(256) void k_curv_lsqr4(const Batch<P> B)
+{
+    const Params &prm = B.p[blockIdx.y];
+    if (prm.curv != 1) return;
+    const Fields<P> &F = B.f[blockIdx.y];
+    using R = typename P::R;
+    const int n = list_count(F.sc);
+    const int l = threadIdx.x & 3;
+    for (int k = blockIdx.x * 64 + (threadIdx.x >> 2); k < n; k += gridDim.x * 64) {
+        const int i = F.ilist[k];
+        const int yz = i / F.nx, x = i - yz * F.nx, z = yz / F.ny, y = yz - z * F.ny;
+        const LsqrView<P> V{F, x, y, z};
+        LsqrFrame f;
+        V.normal(0, 0, 0, f.nc);
+        f.ok = !(f.nc[0] == 0.0 && f.nc[1] == 0.0 && f.nc[2] == 0.0);
+        // obstacles in the block: each lane scans its share
+        bool ob = false;
+#pragma unroll
+        for (int t = 0; t < 7; ++t) {
+            const int s = l + 4 * t;
+            if (s < 27) ob |= (V.flag(s % 3 - 1, (s / 3) % 3 - 1, s / 9 - 1) & FL_OBST) != 0;
+        }
+        ob |= __shfl_xor(ob ? 1 : 0, 1, 4) != 0;
+        ob |= __shfl_xor(ob ? 1 : 0, 2, 4) != 0;
+        lsqr_frame_finish(V, prm, f, ob);
+        LsqrSums S;
+        if (f.ok) {
+#pragma unroll
+            for (int t = 0; t < 7; ++t) {
+                const int s = l + 4 * t;
+                if (s < 27) lsqr_cell_rows(V, prm, f, s % 3 - 1, (s / 3) % 3 - 1, s / 9 - 1, S);
+            }
+            if (f.has_obst)
+                for (int t = 0; t < 7; ++t) {
+                    const int s = l + 4 * t;
+                    if (s < 27) lsqr_contact_rows(V, prm, f, s % 3 - 1, (s / 3) % 3 - 1, s / 9 - 1, S);
+                }
+        }
+#pragma unroll
+        for (int m = 1; m < 4; m <<= 1) {
+#pragma unroll
+            for (int e = 0; e < 15; ++e) S.G[e] += __shfl_xor(S.G[e], m, 4);
+#pragma unroll
+            for (int e = 0; e < 5; ++e) S.g[e] += __shfl_xor(S.g[e], m, 4);
+            S.rows += __shfl_xor(S.rows, m, 4);
+        }
+        const double K = f.ok ? lsqr_solve_curvature(f, S) : 0.0;
+        if (l == 0) F.K[i] = R(K);
     }
 }
 
