@@ -690,96 +690,103 @@ __host__ __device__ inline void contact_condition_adj(const View &V, int dx, int
     c[3] += ajb;
 }
 
-// Reverse of lsqr_curvature for dL/dK = Kb: accumulates dL/dn_j and dL/da_j
-// of the 27 cells of the block (cb[4 s + 0..2], cb[4 s + 3], s = slot27)
-// and dL/dtheta. Recomputes the forward fit first (same rows, same order,
-// same model choice).
-template <class View>
-__host__ __device__ inline void lsqr_curvature_adj(const View &V, const Params &prm, double Kb, double *cb, double &thb)
+// Sum of v over the L lanes of a group (xor butterfly; L = 1: nothing).
+template <int L>
+__host__ __device__ inline double group_sum(double v)
 {
+    if constexpr (L > 1) {
+#pragma unroll
+        for (int m = 1; m < L; m <<= 1) v += __shfl_xor(v, m, L);
+    }
+    return v;
+}
+template <int L>
+__host__ __device__ inline int group_sum_int(int v)
+{
+    if constexpr (L > 1) {
+#pragma unroll
+        for (int m = 1; m < L; m <<= 1) v += __shfl_xor(v, m, L);
+    }
+    return v;
+}
+
+// Reverse of the LSQR curvature for dL/dK = Kb, by the L lanes of a group
+// (lane = 0..L-1; L = 1 is the plain serial form). The forward fit is
+// recomputed (same rows and model choice as lsqr_curvature, sums reduced
+// over the lanes): the frame, the centre's hard constraint, the normal
+// equations, their solution x and y = G^-1 xbar are the same on every lane.
+// Lane l owns the block cells s = l, l + L, ... (s = slot27): it forms
+// their rows' adjoints (bbar = m.y, mbar = r y - (m.y) x per row) and
+// writes dL/dn_s, dL/da_s into cb[4 s + 0..3]. The adjoints of the shared
+// quantities (centre point, frame, hard-constraint values, theta) are
+// reduced over the lanes; lane 0 then reverses the centre's hard
+// constraint and the frame into slot 13 and returns dL/dtheta in thb (the
+// other lanes return 0).
+template <int L, class View>
+__host__ __device__ inline void lsqr_curvature_adj(const View &V, const Params &prm, double Kb, int lane, double *cb,
+                                                   double &thb)
+{
+    thb = 0.0;
     double nc[3];
     V.normal(0, 0, 0, nc);
     if (nc[0] == 0.0 && nc[1] == 0.0 && nc[2] == 0.0) return;
     int ax = 0;
     if (fabs(nc[1]) < fabs(nc[ax])) ax = 1;
     if (fabs(nc[2]) < fabs(nc[ax])) ax = 2;
-    double tu[3] = {-nc[ax] * nc[0], -nc[ax] * nc[1], -nc[ax] * nc[2]};
-    tu[ax] += 1.0;
+    const double nax = ax == 0 ? nc[0] : (ax == 1 ? nc[1] : nc[2]);
+    double tu[3] = {-nax * nc[0] + (ax == 0 ? 1.0 : 0.0), -nax * nc[1] + (ax == 1 ? 1.0 : 0.0),
+                    -nax * nc[2] + (ax == 2 ? 1.0 : 0.0)};
     const double ltu = sqrt(dot(tu, tu));
     tu[0] /= ltu; tu[1] /= ltu; tu[2] /= ltu;
     const double tv[3] = {nc[1] * tu[2] - nc[2] * tu[1], nc[2] * tu[0] - nc[0] * tu[2], nc[0] * tu[1] - nc[1] * tu[0]};
     const double ac = V.plic(0, 0, 0);
     const double pc[3] = {ac * nc[0], ac * nc[1], ac * nc[2]};
-    bool has_obst = false;
-    for (int c = -1; c <= 1; ++c)
-        for (int b = -1; b <= 1; ++b)
-            for (int a = -1; a <= 1; ++a) has_obst |= (V.flag(a, b, c) & FL_OBST) != 0;
-    bool hard = false;
-    double huc = 0, hvc = 0, hu = 0, hv = 0;
-    if (has_obst && (V.flag(0, 0, 0) & FL_NEAR_OBST))
-        hard = contact_condition(V, 0, 0, 0, pc, nc, tu, tv, prm, huc, hvc, hu, hv);
-
-    // ---- forward fit
-    Gram<5> g5;
-    Gram<3> g3;
-    Gram<1> g1;
-    int rows = 0;
-    auto add_row = [&](double r0, double r1, double r2, double r3, double r4, double b) {
-        ++rows;
-        if (!hard) {
-            const double a5[5] = {r0, r1, r2, r3, r4};
-            g5.add(a5, b);
-            const double a3[3] = {r0 + r1, r3, r4};
-            g3.add(a3, b);
-        } else {
-            const double e0 = r0 - r3 * (2.0 * huc), e1 = r1 - r4 * (2.0 * hvc);
-            const double e2 = r2 - r3 * hvc - r4 * huc;
-            const double be = b - r3 * hu - r4 * hv;
-            const double a3[3] = {e0, e1, e2};
-            g3.add(a3, be);
-            const double a1[1] = {e0 + e1};
-            g1.add(a1, be);
-        }
-    };
-    for (int c = -1; c <= 1; ++c)
-        for (int b = -1; b <= 1; ++b)
-            for (int a = -1; a <= 1; ++a) {
-                if (a == 0 && b == 0 && c == 0) continue;
-                if (!(V.flag(a, b, c) & FL_IF)) continue;
-                double nj[3];
-                V.normal(a, b, c, nj);
-                if (nj[0] == 0.0 && nj[1] == 0.0 && nj[2] == 0.0) continue;
-                const double aj = V.plic(a, b, c);
-                const double r[3] = {a + aj * nj[0] - pc[0], b + aj * nj[1] - pc[1], c + aj * nj[2] - pc[2]};
-                const double u = dot(r, tu), v = dot(r, tv), w = dot(r, nc);
-                add_row(u * u, v * v, u * v, u, v, w);
-            }
-    if (has_obst) {
-        for (int c = -1; c <= 1; ++c)
-            for (int b = -1; b <= 1; ++b)
-                for (int a = -1; a <= 1; ++a) {
-                    if (a == 0 && b == 0 && c == 0) continue;
-                    const uint8_t fj = V.flag(a, b, c);
-                    if (!((fj & FL_IF) && (fj & FL_NEAR_OBST))) continue;
-                    double uc, vc, ru, rv;
-                    if (!contact_condition(V, a, b, c, pc, nc, tu, tv, prm, uc, vc, ru, rv)) continue;
-                    add_row(2.0 * uc, 0.0, vc, 1.0, 0.0, ru);
-                    add_row(0.0, 2.0 * vc, uc, 0.0, 1.0, rv);
-                }
+    int ob = 0;
+    for (int s = lane; s < 27; s += L) ob |= (V.flag(s % 3 - 1, (s / 3) % 3 - 1, s / 9 - 1) & FL_OBST) != 0;
+    const bool has_obst = group_sum_int<L>(ob) != 0;
+    LsqrFrame fr;
+    for (int k = 0; k < 3; ++k) {
+        fr.nc[k] = nc[k];
+        fr.tu[k] = tu[k];
+        fr.tv[k] = tv[k];
+        fr.pc[k] = pc[k];
     }
+    fr.ok = true;
+    fr.has_obst = has_obst;
+    fr.hard = false;
+    fr.huc = fr.hvc = fr.hu = fr.hv = 0.0;
+    if (has_obst && (V.flag(0, 0, 0) & FL_NEAR_OBST))
+        fr.hard = contact_condition(V, 0, 0, 0, pc, nc, tu, tv, prm, fr.huc, fr.hvc, fr.hu, fr.hv);
+    const bool hard = fr.hard;
+    const double huc = fr.huc, hvc = fr.hvc, hu = fr.hu, hv = fr.hv;
+
+    // ---- forward fit, rows split over the lanes
+    LsqrSums S;
+    for (int s = lane; s < 27; s += L) lsqr_cell_rows(V, prm, fr, s % 3 - 1, (s / 3) % 3 - 1, s / 9 - 1, S);
+    if (has_obst)
+        for (int s = lane; s < 27; s += L) lsqr_contact_rows(V, prm, fr, s % 3 - 1, (s / 3) % 3 - 1, s / 9 - 1, S);
+    for (int e = 0; e < 15; ++e) S.G[e] = group_sum<L>(S.G[e]);
+    for (int e = 0; e < 5; ++e) S.g[e] = group_sum<L>(S.g[e]);
+    S.rows = group_sum_int<L>(S.rows);
     // model: 0 none, 1 free 5, 2 free isotropic 3, 3 hard 3, 4 hard isotropic 1
+    // (the same choice as lsqr_solve_curvature)
     int model = 0;
     double x[5] = {0, 0, 0, 0, 0};
+    double Gm[15];
     double A = 0, Bq = 0, C = 0, H = 0, I = 0;
+    const double *G = S.G, *g = S.g;
+    const double G3i[6] = {G[0] + 2.0 * G[1] + G[2], G[6] + G[7], G[9], G[10] + G[11], G[13], G[14]};
+    const double G1[1] = {G[0] + 2.0 * G[1] + G[2]};
     if (!hard) {
         double x5[5];
-        if (rows >= 5 && g5.solve(x5)) {
+        if (S.rows >= 5 && packed_solve<5>(G, g, x5)) {
             model = 1;
             for (int k = 0; k < 5; ++k) x[k] = x5[k];
             A = x5[0]; Bq = x5[1]; C = x5[2]; H = x5[3]; I = x5[4];
-        } else {
+        } else if (S.rows >= 3) {
+            const double g3[3] = {g[0] + g[1], g[3], g[4]};
             double x3[3];
-            if (rows >= 3 && g3.solve(x3)) {
+            if (packed_solve<3>(G3i, g3, x3)) {
                 model = 2;
                 x[0] = x3[0]; x[1] = x3[1]; x[2] = x3[2];
                 A = x3[0]; Bq = x3[0]; C = 0.0; H = x3[1]; I = x3[2];
@@ -787,13 +794,14 @@ __host__ __device__ inline void lsqr_curvature_adj(const View &V, const Params &
         }
     } else {
         double x3[3];
-        if (rows >= 3 && g3.solve(x3)) {
+        if (S.rows >= 3 && packed_solve<3>(G, g, x3)) {
             model = 3;
             x[0] = x3[0]; x[1] = x3[1]; x[2] = x3[2];
             A = x3[0]; Bq = x3[1]; C = x3[2];
-        } else {
+        } else if (S.rows >= 1) {
+            const double g1[1] = {g[0] + g[1]};
             double x1[1];
-            if (rows >= 1 && g1.solve(x1)) {
+            if (packed_solve<1>(G1, g1, x1)) {
                 model = 4;
                 x[0] = x1[0];
                 A = x1[0]; Bq = x1[0]; C = 0.0;
@@ -810,46 +818,41 @@ __host__ __device__ inline void lsqr_curvature_adj(const View &V, const Params &
     const double Nb = 2.0 * Kb / (gg * sqrt(gg));
     const double ggb = -3.0 * Nn * Kb / (gg * gg * sqrt(gg));
     double Ab = Nb * (1.0 + I * I), Bb = Nb * (1.0 + H * H), Cb = -Nb * H * I;
-    double Hb = Nb * (2.0 * Bq * H - C * I) + 2.0 * H * ggb;
-    double Ib = Nb * (2.0 * A * I - C * H) + 2.0 * I * ggb;
-    double hucb = 0, hvcb = 0, hub = 0, hvb = 0;
+    const double Hb = Nb * (2.0 * Bq * H - C * I) + 2.0 * H * ggb;
+    const double Ib = Nb * (2.0 * A * I - C * H) + 2.0 * I * ggb;
+    // direct (not per row) adjoints of the centre's hard-constraint values
+    double hucb0 = 0, hvcb0 = 0, hub0 = 0, hvb0 = 0;
     if (hard) {
         // H = hu - 2 huc A - hvc C, I = hv - 2 hvc B - huc C
-        hub += Hb;
-        hvb += Ib;
-        hucb += -2.0 * A * Hb - C * Ib;
-        hvcb += -C * Hb - 2.0 * Bq * Ib;
+        hub0 = Hb;
+        hvb0 = Ib;
+        hucb0 = -2.0 * A * Hb - C * Ib;
+        hvcb0 = -C * Hb - 2.0 * Bq * Ib;
         Ab += -2.0 * huc * Hb;
         Bb += -2.0 * hvc * Ib;
         Cb += -hvc * Hb - huc * Ib;
     }
-    // adjoint of the solved vector and y = G^-1 xbar
+    // y = G^-1 xbar for the chosen model
     double y[5] = {0, 0, 0, 0, 0};
     if (model == 1) {
-        Gram<5> gy = g5;
         const double xb[5] = {Ab, Bb, Cb, Hb, Ib};
-        for (int k = 0; k < 5; ++k) gy.g[k] = xb[k];
         double yy[5];
-        gy.solve(yy);
+        packed_solve<5>(G, xb, yy);
         for (int k = 0; k < 5; ++k) y[k] = yy[k];
     } else if (model == 2 || model == 3) {
-        Gram<3> gy = g3;
-        if (model == 2) {
-            gy.g[0] = Ab + Bb; gy.g[1] = Hb; gy.g[2] = Ib;
-        } else {
-            gy.g[0] = Ab; gy.g[1] = Bb; gy.g[2] = Cb;
-        }
+        const double xb[3] = {model == 2 ? Ab + Bb : Ab, model == 2 ? Hb : Bb, model == 2 ? Ib : Cb};
         double yy[3];
-        gy.solve(yy);
+        packed_solve<3>(model == 2 ? G3i : G, xb, yy);
         for (int k = 0; k < 3; ++k) y[k] = yy[k];
     } else {
-        Gram<1> gy = g1;
-        gy.g[0] = Ab + Bb;
+        const double xb[1] = {Ab + Bb};
         double yy[1];
-        gy.solve(yy);
+        packed_solve<1>(G1, xb, yy);
         y[0] = yy[0];
     }
-    // adjoint of one row (r0..r4 | b) of the model: rb[0..4], bb
+    // per-row adjoints; the hard-constraint adjoints they produce are summed
+    // in hucb .. hvb (this lane's rows only)
+    double hucb = 0, hvcb = 0, hub = 0, hvb = 0;
     auto row_adj = [&](const double (&r)[5], double b, double (&rb)[5], double &bb) {
         for (int k = 0; k < 5; ++k) rb[k] = 0.0;
         bb = 0.0;
@@ -904,57 +907,70 @@ __host__ __device__ inline void lsqr_curvature_adj(const View &V, const Params &
         }
     };
     double pcb[3] = {0, 0, 0}, ncb[3] = {0, 0, 0}, tub[3] = {0, 0, 0}, tvb[3] = {0, 0, 0};
-    // ---- data rows (same order as the forward)
-    for (int c = -1; c <= 1; ++c)
-        for (int b = -1; b <= 1; ++b)
-            for (int a = -1; a <= 1; ++a) {
-                if (a == 0 && b == 0 && c == 0) continue;
-                if (!(V.flag(a, b, c) & FL_IF)) continue;
-                double nj[3];
-                V.normal(a, b, c, nj);
-                if (nj[0] == 0.0 && nj[1] == 0.0 && nj[2] == 0.0) continue;
-                const double aj = V.plic(a, b, c);
-                const double r[3] = {a + aj * nj[0] - pc[0], b + aj * nj[1] - pc[1], c + aj * nj[2] - pc[2]};
-                const double u = dot(r, tu), v = dot(r, tv), w = dot(r, nc);
-                const double row[5] = {u * u, v * v, u * v, u, v};
-                double rb5[5], bb;
-                row_adj(row, w, rb5, bb);
-                const double ub = 2.0 * u * rb5[0] + v * rb5[2] + rb5[3];
-                const double vb = 2.0 * v * rb5[1] + u * rb5[2] + rb5[4];
-                double rr[3];
-                for (int k = 0; k < 3; ++k) {
-                    rr[k] = ub * tu[k] + vb * tv[k] + bb * nc[k];
-                    tub[k] += ub * r[k];
-                    tvb[k] += vb * r[k];
-                    ncb[k] += bb * r[k];
-                    pcb[k] -= rr[k];
-                }
-                double *cs = cb + 4 * slot27(a, b, c);
-                cs[0] += aj * rr[0];
-                cs[1] += aj * rr[1];
-                cs[2] += aj * rr[2];
-                cs[3] += dot(nj, rr);
-            }
-    // ---- contact rows of the other contact-line cells
-    if (has_obst) {
-        for (int c = -1; c <= 1; ++c)
-            for (int b = -1; b <= 1; ++b)
-                for (int a = -1; a <= 1; ++a) {
-                    if (a == 0 && b == 0 && c == 0) continue;
-                    const uint8_t fj = V.flag(a, b, c);
-                    if (!((fj & FL_IF) && (fj & FL_NEAR_OBST))) continue;
-                    double uc, vc, ru, rv;
-                    if (!contact_condition(V, a, b, c, pc, nc, tu, tv, prm, uc, vc, ru, rv)) continue;
-                    const double row1[5] = {2.0 * uc, 0.0, vc, 1.0, 0.0};
-                    const double row2[5] = {0.0, 2.0 * vc, uc, 0.0, 1.0};
-                    double p5[5], q5[5], pb, qb;
-                    row_adj(row1, ru, p5, pb);
-                    row_adj(row2, rv, q5, qb);
-                    const double ucb = 2.0 * p5[0] + q5[2];
-                    const double vcb = p5[2] + 2.0 * q5[1];
-                    contact_condition_adj(V, a, b, c, pc, nc, tu, tv, prm, ucb, vcb, pb, qb, pcb, ncb, tub, tvb, cb, thb);
-                }
+    double thl = 0.0;
+    // ---- data rows of this lane's block cells
+    for (int s = lane; s < 27; s += L) {
+        const int a = s % 3 - 1, b = (s / 3) % 3 - 1, c = s / 9 - 1;
+        if (a == 0 && b == 0 && c == 0) continue;
+        if (!(V.flag(a, b, c) & FL_IF)) continue;
+        double nj[3];
+        V.normal(a, b, c, nj);
+        if (nj[0] == 0.0 && nj[1] == 0.0 && nj[2] == 0.0) continue;
+        const double aj = V.plic(a, b, c);
+        const double r[3] = {a + aj * nj[0] - pc[0], b + aj * nj[1] - pc[1], c + aj * nj[2] - pc[2]};
+        const double u = dot(r, tu), v = dot(r, tv), w = dot(r, nc);
+        const double row[5] = {u * u, v * v, u * v, u, v};
+        double rb5[5], bb;
+        row_adj(row, w, rb5, bb);
+        const double ub = 2.0 * u * rb5[0] + v * rb5[2] + rb5[3];
+        const double vb = 2.0 * v * rb5[1] + u * rb5[2] + rb5[4];
+        double rr[3];
+        for (int k = 0; k < 3; ++k) {
+            rr[k] = ub * tu[k] + vb * tv[k] + bb * nc[k];
+            tub[k] += ub * r[k];
+            tvb[k] += vb * r[k];
+            ncb[k] += bb * r[k];
+            pcb[k] -= rr[k];
+        }
+        double *cs = cb + 4 * s;
+        cs[0] += aj * rr[0];
+        cs[1] += aj * rr[1];
+        cs[2] += aj * rr[2];
+        cs[3] += dot(nj, rr);
     }
+    // ---- contact rows of this lane's contact-line cells
+    if (has_obst) {
+        for (int s = lane; s < 27; s += L) {
+            const int a = s % 3 - 1, b = (s / 3) % 3 - 1, c = s / 9 - 1;
+            if (a == 0 && b == 0 && c == 0) continue;
+            const uint8_t fj = V.flag(a, b, c);
+            if (!((fj & FL_IF) && (fj & FL_NEAR_OBST))) continue;
+            double uc, vc, ru, rv;
+            if (!contact_condition(V, a, b, c, pc, nc, tu, tv, prm, uc, vc, ru, rv)) continue;
+            const double row1[5] = {2.0 * uc, 0.0, vc, 1.0, 0.0};
+            const double row2[5] = {0.0, 2.0 * vc, uc, 0.0, 1.0};
+            double p5[5], q5[5], pb, qb;
+            row_adj(row1, ru, p5, pb);
+            row_adj(row2, rv, q5, qb);
+            const double ucb = 2.0 * p5[0] + q5[2];
+            const double vcb = p5[2] + 2.0 * q5[1];
+            contact_condition_adj(V, a, b, c, pc, nc, tu, tv, prm, ucb, vcb, pb, qb, pcb, ncb, tub, tvb, cb, thl);
+        }
+    }
+    // ---- shared adjoints summed over the lanes
+    for (int k = 0; k < 3; ++k) {
+        pcb[k] = group_sum<L>(pcb[k]);
+        ncb[k] = group_sum<L>(ncb[k]);
+        tub[k] = group_sum<L>(tub[k]);
+        tvb[k] = group_sum<L>(tvb[k]);
+    }
+    hucb = group_sum<L>(hucb) + hucb0;
+    hvcb = group_sum<L>(hvcb) + hvcb0;
+    hub = group_sum<L>(hub) + hub0;
+    hvb = group_sum<L>(hvb) + hvb0;
+    thl = group_sum<L>(thl);
+    if (lane != 0) return;
+    thb = thl;
     // ---- hard constraint of the centre
     if (hard) contact_condition_adj(V, 0, 0, 0, pc, nc, tu, tv, prm, hucb, hvcb, hub, hvb, pcb, ncb, tub, tvb, cb, thb);
     // ---- frame: t_v = n x t_u, t_u = w/|w|, w = e_ax - n_ax n; p_c = a_c n
@@ -968,8 +984,10 @@ __host__ __device__ inline void lsqr_curvature_adj(const View &V, const Params &
     double wb[3];
     for (int k = 0; k < 3; ++k) wb[k] = (tub[k] - tt * tu[k]) / ltu;
     const double wn = dot(wb, nc);
-    for (int k = 0; k < 3; ++k) ncb[k] += -nc[ax] * wb[k];
-    ncb[ax] += -wn;
+    for (int k = 0; k < 3; ++k) ncb[k] += -nax * wb[k];
+    ncb[0] += ax == 0 ? -wn : 0.0;
+    ncb[1] += ax == 1 ? -wn : 0.0;
+    ncb[2] += ax == 2 ? -wn : 0.0;
     const double acb = dot(pcb, nc);
     for (int k = 0; k < 3; ++k) ncb[k] += ac * pcb[k];
     double *c0 = cb + 4 * slot27(0, 0, 0);
@@ -979,23 +997,31 @@ __host__ __device__ inline void lsqr_curvature_adj(const View &V, const Params &
     c0[3] += acb;
 }
 
-// Per interface cell: partials of K w.r.t. the normals and PLIC offsets of
-// its block, scaled by dL/dK, into contrib; dL/dtheta into tacc.
+// Per interface cell, 8 lanes: partials of K w.r.t. the normals and PLIC
+// offsets of its block, scaled by dL/dK, into contrib; dL/dtheta into tacc.
+constexpr int ADJ_LANES = 8;
+
 template <class P>
 __global__ __launch_bounds__(256) void k_adj_lsqr_cell(const Fields<P> F, const Adj A, const Params prm)
 {
     const int n = F.sc->icount;
-    for (int k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256) {
+    const int lane = threadIdx.x % ADJ_LANES;
+    constexpr int per_block = 256 / ADJ_LANES;
+    for (int k = blockIdx.x * per_block + threadIdx.x / ADJ_LANES; k < n; k += gridDim.x * per_block) {
         const int i = F.ilist[k];
         double *cb = A.contrib + (size_t)CONTRIB * k;
-        for (int s = 0; s < CONTRIB; ++s) cb[s] = 0.0;
+        // each slot is written only by the lane that owns it (slot 13, the
+        // centre, by lane 0), and cleared by that lane
+        for (int s = lane; s < 27; s += ADJ_LANES)
+            if (s != 13) cb[4 * s] = cb[4 * s + 1] = cb[4 * s + 2] = cb[4 * s + 3] = 0.0;
+        if (lane == 0) cb[52] = cb[53] = cb[54] = cb[55] = 0.0;
         const double kb = A.kbar[i];
-        if (kb == 0.0) continue;
+        if (kb == 0.0) continue;  // the same for the whole group
         const int yz = i / F.nx, x = i - yz * F.nx, z = yz / F.ny, y = yz - z * F.ny;
         const LsqrView<P> V{F, x, y, z};
         double thb = 0.0;
-        lsqr_curvature_adj(V, prm, kb, cb, thb);
-        A.tacc[i] += thb;
+        lsqr_curvature_adj<ADJ_LANES>(V, prm, kb, lane, cb, thb);
+        if (lane == 0) A.tacc[i] += thb;
     }
 }
 

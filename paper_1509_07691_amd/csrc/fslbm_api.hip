@@ -164,6 +164,7 @@ struct fslbm_lattice {
     unsigned version;  // bumped whenever launch arguments change
     unsigned long long epoch;  // bumped whenever the state changes other than by stepping
     int frozen;        // 1 inside a frozen-topology window
+    int icount0;       // interface cells at creation (sizes the list-kernel grids)
     fslbm_batch self;
     AdjWindow adj;
 };
@@ -536,6 +537,16 @@ Batch<P> make_batch(const fslbm_batch *b, int &maxN, bool &any_srt, bool &any_tr
 
 inline hipStream_t bstream(const fslbm_batch *b) { return b->hs[0]->stream; }
 
+// Grid of the interface-list kernels of a batch: about one thread per
+// interface cell at creation (the loops are grid-stride, so later growth is
+// still covered), at least 8 and at most 512 blocks per lattice.
+inline int batch_list_blocks(const fslbm_batch *b, int cells_per_block)
+{
+    int m = 0;
+    for (auto *h : b->hs) m = std::max(m, h->icount0);
+    return std::min(512, std::max(8, (m + cells_per_block - 1) / cells_per_block));
+}
+
 template <class P>
 int enqueue_compaction(const fslbm_batch *b, const Batch<P> &A, int maxN, int which, int force)
 {
@@ -559,14 +570,14 @@ int enqueue_geometry(const fslbm_batch *b, const Batch<P> &A, int maxN)
         any_fd |= h->curv == FSLBM_CURV_FD;
         any_lsqr |= h->curv == FSLBM_CURV_LSQR;
     }
-    const dim3 cg4(std::min(GEOM_GRID, std::max(1, maxN / 256)), n);
+    const dim3 cg4(batch_list_blocks(b, 64), n);
     if (any_fd && any_lsqr) {
         k_geometry_mixed<P><<<tg, 256, 0, st>>>(A);
         k_curv_lsqr4<P><<<cg4, 256, 0, st>>>(A);
     } else if (any_fd) {
         k_geometry_fd<P><<<tg, 256, 0, st>>>(A);
     } else if (any_lsqr) {
-        k_normals_plic<P><<<dim3(list_blocks(maxN), n), 256, 0, st>>>(A);
+        k_normals_plic<P><<<dim3(batch_list_blocks(b, 256), n), 256, 0, st>>>(A);
         k_curv_lsqr4<P><<<cg4, 256, 0, st>>>(A);
     }
     HIP_OK(hipGetLastError());
@@ -602,7 +613,7 @@ int enqueue_step_kernels(fslbm_batch *b, const void *fsrc = nullptr, void *fdst 
     };
     const unsigned n = (unsigned)b->hs.size();
     const hipStream_t st = bstream(b);
-    const dim3 cg(std::min(SC_GRID, cell_blocks(maxN)), n), lg(list_blocks(maxN), n);
+    const dim3 cg(std::min(SC_GRID, cell_blocks(maxN)), n), lg(batch_list_blocks(b, 256), n);
     mark(b, 0);
     if (b->split_interface) {
         if (any_srt) k_stream_collide<P, 0, 1><<<cg, 256, 0, st>>>(A);
@@ -615,19 +626,24 @@ int enqueue_step_kernels(fslbm_batch *b, const void *fsrc = nullptr, void *fdst 
         if (any_trt) k_stream_collide<P, 1, 0><<<cg, 256, 0, st>>>(A);
         mark(b, 1);
     }
+    // with frozen cell types no cell converts: only phi = m / rho remains
+    bool frozen = true;
+    for (auto *h : b->hs) frozen &= h->frozen != 0;
     mark(b, 2);
-    k_conv_mark_init<P><<<lg, 256, 0, st>>>(A);
-    k_conv_share<P><<<lg, 256, 0, st>>>(A);
+    if (!frozen) k_conv_mark_init<P><<<lg, 256, 0, st>>>(A);
+    if (!frozen) k_conv_share<P><<<lg, 256, 0, st>>>(A);
     k_conv_gather<P><<<lg, 256, 0, st>>>(A);
-    k_conv_flags<P><<<lg, 256, 0, st>>>(A);
+    if (!frozen) k_conv_flags<P><<<lg, 256, 0, st>>>(A);
     mark(b, 3);
     HIP_OK(hipGetLastError());
-    k_list_keep<P><<<lg, 256, 0, st>>>(A);
-    k_list_finish<P><<<lg, 256, 0, st>>>(A);
+    if (!frozen) {
+        k_list_keep<P><<<lg, 256, 0, st>>>(A);
+        k_list_finish<P><<<lg, 256, 0, st>>>(A);
+    }
     HIP_OK(hipGetLastError());
     int rc = 0;
     mark(b, 4);
-    k_obstacle_fill<P><<<lg, 256, 0, st>>>(A, 1);
+    k_obstacle_fill<P><<<dim3(list_blocks(maxN), n), 256, 0, st>>>(A, 1);
     rc = enqueue_geometry<P>(b, A, maxN);
     if (rc) return rc;
     mark(b, 5);
@@ -1255,7 +1271,13 @@ int fslbm_create(int nx, int ny, int nz, int precision, int curv_model, const do
     batch_init(&h->self);
     h->self.hs.push_back(h);
     h->self.prec = precision;
-    const int rc = dispatch<OpInit>(h, fill, obstacle);
+    h->icount0 = 1 << 20;  // large until counted: the creation's own geometry launch
+    int rc = dispatch<OpInit>(h, fill, obstacle);
+    if (!rc) {
+        int ic = 0, oc = 0;
+        rc = read_counts(h, ic, oc);
+        h->icount0 = ic;
+    }
     if (rc) {
         delete h;
         return rc;
