@@ -100,8 +100,8 @@ def traffic_from_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, 
         vals = [float(r["Counter_Value"]) for r in csv.DictReader(open(path)) if kernel_part in r["Kernel_Name"]]
         return sum(vals) / len(vals), len(vals)
 
-    f_kib, nf = mean_kib(fetch_csv, "k_stream_collide")
-    w_kib, nw = mean_kib(write_csv, "k_stream_collide")
+    f_kib, nf = mean_kib(fetch_csv, "k_stream_collide<")
+    w_kib, nw = mean_kib(write_csv, "k_stream_collide<")
     cf_kib, _ = mean_kib(copy_fetch_csv, "AUnaryFunctor")
     cw_kib, _ = mean_kib(copy_write_csv, "AUnaryFunctor")
     gib_kib = (4 << 28) / 1024.0

@@ -616,14 +616,14 @@ int enqueue_step_kernels(fslbm_batch *b, const void *fsrc = nullptr, void *fdst 
     const dim3 cg(std::min(SC_GRID, cell_blocks(maxN)), n), lg(batch_list_blocks(b, 256), n);
     mark(b, 0);
     if (b->split_interface) {
-        if (any_srt) k_stream_collide<P, 0, 1><<<cg, 256, 0, st>>>(A);
-        if (any_trt) k_stream_collide<P, 1, 1><<<cg, 256, 0, st>>>(A);
+        if (any_srt) launch_stream_collide<P, 0, 1>(cg, st, A);
+        if (any_trt) launch_stream_collide<P, 1, 1>(cg, st, A);
         mark(b, 1);
         if (any_srt) k_stream_collide_list<P, 0><<<cg, 256, 0, st>>>(A);
         if (any_trt) k_stream_collide_list<P, 1><<<cg, 256, 0, st>>>(A);
     } else {
-        if (any_srt) k_stream_collide<P, 0, 0><<<cg, 256, 0, st>>>(A);
-        if (any_trt) k_stream_collide<P, 1, 0><<<cg, 256, 0, st>>>(A);
+        if (any_srt) launch_stream_collide<P, 0, 0>(cg, st, A);
+        if (any_trt) launch_stream_collide<P, 1, 0>(cg, st, A);
         mark(b, 1);
     }
     // with frozen cell types no cell converts: only phi = m / rho remains

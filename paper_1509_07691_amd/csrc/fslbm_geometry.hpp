@@ -87,10 +87,14 @@ template <class G> struct CubeCut {
 
 // Plane offset a (point p = centre + a n) whose liquid side n.(x - centre) >= a
 // cuts volume phi out of the unit cell (Sec. II.B). The liquid volume at
-// offset a is V(1/2 - a/|n|_1); the root t of V(t) = phi is found by Newton
-// steps kept inside a bisection bracket, stopping when the step falls below
-// the type's resolution. This reaches the root to rounding, within the 4e-13
-// bound of the paper's 40-step bisection.
+// offset a is V(1/2 - a/|n|_1). For phi <= 1/2 (else by the point
+// reflection) the root t <= 1/2 of V(t) = phi is found piece by piece: the
+// corner tetrahedron (t <= s1: a cube root), the wedge (s1 <= t <= s2: a
+// quadratic) and the prism (t >= s1 + s2: linear) in closed form; the cubic
+// piece in between by Newton steps kept inside its bracket, started from the
+// wedge's root and stopped when a step falls below the type's resolution.
+// This reaches the root to rounding, within the 4e-13 bound of the paper's
+// 40-step bisection.
 template <class G>
 __host__ __device__ inline G plic_offset(G nx, G ny, G nz, G phi)
 {
@@ -103,22 +107,45 @@ __host__ __device__ inline G plic_offset(G nx, G ny, G nz, G phi)
     if (m0 > m1) { const G t = m0; m0 = m1; m1 = t; }
     if (m1 > m2) { const G t = m1; m1 = m2; m2 = t; }
     if (m0 > m1) { const G t = m0; m0 = m1; m1 = t; }
-    const CubeCut<G> cut(m0, m1, m2);
-    const G tol = sizeof(G) == 8 ? G(1e-15) : G(2e-7);
-    G lo = 0, hi = 1, t = phi;
-    for (int it = 0; it < 64; ++it) {
-        G v, dv;
-        cut.eval(t, v, dv);
-        v -= phi;
-        if (v <= G(0)) lo = t;  // V(lo) <= phi
-        else hi = t;            // V(hi) > phi
-        if (v == G(0) || hi - lo <= tol) break;
-        G tn = dv > G(0) ? t - v / dv : G(-1);
-        if (!(tn > lo && tn < hi)) tn = G(0.5) * (lo + hi);
-        const G step = fabs(tn - t);
-        t = tn;
-        if (step <= tol) break;
+    const G s1 = m0, s2 = m1, s3 = m2;
+    const bool flip = phi > G(0.5);
+    const G p = flip ? G(1) - phi : phi;
+    G t;
+    if (!(s2 > G(0))) {
+        t = p;  // normal along an axis: V(t) = t
+    } else {
+        const G d = G(6) * s2 * s3;
+        const G v1 = s1 * s1 / d;                                   // V(s1)
+        const G v2 = (G(3) * s2 * s2 - G(3) * s2 * s1 + s1 * s1) / d;  // V(s2)
+        const G wedge = (G(3) * s1 + sqrt(fmax(G(12) * d * p - G(3) * s1 * s1, G(0)))) / G(6);
+        const G s12 = s1 + s2;
+        if (p <= v1) {
+            t = cbrt(d * s1 * p);
+        } else if (p <= v2) {
+            t = wedge;
+        } else if (s12 <= G(0.5) && p >= s12 / (G(2) * s3)) {
+            t = s3 * p + G(0.5) * s12;
+        } else {
+            const CubeCut<G> cut(s1, s2, s3);
+            const G tol = sizeof(G) == 8 ? G(1e-15) : G(2e-7);
+            G lo = s2, hi = fmin(s12, G(0.5));
+            t = fmin(fmax(wedge, lo), hi);
+            for (int it = 0; it < 40; ++it) {
+                G v, dv;
+                cut.eval(t, v, dv);
+                v -= p;
+                if (v <= G(0)) lo = t;  // V(lo) <= p
+                else hi = t;            // V(hi) > p
+                if (v == G(0) || hi - lo <= tol) break;
+                G tn = dv > G(0) ? t - v / dv : G(-1);
+                if (!(tn > lo && tn < hi)) tn = G(0.5) * (lo + hi);
+                const G step = fabs(tn - t);
+                t = tn;
+                if (step <= tol) break;
+            }
+        }
     }
+    if (flip) t = G(1) - t;
     return l1 * (G(0.5) - t);
 }
 

@@ -315,7 +315,7 @@ __device__ inline void fluid_cell(const Fields<P> &F, const Params &prm, int i, 
 // takes one contiguous run of the box, so the rows it pulls from stay in
 // one XCD's L2.
 template <class P, int COLL, int MODE>
-__global__ __launch_bounds__(256) void k_stream_collide(const Batch<P> B)
+__device__ inline void stream_collide_box(const Batch<P> &B)
 {
     const Params &prm = B.p[blockIdx.y];
     if (prm.coll != COLL) return;
@@ -349,6 +349,27 @@ __global__ __launch_bounds__(256) void k_stream_collide(const Batch<P> B)
             }
         }
     }
+}
+
+// FP32 arithmetic: 4 waves per SIMD (the boundary path then fits in 128
+// VGPRs); FP64 keeps the compiler's register choice (it would spill).
+template <class P, int COLL, int MODE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_stream_collide(const Batch<P> B)
+{
+    stream_collide_box<P, COLL, MODE>(B);
+}
+template <int COLL, int MODE>
+__global__ __launch_bounds__(256) void k_stream_collide_f64(const Batch<Prec<P_F64>> B)
+{
+    stream_collide_box<Prec<P_F64>, COLL, MODE>(B);
+}
+template <class P, int COLL, int MODE>
+inline void launch_stream_collide(dim3 grid, hipStream_t st, const Batch<P> &A)
+{
+    if constexpr (P::SHIFT == false && sizeof(typename P::T) == 8)
+        k_stream_collide_f64<COLL, MODE><<<grid, 256, 0, st>>>(A);
+    else
+        k_stream_collide<P, COLL, MODE><<<grid, 256, 0, st>>>(A);
 }
 
 // The fluid cells that the lean box pass (MODE 1) leaves out, one thread
