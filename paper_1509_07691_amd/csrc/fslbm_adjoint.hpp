@@ -14,11 +14,13 @@
 // those at t. Every kernel is written as a gather (one writer per value) so
 // the results do not depend on scheduling:
 //   k_adj_prepass      phi_{t+1} = m_{t+1}/rho_{t+1} -> mbar, rhob
-//   k_adj_stream       per fluid cell: transposed collision, mass exchange
-//                      and boundary rules; the adjoint of each pulled value
-//                      is left at the receiving cell (gin), the adjoint of
-//                      the cell's own outgoing values in own, dL/dK in kbar
-//   k_adj_gather       lam_q(x) = own_q(x) + gin_q(x + c_q)
+//   k_adj_stream       per fluid cell: gathers lam_q(x) = own_q(x) +
+//                      gin_q(x + c_q) of the previous reverse step, then the
+//                      transposed collision, mass exchange and boundary
+//                      rules; the adjoint of each pulled value is left at
+//                      the receiving cell (gin), the adjoint of the cell's
+//                      own outgoing values in own (both double-buffered),
+//                      dL/dK in kbar
 //   FD:   k_adj_fd_*   transposed stencils of K = -div(n^), n^ from the
 //                      K8-mollified fill level
 //   LSQR: k_adj_lsqr_* reverse of the least-squares fit per interface cell
@@ -37,9 +39,10 @@
 namespace fslbm {
 
 struct Adj {
-    double *lam;    // 19 planes: dL/df'(t)
+    const double *gin_in, *own_in;  // the previous reverse step's gin and own
     double *gin;    // 19 planes: dL/df_in,q(x), kept at the receiving cell x
     double *own;    // 19 planes: the cell's own share of dL/df'_q(x)
+    double *refl;   // 18 per interface-list entry: transposed reflection weights
     double *mbar;   // dL/dm
     double *phib;   // dL/dphi (at obstacle cells: scratch of the reflection)
     double *rhob;   // dL/drho(t+1) at interface cells
@@ -210,12 +213,12 @@ __device__ inline void cell_adj(const Fields<P> &F, const Adj &A, const Params &
         up[q] = nb.at(-dir_x(q), -dir_y(q), -dir_z(q));
         own[q] = i;
     }
-    double yb[NQ];
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) yb[q] = A.lam[q * N + i];
     double pl[NQ];
     load_dirs_d<P>(F, up, pl);
-    if (fl == FL_LIQ) {  // every upstream node is fluid: plain pull
+    double yb[NQ];  // dL/df'_q(x) = own_q(x) + gin_q(x + c_q) (x + c_q = up[opp(q)])
+    if (fl == FL_LIQ) {  // every neighbour is fluid: plain pull
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) yb[q] = A.gin_in[q * N + up[opp(q)]];
         double fb[NQ];
         collide_adj<COLL>(pl, yb, prm, fb);
 #pragma unroll
@@ -229,6 +232,9 @@ __device__ inline void cell_adj(const Fields<P> &F, const Adj &A, const Params &
     nt[0] = FL_LIQ;
 #pragma unroll
     for (int q = 1; q < NQ; ++q) nt[q] = F.flags[up[q]] & FL_TYPE;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+        yb[q] = A.own_in[q * N + i] + ((nt[opp(q)] & FL_FLUID) ? A.gin_in[q * N + up[opp(q)]] : 0.0);
     double Kc = 0, phx = 0, cnx = 0, cny = 0, cnz = 0;
     if (is_if) {
         Kc = double(F.K[i]);
@@ -357,32 +363,6 @@ __global__ __launch_bounds__(256) void k_adj_stream(const Fields<P> F, const Adj
     }
 }
 
-// lam_q(x) = own_q(x) + gin_q(x + c_q) (the downstream cell pulled f'_q(x)).
-template <class P>
-__global__ __launch_bounds__(256) void k_adj_gather(const Fields<P> F, const Adj A)
-{
-    const CellRange box = CellRange::from(F.sc->fbox);
-    const int n = box.size();
-    const int nxy = F.nx * F.ny;
-    const size_t N = F.N;
-    for (int k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256) {
-        const int bx = k % box.ex, r = k / box.ex, by = r % box.ey, bz = r / box.ey;
-        const int x = box.x0 + bx, y = box.y0 + by, z = box.z0 + bz;
-        const int i = x + F.nx * y + nxy * z;
-        const uint8_t fl = F.flags[i];
-        if (!(fl & FL_FLUID)) continue;
-        const Nbr nb(x, y, z, F.nx, F.ny, F.nz);
-        const bool has_own = fl != FL_LIQ;
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            const int d = nb.at(dir_x(q), dir_y(q), dir_z(q));
-            double v = has_own ? A.own[q * N + i] : 0.0;
-            if (F.flags[d] & FL_FLUID) v += A.gin[q * N + d];
-            A.lam[q * N + i] = v;
-        }
-    }
-}
-
 // ------------------------------------------------ FD curvature (reverse)
 // Forward (Sec. II.A): ms = K8 * phi / 942, g = PY(ms), n = g/|g|,
 // K = -(PY_x n_x + PY_y n_y + PY_z n_z)/32 at interface cells. Each PY
@@ -483,18 +463,21 @@ __global__ __launch_bounds__(256) void k_adj_fd_phib(const Fields<P> F, const Ad
 // --------------------------------------- obstacle fill reflection (reverse)
 // phi(o) = sum_j w_oj phi(j) / sum_j w_oj over fluid neighbours j with
 // aperture w_oj > sqrt(2)/2; interface cell i gathers phib(o) w_oi / den_o
-// from each obstacle neighbour o.
+// from each obstacle neighbour o. The weights depend on the cell types only,
+// so they are computed once per reverse sweep (k_adj_reflect_setup).
 template <class P>
-__global__ __launch_bounds__(256) void k_adj_reflect(const Fields<P> F, const Adj A)
+__global__ __launch_bounds__(256) void k_adj_reflect_setup(const Fields<P> F, const Adj A)
 {
     const int n = F.sc->icount;
     const double alpha = 0.70710678118654752440 + 1e-12;
     for (int k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256) {
         const int i = F.ilist[k];
-        if (!(F.flags[i] & FL_NEAR_OBST)) continue;
+        double *c = A.refl + (size_t)(NQ - 1) * k;
+        const bool near = (F.flags[i] & FL_NEAR_OBST) != 0;
         const Nbr ni(i, F.nx, F.ny, F.nz);
-        double acc = 0.0;
         for (int q = 1; q < NQ; ++q) {
+            c[q - 1] = 0.0;
+            if (!near) continue;
             const int o = ni.at(dir_x(q), dir_y(q), dir_z(q));
             if (!(F.flags[o] & FL_OBST)) continue;
             const Nbr no(o, F.nx, F.ny, F.nz);
@@ -517,8 +500,24 @@ __global__ __launch_bounds__(256) void k_adj_reflect(const Fields<P> F, const Ad
                     if (p == opp(q)) wi = w;  // o + c_p = i
                 }
             }
-            if (den > 0.0 && wi > 0.0) acc += A.phib[o] * wi / den;
+            if (den > 0.0 && wi > 0.0) c[q - 1] = wi / den;
         }
+    }
+}
+
+template <class P>
+__global__ __launch_bounds__(256) void k_adj_reflect(const Fields<P> F, const Adj A)
+{
+    const int n = F.sc->icount;
+    for (int k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256) {
+        const int i = F.ilist[k];
+        if (!(F.flags[i] & FL_NEAR_OBST)) continue;
+        const Nbr ni(i, F.nx, F.ny, F.nz);
+        const double *c = A.refl + (size_t)(NQ - 1) * k;
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 1; q < NQ; ++q)
+            if (c[q - 1] != 0.0) acc += A.phib[ni.at(dir_x(q), dir_y(q), dir_z(q))] * c[q - 1];
         A.phib[i] += acc;
     }
 }
@@ -1025,29 +1024,44 @@ __global__ __launch_bounds__(256) void k_adj_lsqr_cell(const Fields<P> F, const 
     }
 }
 
-// Per interface cell j: gather dL/dn_j, dL/da_j over the blocks containing
-// j, pass dL/da_j through the PLIC offset (into phib and dL/dn_j) and dL/dn_j
+// Per interface cell j, 8 lanes: gather dL/dn_j, dL/da_j over the blocks
+// containing j (lane l takes the block offsets s = l, l + 8, ...) and the
+// Parker-Youngs gradient g of phi at j (the same split); lane 0 then passes
+// dL/da_j through the PLIC offset (into phib and dL/dn_j) and dL/dn_j
 // through n = g/|g| into gb.
 template <class P>
 __global__ __launch_bounds__(256) void k_adj_lsqr_plic(const Fields<P> F, const Adj A)
 {
     const int n = F.sc->icount;
     const size_t N = F.N;
-    for (int k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256) {
+    const int lane = threadIdx.x % ADJ_LANES;
+    constexpr int per_block = 256 / ADJ_LANES;
+    for (int k = blockIdx.x * per_block + threadIdx.x / ADJ_LANES; k < n; k += gridDim.x * per_block) {
         const int j = F.ilist[k];
         const Nbr nb(j, F.nx, F.ny, F.nz);
-        double nbar[3] = {0, 0, 0}, abar = 0;
-        for (int c = -1; c <= 1; ++c)
-            for (int b = -1; b <= 1; ++b)
-                for (int a = -1; a <= 1; ++a) {
-                    const int i = nb.at(-a, -b, -c);  // j = i + (a, b, c)
-                    if (!(F.flags[i] & FL_IF)) continue;
-                    const double *cs = A.contrib + (size_t)CONTRIB * A.pos[i] + 4 * slot27(a, b, c);
-                    nbar[0] += cs[0];
-                    nbar[1] += cs[1];
-                    nbar[2] += cs[2];
-                    abar += cs[3];
-                }
+        double nbar[3] = {0, 0, 0}, abar = 0, g[3] = {0, 0, 0};
+        for (int s = lane; s < 27; s += ADJ_LANES) {
+            const int a = s % 3 - 1, b = (s / 3) % 3 - 1, c = s / 9 - 1;
+            const int i = nb.at(-a, -b, -c);  // j = i + (a, b, c)
+            if (F.flags[i] & FL_IF) {
+                const double *cs = A.contrib + (size_t)CONTRIB * A.pos[i] + 4 * s;
+                nbar[0] += cs[0];
+                nbar[1] += cs[1];
+                nbar[2] += cs[2];
+                abar += cs[3];
+            }
+            // PY weights: central difference along one axis, (1, 2, 1) across
+            const double ph = double(F.phi[nb.at(a, b, c)]);
+            g[0] += a * pyw(b) * pyw(c) * ph;
+            g[1] += b * pyw(a) * pyw(c) * ph;
+            g[2] += c * pyw(a) * pyw(b) * ph;
+        }
+        for (int d = 0; d < 3; ++d) {
+            nbar[d] = group_sum<ADJ_LANES>(nbar[d]);
+            g[d] = group_sum<ADJ_LANES>(g[d]);
+        }
+        abar = group_sum<ADJ_LANES>(abar);
+        if (lane != 0) continue;
         const double nj[3] = {double(F.nrm[j]), double(F.nrm[N + j]), double(F.nrm[2 * N + j])};
         double o[3] = {0, 0, 0};
         if (nj[0] != 0.0 || nj[1] != 0.0 || nj[2] != 0.0) {
@@ -1055,11 +1069,9 @@ __global__ __launch_bounds__(256) void k_adj_lsqr_plic(const Fields<P> F, const 
             plic_derivs(nj, double(F.phi[j]), double(F.plic[j]), dphi, dn);
             A.phib[j] += abar * dphi;
             for (int d = 0; d < 3; ++d) nbar[d] += abar * dn[d];
-            double gx, gy, gz;
-            py_grad(F.phi, nb, gx, gy, gz);
-            const double len = sqrt(gx * gx + gy * gy + gz * gz);
+            const double len = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
             if (len > 1e-12) {
-                const double u[3] = {gx / len, gy / len, gz / len};
+                const double u[3] = {g[0] / len, g[1] / len, g[2] / len};
                 const double d = dot(nbar, u);
                 for (int e = 0; e < 3; ++e) o[e] = (nbar[e] - d * u[e]) / len;
             }

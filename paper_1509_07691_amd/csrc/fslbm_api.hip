@@ -126,7 +126,7 @@ struct AdjWindow {
     std::vector<long long> ck;  // checkpoint times 0, K, 2K, ..., T
     size_t f_bytes = 0, snap_bytes = 0, slot_bytes = 0;
     size_t off_ck = 0, off_ring = 0;
-    size_t off_lam = 0, off_gin = 0, off_own = 0, off_scal = 0, off_gb = 0, off_contrib = 0, off_pos = 0,
+    size_t off_gin[2] = {0, 0}, off_own[2] = {0, 0}, off_refl = 0, off_scal = 0, off_gb = 0, off_contrib = 0, off_pos = 0,
            off_part = 0, total = 0;
 };
 
@@ -941,9 +941,11 @@ size_t adj_layout(AdjWindow &w, const fslbm_lattice *h)
         off = align256(off + bytes);
         return o;
     };
-    w.off_lam = take(19 * N * 8);
-    w.off_gin = take(19 * N * 8);
-    w.off_own = take(19 * N * 8);
+    for (int b = 0; b < 2; ++b) {
+        w.off_gin[b] = take(19 * N * 8);
+        w.off_own[b] = take(19 * N * 8);
+    }
+    w.off_refl = take((size_t)(NQ - 1) * std::max(1, w.icount) * 8);
     w.off_scal = take(8 * N * 8);  // mbar phib rhob kbar sacc tacc ms msb
     w.off_gb = take(3 * N * 8);
     w.off_contrib = take((size_t)CONTRIB * std::max(1, w.icount) * 8);
@@ -962,14 +964,18 @@ size_t adj_layout(AdjWindow &w, const fslbm_lattice *h)
     return off;
 }
 
-Adj adj_fields(const AdjWindow &w, const fslbm_lattice *h)
+// Adjoint fields; gin / own of the previous reverse step are read from
+// buffer `par` and written to buffer 1 - par.
+Adj adj_fields(const AdjWindow &w, const fslbm_lattice *h, int par)
 {
     const size_t N = h->N;
     char *b = w.ws;
     Adj A;
-    A.lam = (double *)(b + w.off_lam);
-    A.gin = (double *)(b + w.off_gin);
-    A.own = (double *)(b + w.off_own);
+    A.gin_in = (const double *)(b + w.off_gin[par]);
+    A.own_in = (const double *)(b + w.off_own[par]);
+    A.gin = (double *)(b + w.off_gin[1 - par]);
+    A.own = (double *)(b + w.off_own[1 - par]);
+    A.refl = (double *)(b + w.off_refl);
     double *s = (double *)(b + w.off_scal);
     A.mbar = s;
     A.phib = s + N;
@@ -1078,8 +1084,9 @@ int enqueue_geometry_adjoint(fslbm_lattice *h, const Fields<P> &F, const Adj &A,
         k_adj_fd_msb<P><<<cg, 256, 0, st>>>(F, A);
         k_adj_fd_phib<P><<<cg, 256, 0, st>>>(F, A);
     } else {
-        k_adj_lsqr_cell<P><<<lg, 256, 0, st>>>(F, A, prm);
-        k_adj_lsqr_plic<P><<<lg, 256, 0, st>>>(F, A);
+        const int l8 = std::min(2048, std::max(1, (h->adj.icount + 31) / 32));  // 32 cells per block
+        k_adj_lsqr_cell<P><<<l8, 256, 0, st>>>(F, A, prm);
+        k_adj_lsqr_plic<P><<<l8, 256, 0, st>>>(F, A);
         k_adj_lsqr_phib<P><<<lg, 256, 0, st>>>(F, A);
     }
     k_adj_reflect<P><<<lg, 256, 0, st>>>(F, A);
@@ -1095,9 +1102,13 @@ int do_adj_backward(fslbm_lattice *h, const double *dphi, int in_dev, double *ds
     const hipStream_t st = h->stream;
     const int N = h->N;
     const int cg = std::min(4096, cell_blocks(N)), lg = list_blocks(N);
-    const Adj A = adj_fields(w, h);
-    // adjoint state at T: lam = 0, mbar = 0, phib = dL/dphi_T
-    k_adj_zero<<<4096, 256, 0, st>>>(A.lam, 19 * (size_t)N);
+    int par = 0;
+    Adj A = adj_fields(w, h, par);
+    // adjoint state at T: lam = 0 (gin = own = 0), mbar = 0, phib = dL/dphi_T
+    for (int b = 0; b < 2; ++b) {
+        k_adj_zero<<<4096, 256, 0, st>>>((double *)(w.ws + w.off_gin[b]), 19 * (size_t)N);
+        k_adj_zero<<<4096, 256, 0, st>>>((double *)(w.ws + w.off_own[b]), 19 * (size_t)N);
+    }
     k_adj_zero<<<4096, 256, 0, st>>>((double *)(w.ws + w.off_scal), 8 * (size_t)N);
     k_adj_zero<<<4096, 256, 0, st>>>(A.gb, 3 * (size_t)N);
     HIP_OK(hipGetLastError());
@@ -1110,6 +1121,7 @@ int do_adj_backward(fslbm_lattice *h, const double *dphi, int in_dev, double *ds
     {
         const Fields<P> F = make_fields<P>(h);
         k_adj_begin<P><<<lg, 256, 0, st>>>(F, A, src);
+        k_adj_reflect_setup<P><<<lg, 256, 0, st>>>(F, A);
         HIP_OK(hipGetLastError());
     }
     h->frozen = 1;
@@ -1136,9 +1148,10 @@ int do_adj_backward(fslbm_lattice *h, const double *dphi, int in_dev, double *ds
             k_adj_prepass<P><<<lg, 256, 0, st>>>(F, A, (const typename P::R *)nxt.snap);
             k_snap<P><<<lg, 256, 0, st>>>(F, (typename P::R *)cur.snap, 0);
             F.fsrc = (const typename P::S *)cur.f;
+            A = adj_fields(w, h, par);
             if (h->coll == FSLBM_SRT) k_adj_stream<P, 0><<<cg, 256, 0, st>>>(F, A, prm);
             else k_adj_stream<P, 1><<<cg, 256, 0, st>>>(F, A, prm);
-            k_adj_gather<P><<<cg, 256, 0, st>>>(F, A);
+            par ^= 1;
             HIP_OK(hipGetLastError());
             rc = enqueue_geometry_adjoint<P>(h, F, A, prm);
         }
