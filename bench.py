@@ -194,6 +194,41 @@ def adjoint_cost(dev, stream, steps, K, precision):
             "workspace_GB": round(ws_gb, 2)}
 
 
+def advection_table(dev, precision):
+    """Pure advection test of Sec. III.A (sigma = 0, f = feq(1, u0)): a gas
+    bubble of diameter d in a periodic 3d x 2d x 2d box translated by d along
+    x, for d = 10, 20, 40, 80 under convective (u0 = 0.05) and diffusive
+    (u0 = 0.05 * 10 / d) scaling; L1 and L2 errors of phi."""
+    import torch
+    from paper_1509_07691_amd import inputs as I
+    from paper_1509_07691_amd.fslbm import Lattice
+
+    rows = []
+    for d in (10, 20, 40, 80):
+        fill, obst = I.advected_bubble(d)
+        for scaling, u0 in (("convective", 0.05), ("diffusive", 0.05 * 10 / d)):
+            if scaling == "diffusive" and d == 10:
+                rows.append(dict(rows[-1], scaling="diffusive"))
+                continue
+            lat = Lattice(fill, obst, precision=precision, curv_model="fd", sigma=0.0, tau=1.0, device=dev)
+            u = np.zeros((3,) + fill.shape)
+            u[0] = u0
+            lat.set_equilibrium(1.0, u)
+            T = int(round(d / u0))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            lat.step(T)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            l1, l2 = I.advection_errors(fill, lat.fill(), d)
+            rows.append({"d": d, "scaling": scaling, "u0": u0, "steps": T, "L1": round(l1, 5), "L2": round(l2, 5),
+                         "ms_per_step": round(1e3 * el / T, 4)})
+            print(f"# advection d={d} {scaling}: L1 {l1:.4f} L2 {l2:.4f}", file=sys.stderr, flush=True)
+            lat.close()
+            torch.cuda.empty_cache()
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -215,6 +250,8 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=2000,
                     help="steps of the differentiation window timed for the adjoint cost (0: skip)")
     ap.add_argument("--adjoint-k", type=int, default=100, help="checkpoint interval of that window")
+    ap.add_argument("--advection", action="store_true",
+                    help="only run the pure advection test table (d = 10..80) and print it")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
@@ -233,6 +270,9 @@ def main():
     from paper_1509_07691_amd.fslbm import Batch, Lattice
 
     dev = torch.device("cuda:0")
+    if args.advection:
+        print(json.dumps({"advection": advection_table(dev, "f64")}))
+        return
     if args.copy_calibration:
         # a plain elementwise copy: 1 GiB read and 1 GiB written per launch
         src = torch.ones(1 << 28, dtype=torch.float32, device=dev)

@@ -212,3 +212,23 @@ def test_batch_and_graph_replay_match_eager_steps(Lattice):
                 np.testing.assert_array_equal(a, d)
     for bb in (b1, b2, b3):
         bb.close()
+
+
+def test_advection_test_fp64(Lattice):
+    """Pure advection (Sec. III.A): sigma = 0, f = feq(1, u0), gas bubble of
+    diameter 10 translated by its diameter; cell types, interface lists and
+    fill levels against the oracle."""
+    d, u0 = 10, 0.05
+    fill, obst = I.advected_bubble(d)
+    g, o = pair(Lattice, fill, obst, "fd", sigma=0.0, tau=1.0)
+    u = np.zeros((3,) + fill.shape)
+    u[0] = u0
+    g.set_equilibrium(1.0, u)
+    o.set_equilibrium(np.ones(fill.shape), u)
+    for n in (50, 150):
+        g.step(n)
+        o.step(n)
+        compare(g, o, 1e-10, what=f"advection after +{n}")
+    l1g = I.advection_errors(fill, g.fill(), d)
+    l1o = I.advection_errors(fill, o.fill(), d)
+    assert abs(l1g[0] - l1o[0]) < 1e-12 and abs(l1g[1] - l1o[1]) < 1e-12
