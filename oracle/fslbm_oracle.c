@@ -465,6 +465,55 @@ static void normals_and_plic(orc_lattice *L)
     }
 }
 
+/* FD wetting (Sec. II.A, eq. contactNormal). At an obstacle cell x_o next
+ * to the fluid, w is the normalised sum of the directions to its
+ * non-obstacle neighbours (out of the wall) and x_b = x_o + c_b the neighbour
+ * along the lattice direction closest to w (the first one on ties). When x_b
+ * is an interface cell with mollified unit normal n_b, the wall value
+ * m = n_w cos(theta) + n_t sin(theta), with n_w = -w (into the wall) and n_t
+ * the normalised projection of n_b onto the wall, is extrapolated linearly
+ * to the obstacle node, which lies half a cell beyond the wall on the line
+ * from x_b: n(x_o) = normalise(2 m - n_b). The normals of the other cells,
+ * and those of x_b themselves, are left as computed. nm holds three planes. */
+static void fd_contact_normals(const orc_lattice *L, double *nm)
+{
+    const long n = L->n;
+    const double ct = cos(L->p.theta), st = sin(L->p.theta);
+    for (long i = 0; i < n; ++i) {
+        if (L->type[i] != ORC_OBSTACLE) continue;
+        double w[3] = {0, 0, 0};
+        for (int q = 1; q < NQ; ++q)
+            if (L->type[nbr(L, i, CX[q], CY[q], CZ[q])] != ORC_OBSTACLE) {
+                w[0] += CX[q]; w[1] += CY[q]; w[2] += CZ[q];
+            }
+        const double lw = sqrt(dot3(w, w));
+        if (lw <= 0.0) continue;
+        for (int k = 0; k < 3; ++k) w[k] /= lw;
+        int qb = 0;
+        double best = -2.0;
+        for (int q = 1; q < NQ; ++q) {
+            const double cl = sqrt((double)(CX[q] * CX[q] + CY[q] * CY[q] + CZ[q] * CZ[q]));
+            const double a = (CX[q] * w[0] + CY[q] * w[1] + CZ[q] * w[2]) / cl;
+            if (a > best) { best = a; qb = q; }
+        }
+        const long j = nbr(L, i, CX[qb], CY[qb], CZ[qb]);
+        if (L->type[j] != ORC_INTERFACE) continue;
+        const double nb[3] = {nm[j], nm[n + j], nm[2 * n + j]};
+        if (dot3(nb, nb) == 0.0) continue;
+        const double nw[3] = {-w[0], -w[1], -w[2]};
+        const double nn = dot3(nb, nw);
+        double nt[3] = {nb[0] - nn * nw[0], nb[1] - nn * nw[1], nb[2] - nn * nw[2]};
+        const double lt = sqrt(dot3(nt, nt));
+        if (lt < 1e-12) continue;
+        for (int k = 0; k < 3; ++k) nt[k] /= lt;
+        double e[3];
+        for (int k = 0; k < 3; ++k) e[k] = 2.0 * (nw[k] * ct + nt[k] * st) - nb[k];
+        const double le = sqrt(dot3(e, e));
+        if (le < 1e-12) continue;
+        for (int k = 0; k < 3; ++k) nm[k * n + i] = e[k] / le;
+    }
+}
+
 /* FD curvature (Sec. II.A): mollify phi with the K8 kernel of support
  * eps = 2 (Williams 1998), K8(r) ~ (1 - r^2/eps^2)^4, on the 27 points of the
  * 3x3x3 block: weights 256, 81, 16, 1 for distance 0, 1, sqrt2, sqrt3,
@@ -492,6 +541,7 @@ static void curvature_fd(orc_lattice *L)
         double len = sqrt(dot3(g, g));
         for (int k = 0; k < 3; ++k) nm[k * n + i] = len > 1e-12 ? g[k] / len : 0.0;
     }
+    fd_contact_normals(L, nm);
     for (long i = 0; i < n; ++i) {
         L->K[i] = 0.0;
         if (L->type[i] != ORC_INTERFACE) continue;

@@ -384,32 +384,133 @@ __global__ __launch_bounds__(256) void k_adj_fd_mol(const Fields<P> F, const Adj
     }
 }
 
-// gb = (I - n n^T) nbar / |g| with nbar = PY(kbar)/32.
+// Reverse of the FD contact normal n = normalise(2 m - n_b), m = n_w
+// cos(theta) + n_t sin(theta), n_t = normalise(n_b - (n_b.n_w) n_w): given
+// nbar = dL/dn, adds dL/dn_b to nbb and dL/dtheta to thb. Returns false
+// (nothing added) where the forward kept the mollified normal.
+__device__ inline bool fd_contact_normal_adj(const double (&w)[3], const double (&nb)[3], double ct, double st,
+                                             const double (&ob)[3], double (&nbb)[3], double &thb)
+{
+    const double nw[3] = {-w[0], -w[1], -w[2]};
+    const double nn = nb[0] * nw[0] + nb[1] * nw[1] + nb[2] * nw[2];
+    const double ntr[3] = {nb[0] - nn * nw[0], nb[1] - nn * nw[1], nb[2] - nn * nw[2]};
+    const double lt = sqrt(dot(ntr, ntr));
+    if (lt < 1e-12) return false;
+    const double nt[3] = {ntr[0] / lt, ntr[1] / lt, ntr[2] / lt};
+    double e[3];
+    for (int k = 0; k < 3; ++k) e[k] = 2.0 * (nw[k] * ct + nt[k] * st) - nb[k];
+    const double le = sqrt(dot(e, e));
+    if (le < 1e-12) return false;
+    const double no[3] = {e[0] / le, e[1] / le, e[2] / le};
+    const double on = dot(ob, no);
+    double eb[3], mb[3];
+    for (int k = 0; k < 3; ++k) {
+        eb[k] = (ob[k] - on * no[k]) / le;
+        mb[k] = 2.0 * eb[k];
+        nbb[k] -= eb[k];
+    }
+    thb += -st * dot(mb, nw) + ct * dot(mb, nt);
+    const double ntb[3] = {st * mb[0], st * mb[1], st * mb[2]};
+    const double tt = dot(ntb, nt);
+    double trb[3];
+    for (int k = 0; k < 3; ++k) trb[k] = (ntb[k] - tt * nt[k]) / lt;
+    const double tw = dot(trb, nw);
+    for (int k = 0; k < 3; ++k) nbb[k] += trb[k] - tw * nw[k];
+    return true;
+}
+
+// Base direction qb of obstacle cell o for FD wetting (0: no contact
+// normal): the lattice direction closest to the normalised sum w of the
+// directions to o's non-obstacle neighbours, when o + c_qb is an interface
+// cell (the forward rule, in FP64).
 template <class P>
-__global__ __launch_bounds__(256) void k_adj_fd_nbar(const Fields<P> F, const Adj A)
+__device__ inline int fd_contact_base_d(const Fields<P> &F, const Nbr &no, double (&w)[3])
+{
+    int sx = 0, sy = 0, sz = 0;
+    for (int q = 1; q < NQ; ++q)
+        if (!(F.flags[no.at(dir_x(q), dir_y(q), dir_z(q))] & FL_OBST)) {
+            sx += dir_x(q); sy += dir_y(q); sz += dir_z(q);
+        }
+    const double lw = sqrt(double(sx * sx + sy * sy + sz * sz));
+    if (!(lw > 0.0)) return 0;
+    w[0] = sx / lw; w[1] = sy / lw; w[2] = sz / lw;
+    int qb = 0;
+    double best = -2.0;
+    for (int q = 1; q < NQ; ++q) {
+        const double cl = sqrt(double(dir_len2(q)));
+        const double a = (dir_x(q) * w[0] + dir_y(q) * w[1] + dir_z(q) * w[2]) / cl;
+        if (a > best) { best = a; qb = q; }
+    }
+    return (F.flags[no.at(dir_x(qb), dir_y(qb), dir_z(qb))] & FL_IF) ? qb : 0;
+}
+
+__device__ inline bool unit_of(const double g[3], double (&n)[3], double &len)
+{
+    len = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+    if (!(len > 1e-12)) return false;
+    n[0] = g[0] / len; n[1] = g[1] / len; n[2] = g[2] / len;
+    return true;
+}
+
+// gb = (I - n n^T) nbar / |g| with nbar = PY(kbar)/32. With FD wetting an
+// obstacle cell whose normal is the contact normal gets gb = 0, and its nbar
+// goes through the contact normal to its base interface cell (gathered
+// there) and to theta (tacc of the base cell).
+template <class P>
+__global__ __launch_bounds__(256) void k_adj_fd_nbar(const Fields<P> F, const Adj A, const Params prm)
 {
     const size_t N = F.N;
+    const bool walls = F.sc->ocount > 0;
     for (int i = blockIdx.x * 256 + threadIdx.x; i < F.N; i += gridDim.x * 256) {
         const Nbr nb(i, F.nx, F.ny, F.nz);
-        double bx, by, bz;
-        py_grad(A.kbar, nb, bx, by, bz);
-        double o0 = 0.0, o1 = 0.0, o2 = 0.0;
-        if (bx != 0.0 || by != 0.0 || bz != 0.0) {
-            bx /= 32.0; by /= 32.0; bz /= 32.0;
-            double gx, gy, gz;
-            py_grad(A.ms, nb, gx, gy, gz);
-            const double len = sqrt(gx * gx + gy * gy + gz * gz);
-            if (len > 1e-12) {
-                const double nx = gx / len, ny = gy / len, nz = gz / len;
-                const double d = bx * nx + by * ny + bz * nz;
-                o0 = (bx - d * nx) / len;
-                o1 = (by - d * ny) / len;
-                o2 = (bz - d * nz) / len;
+        const uint8_t fl = F.flags[i];
+        double b[3];
+        py_grad(A.kbar, nb, b[0], b[1], b[2]);
+        for (int k = 0; k < 3; ++k) b[k] /= 32.0;
+        double o[3] = {0.0, 0.0, 0.0};
+        bool overridden = false;
+        if (walls && (fl & FL_OBST)) {
+            double w[3];
+            const int qb = fd_contact_base_d(F, nb, w);
+            if (qb) {
+                const Nbr nj(nb.at(dir_x(qb), dir_y(qb), dir_z(qb)), F.nx, F.ny, F.nz);
+                double g[3], n[3], len, nbb[3] = {0, 0, 0}, thb = 0.0;
+                py_grad(A.ms, nj, g[0], g[1], g[2]);
+                const double ob[3] = {0, 0, 0};
+                overridden = unit_of(g, n, len) && fd_contact_normal_adj(w, n, prm.cos_theta, prm.sin_theta, ob, nbb, thb);
             }
         }
-        A.gb[i] = o0;
-        A.gb[N + i] = o1;
-        A.gb[2 * N + i] = o2;
+        if (!overridden && walls && (fl & FL_IF) && (fl & FL_NEAR_OBST)) {
+            // obstacle neighbours o = i - c_q whose base cell is i
+            double g[3], n[3], len;
+            py_grad(A.ms, nb, g[0], g[1], g[2]);
+            if (unit_of(g, n, len)) {
+                double thb = 0.0;
+                for (int q = 1; q < NQ; ++q) {
+                    const int oc = nb.at(-dir_x(q), -dir_y(q), -dir_z(q));
+                    if (!(F.flags[oc] & FL_OBST)) continue;
+                    const Nbr no(oc, F.nx, F.ny, F.nz);
+                    double w[3];
+                    if (fd_contact_base_d(F, no, w) != q) continue;
+                    double ob[3];
+                    py_grad(A.kbar, no, ob[0], ob[1], ob[2]);
+                    for (int k = 0; k < 3; ++k) ob[k] /= 32.0;
+                    fd_contact_normal_adj(w, n, prm.cos_theta, prm.sin_theta, ob, b, thb);
+                }
+                A.tacc[i] += thb;
+            }
+        }
+        if (!overridden && (b[0] != 0.0 || b[1] != 0.0 || b[2] != 0.0)) {
+            double g[3], n[3], len;
+            py_grad(A.ms, nb, g[0], g[1], g[2]);
+            if (unit_of(g, n, len)) {
+                const double d = b[0] * n[0] + b[1] * n[1] + b[2] * n[2];
+                for (int k = 0; k < 3; ++k) o[k] = (b[k] - d * n[k]) / len;
+            }
+        }
+        A.gb[i] = o[0];
+        A.gb[N + i] = o[1];
+        A.gb[2 * N + i] = o[2];
     }
 }
 

@@ -55,7 +55,8 @@ size_t fbytes(int prec)
 size_t rbytes(int prec) { return prec == P_F64 ? 8 : 4; }
 
 struct Layout {
-    size_t fA, fB, flags, conv, mark, m, rho, phi, K, nrm, plic, share, phis, nmol, ilist, olist, wlist, newlist, ilist_tmp,
+    size_t fA, fB, flags, conv, mark, m, rho, phi, K, nrm, plic, share, phis, nmol, cnrm, ilist, olist, wlist, newlist,
+        ilist_tmp,
         staging,
         counts, part, sc, total;
 };
@@ -86,6 +87,7 @@ Layout make_layout(long long N, int prec)
     L.share = take(N * rb);
     L.phis = take(N * rb);
     L.nmol = take(3 * N * rb);
+    L.cnrm = take(3 * N * rb);
     L.ilist = take(4 * N);
     L.olist = take(4 * N);
     L.wlist = take(4 * N);
@@ -216,6 +218,7 @@ Fields<P> make_fields(const fslbm_lattice *h)
     F.share = (R *)(w + L.share);
     F.phis = (R *)(w + L.phis);
     F.nmol = (R *)(w + L.nmol);
+    F.cnrm = (R *)(w + L.cnrm);
     F.ilist = (int32_t *)(w + L.ilist);
     F.olist = (int32_t *)(w + L.olist);
     F.wlist = (int32_t *)(w + L.wlist);
@@ -306,6 +309,7 @@ __global__ void k_init_fields(Fields<P> F, const double *fill, const uint8_t *ty
     for (int c = 0; c < 3; ++c) {
         F.nrm[c * N + i] = 0;
         F.nmol[c * N + i] = 0;
+        F.cnrm[c * N + i] = 0;
     }
     F.mark[i] = 0;
     typename P::S *dst = F.fdst;
@@ -571,6 +575,7 @@ int enqueue_geometry(const fslbm_batch *b, const Batch<P> &A, int maxN)
         any_lsqr |= h->curv == FSLBM_CURV_LSQR;
     }
     const dim3 cg4(batch_list_blocks(b, 64), n);
+    if (any_fd) k_fd_contact_normals<P><<<dim3(list_blocks(maxN), n), 256, 0, st>>>(A);
     if (any_fd && any_lsqr) {
         k_geometry_mixed<P><<<tg, 256, 0, st>>>(A);
         k_curv_lsqr4<P><<<cg4, 256, 0, st>>>(A);
@@ -1080,7 +1085,7 @@ int enqueue_geometry_adjoint(fslbm_lattice *h, const Fields<P> &F, const Adj &A,
     const int cg = std::min(4096, cell_blocks(N)), lg = list_blocks(N);
     if (h->curv == FSLBM_CURV_FD) {
         k_adj_fd_mol<P><<<cg, 256, 0, st>>>(F, A);
-        k_adj_fd_nbar<P><<<cg, 256, 0, st>>>(F, A);
+        k_adj_fd_nbar<P><<<cg, 256, 0, st>>>(F, A, prm);
         k_adj_fd_msb<P><<<cg, 256, 0, st>>>(F, A);
         k_adj_fd_phib<P><<<cg, 256, 0, st>>>(F, A);
     } else {

@@ -178,6 +178,7 @@ template <class P> struct Fields {
     uint8_t *conv;
     uint32_t *mark;
     R *m, *rho, *phi, *K, *nrm, *plic, *share, *phis, *nmol;
+    R *cnrm;           // FD wetting: contact normal of obstacle cells (3 planes, 0 = none)
     int32_t *ilist, *olist;
     int32_t *wlist;    // static: non-obstacle cells with an obstacle D3Q19 neighbour
     int32_t *newlist, *ilist_tmp;  // new interface cells; scratch for the list rebuild

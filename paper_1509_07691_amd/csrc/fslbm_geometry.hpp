@@ -319,6 +319,127 @@ template <class G> struct FdLds {
     G mol[1728];  // mollified phi 12^3 (origin -2)
 };
 
+// Unit normal of the K8-mollified fill level at cell j, from global memory,
+// with the same operations in the same order as the tiled FD kernel.
+template <class P>
+__device__ inline void fd_mollified_normal(const Fields<P> &F, int j, typename P::G (&n)[3])
+{
+    using G = typename P::G;
+    const Nbr nj(j, F.nx, F.ny, F.nz);
+    G m[27];
+#pragma unroll
+    for (int c = -1; c <= 1; ++c)
+#pragma unroll
+        for (int b = -1; b <= 1; ++b)
+#pragma unroll
+            for (int a = -1; a <= 1; ++a) {
+                const Nbr nk(nj.at(a, b, c), F.nx, F.ny, F.nz);
+                G s = G(0);
+#pragma unroll
+                for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+                    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+                        for (int dx = -1; dx <= 1; ++dx)
+                            s += G(k8w(dx * dx + dy * dy + dz * dz)) * G(F.phi[nk.at(dx, dy, dz)]);
+                m[(c + 1) * 9 + (b + 1) * 3 + (a + 1)] = s / G(942);
+            }
+    auto at = [&](int dx, int dy, int dz) { return m[(dz + 1) * 9 + (dy + 1) * 3 + (dx + 1)]; };
+    G gx = G(0), gy = G(0), gz = G(0);
+#pragma unroll
+    for (int a = -1; a <= 1; ++a)
+#pragma unroll
+        for (int b = -1; b <= 1; ++b) {
+            const G w = G(pyw(a) * pyw(b));
+            gx += w * (at(1, a, b) - at(-1, a, b));
+            gy += w * (at(a, 1, b) - at(a, -1, b));
+            gz += w * (at(a, b, 1) - at(a, b, -1));
+        }
+    unit_normal(gx, gy, gz, n);
+}
+
+// FD wetting (Sec. II.A, eq. contactNormal) at obstacle cell o: w is the
+// normalised sum of the directions to its non-obstacle neighbours (out of
+// the wall) and x_b = o + c_qb the neighbour along the lattice direction
+// closest to w (the first on ties). Returns qb, or 0 when x_b is not an
+// interface cell.
+template <class P>
+__device__ inline int fd_contact_base(const Fields<P> &F, const Nbr &no, typename P::G (&w)[3])
+{
+    using G = typename P::G;
+    int sx = 0, sy = 0, sz = 0;
+#pragma unroll
+    for (int q = 1; q < NQ; ++q)
+        if (!(F.flags[no.at(dir_x(q), dir_y(q), dir_z(q))] & FL_OBST)) {
+            sx += dir_x(q); sy += dir_y(q); sz += dir_z(q);
+        }
+    const G lw = sqrt(G(sx * sx + sy * sy + sz * sz));
+    if (!(lw > G(0))) return 0;
+    w[0] = G(sx) / lw; w[1] = G(sy) / lw; w[2] = G(sz) / lw;
+    int qb = 0;
+    G best = G(-2);
+#pragma unroll
+    for (int q = 1; q < NQ; ++q) {
+        const G cl = sqrt(G(dir_len2(q)));
+        const G a = (G(dir_x(q)) * w[0] + G(dir_y(q)) * w[1] + G(dir_z(q)) * w[2]) / cl;
+        if (a > best) { best = a; qb = q; }
+    }
+    return (F.flags[no.at(dir_x(qb), dir_y(qb), dir_z(qb))] & FL_IF) ? qb : 0;
+}
+
+// The wall value m = n_w cos(theta) + n_t sin(theta) (n_w = -w into the wall,
+// n_t the normalised projection of the base cell's mollified normal n_b onto
+// the wall), extrapolated to the obstacle node half a cell beyond the wall:
+// n = normalise(2 m - n_b). False when n_b has no component along the wall.
+template <class G>
+__device__ inline bool fd_contact_normal(const G (&w)[3], const G (&nb)[3], G ct, G st, G (&out)[3])
+{
+    const G nw[3] = {-w[0], -w[1], -w[2]};
+    const G nn = nb[0] * nw[0] + nb[1] * nw[1] + nb[2] * nw[2];
+    G nt[3] = {nb[0] - nn * nw[0], nb[1] - nn * nw[1], nb[2] - nn * nw[2]};
+    const G lt = sqrt(nt[0] * nt[0] + nt[1] * nt[1] + nt[2] * nt[2]);
+    if (lt < G(1e-12)) return false;
+    nt[0] /= lt; nt[1] /= lt; nt[2] /= lt;
+    G e[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) e[k] = G(2) * (nw[k] * ct + nt[k] * st) - nb[k];
+    const G le = sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+    if (le < G(1e-12)) return false;
+    out[0] = e[0] / le; out[1] = e[1] / le; out[2] = e[2] / le;
+    return true;
+}
+
+// Contact normals of the obstacle-list cells of FD lattices (0 where none).
+template <class P>
+__global__ __launch_bounds__(256) void k_fd_contact_normals(const Batch<P> B)
+{
+    const Params &prm = B.p[blockIdx.y];
+    if (prm.curv != 0) return;
+    const Fields<P> &F = B.f[blockIdx.y];
+    using G = typename P::G;
+    using R = typename P::R;
+    const int n = F.sc->ocount;
+    const size_t N = F.N;
+    const G ct = G(prm.cos_theta), st = G(prm.sin_theta);
+    for (int k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256) {
+        const int o = F.olist[k];
+        const Nbr no(o, F.nx, F.ny, F.nz);
+        G w[3], out[3] = {G(0), G(0), G(0)};
+        const int qb = fd_contact_base(F, no, w);
+        if (qb) {
+            G nb[3];
+            fd_mollified_normal(F, no.at(dir_x(qb), dir_y(qb), dir_z(qb)), nb);
+            if (nb[0] != G(0) || nb[1] != G(0) || nb[2] != G(0)) {
+                G c[3];
+                if (fd_contact_normal(w, nb, ct, st, c)) { out[0] = c[0]; out[1] = c[1]; out[2] = c[2]; }
+            }
+        }
+        F.cnrm[o] = R(out[0]);
+        F.cnrm[N + o] = R(out[1]);
+        F.cnrm[2 * N + o] = R(out[2]);
+    }
+}
+
 template <class P>
 __device__ inline void geometry_fd_tiles(const Fields<P> &F)
 {
@@ -362,12 +483,22 @@ __device__ inline void geometry_fd_tiles(const Fields<P> &F)
             L.mol[c] = s / G(942);
         }
         __syncthreads();
-        // unit normals of the mollified field on 10^3
+        // unit normals of the mollified field on 10^3; obstacle cells with a
+        // contact normal (FD wetting) take it instead
+        const bool walls = F.sc->ocount > 0;
         for (int c = threadIdx.x; c < 1000; c += 256) {
             const int x = c % 10, y = (c / 10) % 10, z = c / 100;
             G gx, gy, gz, n[3];
             py_grad_lds<12>(L.mol, x + 1, y + 1, z + 1, gx, gy, gz);
             unit_normal(gx, gy, gz, n);
+            if (walls) {
+                const int gi = gidx(ox - 1 + x, oy - 1 + y, oz - 1 + z, F.nx, F.ny, F.nz);
+                if (F.flags[gi] & FL_OBST) {
+                    const size_t N = F.N;
+                    const G c0 = G(F.cnrm[gi]), c1 = G(F.cnrm[N + gi]), c2 = G(F.cnrm[2 * N + gi]);
+                    if (c0 != G(0) || c1 != G(0) || c2 != G(0)) { n[0] = c0; n[1] = c1; n[2] = c2; }
+                }
+            }
             L.buf[c] = n[0];
             L.buf[1000 + c] = n[1];
             L.buf[2000 + c] = n[2];

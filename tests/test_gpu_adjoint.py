@@ -6,7 +6,8 @@ Loss L = sum over non-obstacle cells of (phi_T - phi*)^2 (the fill level of
 liquid and gas cells is constant, so only interface cells contribute), with
 phi* = phi_T of the oracle at other parameters plus 0.01 v, v a seeded
 field on the interface cells. Gradients: dL/dsigma (relative step 1e-4),
-dL/dtheta (step 1e-4 rad, LSQR with walls), dL/dphi_0 at 12 seeded
+dL/dtheta (step 1e-4 rad, with walls: the LSQR contact condition or the FD
+contact normal), dL/dphi_0 at 12 seeded
 interface cells (step min(1e-5, 1e-3 min(phi_0, 1 - phi_0))) and the
 directional derivative <dL/dphi_0, v> (step 1e-5), each a central
 difference Richardson-extrapolated over the step and twice the step. The window has T = 24 steps with checkpoints
@@ -49,6 +50,9 @@ def case(name):
     if name == "fd_droplet_trt":
         fill, obst = I.droplet(20, 5.0, noise=1e-6, seed=4)
         return fill, obst, "fd", dict(sigma=5e-3, tau=0.7, theta=math.pi / 2, collision="trt"), None
+    if name == "fd_sessile":
+        fill, obst = I.sessile_droplet(22, 22, 12, 6.0, noise=1e-6, seed=7)
+        return fill, obst, "fd", dict(sigma=5e-3, tau=0.8, theta=math.radians(70.0)), None
     if name == "lsqr_sessile":
         fill, obst = I.sessile_droplet(22, 22, 12, 6.0, noise=1e-6, seed=5)
         return fill, obst, "lsqr", dict(sigma=5e-3, tau=0.8, theta=math.radians(70.0)), None
@@ -83,7 +87,7 @@ def setup(name):
     # target: the window at other parameters, moved by 0.01 v
     prm_t = dict(prm)
     prm_t["sigma"] = 0.8 * prm["sigma"]
-    prm_t["theta"] = prm["theta"] + 0.1 if model == "lsqr" else prm["theta"]
+    prm_t["theta"] = prm["theta"] + 0.1
     target = oracle_phi(fill, obst, model, prm_t, u)[0] + 0.01 * v
     # interface cells strictly inside (0, 1), where a small change of phi_0
     # keeps the cell types
@@ -142,7 +146,7 @@ def gpu_gradients(Lattice, fill, obst, model, prm, u, target, keep, precision):
 
 def check(name, Lattice, precision, tol):
     fill, obst, model, prm, u, target, keep, v, inner = setup(name)
-    with_theta = model == "lsqr" and obst is not None and obst.any()
+    with_theta = obst is not None and obst.any()
     fd = fd_gradients(fill, obst, model, prm, u, target, keep, v, inner, with_theta)
     phi, d0, ds, dt, g = gpu_gradients(Lattice, fill, obst, model, prm, u, target, keep, precision)
     phi_o, _ = oracle_phi(fill, obst, model, prm, u)
@@ -166,7 +170,7 @@ def check(name, Lattice, precision, tol):
     assert ds2 == ds and dt2 == dt and np.array_equal(d0b.cpu().numpy(), d0)
 
 
-@pytest.mark.parametrize("name", ["fd_droplet_moving", "fd_droplet_trt", "lsqr_droplet", "lsqr_sessile"])
+@pytest.mark.parametrize("name", ["fd_droplet_moving", "fd_droplet_trt", "fd_sessile", "lsqr_droplet", "lsqr_sessile"])
 def test_adjoint_fp64_vs_oracle_fd(Lattice, name):
     check(name, Lattice, "f64", 1e-6)
 

@@ -113,11 +113,13 @@ def test_moving_droplet_conversions_fp64(Lattice, model):
     assert abs(g.mass() - M0) / M0 < 1e-13
 
 
+@pytest.mark.parametrize("model", ["lsqr", "fd"])
 @pytest.mark.parametrize("theta", [60.0, 120.0])
-def test_sessile_wetting_fp64(Lattice, theta):
-    """Hemisphere on a no-slip wall, LSQR with the wetting condition."""
+def test_sessile_wetting_fp64(Lattice, theta, model):
+    """Hemisphere on a no-slip wall with the wetting condition: the LSQR
+    gradient condition, or the FD contact normal at obstacle nodes."""
     fill, obst = I.sessile_droplet(28, 28, 14, 7.0, noise=1e-6)
-    g, o = pair(Lattice, fill, obst, "lsqr", sigma=2e-3, tau=0.8, theta=math.radians(theta))
+    g, o = pair(Lattice, fill, obst, model, sigma=2e-3, tau=0.8, theta=math.radians(theta))
     ifc = o.flags() == O.INTERFACE
     np.testing.assert_allclose(g.curvature()[ifc], o.curvature()[ifc], rtol=0, atol=1e-11)
     for n in (1, 30, 120):

@@ -280,7 +280,7 @@ def test_planes_have_zero_curvature(model):
 
 
 # ------------------------------------- wetting (eq. contactNormal, contactConstraint)
-def _vertical_wall_slab(theta_deg):
+def _vertical_wall_slab(theta_deg, model=O.CURV_LSQR):
     nx, ny, nz = 16, 4, 8
     fill = np.zeros((nz, ny, nx))
     fill[:, :, 4:10] = 1.0
@@ -289,7 +289,7 @@ def _vertical_wall_slab(theta_deg):
     obst = np.zeros(fill.shape, np.uint8)
     obst[0] = obst[nz - 1] = 1
     fill[0] = fill[nz - 1] = 0
-    orc = O.Oracle(fill, obst, curv_model=O.CURV_LSQR, theta=math.radians(theta_deg))
+    orc = O.Oracle(fill, obst, curv_model=model, theta=math.radians(theta_deg))
     K = orc.curvature()
     contact = np.zeros(fill.shape, bool)
     contact[1] = contact[nz - 2] = True
@@ -297,18 +297,23 @@ def _vertical_wall_slab(theta_deg):
     return K, contact, orc
 
 
-def test_wetting_ninety_degrees_keeps_vertical_plane_flat():
-    K, contact, _ = _vertical_wall_slab(90.0)
+@pytest.mark.parametrize("model", [O.CURV_LSQR, O.CURV_FD])
+def test_wetting_ninety_degrees_keeps_vertical_plane_flat(model):
+    K, contact, _ = _vertical_wall_slab(90.0, model)
     assert contact.sum() == 16
     assert np.abs(K).max() < 1e-10
 
 
-def test_wetting_angle_bends_the_interface_the_right_way():
+@pytest.mark.parametrize("model", [O.CURV_LSQR, O.CURV_FD])
+def test_wetting_angle_bends_the_interface_the_right_way(model):
     """A smaller prescribed angle makes the liquid spread along the wall: the
     interface near the contact line turns concave seen from the liquid (K < 0,
-    lower liquid pressure draws liquid to the wall); a larger one the reverse."""
-    K60, c, _ = _vertical_wall_slab(60.0)
-    K120, _, _ = _vertical_wall_slab(120.0)
+    lower liquid pressure draws liquid to the wall); a larger one the reverse.
+    FD: the contact normal enters through the obstacle node below each
+    contact cell, LSQR through the gradient condition; either way the
+    contribution is odd in cos(theta) about 90 degrees."""
+    K60, c, _ = _vertical_wall_slab(60.0, model)
+    K120, _, _ = _vertical_wall_slab(120.0, model)
     assert np.all(K60[c] < -1e-3)
     assert np.all(K120[c] > 1e-3)
     np.testing.assert_allclose(K60[c], -K120[c], rtol=1e-9)
@@ -352,11 +357,12 @@ def _theta_star(orc, cx, cy):
 
 
 @pytest.mark.slow
-def test_sessile_droplet_angle_follows_prescribed_angle():
+@pytest.mark.parametrize("model", [O.CURV_LSQR, O.CURV_FD])
+def test_sessile_droplet_angle_follows_prescribed_angle(model):
     res = {}
     for th in (60.0, 90.0, 120.0):
         fill, obst = I.sessile_droplet(28, 28, 14, 7.0, noise=1e-6)
-        orc = O.Oracle(fill, obst, sigma=2e-3, tau=0.8, curv_model=O.CURV_LSQR, theta=math.radians(th))
+        orc = O.Oracle(fill, obst, sigma=2e-3, tau=0.8, curv_model=model, theta=math.radians(th))
         M0 = orc.mass()
         orc.step(400)
         assert abs(orc.mass() - M0) / M0 < 1e-12
