@@ -229,6 +229,133 @@ def advection_table(dev, precision):
     return rows
 
 
+# Printed values of the equilibrium-bubble study (Sec. III.A.1, Figs.
+# spuriousConvergence and curvatureError / curvatureStdev) after 500,000
+# steps at dt = 1e-4, physical units: max and average spurious speed,
+# L2(kappa) and STDEV(kappa).
+PAPER_LAPLACE = {
+    ("fd", 48): (2.8325e-2, 3.585375e-4, 0.0902448, 1.0521024),
+    ("fd", 96): (2.1301458e-3, 4.27811458e-6, 0.0490684, 0.343152),
+    ("fd", 144): (8.639653e-4, 7.64131944e-7, 0.016254, 0.127167408),
+    ("fd", 192): (2.749667e-4, 4.334734375e-7, 0.0155673, 0.123288192),
+    ("lsqr", 48): (2.3191875e-10, 1.63838542e-11, 0.0180768, 2.31408e-7),
+    ("lsqr", 96): (1.51490625e-10, 9.93127083e-12, 0.00421798, 3.1994304e-7),
+    ("lsqr", 144): (1.98145139e-11, 7.88409722e-13, 0.00177479, 8.449776e-8),
+    ("lsqr", 192): (7.79395833e-12, 4.72019271e-13, 0.000991554, 8.448192e-8),
+}
+
+
+def bubble_measures(lat, n, dt, u0=0.0):
+    """Spurious speed (max, average over fluid cells; deviation from the
+    background velocity u0 along x) and the curvature error of the bubble
+    surface, all in the physical units of the unit cube: speed u dx/dt,
+    kappa = -K/(2 dx) with K the library's curvature (-2/R_L for a bubble),
+    L2(kappa) = sqrt(sum (kappa - 1/R)^2 / sum (1/R)^2) and STDEV(kappa)
+    over the interface cells."""
+    from paper_1509_07691_amd.fslbm import FSLBM_LIQUID, FSLBM_INTERFACE
+
+    dx = 1.0 / n
+    fl = lat.flags()
+    fluid = (fl == FSLBM_LIQUID) | (fl == FSLBM_INTERFACE)
+    u = lat.velocity()
+    u[0] -= u0
+    speed = np.sqrt((u ** 2).sum(0))[fluid] * dx / dt
+    kap = -lat.curvature()[fl == FSLBM_INTERFACE] / (2.0 * dx)
+    k0 = 8.0  # 1/R with R = 0.125
+    l2 = float(np.sqrt(((kap - k0) ** 2).sum() / (k0 * k0 * kap.size)))
+    return float(speed.max()), float(speed.mean()), l2, float(kap.std())
+
+
+def laplace_table(dev, resolutions, steps, models=("fd", "lsqr"), precision="f64"):
+    """Equilibrium bubble of Sec. III.A.1 with the bubble model: dx = 1/n,
+    dt = 1e-4, no-slip walls at z = 0 and 1; spurious speeds at log-spaced
+    times and the curvature error at the end, beside the printed values."""
+    import torch
+    from paper_1509_07691_amd import inputs as I
+    from paper_1509_07691_amd.fslbm import Lattice
+
+    dt = 1e-4
+    rows = []
+    for n in resolutions:
+        fill, obst = I.laplace_bubble(n)
+        tau, sig = I.renardy_units(n, dt)
+        for model in models:
+            lat = Lattice(fill, obst, precision=precision, curv_model=model, sigma=sig, tau=tau, bubble=True,
+                          device=dev)
+            hist, t = [], 0
+            marks = [m for m in (1000, 2000, 5000, 10000, 20000, 50000, 100000, 200000, 500000, 1000000)
+                     if m < steps] + [steps]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for m in marks:
+                lat.step(m - t)
+                t = m
+                umax, uavg, l2, sd = bubble_measures(lat, n, dt)
+                hist.append([t, umax, uavg])
+                print(f"# laplace n={n} {model} t={t}: max|u| {umax:.3e} avg {uavg:.3e} L2(k) {l2:.4g} "
+                      f"std {sd:.3e} rho_g {lat.gas_density():.9f}", file=sys.stderr, flush=True)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            paper = PAPER_LAPLACE.get((model, n))
+            rows.append({"n": n, "model": model, "tau": round(tau, 4), "sigma_L": sig, "steps": steps,
+                         "max_u": umax, "avg_u": uavg, "L2_kappa": l2, "stdev_kappa": sd,
+                         "rho_gas_t": lat.gas_density(), "history": hist,
+                         "paper_500k": None if paper is None else dict(zip(("max_u", "avg_u", "L2_kappa",
+                                                                               "stdev_kappa"), paper)),
+                         "ms_per_step_incl_readout": round(1e3 * el / steps, 4)})
+            lat.close()
+            torch.cuda.empty_cache()
+    return rows
+
+
+def moving_bubble_table(dev, resolutions, models=("fd", "lsqr"), precision="f64", samples=10):
+    """Moving frame of Sec. III.A.2: the equilibrium bubble with a uniform
+    background velocity u0 = 1 along x, traversing the periodic unit cube
+    once (T = n / u0_L steps, u0_L = dt/dx) under diffusive scaling
+    dt = 1e-4 (48/n)^2; L2(kappa) and the spurious speed relative to u0
+    over time. The box is periodic in z as well (walls at rest would not
+    be a moving frame)."""
+    import torch
+    from paper_1509_07691_amd import inputs as I
+    from paper_1509_07691_amd.fslbm import Lattice
+
+    rows = []
+    for n in resolutions:
+        dt = 1e-4 * (48.0 / n) ** 2
+        shape = (n, n, n)
+        fill = np.clip(1.0 - I.sphere_fraction(shape, (n / 2, n / 2, n / 2), n / 8.0), 0.0, 1.0)
+        obst = np.zeros(shape, np.uint8)
+        tau, sig = I.renardy_units(n, dt)
+        u0 = dt * n
+        T = int(round(n / u0))
+        for model in models:
+            lat = Lattice(fill, obst, precision=precision, curv_model=model, sigma=sig, tau=tau, bubble=True,
+                          device=dev)
+            u = np.zeros((3,) + shape)
+            u[0] = u0
+            lat.set_equilibrium(1.0, u)
+            hist, t = [], 0
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for k in range(1, samples + 1):
+                m = (T * k) // samples
+                lat.step(m - t)
+                t = m
+                umax, uavg, l2, sd = bubble_measures(lat, n, dt, u0)
+                hist.append([t, round(t / T, 3), l2, umax, uavg])
+                print(f"# moving n={n} {model} t={t}/{T}: L2(k) {l2:.4g} max|u-u0| {umax:.3e}",
+                      file=sys.stderr, flush=True)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            l1, l2phi = I.advection_errors(fill, lat.fill(), 0)
+            rows.append({"n": n, "model": model, "tau": round(tau, 4), "sigma_L": sig, "u0_lattice": u0,
+                         "steps": T, "history_t_frac_L2kappa_maxu_avgu": hist, "phi_L1_after_one_pass": l1,
+                         "phi_L2_after_one_pass": l2phi, "ms_per_step_incl_readout": round(1e3 * el / T, 4)})
+            lat.close()
+            torch.cuda.empty_cache()
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -252,6 +379,12 @@ def main():
     ap.add_argument("--adjoint-k", type=int, default=100, help="checkpoint interval of that window")
     ap.add_argument("--advection", action="store_true",
                     help="only run the pure advection test table (d = 10..80) and print it")
+    ap.add_argument("--laplace", type=int, nargs="*", metavar="N",
+                    help="equilibrium-bubble study at dx = 1/N (default 48 96) instead of the bench")
+    ap.add_argument("--laplace-steps", type=int, default=500000)
+    ap.add_argument("--moving", type=int, nargs="*", metavar="N",
+                    help="moving-frame bubble at dx = 1/N (default 48 96) instead of the bench")
+    ap.add_argument("--models", default="fd,lsqr")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
@@ -272,6 +405,15 @@ def main():
     dev = torch.device("cuda:0")
     if args.advection:
         print(json.dumps({"advection": advection_table(dev, "f64")}))
+        return
+    models = tuple(args.models.split(","))
+    if args.laplace is not None:
+        res = args.laplace or [48, 96]
+        print(json.dumps({"laplace": laplace_table(dev, res, args.laplace_steps, models)}))
+        return
+    if args.moving is not None:
+        res = args.moving or [48, 96]
+        print(json.dumps({"moving_bubble": moving_bubble_table(dev, res, models)}))
         return
     if args.copy_calibration:
         # a plain elementwise copy: 1 GiB read and 1 GiB written per launch

@@ -74,11 +74,20 @@ enum fslbm_option {
     FSLBM_OPT_GRAPH = 4,      /* 1: replay each step as a captured HIP graph
                                  (ignored while timing is on or on the null
                                  stream), 0: plain launches (default) */
-    FSLBM_OPT_SPLIT_INTERFACE = 5  /* 1: two stream-collide passes, a lean one
+    FSLBM_OPT_SPLIT_INTERFACE = 5, /* 1: two stream-collide passes, a lean one
                                  for liquid cells away from walls and one for
                                  interface and wall-adjacent cells; 0
                                  (default): one pass for all fluid cells.
                                  Results are identical either way. */
+    FSLBM_OPT_BUBBLE = 6      /* 1: bubble model (Sec. III.A.1): the whole gas
+                                 of the lattice is one bubble whose pressure
+                                 follows its volume isothermally,
+                                 rho_gas(t) = rho_gas V0 / V(t), with V the
+                                 gas volume (non-obstacle cells minus liquid
+                                 cells minus the fill of interface cells) and
+                                 V0 its value when the option is set; 0
+                                 (default): constant rho_gas. Not covered by
+                                 the adjoint (FSLBM_E_STATE there). */
 };
 
 /* Device workspace needed for a lattice (bytes, written to *bytes).
@@ -143,6 +152,9 @@ int fslbm_read_flags(fslbm_t h, uint8_t *out, int out_is_device);
  * *count receives the number of interface cells (FSLBM_E_SHAPE if it
  * exceeds capacity; out may be NULL to query the count). */
 int fslbm_read_interface_list(fslbm_t h, int32_t *out, int64_t capacity, int64_t *count);
+/* Gas density used by the step (rho_gas, or rho_gas(t) of the bubble
+ * model); synchronises. */
+int fslbm_gas_density(fslbm_t h, double *rho_gas);
 /* Total mass: sum of rho over liquid cells + sum of m over interface cells +
  * excess mass that found no receiving cell; FP64, fixed summation order. */
 int fslbm_mass(fslbm_t h, double *total);

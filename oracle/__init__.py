@@ -35,7 +35,8 @@ class _Params(ctypes.Structure):
     _fields_ = [("sigma", ctypes.c_double), ("tau", ctypes.c_double),
                 ("theta", ctypes.c_double), ("rho_gas", ctypes.c_double),
                 ("eps_c", ctypes.c_double), ("trt_magic", ctypes.c_double),
-                ("curv_model", ctypes.c_int), ("collision", ctypes.c_int), ("frozen", ctypes.c_int)]
+                ("curv_model", ctypes.c_int), ("collision", ctypes.c_int), ("frozen", ctypes.c_int),
+                ("bubble", ctypes.c_int)]
 
 
 _lib = None
@@ -65,6 +66,8 @@ def lib():
         L.orc_get_mass.argtypes = [vp]
         L.orc_get_reservoir.restype = ctypes.c_double
         L.orc_get_reservoir.argtypes = [vp]
+        L.orc_get_gas_density.restype = ctypes.c_double
+        L.orc_get_gas_density.argtypes = [vp]
         L.orc_interface_list.restype = ctypes.c_long
         L.orc_interface_list.argtypes = [vp, ip]
         L.orc_cut_volume.restype = ctypes.c_double
@@ -120,7 +123,7 @@ class Oracle:
 
     def __init__(self, fill, obstacle=None, *, sigma=0.0, tau=1.0, theta=np.pi / 2,
                  rho_gas=1.0, eps_c=1e-3, curv_model=CURV_FD, collision=SRT,
-                 trt_magic=3.0 / 16.0, frozen=False):
+                 trt_magic=3.0 / 16.0, frozen=False, bubble=False):
         fill = np.ascontiguousarray(fill, dtype=np.float64)
         self.shape = fill.shape
         nz, ny, nx = fill.shape
@@ -128,7 +131,8 @@ class Oracle:
         if obstacle is None:
             obstacle = np.zeros(fill.shape, dtype=np.uint8)
         obstacle = np.ascontiguousarray(obstacle, dtype=np.uint8)
-        p = _Params(sigma, tau, theta, rho_gas, eps_c, trt_magic, curv_model, collision, 1 if frozen else 0)
+        p = _Params(sigma, tau, theta, rho_gas, eps_c, trt_magic, curv_model, collision, 1 if frozen else 0,
+                    1 if bubble else 0)
         h = lib().orc_create(nx, ny, nz, _dptr(fill),
                              obstacle.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte)), ctypes.byref(p))
         if not h:
@@ -197,6 +201,9 @@ class Oracle:
 
     def reservoir(self):
         return lib().orc_get_reservoir(self._h)
+
+    def gas_density(self):
+        return lib().orc_get_gas_density(self._h)
 
     def interface_list(self):
         c = lib().orc_interface_list(self._h, None)

@@ -63,6 +63,9 @@ struct orc_lattice {
     double *nrm;    /* unit Parker-Youngs normal of raw phi, interface, 3n */
     double *plic;   /* PLIC plane offset a, interface cells */
     double reservoir;
+    double gas_v0;   /* bubble model: gas volume at creation */
+    double rho_g;    /* gas density used by the step: rho_gas, or with the
+                      * bubble model rho_gas * V0 / V(t) */
     int *nb;        /* 27 neighbour indices per cell, offset (dx,dy,dz) at
                      * slot (dz+1)*9 + (dy+1)*3 + (dx+1), periodic wrap */
 };
@@ -442,6 +445,29 @@ static void obstacle_fill(orc_lattice *L)
     }
 }
 
+/* ---- bubble model (Sec. III.A.1) ------------------------------------------ */
+/* Gas volume V = sum over non-obstacle cells of (1 - phi): 1 per gas cell,
+ * 1 - phi per interface cell. With the bubble model the whole gas of the
+ * lattice is one bubble whose pressure follows its volume isothermally,
+ * p_g(t) V(t) = p_g(0) V(0), i.e. rho_gas(t) = rho_gas V0 / V(t). */
+static double gas_volume(const orc_lattice *L)
+{
+    double v = 0.0;
+    for (long i = 0; i < L->n; ++i)
+        if (L->type[i] != ORC_OBSTACLE) v += 1.0 - L->phi[i];
+    return v;
+}
+
+static void update_gas_density(orc_lattice *L)
+{
+    if (!L->p.bubble) {
+        L->rho_g = L->p.rho_gas;
+        return;
+    }
+    const double v = gas_volume(L);
+    L->rho_g = v > 0.0 ? L->p.rho_gas * L->gas_v0 / v : L->p.rho_gas;
+}
+
 /* ---- curvature ---------------------------------------------------------- */
 /* Normals from raw phi at interface cells (the corner rule uses them with
  * both models) and, for the LSQR model, PLIC offsets (Sec. II.B: the PLIC
@@ -725,6 +751,8 @@ orc_lattice *orc_create(int nx, int ny, int nz, const double *fill, const unsign
         }
     }
     obstacle_fill(L);
+    L->gas_v0 = gas_volume(L);
+    L->rho_g = L->p.rho_gas;
     curvature(L);
     return L;
 }
@@ -759,7 +787,7 @@ static void one_step(orc_lattice *L)
         double rb0, ub[3];
         moments(fo, &rb0, ub);
         double Kc = t == ORC_INTERFACE ? L->K[i] : 0.0;
-        double rhob = 3.0 * (p->rho_gas / 3.0 + p->sigma * Kc);
+        double rhob = 3.0 * (L->rho_g / 3.0 + p->sigma * Kc);
         int has_gas = 0;
         double nw[3] = {0, 0, 0};
         for (int q = 1; q < NQ; ++q) {
@@ -928,6 +956,7 @@ static void one_step(orc_lattice *L)
         }
     }
     obstacle_fill(L);
+    update_gas_density(L);
     /* Phase 5: curvature for the next step's pressure jump. */
     curvature(L);
     free(mnew); free(rnew); free(st); free(st2); free(newi); free(share);
@@ -945,6 +974,7 @@ void orc_get_curvature(const orc_lattice *L, double *out) { memcpy(out, L->K, si
 void orc_get_plic(const orc_lattice *L, double *out) { memcpy(out, L->plic, sizeof(double) * L->n); }
 void orc_get_mass_field(const orc_lattice *L, double *out) { memcpy(out, L->m, sizeof(double) * L->n); }
 double orc_get_reservoir(const orc_lattice *L) { return L->reservoir; }
+double orc_get_gas_density(const orc_lattice *L) { return L->rho_g; }
 
 void orc_get_normal(const orc_lattice *L, double *out3)
 {
@@ -960,7 +990,7 @@ void orc_get_density(const orc_lattice *L, double *out)
             for (int q = 0; q < NQ; ++q) r += L->f[q * L->n + i];
             out[i] = r;
         } else {
-            out[i] = L->type[i] == ORC_GAS ? L->p.rho_gas : 0.0;
+            out[i] = L->type[i] == ORC_GAS ? L->rho_g : 0.0;
         }
     }
 }

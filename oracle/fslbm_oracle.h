@@ -32,6 +32,7 @@ typedef struct {
     int curv_model;    /* ORC_CURV_FD or ORC_CURV_LSQR */
     int collision;     /* ORC_SRT or ORC_TRT */
     int frozen;        /* 1: cell types stay fixed (no fill/empty conversion) */
+    int bubble;        /* 1: the gas pressure follows the gas volume (one bubble) */
 } orc_params;
 
 typedef struct orc_lattice orc_lattice;
@@ -54,6 +55,8 @@ void orc_get_plic(const orc_lattice *L, double *out);
 void orc_get_mass_field(const orc_lattice *L, double *out);
 double orc_get_mass(const orc_lattice *L);
 double orc_get_reservoir(const orc_lattice *L);
+/* Gas density rho_gas(t) of the bubble model (rho_gas when it is off). */
+double orc_get_gas_density(const orc_lattice *L);
 long orc_interface_list(const orc_lattice *L, int *out);
 void orc_get_pdf(const orc_lattice *L, double *out19n);
 void orc_set_pdf(orc_lattice *L, const double *in19n);

@@ -167,6 +167,8 @@ struct fslbm_lattice {
     unsigned long long epoch;  // bumped whenever the state changes other than by stepping
     int frozen;        // 1 inside a frozen-topology window
     int icount0;       // interface cells at creation (sizes the list-kernel grids)
+    int bubble;        // bubble model on (FSLBM_OPT_BUBBLE)
+    double n_free;     // non-obstacle cells
     fslbm_batch self;
     AdjWindow adj;
 };
@@ -193,6 +195,8 @@ Params make_params(const fslbm_lattice *h)
     p.curv = h->curv;
     p.coll = h->coll;
     p.frozen = h->frozen;
+    p.bubble = h->bubble;
+    p.n_free = h->n_free;
     return p;
 }
 
@@ -225,6 +229,7 @@ Fields<P> make_fields(const fslbm_lattice *h)
     F.newlist = (int32_t *)(w + L.newlist);
     F.ilist_tmp = (int32_t *)(w + L.ilist_tmp);
     F.counts = (int *)(w + L.counts);
+    F.part = (double *)(w + L.part);
     F.sc = (DevScalars *)(w + L.sc);
     F.nx = h->nx;
     F.ny = h->ny;
@@ -257,6 +262,10 @@ __global__ void k_init_scalars(DevScalars *sc)
     sc->mass = 0.0;
     sc->bad = 0;
     sc->wcount = 0;
+    sc->gas_v0 = 0.0;
+    sc->rho_gas_t = 0.0;
+    sc->bubble_init = 0;
+    sc->pad2 = 0;
     for (int k = 0; k < 6; ++k) sc->bbox[k] = 0;
     sc->fbox[0] = sc->fbox[1] = sc->fbox[2] = 1 << 30;
     sc->fbox[3] = sc->fbox[4] = sc->fbox[5] = -1;
@@ -418,7 +427,7 @@ __device__ inline void load_all(const Fields<P> &F, int i, typename P::T (&f)[NQ
 enum ReadWhat { RD_FILL, RD_PRESSURE, RD_CURV, RD_VEL, RD_NORMAL, RD_PLIC, RD_MASS };
 
 template <class P>
-__global__ void k_read(Fields<P> F, double rho_gas, int what, int comp, double *out)
+__global__ void k_read(Fields<P> F, double rho_gas, int bubble, int what, int comp, double *out)
 {
     using T = typename P::T;
     const int i = blockIdx.x * 256 + threadIdx.x;
@@ -443,7 +452,7 @@ __global__ void k_read(Fields<P> F, double rho_gas, int what, int comp, double *
             if (what == RD_PRESSURE) v = double(r) / 3.0;
             else v = double(comp == 0 ? ux : (comp == 1 ? uy : uz));
         } else if (what == RD_PRESSURE) {
-            v = (fl & FL_GAS) ? rho_gas / 3.0 : 0.0;
+            v = (fl & FL_GAS) ? (bubble ? F.sc->rho_gas_t : rho_gas) / 3.0 : 0.0;
         }
         break;
     }
@@ -649,6 +658,12 @@ int enqueue_step_kernels(fslbm_batch *b, const void *fsrc = nullptr, void *fdst 
     int rc = 0;
     mark(b, 4);
     k_obstacle_fill<P><<<dim3(list_blocks(maxN), n), 256, 0, st>>>(A, 1);
+    bool any_bubble = false;
+    for (auto *h : b->hs) any_bubble |= h->bubble != 0;
+    if (any_bubble) {
+        k_bubble_partial<P><<<dim3(VOL_BLOCKS, n), 256, 0, st>>>(A);
+        k_bubble_final<P><<<dim3(1, n), 1024, 0, st>>>(A, VOL_BLOCKS);
+    }
     rc = enqueue_geometry<P>(b, A, maxN);
     if (rc) return rc;
     mark(b, 5);
@@ -811,7 +826,7 @@ int do_read(fslbm_lattice *h, int what, double *out, int out_is_device)
     double *staging = (double *)(h->ws + h->L.staging);
     for (int c = 0; c < comps; ++c) {
         double *dst = out_is_device ? out + (size_t)c * N : staging;
-        k_read<P><<<cell_blocks(N), 256, 0, h->stream>>>(F, h->rho_gas, what, c, dst);
+        k_read<P><<<cell_blocks(N), 256, 0, h->stream>>>(F, h->rho_gas, h->bubble, what, c, dst);
         HIP_OK(hipGetLastError());
         if (!out_is_device)
             HIP_OK(hipMemcpyAsync(out + (size_t)c * N, staging, sizeof(double) * N, hipMemcpyDeviceToHost, h->stream));
@@ -1227,6 +1242,23 @@ template <class P> struct OpMass { static int run(fslbm_lattice *h, double *t) {
 template <class P> struct OpCheck { static int run(fslbm_lattice *h) { return do_check<P>(h); } };
 template <class P> struct OpEq { static int run(fslbm_lattice *h, const double *r, const double *u) { return do_set_equilibrium<P>(h, r, u); } };
 
+__global__ void k_bubble_arm(DevScalars *sc) { sc->bubble_init = 1; }
+
+template <class P>
+int do_bubble_start(fslbm_lattice *h)
+{
+    int maxN;
+    bool s_, t_;
+    const Batch<P> A = make_batch<P>(&h->self, maxN, s_, t_);
+    const Fields<P> F = make_fields<P>(h);
+    k_bubble_arm<<<1, 1, 0, h->stream>>>(F.sc);
+    k_bubble_partial<P><<<dim3(VOL_BLOCKS, 1), 256, 0, h->stream>>>(A);
+    k_bubble_final<P><<<dim3(1, 1), 1024, 0, h->stream>>>(A, VOL_BLOCKS);
+    HIP_OK(hipGetLastError());
+    return 0;
+}
+template <class P> struct OpBubble { static int run(fslbm_lattice *h) { return do_bubble_start<P>(h); } };
+
 template <class P> struct OpFill { static int run(fslbm_lattice *h, const double *f, int d) { return do_set_interface_fill<P>(h, f, d); } };
 template <class P> struct OpAdjF { static int run(fslbm_lattice *h, long long T, int K, void *w, size_t b) { return do_adj_forward<P>(h, T, K, w, b); } };
 template <class P> struct OpAdjB {
@@ -1286,6 +1318,13 @@ int fslbm_create(int nx, int ny, int nz, int precision, int curv_model, const do
     h->version = 0;
     h->epoch = 0;
     h->frozen = 0;
+    h->bubble = 0;
+    {
+        long long nf = N;
+        if (obstacle)
+            for (long long i = 0; i < N; ++i) nf -= obstacle[i] != 0;
+        h->n_free = double(nf);
+    }
     batch_init(&h->self);
     h->self.hs.push_back(h);
     h->self.prec = precision;
@@ -1339,6 +1378,11 @@ int fslbm_set_option(fslbm_t h, int key, double value)
         h->version += 1;
         h->epoch += 1;
         return 0;
+    case FSLBM_OPT_BUBBLE:
+        h->version += 1;
+        h->epoch += 1;
+        h->bubble = value != 0.0;
+        return h->bubble ? dispatch<OpBubble>(h) : 0;
     case FSLBM_OPT_TIMING:
     case FSLBM_OPT_GRAPH:
     case FSLBM_OPT_SPLIT_INTERFACE: return fslbm_batch_set_option(&h->self, key, value);
@@ -1498,6 +1542,20 @@ int fslbm_read_interface_list(fslbm_t h, int32_t *out, int64_t capacity, int64_t
     return 0;
 }
 
+int fslbm_gas_density(fslbm_t h, double *rho_gas)
+{
+    if (!h) return fail(FSLBM_E_STATE, "null handle");
+    if (!rho_gas) return fail(FSLBM_E_ARG, "rho_gas is NULL");
+    if (!h->bubble) {
+        *rho_gas = h->rho_gas;
+        return 0;
+    }
+    const DevScalars *sc = (const DevScalars *)(h->ws + h->L.sc);
+    HIP_OK(hipMemcpyAsync(rho_gas, &sc->rho_gas_t, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIP_OK(hipStreamSynchronize(h->stream));
+    return 0;
+}
+
 int fslbm_mass(fslbm_t h, double *total)
 {
     if (!h) return fail(FSLBM_E_STATE, "null handle");
@@ -1607,6 +1665,7 @@ int fslbm_adjoint_forward(fslbm_t h, int64_t nsteps, int K, void *workspace, siz
     if (!h) return fail(FSLBM_E_STATE, "null handle");
     if (nsteps < 1 || K < 1) return fail(FSLBM_E_ARG, "nsteps and K must be >= 1");
     if (!workspace) return fail(FSLBM_E_ARG, "workspace is NULL");
+    if (h->bubble) return fail(FSLBM_E_STATE, "the adjoint does not cover the bubble model");
     if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return fail(FSLBM_E_ARG, "workspace not 256-byte aligned");
     return dispatch<OpAdjF>(h, (long long)nsteps, K, workspace, workspace_bytes);
 }
@@ -1620,6 +1679,7 @@ int fslbm_adjoint_backward(fslbm_t h, const double *dL_dfill_T, int in_is_device
     if (!w.recorded) return fail(FSLBM_E_STATE, "no window recorded (call fslbm_adjoint_forward first)");
     if (h->steps != w.t_end || h->epoch != w.epoch)
         return fail(FSLBM_E_STATE, "the lattice changed since the window was recorded");
+    if (h->bubble) return fail(FSLBM_E_STATE, "the adjoint does not cover the bubble model");
     return dispatch<OpAdjB>(h, dL_dfill_T, in_is_device, dL_dsigma, dL_dtheta, dL_dfill_0, out_is_device);
 }
 

@@ -601,4 +601,63 @@ __global__ __launch_bounds__(256) void k_obstacle_fill(const Batch<P> B, int end
     }
 }
 
+// ------------------------------------------------ bubble model (Sec. III.A.1)
+// The whole gas of a lattice is one bubble with isothermal pressure,
+// p_g(t) V(t) = p_g(0) V(0), so rho_gas(t) = rho_gas V0 / V(t) with the gas
+// volume V = (non-obstacle cells) - (liquid cells + sum of phi over
+// interface cells). The liquid volume is summed over the fluid box in a
+// fixed partition (VOL_BLOCKS blocks, fixed order within each), after the
+// step's conversions.
+constexpr int VOL_BLOCKS = 1024;
+
+template <class P>
+__global__ __launch_bounds__(256) void k_bubble_partial(const Batch<P> B)
+{
+    const Params &prm = B.p[blockIdx.y];
+    if (!prm.bubble) return;
+    const Fields<P> &F = B.f[blockIdx.y];
+    __shared__ double s[256];
+    const CellRange box = CellRange::from(F.sc->fbox);
+    const int n = box.size();
+    const int chunk = (n + gridDim.x - 1) / gridDim.x;
+    const int b0 = min(n, (int)blockIdx.x * chunk), b1 = min(n, b0 + chunk);
+    double acc = 0.0;
+    for (int k = b0 + threadIdx.x; k < b1; k += 256) {
+        const int i = box.cell(k, F.nx, F.ny);
+        const uint8_t fl = F.flags[i];
+        if (fl & FL_LIQ) acc += 1.0;
+        else if (fl & FL_IF) acc += double(F.phi[i]);
+    }
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) F.part[blockIdx.x] = s[0];
+}
+
+template <class P>
+__global__ __launch_bounds__(1024) void k_bubble_final(const Batch<P> B, int nblocks)
+{
+    const Params &prm = B.p[blockIdx.y];
+    if (!prm.bubble) return;
+    const Fields<P> &F = B.f[blockIdx.y];
+    __shared__ double s[1024];
+    s[threadIdx.x] = (int)threadIdx.x < nblocks ? F.part[threadIdx.x] : 0.0;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if (threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double v = prm.n_free - s[0];
+        if (F.sc->bubble_init) {
+            F.sc->gas_v0 = v;
+            F.sc->bubble_init = 0;
+        }
+        F.sc->rho_gas_t = v > 0.0 ? prm.rho_gas * F.sc->gas_v0 / v : prm.rho_gas;
+    }
+}
+
 }  // namespace fslbm

@@ -124,6 +124,10 @@ struct DevScalars {
     int wcount;         // number of cells in wlist (static)
     int bbox[6];        // min x, y, z and max x, y, z of the interface cells
     int fbox[6];        // the same for the fluid cells; never shrinks
+    double gas_v0;      // bubble model: gas volume when it was switched on
+    double rho_gas_t;   // bubble model: gas density rho_gas V0 / V(t)
+    int bubble_init;    // 1: the next volume reduction sets gas_v0
+    int pad2;
 };
 
 // A box of cells [x0, x0+ex) x [y0, y0+ey) x [z0, z0+ez) enumerated with x
@@ -167,7 +171,16 @@ struct Params {
     int curv;          // 0 FD, 1 LSQR
     int coll;          // 0 SRT, 1 TRT
     int frozen;        // 1: cell types stay fixed (no fill / empty conversion)
+    int bubble;        // 1: the gas pressure follows the gas volume (one bubble)
+    double n_free;     // number of non-obstacle cells
 };
+
+// Gas density of the reconstruction: rho_gas, or the bubble model's
+// rho_gas V0 / V(t) (Sec. III.A.1).
+__device__ inline double gas_density(const Params &p, const DevScalars *sc)
+{
+    return p.bubble ? sc->rho_gas_t : p.rho_gas;
+}
 
 template <class P> struct Fields {
     using S = typename P::S;
@@ -183,6 +196,7 @@ template <class P> struct Fields {
     int32_t *wlist;    // static: non-obstacle cells with an obstacle D3Q19 neighbour
     int32_t *newlist, *ilist_tmp;  // new interface cells; scratch for the list rebuild
     int *counts;       // per-block counts of the list compaction
+    double *part;      // per-block partial sums of reductions
     DevScalars *sc;
     int nx, ny, nz;
     int N;

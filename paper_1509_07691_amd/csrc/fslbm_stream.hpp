@@ -176,7 +176,7 @@ __device__ inline void boundary_cell(const Fields<P> &F, const Params &prm, int 
     T rb0, ubx, uby, ubz;
     moments(fo, rb0, ubx, uby, ubz);
     const T ubsq = ubx * ubx + uby * uby + ubz * ubz;
-    const T rhob = T(3) * (T(prm.rho_gas) / T(3) + T(prm.sigma) * Kc);
+    const T rhob = T(3) * (T(gas_density(prm, F.sc)) / T(3) + T(prm.sigma) * Kc);
     // corner rule: the outgoing link c_o = -c_q takes the free-surface rule
     // when c_o . (P n) < 0, P the projection onto the wall plane; evaluated
     // as (P c_o) . n with P c_o |nw|^2 = c_o |nw|^2 - (c_o . nw) nw in exact
@@ -269,7 +269,7 @@ __device__ inline void fluid_cell(const Fields<P> &F, const Params &prm, int i, 
         T rb0, ubx, uby, ubz;
         moments(fo, rb0, ubx, uby, ubz);
         const T ubsq = ubx * ubx + uby * uby + ubz * ubz;
-        const T rhob = T(3) * (T(prm.rho_gas) / T(3) + T(prm.sigma) * Kc);
+        const T rhob = T(3) * (T(gas_density(prm, F.sc)) / T(3) + T(prm.sigma) * Kc);
         const bool corner = is_if && has_gas && (nwx | nwy | nwz) != 0;
         const int ww = nwx * nwx + nwy * nwy + nwz * nwz;
 #pragma unroll

@@ -25,6 +25,7 @@ FSLBM_SRT, FSLBM_TRT = 0, 1
 FSLBM_GAS, FSLBM_LIQUID, FSLBM_INTERFACE, FSLBM_OBSTACLE = 0, 1, 2, 3
 FSLBM_OPT_EPS_C, FSLBM_OPT_COLLISION, FSLBM_OPT_TRT_MAGIC, FSLBM_OPT_TIMING, FSLBM_OPT_GRAPH = 0, 1, 2, 3, 4
 FSLBM_OPT_SPLIT_INTERFACE = 5
+FSLBM_OPT_BUBBLE = 6
 
 PRECISIONS = {"f64": FSLBM_F64, "f32": FSLBM_F32, "f16": FSLBM_F16_STORE, "bf16": FSLBM_BF16_STORE}
 MODELS = {"fd": FSLBM_CURV_FD, "lsqr": FSLBM_CURV_LSQR}
@@ -68,6 +69,7 @@ def load_library(path: str = LIB_PATH):
         "fslbm_read_flags": [vp, vp, i32],
         "fslbm_read_interface_list": [vp, ctypes.POINTER(ctypes.c_int32), i64, ctypes.POINTER(i64)],
         "fslbm_mass": [vp, dp],
+        "fslbm_gas_density": [vp, dp],
         "fslbm_check_numeric": [vp],
         "fslbm_steps_taken": [vp, ctypes.POINTER(i64)],
         "fslbm_read_timing": [vp, dp, ctypes.POINTER(i64)],
@@ -202,6 +204,12 @@ def fslbm_read_interface_list(h):
     return out[:cnt.value]
 
 
+def fslbm_gas_density(h):
+    out = ctypes.c_double(0.0)
+    _check(load_library().fslbm_gas_density(h, ctypes.byref(out)))
+    return out.value
+
+
 def fslbm_mass(h):
     out = ctypes.c_double(0.0)
     _check(load_library().fslbm_mass(h, ctypes.byref(out)))
@@ -323,7 +331,7 @@ class Lattice:
 
     def __init__(self, fill, obstacle=None, *, precision="f64", curv_model="fd", sigma=0.0, tau=1.0,
                  theta=math.pi / 2, rho_gas=1.0, eps_c=None, collision="srt", trt_magic=None,
-                 device="cuda:0", stream=None):
+                 bubble=False, device="cuda:0", stream=None):
         import torch
 
         fill = np.ascontiguousarray(fill, dtype=np.float64)
@@ -348,6 +356,8 @@ class Lattice:
         fslbm_set_option(self._h, FSLBM_OPT_COLLISION, FSLBM_TRT if collision == "trt" else FSLBM_SRT)
         self.sigma, self.tau, self.theta, self.rho_gas = sigma, tau, theta, rho_gas
         fslbm_set_params(self._h, sigma, tau, theta, rho_gas)
+        if bubble:
+            fslbm_set_option(self._h, FSLBM_OPT_BUBBLE, 1)
         self._adj_ws = None
 
     @property
@@ -433,6 +443,12 @@ class Lattice:
 
     def set_split_interface(self, on=True):
         fslbm_set_option(self._h, FSLBM_OPT_SPLIT_INTERFACE, 1 if on else 0)
+
+    def set_bubble(self, on=True):
+        fslbm_set_option(self._h, FSLBM_OPT_BUBBLE, 1 if on else 0)
+
+    def gas_density(self):
+        return fslbm_gas_density(self._h)
 
     def timing(self):
         return fslbm_read_timing(self._h)

@@ -34,6 +34,8 @@ __all__ = [
     "advected_bubble",
     "advection_errors",
     "lattice_units",
+    "laplace_bubble",
+    "renardy_units",
 ]
 
 _GL_X, _GL_W = np.polynomial.legendre.leggauss(12)
@@ -293,6 +295,35 @@ def flat_film(nx: int, ny: int, nz: int, height: float):
     fill[0] = 0.0
     fill[nz - 1] = 0.0
     return fill, obst
+
+
+def laplace_bubble(n: int, noise: float = 0.0, seed: int = 0):
+    """The equilibrium-bubble setup of Sec. III.A.1 at dx = 1/n: a unit cube
+    of liquid (n^3 fluid cells, periodic in x and y) between no-slip walls at
+    z = 0 and z = 1, with a gas bubble of radius n/8 at its centre.
+
+    Obstacle layers fill k = 0 and k = n+1, so the wall planes are z = 1 and
+    z = n+1 in cell-corner coordinates and the centre is
+    (n/2, n/2, n/2 + 1).
+    """
+    shape = (n + 2, n, n)
+    fill = 1.0 - sphere_fraction(shape, (n / 2, n / 2, n / 2 + 1.0), n / 8.0)
+    fill = np.clip(fill, 0.0, 1.0)
+    obst = np.zeros(shape, dtype=np.uint8)
+    obst[0] = 1
+    obst[n + 1] = 1
+    fill[0] = 0.0
+    fill[n + 1] = 0.0
+    if noise:
+        fill = perturb_interface(fill, noise, seed)
+    return fill, obst
+
+
+def renardy_units(n: int, dt: float = 1e-4):
+    """(tau, sigma_L) of the equilibrium-bubble problem (Sec. III.A.1:
+    liquid density 4, viscosity 1, surface tension 0.357 in units of the
+    unit cube) at dx = 1/n and time step dt."""
+    return lattice_units(1.0 / n, dt, 1.0 / 4.0, 0.357, 4.0)
 
 
 def lattice_units(dx: float, dt: float, nu: float, sigma: float, rho: float):

@@ -234,3 +234,41 @@ def test_advection_test_fp64(Lattice):
     l1g = I.advection_errors(fill, g.fill(), d)
     l1o = I.advection_errors(fill, o.fill(), d)
     assert abs(l1g[0] - l1o[0]) < 1e-12 and abs(l1g[1] - l1o[1]) < 1e-12
+
+
+@pytest.mark.parametrize("model", ["fd", "lsqr"])
+def test_bubble_model_fp64(Lattice, model):
+    """Equilibrium-bubble setup (walls at z = 0, 1) with the bubble model:
+    the gas density follows the gas volume every step."""
+    fill, obst = I.laplace_bubble(32)
+    g, o = pair(Lattice, fill, obst, model, sigma=1e-3, tau=0.8, bubble=True)
+    assert g.gas_density() == o.gas_density() == 1.0
+    g.step(200)
+    o.step(200)
+    compare(g, o, 1e-10, what=f"bubble {model}", vscale=1e-3 / (0.3 / 3.0))
+    assert g.gas_density() != 1.0
+    assert abs(g.gas_density() - o.gas_density()) < 1e-13
+
+
+def test_moving_bubble_fp64(Lattice):
+    """Moving frame of reference: a uniform background velocity along x,
+    the bubble model and LSQR curvature."""
+    fill, obst = I.laplace_bubble(32)
+    g, o = pair(Lattice, fill, obst, "lsqr", sigma=1e-3, tau=0.8, bubble=True)
+    u = np.zeros((3,) + fill.shape)
+    u[0] = 0.02
+    g.set_equilibrium(1.0, u)
+    o.set_equilibrium(1.0, u)
+    g.step(150)
+    o.step(150)
+    compare(g, o, 1e-10, what="moving bubble", vscale=0.02)
+    assert abs(g.gas_density() - o.gas_density()) < 1e-13
+
+
+def test_bubble_model_fp32(Lattice):
+    fill, obst = I.laplace_bubble(32)
+    g, o = pair(Lattice, fill, obst, "lsqr", precision="f32", sigma=1e-3, tau=0.8, bubble=True)
+    g.step(100)
+    o.step(100)
+    compare(g, o, 1e-5, exact_flags=False, what="bubble f32", vscale=1e-3 / (0.3 / 3.0))
+    assert abs(g.gas_density() - o.gas_density()) / o.gas_density() < 1e-5
