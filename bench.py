@@ -266,6 +266,25 @@ def bubble_measures(lat, n, dt, u0=0.0):
     return float(speed.max()), float(speed.mean()), l2, float(kap.std())
 
 
+def gas_link_kappa_stdev(lat, n):
+    """STDEV(kappa) over the interface cells that have a gas neighbour along
+    one of the D3Q19 directions, i.e. the cells whose curvature enters the
+    pressure boundary condition."""
+    from paper_1509_07691_amd.fslbm import FSLBM_GAS, FSLBM_INTERFACE
+
+    fl = lat.flags()
+    gas = fl == FSLBM_GAS
+    near = np.zeros_like(gas)
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx_ in (-1, 0, 1):
+                if 0 < abs(dz) + abs(dy) + abs(dx_) <= 2:
+                    near |= np.roll(gas, (dz, dy, dx_), axis=(0, 1, 2))
+    sel = (fl == FSLBM_INTERFACE) & near
+    kap = -lat.curvature()[sel] * n / 2.0
+    return float(kap.std()), int(sel.sum()), int((fl == FSLBM_INTERFACE).sum())
+
+
 def laplace_table(dev, resolutions, steps, models=("fd", "lsqr"), precision="f64"):
     """Equilibrium bubble of Sec. III.A.1 with the bubble model: dx = 1/n,
     dt = 1e-4, no-slip walls at z = 0 and 1; spurious speeds at log-spaced
@@ -297,8 +316,10 @@ def laplace_table(dev, resolutions, steps, models=("fd", "lsqr"), precision="f64
             torch.cuda.synchronize()
             el = time.perf_counter() - t0
             paper = PAPER_LAPLACE.get((model, n))
+            sd_gl, n_gl, n_if = gas_link_kappa_stdev(lat, n)
             rows.append({"n": n, "model": model, "tau": round(tau, 4), "sigma_L": sig, "steps": steps,
                          "max_u": umax, "avg_u": uavg, "L2_kappa": l2, "stdev_kappa": sd,
+                         "stdev_kappa_gas_link_cells": sd_gl, "gas_link_cells": n_gl, "interface_cells": n_if,
                          "rho_gas_t": lat.gas_density(), "history": hist,
                          "paper_500k": None if paper is None else dict(zip(("max_u", "avg_u", "L2_kappa",
                                                                                "stdev_kappa"), paper)),

@@ -16,7 +16,9 @@
  *      the corner-node rule of Fig. inhomo; mass exchange (eq. advection1/2)
  *      in mass form; moments; collision (eq. lbe2, SRT or TRT)
  *   2  fill / empty classification of interface cells
- *   3  cell-type conversion and excess-mass redistribution
+ *   3  cell-type conversion, closure of the interface layer (every
+ *      interface cell keeps a gas and a liquid D3Q19 neighbour, Sec. II.D)
+ *      and excess-mass redistribution
  *   4  fill levels phi = m / rho, obstacle fill reflection (Sec. II.A)
  *   5  interface normals (eq. normal) and PLIC points (Sec. II.B), curvature
  *      by FD (eq. curvature, K8 mollifier) or LSQR (Sec. II.C, eqs.
@@ -29,7 +31,8 @@
  * unpinned: the conversion rules of step 3 (thresholds, priority, new-cell
  * initialisation, excess split), which the paper defers to Koerner et al.;
  * they are checked only through mass conservation and the cell-type
- * invariants of Sec. II.
+ * invariants of Sec. II (no liquid cell next to a gas cell; every interface
+ * cell with a gas and a liquid neighbour).
  */
 #include "fslbm_oracle.h"
 
@@ -696,6 +699,39 @@ static void curvature(orc_lattice *L)
  * D3Q19 neighbour becomes an interface cell with phi = 1, so that every
  * gas-liquid contact runs through an interface cell. f starts at
  * feq(rho = 1, u = 0) and the interface mass at m = phi. */
+/* ---- closure of the interface layer (Sec. II.D) --------------------------
+ * The interface tracking defines an interface cell as a cell whose D3Q19
+ * neighbourhood holds both gas and liquid cells. Given cell types t (no
+ * liquid cell next to a gas cell), the interface cells that break this are
+ * reclassified in two passes: first those without a gas neighbour become
+ * liquid, then, on the updated types, those without a liquid neighbour
+ * become gas. Neither pass can put a liquid cell next to a gas cell, and
+ * neither undoes what the other established, so one round suffices.
+ * out[i] = 1 (to liquid), 2 (to gas) or 0. */
+static int any_nbr_of(const orc_lattice *L, const unsigned char *t, long i, unsigned char want)
+{
+    for (int q = 1; q < NQ; ++q)
+        if (t[nbr(L, i, CX[q], CY[q], CZ[q])] == want) return 1;
+    return 0;
+}
+
+static void close_layer(const orc_lattice *L, const unsigned char *t, unsigned char *out)
+{
+    const long n = L->n;
+    unsigned char *tb = (unsigned char *)malloc(n);
+    for (long i = 0; i < n; ++i) {
+        out[i] = 0;
+        tb[i] = t[i];
+        if (t[i] == ORC_INTERFACE && !any_nbr_of(L, t, i, ORC_GAS)) {
+            out[i] = 1;
+            tb[i] = ORC_LIQUID;
+        }
+    }
+    for (long i = 0; i < n; ++i)
+        if (tb[i] == ORC_INTERFACE && !any_nbr_of(L, tb, i, ORC_LIQUID)) out[i] = 2;
+    free(tb);
+}
+
 orc_lattice *orc_create(int nx, int ny, int nz, const double *fill, const unsigned char *obstacle,
                         const orc_params *p)
 {
@@ -736,6 +772,13 @@ orc_lattice *orc_create(int nx, int ny, int nz, const double *fill, const unsign
         if (t0[i] != ORC_LIQUID) continue;
         for (int q = 1; q < NQ; ++q)
             if (t0[nbr(L, i, CX[q], CY[q], CZ[q])] == ORC_GAS) { L->type[i] = ORC_INTERFACE; break; }
+    }
+    /* interface cells lacking a gas or a liquid neighbour: liquid (phi = 1)
+     * or gas (phi = 0) */
+    close_layer(L, L->type, t0);
+    for (long i = 0; i < n; ++i) {
+        if (t0[i] == 1) L->type[i] = ORC_LIQUID;
+        else if (t0[i] == 2) L->type[i] = ORC_GAS;
     }
     free(t0);
     for (long i = 0; i < n; ++i) {
@@ -908,39 +951,55 @@ static void one_step(orc_lattice *L)
             mnew[i] = r;
         }
     }
-    /* Excess mass: a filled cell keeps m = rho and hands on m - rho, an emptied
-     * cell hands on m. It is split equally over the cell's D3Q19 neighbours
-     * that are interface cells after the conversion (old interface cells that
-     * do not convert, and new interface cells). With no such neighbour the
-     * excess goes to a global reservoir. */
+    /* Types after the conversions, then the closure of the interface layer
+     * on them: a cell of the layer without a gas neighbour leaves it as
+     * liquid, one without a liquid neighbour as gas (none with frozen types). */
+    unsigned char *t1 = (unsigned char *)calloc(n, 1);
+    unsigned char *cl = (unsigned char *)calloc(n, 1);
+    for (long i = 0; i < n; ++i) {
+        t1[i] = L->type[i];
+        if (L->type[i] == ORC_INTERFACE && st2[i] == ST_FILL) t1[i] = ORC_LIQUID;
+        else if (L->type[i] == ORC_INTERFACE && st2[i] == ST_EMPTY) t1[i] = ORC_GAS;
+        else if (newi[i]) t1[i] = ORC_INTERFACE;
+    }
+    if (!p->frozen) close_layer(L, t1, cl);
+    /* Excess mass: every cell that leaves the interface layer in this step
+     * (filled, emptied, or closed) hands on its excess, m - rho when it
+     * becomes liquid and m when it becomes gas, with m and rho as they
+     * stand before the redistribution (new cells from gas: m = 0, from
+     * liquid: m = rho). It is split equally over the cell's D3Q19
+     * neighbours that are interface cells after the step. With no such
+     * neighbour the excess goes to a global reservoir. */
     double *share = (double *)calloc(n, sizeof(double));
     for (long i = 0; i < n; ++i) {
-        if (st2[i] == ST_NONE) continue;
-        double mex = st2[i] == ST_FILL ? mnew[i] - rnew[i] : mnew[i];
+        int to_liq = (L->type[i] == ORC_INTERFACE && st2[i] == ST_FILL) || cl[i] == 1;
+        int to_gas = (L->type[i] == ORC_INTERFACE && st2[i] == ST_EMPTY) || cl[i] == 2;
+        if (!to_liq && !to_gas) continue;
+        double mex = to_liq ? mnew[i] - rnew[i] : mnew[i];
         int cnt = 0;
         for (int q = 1; q < NQ; ++q) {
             long j = nbr(L, i, CX[q], CY[q], CZ[q]);
-            int recv = (L->type[j] == ORC_INTERFACE && st2[j] == ST_NONE) || newi[j] != 0;
-            cnt += recv;
+            cnt += t1[j] == ORC_INTERFACE && cl[j] == 0;
         }
         if (cnt > 0) share[i] = mex / cnt;
         else L->reservoir += mex;
     }
     for (long i = 0; i < n; ++i) {
-        int recv = (L->type[i] == ORC_INTERFACE && st2[i] == ST_NONE) || newi[i] != 0;
-        if (!recv) continue;
+        if (!(t1[i] == ORC_INTERFACE && cl[i] == 0)) continue;
         double acc = 0.0;
         for (int q = 1; q < NQ; ++q) {
             long j = nbr(L, i, CX[q], CY[q], CZ[q]);
-            if (L->type[j] == ORC_INTERFACE && st2[j] != ST_NONE) acc += share[j];
+            int leaves = (L->type[j] == ORC_INTERFACE && st2[j] != ST_NONE) || cl[j] != 0;
+            if (leaves) acc += share[j];
         }
         mnew[i] = mnew[i] + acc;
     }
     for (long i = 0; i < n; ++i) {
-        if (L->type[i] == ORC_INTERFACE && st2[i] == ST_FILL) L->type[i] = ORC_LIQUID;
-        else if (L->type[i] == ORC_INTERFACE && st2[i] == ST_EMPTY) L->type[i] = ORC_GAS;
-        else if (newi[i]) L->type[i] = ORC_INTERFACE;
+        L->type[i] = t1[i];
+        if (cl[i] == 1) L->type[i] = ORC_LIQUID;
+        else if (cl[i] == 2) L->type[i] = ORC_GAS;
     }
+    free(t1); free(cl);
     /* Phase 4: new state and fill levels. */
     double *tmp = L->f; L->f = L->fnew; L->fnew = tmp;
     for (long i = 0; i < n; ++i) {

@@ -280,8 +280,34 @@ __global__ void k_init_types(const double *fill, uint8_t *types, int N)
     types[i] = types[i] ? FL_OBST : (f >= 1.0 ? FL_LIQ : (f <= 0.0 ? FL_GAS : FL_IF));
 }
 
-// Final flags and fields: a liquid cell with a gas D3Q19 neighbour becomes
-// an interface cell with phi = 1; f' = feq(1, 0); m = phi; rho = 1.
+// Initial interface layer, one pass per stage over all cells (in -> out):
+// STAGE 0: a liquid cell with a gas D3Q19 neighbour becomes an interface
+// cell (phi = 1); STAGE 1: an interface cell without a gas neighbour
+// becomes liquid; STAGE 2: an interface cell without a liquid neighbour
+// becomes gas. Stages 1-2 close the layer (Sec. II.D: an interface cell has
+// both gas and liquid neighbours).
+template <int STAGE>
+__global__ void k_init_layer(const uint8_t *in, uint8_t *out, int nx, int ny, int nz, int N)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= N) return;
+    uint8_t t = in[i];
+    const uint8_t from = STAGE == 0 ? FL_LIQ : FL_IF;
+    if (t == from) {
+        const uint8_t want = STAGE == 2 ? FL_LIQ : FL_GAS;
+        const Nbr nb(i, nx, ny, nz);
+        bool found = false;
+#pragma unroll
+        for (int q = 1; q < NQ; ++q) found |= in[nb.at(dir_x(q), dir_y(q), dir_z(q))] == want;
+        if (STAGE == 0 && found) t = FL_IF;
+        if (STAGE == 1 && !found) t = FL_LIQ;
+        if (STAGE == 2 && !found) t = FL_GAS;
+    }
+    out[i] = t;
+}
+
+// Final flags and fields from the closed layer's types: f' = feq(1, 0);
+// interface cells m = phi (at most 1), rho = 1.
 template <class P>
 __global__ void k_init_fields(Fields<P> F, const double *fill, const uint8_t *types, uint8_t *out_flags)
 {
@@ -290,15 +316,10 @@ __global__ void k_init_fields(Fields<P> F, const double *fill, const uint8_t *ty
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= F.N) return;
     const Nbr nb(i, F.nx, F.ny, F.nz);
-    uint8_t t = types[i];
-    bool gas_nb = false, obst_nb = false;
+    const uint8_t t = types[i];
+    bool obst_nb = false;
 #pragma unroll
-    for (int q = 1; q < NQ; ++q) {
-        const uint8_t u = types[nb.at(dir_x(q), dir_y(q), dir_z(q))];
-        gas_nb |= u == FL_GAS;
-        obst_nb |= u == FL_OBST;
-    }
-    if (t == FL_LIQ && gas_nb) t = FL_IF;
+    for (int q = 1; q < NQ; ++q) obst_nb |= types[nb.at(dir_x(q), dir_y(q), dir_z(q))] == FL_OBST;
     out_flags[i] = t | (obst_nb ? FL_NEAR_OBST : 0);
     R phi = 0, m = 0, rho = 0;
     if (t == FL_LIQ) phi = 1;
@@ -645,6 +666,8 @@ int enqueue_step_kernels(fslbm_batch *b, const void *fsrc = nullptr, void *fdst 
     for (auto *h : b->hs) frozen &= h->frozen != 0;
     mark(b, 2);
     if (!frozen) k_conv_mark_init<P><<<lg, 256, 0, st>>>(A);
+    if (!frozen) k_conv_close<P, 1><<<lg, 256, 0, st>>>(A);
+    if (!frozen) k_conv_close<P, 2><<<lg, 256, 0, st>>>(A);
     if (!frozen) k_conv_share<P><<<lg, 256, 0, st>>>(A);
     k_conv_gather<P><<<lg, 256, 0, st>>>(A);
     if (!frozen) k_conv_flags<P><<<lg, 256, 0, st>>>(A);
@@ -798,6 +821,12 @@ int enqueue_init(fslbm_lattice *h, const double *fill, const uint8_t *obstacle)
     }
     k_init_scalars<<<1, 1, 0, h->stream>>>(F.sc);
     k_init_types<<<cell_blocks(N), 256, 0, h->stream>>>(staging, F.conv, N);
+    // the layer stages rotate over conv -> flags -> mark (as bytes) -> conv;
+    // k_init_fields then resets mark and writes the final flags
+    uint8_t *mark_bytes = (uint8_t *)F.mark;
+    k_init_layer<0><<<cell_blocks(N), 256, 0, h->stream>>>(F.conv, F.flags, h->nx, h->ny, h->nz, N);
+    k_init_layer<1><<<cell_blocks(N), 256, 0, h->stream>>>(F.flags, mark_bytes, h->nx, h->ny, h->nz, N);
+    k_init_layer<2><<<cell_blocks(N), 256, 0, h->stream>>>(mark_bytes, F.conv, h->nx, h->ny, h->nz, N);
     k_init_fields<P><<<cell_blocks(N), 256, 0, h->stream>>>(F, staging, F.conv, F.flags);
     k_fluid_box<<<std::min(1024, cell_blocks(N)), 256, 0, h->stream>>>(F.flags, h->nx, h->ny, N, F.sc);
     // static list of obstacle cells next to non-obstacle cells

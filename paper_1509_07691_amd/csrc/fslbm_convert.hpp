@@ -11,10 +11,17 @@
 //      cells become interface cells; those from gas get
 //      f' = feq(mean rho, mean u) of their liquid/interface neighbours and
 //      m = 0, those from liquid keep f' and get m = rho;
-//   4  a filling cell hands on m - rho, an emptying cell m, split equally
-//      over its D3Q19 neighbours that are interface cells after the step;
-//      with no such neighbour the amount goes to a reservoir;
-//   5  filling cells become liquid, emptying cells gas.
+//   4  closure of the interface layer (Sec. II.D: an interface cell has gas
+//      and liquid D3Q19 neighbours): on the types after rules 1-3, a layer
+//      cell without a gas neighbour becomes liquid; then, on the updated
+//      types, one without a liquid neighbour becomes gas;
+//   5  every cell that leaves the layer hands on m - rho (to liquid) or m
+//      (to gas), split equally over its D3Q19 neighbours that are interface
+//      cells after the step; with no such neighbour the amount goes to a
+//      reservoir;
+//   6  the cells take their new types.
+// Rule 4 starts from a closed layer (creation closes it), so only cells of
+// the step's layer (old interface cells and new cells) can break it.
 // Every kernel runs over the interface list of the step (grid-stride) and is
 // written as a gather: each output value has one writer, or several writers
 // storing the identical value (new cells reached from several converting
@@ -31,10 +38,18 @@ constexpr int LIST_GRID = 256;  // blocks per lattice of the grid-stride list ke
 
 __device__ inline int list_count(const DevScalars *sc) { return *(volatile const int *)&sc->icount; }
 
+// A cell of the step's layer: an interface cell of the old list or a new
+// cell tagged in this step (its conv status is reset when it is tagged).
 template <class P>
-__device__ inline bool is_converter(const Fields<P> &F, int j)
+__device__ inline bool in_layer(const Fields<P> &F, int j, uint32_t tag)
 {
-    return (F.flags[j] & FL_IF) && F.conv[j] != CV_NONE;
+    return (F.flags[j] & FL_IF) || (F.mark[j] & ~3u) == tag;
+}
+
+template <class P>
+__device__ inline bool is_converter(const Fields<P> &F, int j, uint32_t tag)
+{
+    return in_layer(F, j, tag) && F.conv[j] != CV_NONE;
 }
 
 // Rule 2 for cell i: an emptying cell next to a filling cell does not
@@ -86,6 +101,7 @@ __global__ __launch_bounds__(256) void k_conv_mark_init(const Batch<P> B)
             if (st == CV_FILL && tj == FL_GAS) {
                 // the first thread to tag j lists it as a new interface cell
                 if ((atomicExch(&F.mark[j], tag | 1u) & ~3u) != tag) fresh[nfresh++] = j;
+                F.conv[j] = CV_NONE;
                 // mean rho and u over the liquid / interface neighbours of j
                 const Nbr nj(j, F.nx, F.ny, F.nz);
                 T rs = 0, usx = 0, usy = 0, usz = 0;
@@ -128,6 +144,7 @@ __global__ __launch_bounds__(256) void k_conv_mark_init(const Batch<P> B)
                 F.m[j] = R(0);
             } else if (st == CV_EMPTY && tj == FL_LIQ) {
                 if ((atomicExch(&F.mark[j], tag | 2u) & ~3u) != tag) fresh[nfresh++] = j;
+                F.conv[j] = CV_NONE;
                 T fw[NQ];
 #pragma unroll
                 for (int s = 0; s < NQ; ++s) {
@@ -163,14 +180,63 @@ __global__ __launch_bounds__(256) void k_conv_mark_init(const Batch<P> B)
     }
 }
 
+// Cell types after rules 1-3 (CLOSE_* codes read as interface): the
+// classification rule 4 starts from.
+template <class P>
+__device__ inline uint8_t type_after_conversion(const Fields<P> &F, int j, uint32_t tag)
+{
+    const uint8_t f = F.flags[j];
+    if ((F.mark[j] & ~3u) == tag) return FL_IF;
+    if (!(f & FL_IF)) return f & FL_TYPE;
+    const uint8_t st = F.conv[j];
+    return st == CV_FILL ? FL_LIQ : (st == CV_EMPTY ? FL_GAS : FL_IF);
+}
+
+// Cell k of the step's layer: the old list, then the new cells.
+template <class P>
+__device__ inline int layer_cell(const Fields<P> &F, int k, int n)
+{
+    return k < n ? F.ilist[k] : F.newlist[k - n];
+}
+
+// Rule 4. STAGE 1: a layer cell without a gas neighbour (types after rules
+// 1-3) becomes liquid. STAGE 2: a layer cell without a liquid neighbour
+// (those types with the STAGE-1 cells liquid) becomes gas. Each cell writes
+// only its own status, and no status a stage writes is read by that stage.
+template <class P, int STAGE>
+__global__ __launch_bounds__(256) void k_conv_close(const Batch<P> B)
+{
+    const Fields<P> &F = B.f[blockIdx.y];
+    if (F.sc->nconv == 0) return;
+    const uint32_t tag = F.sc->step << 2;
+    const int n = list_count(F.sc), nn = F.sc->nnew;
+    for (int k = blockIdx.x * 256 + threadIdx.x; k < n + nn; k += gridDim.x * 256) {
+        const int i = layer_cell(F, k, n);
+        const uint8_t st = F.conv[i];
+        if (st != CV_NONE) continue;
+        const Nbr nb(i, F.nx, F.ny, F.nz);
+        bool found = false;
+#pragma unroll
+        for (int q = 1; q < NQ; ++q) {
+            const int j = nb.at(dir_x(q), dir_y(q), dir_z(q));
+            const uint8_t t = type_after_conversion(F, j, tag);
+            if (STAGE == 1) {
+                found |= t == FL_GAS;
+            } else {
+                found |= t == FL_LIQ || (t == FL_IF && F.conv[j] == CV_CLOSE_LIQ);
+            }
+        }
+        if (!found) F.conv[i] = STAGE == 1 ? CV_CLOSE_LIQ : CV_CLOSE_GAS;
+    }
+}
+
 template <class P>
 __device__ inline bool is_receiver(const Fields<P> &F, int j, uint32_t tag)
 {
-    const uint8_t f = F.flags[j];
-    return ((f & FL_IF) && F.conv[j] == CV_NONE) || (F.mark[j] & ~3u) == tag;
+    return in_layer(F, j, tag) && F.conv[j] == CV_NONE;
 }
 
-// Rule 4, first half: each converting cell computes its share.
+// Rule 5, first half: each cell that leaves the layer computes its share.
 template <class P>
 __global__ __launch_bounds__(256) void k_conv_share(const Batch<P> B)
 {
@@ -178,12 +244,12 @@ __global__ __launch_bounds__(256) void k_conv_share(const Batch<P> B)
     using R = typename P::R;
     if (F.sc->nconv == 0) return;
     const uint32_t tag = F.sc->step << 2;
-    const int n = list_count(F.sc);
-    for (int k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256) {
-        const int i = F.ilist[k];
+    const int n = list_count(F.sc), nn = F.sc->nnew;
+    for (int k = blockIdx.x * 256 + threadIdx.x; k < n + nn; k += gridDim.x * 256) {
+        const int i = layer_cell(F, k, n);
         const uint8_t st = F.conv[i];
         if (st == CV_NONE) continue;
-        const R mex = st == CV_FILL ? F.m[i] - F.rho[i] : F.m[i];
+        const R mex = cv_to_liquid(st) ? F.m[i] - F.rho[i] : F.m[i];
         const Nbr nb(i, F.nx, F.ny, F.nz);
         int cnt = 0;
 #pragma unroll
@@ -198,7 +264,7 @@ __global__ __launch_bounds__(256) void k_conv_share(const Batch<P> B)
 }
 
 template <class P>
-__device__ inline typename P::R gathered_excess(const Fields<P> &F, int j)
+__device__ inline typename P::R gathered_excess(const Fields<P> &F, int j, uint32_t tag)
 {
     using R = typename P::R;
     const Nbr nb(j, F.nx, F.ny, F.nz);
@@ -206,14 +272,15 @@ __device__ inline typename P::R gathered_excess(const Fields<P> &F, int j)
 #pragma unroll
     for (int q = 1; q < NQ; ++q) {
         const int w = nb.at(dir_x(q), dir_y(q), dir_z(q));
-        if (is_converter(F, w)) acc += F.share[w];
+        if (is_converter(F, w, tag)) acc += F.share[w];
     }
     return acc;
 }
 
-// Rule 4, second half: receivers gather their neighbours' shares in fixed
+// Rule 5, second half: receivers gather their neighbours' shares in fixed
 // direction order. This kernel also sets phi = m / rho of every interface
-// cell for the new time level, so it runs in every step.
+// cell for the new time level, so it runs in every step. Every new cell is
+// next to a filling or emptying cell of the old list, whose thread sets it.
 template <class P>
 __global__ __launch_bounds__(256) void k_conv_gather(const Batch<P> B)
 {
@@ -226,28 +293,36 @@ __global__ __launch_bounds__(256) void k_conv_gather(const Batch<P> B)
         const int i = F.ilist[k];
         const uint8_t st = any ? F.conv[i] : CV_NONE;
         if (st == CV_NONE) {
-            const R acc = any ? gathered_excess(F, i) : R(0);
+            const R acc = any ? gathered_excess(F, i, tag) : R(0);
             const R mn = F.m[i] + acc;
             F.m[i] = mn;
             F.phi[i] = mn / F.rho[i];
             continue;
         }
-        F.phi[i] = st == CV_FILL ? R(1) : R(0);
+        F.phi[i] = cv_to_liquid(st) ? R(1) : R(0);
+        // a new neighbour of a closing cell is also next to the filling or
+        // emptying cell that made it, whose thread sets it
+        if (st == CV_CLOSE_LIQ || st == CV_CLOSE_GAS) continue;
         const Nbr nb(i, F.nx, F.ny, F.nz);
         for (int q = 1; q < NQ; ++q) {
             const int j = nb.at(dir_x(q), dir_y(q), dir_z(q));
             const uint32_t mk = F.mark[j];
             if ((mk & ~3u) != tag) continue;
+            const uint8_t sj = F.conv[j];
+            if (sj != CV_NONE) {
+                F.phi[j] = cv_to_liquid(sj) ? R(1) : R(0);
+                continue;
+            }
             const R base = (mk & 3u) == 1u ? R(0) : F.rho[j];
-            const R mn = base + gathered_excess(F, j);
+            const R mn = base + gathered_excess(F, j, tag);
             F.m[j] = mn;
             F.phi[j] = mn / F.rho[j];
         }
     }
 }
 
-// Rule 5 and the new interface cells' types; block 0 also resets the list
-// rebuild counters for k_list_keep.
+// Rule 6: the new types of converting and new cells; block 0 also resets
+// the list rebuild counters for k_list_keep.
 template <class P>
 __global__ __launch_bounds__(256) void k_conv_flags(const Batch<P> B)
 {
@@ -265,20 +340,25 @@ __global__ __launch_bounds__(256) void k_conv_flags(const Batch<P> B)
         const uint8_t st = F.conv[i];
         if (st == CV_NONE) continue;
         const uint8_t stat = F.flags[i] & FL_NEAR_OBST;
-        F.flags[i] = stat | (st == CV_FILL ? FL_LIQ : FL_GAS);
+        F.flags[i] = stat | (cv_to_liquid(st) ? FL_LIQ : FL_GAS);
+        if (st == CV_CLOSE_LIQ || st == CV_CLOSE_GAS) continue;  // as in k_conv_gather
         const Nbr nb(i, F.nx, F.ny, F.nz);
         for (int q = 1; q < NQ; ++q) {
             const int j = nb.at(dir_x(q), dir_y(q), dir_z(q));
-            if ((F.mark[j] & ~3u) == tag) F.flags[j] = (F.flags[j] & FL_NEAR_OBST) | FL_IF;
+            if ((F.mark[j] & ~3u) != tag) continue;
+            const uint8_t sj = F.conv[j];
+            const uint8_t tj = sj == CV_NONE ? FL_IF : (cv_to_liquid(sj) ? FL_LIQ : FL_GAS);
+            F.flags[j] = (F.flags[j] & FL_NEAR_OBST) | tj;
         }
     }
 }
 
 // ------------------------------------------------ interface-list update
-// After a step with conversions the list becomes (cells that stay) + (new
-// cells). The order of the list does not enter any result (every per-cell
-// computation is independent), so kept cells are appended with an atomic
-// counter; the interface bounding box is recomputed on the way.
+// After a step with conversions the list becomes the cells of the step's
+// layer (old list, then new cells) that are interface cells. The order of
+// the list does not enter any result (every per-cell computation is
+// independent), so kept cells are appended with an atomic counter; the
+// interface bounding box is recomputed on the way.
 __device__ inline int block_exclusive_scan(int v, int *lds_wave, int &total)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -342,7 +422,7 @@ __device__ inline void box_add(const Fields<P> &F, int i, int (&lo)[3], int (&hi
     hi[0] = max(hi[0], x); hi[1] = max(hi[1], y); hi[2] = max(hi[2], z);
 }
 
-// Cells of the old list that are still interface cells, written in list
+// Cells of the step's layer that are interface cells, written in layer
 // order within each block: a counting pass, one atomic for the block's
 // base, then the ordered write with a block prefix sum.
 template <class P>
@@ -350,13 +430,13 @@ __global__ __launch_bounds__(256) void k_list_keep(const Batch<P> B)
 {
     const Fields<P> &F = B.f[blockIdx.y];
     if (F.sc->nconv == 0) return;
-    const int n = list_count(F.sc);
+    const int n = list_count(F.sc), nl = n + F.sc->nnew;
     int k0, k1;
-    block_share(n, k0, k1);
+    block_share(nl, k0, k1);
     __shared__ int lw[4];
     __shared__ int base_s;
     int cnt = 0;
-    for (int k = k0 + threadIdx.x; k < k1; k += 256) cnt += (F.flags[F.ilist[k]] & FL_IF) != 0;
+    for (int k = k0 + threadIdx.x; k < k1; k += 256) cnt += (F.flags[layer_cell(F, k, n)] & FL_IF) != 0;
     int total;
     block_exclusive_scan(cnt, lw, total);
     if (threadIdx.x == 0) base_s = total > 0 ? atomicAdd(&F.sc->nkeep, total) : 0;
@@ -365,7 +445,7 @@ __global__ __launch_bounds__(256) void k_list_keep(const Batch<P> B)
     int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {-1, -1, -1};
     for (int kk = k0; kk < k1; kk += 256) {
         const int k = kk + threadIdx.x;
-        const int i = k < k1 ? F.ilist[k] : 0;
+        const int i = k < k1 ? layer_cell(F, k, n) : 0;
         const bool keep = k < k1 && (F.flags[i] & FL_IF);
         int tot;
         const int ex = block_exclusive_scan(keep ? 1 : 0, lw, tot);
@@ -378,7 +458,9 @@ __global__ __launch_bounds__(256) void k_list_keep(const Batch<P> B)
     block_box_update(lo, hi, F.sc->bbox);
 }
 
-// New list = kept cells + new cells; the new cells extend both boxes.
+// New list = the kept cells. The fluid box grows by every new cell (a new
+// cell from gas is fluid whether it stays in the layer or closes to
+// liquid); the interface box came from k_list_keep.
 template <class P>
 __global__ __launch_bounds__(256) void k_list_finish(const Batch<P> B)
 {
@@ -387,18 +469,11 @@ __global__ __launch_bounds__(256) void k_list_finish(const Batch<P> B)
     const int nk = F.sc->nkeep, nn = F.sc->nnew;
     int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {-1, -1, -1};
     for (int k = blockIdx.x * 256 + threadIdx.x; k < nk + nn; k += gridDim.x * 256) {
-        if (k < nk) {
-            F.ilist[k] = F.ilist_tmp[k];
-        } else {
-            const int i = F.newlist[k - nk];
-            F.ilist[k] = i;
-            box_add(F, i, lo, hi);
-        }
+        if (k < nk) F.ilist[k] = F.ilist_tmp[k];
+        else box_add(F, F.newlist[k - nk], lo, hi);
     }
-    int lo2[3] = {lo[0], lo[1], lo[2]}, hi2[3] = {hi[0], hi[1], hi[2]};
-    block_box_update(lo, hi, F.sc->bbox);
-    block_box_update(lo2, hi2, F.sc->fbox);  // the fluid region grows by the new cells
-    if (blockIdx.x == 0 && threadIdx.x == 0) F.sc->icount = nk + nn;
+    block_box_update(lo, hi, F.sc->fbox);
+    if (blockIdx.x == 0 && threadIdx.x == 0) F.sc->icount = nk;
 }
 
 // ----------------------------------------------------------- compaction

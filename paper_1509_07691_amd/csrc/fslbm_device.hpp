@@ -49,7 +49,11 @@ enum : uint8_t {
     FL_NEAR_OBST = 16,
 };
 // Conversion status of an interface cell within one step.
-enum : uint8_t { CV_NONE = 0, CV_FILL = 1, CV_EMPTY = 2 };
+// Conversion status of a cell in a step: fills / empties (rules 1-2 of the
+// conversion), or leaves the interface layer by its closure (to liquid /
+// to gas).
+enum : uint8_t { CV_NONE = 0, CV_FILL = 1, CV_EMPTY = 2, CV_CLOSE_LIQ = 3, CV_CLOSE_GAS = 4 };
+__host__ __device__ inline bool cv_to_liquid(uint8_t st) { return st == CV_FILL || st == CV_CLOSE_LIQ; }
 
 // ------------------------------------------------------- precision traits
 // S: stored type of a distribution, T: arithmetic type of the collide,

@@ -89,7 +89,9 @@ def test_static_droplet_fp64_500_steps(Lattice, model):
     for n in (1, 9, 90, 400):
         g.step(n)
         o.step(n)
-        compare(g, o, 1e-10, what=f"{model} after +{n}")
+        # the spurious currents decay towards round-off: velocity relative
+        # to the capillary scale sigma / mu
+        compare(g, o, 1e-10, what=f"{model} after +{n}", vscale=1e-3 / (0.5 / 3.0))
     assert abs(g.mass() - o.mass()) / o.mass() < 1e-13
 
 

@@ -45,7 +45,8 @@ def bubble_run():
     fill, obst = _bubble_box()
     o = O.Oracle(fill, obst, sigma=SIGMA, tau=1.0, curv_model=O.CURV_FD, bubble=True)
     free = obst == 0
-    v0 = float((1.0 - fill)[free].sum())
+    # V0 from the fill levels after the interface layer's closure at creation
+    v0 = float((1.0 - o.fill())[free].sum())
     m0 = o.mass()
     o.step(300)
     return o, fill, obst, v0, m0

@@ -200,6 +200,45 @@ def test_flat_free_surface_stays_at_rest(model):
     np.testing.assert_array_equal(ph[0], ph[1])
 
 
+_D3Q19 = [(dz, dy, dx) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)
+          if 0 < abs(dz) + abs(dy) + abs(dx) <= 2]
+
+
+def _nbr_any(mask):
+    out = np.zeros_like(mask)
+    for d in _D3Q19:
+        out |= np.roll(mask, d, axis=(0, 1, 2))
+    return out
+
+
+def _assert_closed_layer(fl):
+    """Sec. II.D: an interface cell has both gas and liquid D3Q19 neighbours."""
+    ifc = fl == O.INTERFACE
+    assert not np.any(ifc & ~_nbr_any(fl == O.GAS)), "interface cell without a gas neighbour"
+    assert not np.any(ifc & ~_nbr_any(fl == O.LIQUID)), "interface cell without a liquid neighbour"
+
+
+def test_interface_layer_closed_at_creation():
+    # exact volume fractions of a sphere of radius 6 leave cells with
+    # 0 < phi < 1 that have no gas (or no liquid) neighbour; they join the
+    # liquid with phi = 1 (or the gas with phi = 0)
+    fill, obst = I.laplace_bubble(48)
+    inside = (fill > 0) & (fill < 1) & (obst == 0)
+    raw_gas = (fill <= 0) & (obst == 0)
+    raw_liq = fill >= 1
+    assert np.any(inside & ~_nbr_any(raw_gas))  # the input has such cells
+    orc = O.Oracle(fill, obst)
+    fl, ph = orc.flags(), orc.fill()
+    _assert_closed_layer(fl)
+    ifc = fl == O.INTERFACE
+    np.testing.assert_array_equal(ph[ifc], np.minimum(fill[ifc], 1.0))
+    to_liq = inside & (fl == O.LIQUID)
+    to_gas = inside & (fl == O.GAS)
+    assert np.any(to_liq) and np.all(~_nbr_any(raw_gas)[to_liq])
+    assert np.all(ph[to_liq] == 1.0) and np.all(ph[to_gas] == 0.0)
+    assert np.all(fl[raw_liq & ~_nbr_any(raw_gas)] == O.LIQUID)
+
+
 # ---------------------------------------------- mass exchange (eq. advection1)
 @pytest.mark.parametrize("model", [O.CURV_FD, O.CURV_LSQR])
 def test_mass_is_conserved_through_conversions(model):
@@ -216,6 +255,7 @@ def test_mass_is_conserved_through_conversions(model):
         orc.step(10)
         assert abs(orc.mass() - M0) / M0 < 1e-13
         changed = max(changed, int((orc.flags() != fl0).sum()))
+        _assert_closed_layer(orc.flags())
     assert changed > 20  # the drop moved: cells converted
     fl = orc.flags()
     # invariant (Sec. II): only interface cells carry fills strictly in (0,1),
