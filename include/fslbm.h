@@ -59,7 +59,12 @@ enum fslbm_status {
  * FP32; m, phi, rho and K are FP64 in F64 mode and FP32 otherwise. Normals,
  * PLIC points and the least-squares solve are always FP64. */
 enum fslbm_precision { FSLBM_F64 = 0, FSLBM_F32 = 1, FSLBM_F16_STORE = 2, FSLBM_BF16_STORE = 3 };
-enum fslbm_curv_model { FSLBM_CURV_FD = 0, FSLBM_CURV_LSQR = 1 };
+/* Curvature models: FD (Sec. II.A, mollified finite differences, wetting
+ * by the extrapolated contact normal), LSQR (Sec. II.C, least-squares
+ * quadric of the PLIC points, wetting by the contact constraint), TR
+ * (Sec. II.B, triangle fan of the PLIC points with Taubin's estimate; no
+ * wetting, and not covered by the adjoint). */
+enum fslbm_curv_model { FSLBM_CURV_FD = 0, FSLBM_CURV_LSQR = 1, FSLBM_CURV_TR = 2 };
 enum fslbm_collision { FSLBM_SRT = 0, FSLBM_TRT = 1 };
 /* Cell types reported by fslbm_read_flags. */
 enum fslbm_cell { FSLBM_GAS = 0, FSLBM_LIQUID = 1, FSLBM_INTERFACE = 2, FSLBM_OBSTACLE = 3 };
@@ -100,6 +105,10 @@ int fslbm_required_bytes(int nx, int ny, int nz, int precision, size_t *bytes);
  *           derived as obstacle where obstacle[i] != 0, else liquid for
  *           fill >= 1, gas for fill <= 0, interface otherwise; a liquid cell
  *           with a gas D3Q19 neighbour becomes an interface cell with fill 1.
+ *           Then the interface layer is closed (Sec. II.D: an interface cell
+ *           has gas and liquid D3Q19 neighbours): interface cells without a
+ *           gas neighbour become liquid (fill 1), then those without a
+ *           liquid neighbour gas (fill 0). The step keeps this invariant.
  *  obstacle host, n bytes, may be NULL (no walls).
  *  workspace device memory of at least fslbm_required_bytes() bytes, 256-byte
  *           aligned, owned by the caller and kept alive until fslbm_destroy.

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "liboracle_fslbm.so")
 _SRC = os.path.join(_HERE, "fslbm_oracle.c")
 
 GAS, LIQUID, INTERFACE, OBSTACLE = 0, 1, 2, 3
-CURV_FD, CURV_LSQR = 0, 1
+CURV_FD, CURV_LSQR, CURV_TR = 0, 1, 2
 SRT, TRT = 0, 1
 
 
@@ -80,6 +80,8 @@ def lib():
         L.orc_quadric_curvature.argtypes = [ctypes.c_double] * 5
         L.orc_lsqr_fit_points.restype = ctypes.c_int
         L.orc_lsqr_fit_points.argtypes = [ctypes.c_int, dp, dp, dp]
+        L.orc_tr_curvature_points.restype = ctypes.c_double
+        L.orc_tr_curvature_points.argtypes = [ctypes.c_int, dp, dp]
         _lib = L
     return _lib
 
@@ -116,6 +118,13 @@ def lsqr_fit_points(pts, nhat):
     c = np.zeros(5)
     ok = lib().orc_lsqr_fit_points(pts.shape[0], _dptr(pts), _dptr(n), _dptr(c))
     return c if ok else None
+
+
+def tr_curvature_points(d, nhat):
+    """TR curvature K (2 x mean curvature) from neighbour offsets d (m x 3)."""
+    d = np.ascontiguousarray(d, dtype=np.float64).reshape(-1, 3)
+    n = np.ascontiguousarray(nhat, dtype=np.float64)
+    return lib().orc_tr_curvature_points(d.shape[0], _dptr(d), _dptr(n))
 
 
 class Oracle:

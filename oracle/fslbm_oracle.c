@@ -21,8 +21,9 @@
  *      and excess-mass redistribution
  *   4  fill levels phi = m / rho, obstacle fill reflection (Sec. II.A)
  *   5  interface normals (eq. normal) and PLIC points (Sec. II.B), curvature
- *      by FD (eq. curvature, K8 mollifier) or LSQR (Sec. II.C, eqs.
- *      LSQR-model, LSQR-error, anacurv, contactNormal, contactConstraint)
+ *      by FD (eq. curvature, K8 mollifier), LSQR (Sec. II.C, eqs.
+ *      LSQR-model, LSQR-error, anacurv, contactNormal, contactConstraint) or
+ *      TR (Sec. II.B: triangle fan of the PLIC points, Taubin's estimate)
  *
  * Pins: the test suite checks this file against closed forms (PLIC volumes,
  * the graph curvature, planes, spheres, cylinders, lattice viscosity),
@@ -490,7 +491,7 @@ static void normals_and_plic(orc_lattice *L)
         L->nrm[3 * i] = nh[0];
         L->nrm[3 * i + 1] = nh[1];
         L->nrm[3 * i + 2] = nh[2];
-        if (L->p.curv_model == ORC_CURV_LSQR) L->plic[i] = orc_plic_offset(nh, L->phi[i]);
+        if (L->p.curv_model != ORC_CURV_FD) L->plic[i] = orc_plic_offset(nh, L->phi[i]);
     }
 }
 
@@ -683,22 +684,110 @@ static double lsqr_cell(const orc_lattice *L, long i)
     return orc_quadric_curvature(coef[0], coef[1], coef[2], coef[3], coef[4]);
 }
 
+/* TR curvature (Sec. II.B). The paper cites the construction (a triangle
+ * fan of the PLIC points of a 3x3x3 block, Pohl 2007; the curvature of the
+ * polygonal surface by a variant of Taubin 1995) without its details; this
+ * is the reading used here, written from those two methods.
+ *   fan:  the neighbours' points, seen from the centre point p in its
+ *         tangent plane (frame of local_frame), are ordered by their polar
+ *         angle, measured from the direction at 1 rad from t_u (so that
+ *         the lattice's symmetric directions never sit on the branch cut);
+ *         angles within 1e-12 count as equal and keep block order. Points
+ *         on the normal line (u^2 + v^2 < 1e-12) are left out. Consecutive
+ *         points k, k+1 (cyclic) span the triangle (p, p_k, p_k+1) unless
+ *         the angular gap between them is at least pi - 1e-12 (the fan is
+ *         open there, e.g. at a wall).
+ *   Taubin: along each edge p -> p_k the normal curvature is
+ *         kappa_k = 2 (d_k . n) / |d_k|^2 with d_k = p_k - p; each vertex
+ *         is weighted by the area of the fan triangles it belongs to. The
+ *         trace of Taubin's matrix M = sum w_k kappa_k T_k T_k^T (unit
+ *         tangents T_k, weights summing to 1) is sum w_k kappa_k, and his
+ *         principal curvatures 3m1 - m2, 3m2 - m1 add up to 2 tr M, so
+ *         K = kappa_1 + kappa_2 = 2 sum w_k kappa_k.
+ * Fewer than three points, or no triangle, give K = 0. */
+static double edge_curvature(const double d[3], const double n[3]) { return 2.0 * dot3(d, n) / dot3(d, d); }
+
+double orc_tr_curvature_points(int npts, const double *d, const double nhat[3])
+{
+    const double PI = 3.14159265358979323846;
+    double tu[3], tv[3];
+    local_frame(nhat, tu, tv);
+    const double c1 = cos(1.0), s1 = sin(1.0);
+    int idx[32];
+    double ang[32];
+    int m = 0;
+    for (int j = 0; j < npts && m < 32; ++j) {
+        double u = dot3(d + 3 * j, tu), v = dot3(d + 3 * j, tv);
+        if (u * u + v * v < 1e-12) continue;
+        idx[m] = j;
+        ang[m] = atan2(-u * s1 + v * c1, u * c1 + v * s1);
+        m++;
+    }
+    if (m < 3) return 0.0;
+    /* insertion sort by (angle, block order) */
+    for (int a = 1; a < m; ++a) {
+        int ki = idx[a];
+        double ka = ang[a];
+        int b = a - 1;
+        while (b >= 0) {
+            int before = fabs(ang[b] - ka) > 1e-12 ? ka < ang[b] : ki < idx[b];
+            if (!before) break;
+            idx[b + 1] = idx[b];
+            ang[b + 1] = ang[b];
+            --b;
+        }
+        idx[b + 1] = ki;
+        ang[b + 1] = ka;
+    }
+    double num = 0.0, den = 0.0;
+    for (int k = 0; k < m; ++k) {
+        int k1 = (k + 1) % m;
+        double gap = ang[k1] - ang[k] + (k1 == 0 ? 2.0 * PI : 0.0);
+        if (gap >= PI - 1e-12) continue;
+        const double *da = d + 3 * idx[k], *db = d + 3 * idx[k1];
+        double cr[3] = {da[1] * db[2] - da[2] * db[1], da[2] * db[0] - da[0] * db[2], da[0] * db[1] - da[1] * db[0]};
+        double area = 0.5 * sqrt(dot3(cr, cr));
+        num += area * (edge_curvature(da, nhat) + edge_curvature(db, nhat));
+        den += 2.0 * area;
+    }
+    return den > 0.0 ? 2.0 * num / den : 0.0;
+}
+
+static double tr_cell(const orc_lattice *L, long i)
+{
+    const double *nh = L->nrm + 3 * i;
+    if (dot3(nh, nh) == 0.0) return 0.0;
+    double pc[3] = {L->plic[i] * nh[0], L->plic[i] * nh[1], L->plic[i] * nh[2]};
+    double d[26 * 3];
+    int np = 0;
+    for (int c = -1; c <= 1; ++c)
+        for (int b = -1; b <= 1; ++b)
+            for (int a = -1; a <= 1; ++a) {
+                long j = nbr(L, i, a, b, c);
+                if (a == 0 && b == 0 && c == 0) continue;
+                if (L->type[j] != ORC_INTERFACE) continue;
+                const double *nj = L->nrm + 3 * j;
+                if (dot3(nj, nj) == 0.0) continue;
+                d[3 * np] = a + L->plic[j] * nj[0] - pc[0];
+                d[3 * np + 1] = b + L->plic[j] * nj[1] - pc[1];
+                d[3 * np + 2] = c + L->plic[j] * nj[2] - pc[2];
+                np++;
+            }
+    return orc_tr_curvature_points(np, d, nh);
+}
+
 static void curvature(orc_lattice *L)
 {
     normals_and_plic(L);
     if (L->p.curv_model == ORC_CURV_FD) {
         curvature_fd(L);
-    } else {
+    } else if (L->p.curv_model == ORC_CURV_LSQR) {
         for (long i = 0; i < L->n; ++i) L->K[i] = L->type[i] == ORC_INTERFACE ? lsqr_cell(L, i) : 0.0;
+    } else {
+        for (long i = 0; i < L->n; ++i) L->K[i] = L->type[i] == ORC_INTERFACE ? tr_cell(L, i) : 0.0;
     }
 }
 
-/* ---- lattice construction ----------------------------------------------- */
-/* Cell types from the fill level (Sec. II: gas cells have phi = 0, only
- * interface cells lie strictly between 0 and 1). A liquid cell with a gas
- * D3Q19 neighbour becomes an interface cell with phi = 1, so that every
- * gas-liquid contact runs through an interface cell. f starts at
- * feq(rho = 1, u = 0) and the interface mass at m = phi. */
 /* ---- closure of the interface layer (Sec. II.D) --------------------------
  * The interface tracking defines an interface cell as a cell whose D3Q19
  * neighbourhood holds both gas and liquid cells. Given cell types t (no
@@ -732,6 +821,13 @@ static void close_layer(const orc_lattice *L, const unsigned char *t, unsigned c
     free(tb);
 }
 
+/* ---- lattice construction ----------------------------------------------- */
+/* Cell types from the fill level (Sec. II: gas cells have phi = 0, only
+ * interface cells lie strictly between 0 and 1). A liquid cell with a gas
+ * D3Q19 neighbour becomes an interface cell with phi = 1, so that every
+ * gas-liquid contact runs through an interface cell; then the layer is closed
+ * (close_layer). f starts at
+ * feq(rho = 1, u = 0) and the interface mass at m = phi. */
 orc_lattice *orc_create(int nx, int ny, int nz, const double *fill, const unsigned char *obstacle,
                         const orc_params *p)
 {

@@ -19,7 +19,7 @@ extern "C" {
 #endif
 
 enum { ORC_GAS = 0, ORC_LIQUID = 1, ORC_INTERFACE = 2, ORC_OBSTACLE = 3 };
-enum { ORC_CURV_FD = 0, ORC_CURV_LSQR = 1 };
+enum { ORC_CURV_FD = 0, ORC_CURV_LSQR = 1, ORC_CURV_TR = 2 };
 enum { ORC_SRT = 0, ORC_TRT = 1 };
 
 typedef struct {
@@ -29,7 +29,7 @@ typedef struct {
     double rho_gas;    /* gas pressure as a density: p_g = rho_gas / 3 */
     double eps_c;      /* conversion offset of the fill/empty thresholds */
     double trt_magic;  /* TRT Lambda = (tau_e - 1/2)(tau_o - 1/2) */
-    int curv_model;    /* ORC_CURV_FD or ORC_CURV_LSQR */
+    int curv_model;    /* ORC_CURV_FD, ORC_CURV_LSQR or ORC_CURV_TR */
     int collision;     /* ORC_SRT or ORC_TRT */
     int frozen;        /* 1: cell types stay fixed (no fill/empty conversion) */
     int bubble;        /* 1: the gas pressure follows the gas volume (one bubble) */
@@ -69,6 +69,9 @@ int orc_lsq_solve(int rows, int cols, const double *M, const double *b, double *
 double orc_quadric_curvature(double A, double B, double C, double H, double I);
 int orc_lsqr_fit_points(int npts, const double *pts, const double nhat[3],
                         double *coef5);
+/* TR curvature K (= 2 x mean curvature) at a point with unit normal nhat
+ * from its neighbours' offsets d (npts x 3, block order). */
+double orc_tr_curvature_points(int npts, const double *d, const double nhat[3]);
 
 #ifdef __cplusplus
 }

@@ -599,22 +599,20 @@ int enqueue_geometry(const fslbm_batch *b, const Batch<P> &A, int maxN)
     const unsigned n = (unsigned)b->hs.size();
     const hipStream_t st = bstream(b);
     const dim3 tg(std::min(GEOM_GRID, std::max(1, maxN / 512)), n);
-    bool any_fd = false, any_lsqr = false;
+    bool any_fd = false, any_lsqr = false, any_tr = false;
     for (auto *h : b->hs) {
         any_fd |= h->curv == FSLBM_CURV_FD;
         any_lsqr |= h->curv == FSLBM_CURV_LSQR;
+        any_tr |= h->curv == FSLBM_CURV_TR;
     }
-    const dim3 cg4(batch_list_blocks(b, 64), n);
+    const bool any_plic = any_lsqr || any_tr;
+    const dim3 cg4(batch_list_blocks(b, 64), n), cgt(batch_list_blocks(b, 256 / TR_LANES), n);
     if (any_fd) k_fd_contact_normals<P><<<dim3(list_blocks(maxN), n), 256, 0, st>>>(A);
-    if (any_fd && any_lsqr) {
-        k_geometry_mixed<P><<<tg, 256, 0, st>>>(A);
-        k_curv_lsqr4<P><<<cg4, 256, 0, st>>>(A);
-    } else if (any_fd) {
-        k_geometry_fd<P><<<tg, 256, 0, st>>>(A);
-    } else if (any_lsqr) {
-        k_normals_plic<P><<<dim3(batch_list_blocks(b, 256), n), 256, 0, st>>>(A);
-        k_curv_lsqr4<P><<<cg4, 256, 0, st>>>(A);
-    }
+    if (any_fd && any_plic) k_geometry_mixed<P><<<tg, 256, 0, st>>>(A);
+    else if (any_fd) k_geometry_fd<P><<<tg, 256, 0, st>>>(A);
+    else if (any_plic) k_normals_plic<P><<<dim3(batch_list_blocks(b, 256), n), 256, 0, st>>>(A);
+    if (any_lsqr) k_curv_lsqr4<P><<<cg4, 256, 0, st>>>(A);
+    if (any_tr) k_curv_tr<P><<<cgt, 256, 0, st>>>(A);
     HIP_OK(hipGetLastError());
     return 0;
 }
@@ -1323,7 +1321,7 @@ int fslbm_create(int nx, int ny, int nz, int precision, int curv_model, const do
     if (!workspace) return fail(FSLBM_E_ARG, "workspace is NULL");
     if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return fail(FSLBM_E_ARG, "workspace not 256-byte aligned");
     if (precision < 0 || precision > 3) return fail(FSLBM_E_ARG, "unknown precision %d", precision);
-    if (curv_model != FSLBM_CURV_FD && curv_model != FSLBM_CURV_LSQR)
+    if (curv_model != FSLBM_CURV_FD && curv_model != FSLBM_CURV_LSQR && curv_model != FSLBM_CURV_TR)
         return fail(FSLBM_E_ARG, "unknown curvature model %d", curv_model);
     if (!shape_ok(nx, ny, nz)) return fail(FSLBM_E_SHAPE, "lattice %dx%dx%d out of range", nx, ny, nz);
     const long long N = (long long)nx * ny * nz;
@@ -1695,6 +1693,7 @@ int fslbm_adjoint_forward(fslbm_t h, int64_t nsteps, int K, void *workspace, siz
     if (nsteps < 1 || K < 1) return fail(FSLBM_E_ARG, "nsteps and K must be >= 1");
     if (!workspace) return fail(FSLBM_E_ARG, "workspace is NULL");
     if (h->bubble) return fail(FSLBM_E_STATE, "the adjoint does not cover the bubble model");
+    if (h->curv == FSLBM_CURV_TR) return fail(FSLBM_E_STATE, "the adjoint covers the FD and LSQR models");
     if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return fail(FSLBM_E_ARG, "workspace not 256-byte aligned");
     return dispatch<OpAdjF>(h, (long long)nsteps, K, workspace, workspace_bytes);
 }

@@ -866,7 +866,7 @@ __device__ inline void normals_plic_list(const Fields<P> &F)
 template <class P>
 __global__ __launch_bounds__(256) void k_normals_plic(const Batch<P> B)
 {
-    if (B.p[blockIdx.y].curv != 1) return;
+    if (B.p[blockIdx.y].curv == 0) return;  // LSQR and TR
     normals_plic_list(B.f[blockIdx.y]);
 }
 
@@ -950,6 +950,117 @@ __global__ __launch_bounds__(256) void k_curv_lsqr4(const Batch<P> B)
         }
         const double K = f.ok ? lsqr_solve_curvature(f, S) : 0.0;
         if (l == 0) F.K[i] = R(K);
+    }
+}
+
+// TR curvature (Sec. II.B): a triangle fan of the PLIC points of the 3x3x3
+// block around the centre point p, curvature by Taubin's estimate. With
+// d_k = p_k - p, the points are ordered by their polar angle in the tangent
+// plane (measured from the direction 1 rad from t_u; angles within 1e-12
+// keep block order; points with u^2 + v^2 < 1e-12 are left out);
+// consecutive points span the triangle (p, p_k, p_k+1) unless their angular
+// gap is at least pi - 1e-12. Each vertex is weighted by the area of its
+// triangles, and K = 2 sum w_k kappa_k / sum w_k with the edge curvature
+// kappa_k = 2 (d_k . n) / |d_k|^2 (twice the trace of Taubin's matrix).
+// Fewer than three points or no triangle give K = 0.
+//
+// 32 lanes per interface cell: lane s < 27 holds block cell s (x fastest).
+// Each lane finds the successor of its point in the cyclic order by
+// scanning the group with shuffles, adds its triangle (area times the two
+// edge curvatures, and twice the area), and the sums are reduced over the
+// group by an xor butterfly (fixed order).
+constexpr int TR_LANES = 32;
+
+__device__ inline bool tr_before(double aj, int sj, double ak, int sk)
+{
+    return fabs(aj - ak) > 1e-12 ? aj < ak : sj < sk;
+}
+
+template <class P>
+__global__ __launch_bounds__(256) void k_curv_tr(const Batch<P> B)
+{
+    const Params &prm = B.p[blockIdx.y];
+    if (prm.curv != 2) return;
+    const Fields<P> &F = B.f[blockIdx.y];
+    using R = typename P::R;
+    const double PI = 3.14159265358979323846;
+    const double c1 = 0.54030230586813971740, s1 = 0.84147098480789650665;  // cos 1, sin 1
+    const int n = list_count(F.sc);
+    const int s = threadIdx.x & (TR_LANES - 1);
+    const int groups = 256 / TR_LANES;
+    const int n_round = (n + groups - 1) / groups * groups;  // whole groups iterate together
+    for (int k = blockIdx.x * groups + (int)(threadIdx.x / TR_LANES); k < n_round; k += gridDim.x * groups) {
+        const bool live = k < n;
+        const int i = live ? F.ilist[k] : 0;
+        const int yz = i / F.nx, x = i - yz * F.nx, z = yz / F.ny, y = yz - z * F.ny;
+        const LsqrView<P> V{F, x, y, z};
+        LsqrFrame f;
+        V.normal(0, 0, 0, f.nc);
+        f.ok = live && !(f.nc[0] == 0.0 && f.nc[1] == 0.0 && f.nc[2] == 0.0);
+        lsqr_frame_finish(V, prm, f, false);
+        // this lane's point
+        const int a = s % 3 - 1, b = (s / 3) % 3 - 1, c = s / 9 - 1;
+        bool valid = f.ok && s < 27 && s != 13;
+        double d[3] = {0.0, 0.0, 0.0}, ang = 0.0, kap = 0.0;
+        if (valid && (V.flag(a, b, c) & FL_IF)) {
+            double nj[3];
+            V.normal(a, b, c, nj);
+            valid = !(nj[0] == 0.0 && nj[1] == 0.0 && nj[2] == 0.0);
+            if (valid) {
+                const double aj = V.plic(a, b, c);
+                d[0] = a + aj * nj[0] - f.pc[0];
+                d[1] = b + aj * nj[1] - f.pc[1];
+                d[2] = c + aj * nj[2] - f.pc[2];
+                const double u = dot(d, f.tu), v = dot(d, f.tv);
+                valid = u * u + v * v >= 1e-12;
+                ang = atan2(-u * s1 + v * c1, u * c1 + v * s1);
+                kap = 2.0 * dot(d, f.nc) / dot(d, d);
+            }
+        } else {
+            valid = false;
+        }
+        int m = valid ? 1 : 0;
+#pragma unroll
+        for (int w = 1; w < TR_LANES; w <<= 1) m += __shfl_xor(m, w, TR_LANES);
+        // successor in the cyclic order: the first point after this one,
+        // else (this is the last) the first point of all
+        int nxt = -1, first = -1;
+        double a_nxt = 0.0, a_first = 0.0;
+        for (int j = 0; j < TR_LANES; ++j) {
+            const int vj = __shfl(valid ? 1 : 0, j, TR_LANES);
+            const double aj = __shfl(ang, j, TR_LANES);
+            if (!vj) continue;
+            if (first < 0 || tr_before(aj, j, a_first, first)) {
+                first = j;
+                a_first = aj;
+            }
+            if (j != s && tr_before(ang, s, aj, j) && (nxt < 0 || tr_before(aj, j, a_nxt, nxt))) {
+                nxt = j;
+                a_nxt = aj;
+            }
+        }
+        const bool wrap = nxt < 0;
+        const int sj = wrap ? first : nxt;
+        const double dj0 = __shfl(d[0], sj < 0 ? 0 : sj, TR_LANES);
+        const double dj1 = __shfl(d[1], sj < 0 ? 0 : sj, TR_LANES);
+        const double dj2 = __shfl(d[2], sj < 0 ? 0 : sj, TR_LANES);
+        const double kj = __shfl(kap, sj < 0 ? 0 : sj, TR_LANES);
+        double num = 0.0, den = 0.0;
+        if (valid && m >= 3) {
+            const double gap = (wrap ? a_first : a_nxt) - ang + (wrap ? 2.0 * PI : 0.0);
+            if (gap < PI - 1e-12) {
+                const double cr[3] = {d[1] * dj2 - d[2] * dj1, d[2] * dj0 - d[0] * dj2, d[0] * dj1 - d[1] * dj0};
+                const double area = 0.5 * sqrt(dot(cr, cr));
+                num = area * (kap + kj);
+                den = 2.0 * area;
+            }
+        }
+#pragma unroll
+        for (int w = 1; w < TR_LANES; w <<= 1) {
+            num += __shfl_xor(num, w, TR_LANES);
+            den += __shfl_xor(den, w, TR_LANES);
+        }
+        if (live && s == 0) F.K[i] = R(den > 0.0 ? 2.0 * num / den : 0.0);
     }
 }
 

@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfslbm.so")
 
 FSLBM_F64, FSLBM_F32, FSLBM_F16_STORE, FSLBM_BF16_STORE = 0, 1, 2, 3
-FSLBM_CURV_FD, FSLBM_CURV_LSQR = 0, 1
+FSLBM_CURV_FD, FSLBM_CURV_LSQR, FSLBM_CURV_TR = 0, 1, 2
 FSLBM_SRT, FSLBM_TRT = 0, 1
 FSLBM_GAS, FSLBM_LIQUID, FSLBM_INTERFACE, FSLBM_OBSTACLE = 0, 1, 2, 3
 FSLBM_OPT_EPS_C, FSLBM_OPT_COLLISION, FSLBM_OPT_TRT_MAGIC, FSLBM_OPT_TIMING, FSLBM_OPT_GRAPH = 0, 1, 2, 3, 4
@@ -28,7 +28,7 @@ FSLBM_OPT_SPLIT_INTERFACE = 5
 FSLBM_OPT_BUBBLE = 6
 
 PRECISIONS = {"f64": FSLBM_F64, "f32": FSLBM_F32, "f16": FSLBM_F16_STORE, "bf16": FSLBM_BF16_STORE}
-MODELS = {"fd": FSLBM_CURV_FD, "lsqr": FSLBM_CURV_LSQR}
+MODELS = {"fd": FSLBM_CURV_FD, "lsqr": FSLBM_CURV_LSQR, "tr": FSLBM_CURV_TR}
 
 
 class FslbmError(RuntimeError):

@@ -44,7 +44,7 @@ def vel_err(u, uref, mask, vscale=0.0):
     return np.linalg.norm(d) / max(np.linalg.norm(scale), vscale * np.sqrt(mask.sum()), 1e-300)
 
 
-MODELS = {"fd": O.CURV_FD, "lsqr": O.CURV_LSQR}
+MODELS = {"fd": O.CURV_FD, "lsqr": O.CURV_LSQR, "tr": O.CURV_TR}
 
 
 def pair(Lattice, fill, obst, model, precision="f64", **kw):
@@ -68,7 +68,7 @@ def compare(g, o, tol, exact_flags=True, what="", vscale=0.0):
     return e_phi, e_u
 
 
-@pytest.mark.parametrize("model", ["fd", "lsqr"])
+@pytest.mark.parametrize("model", ["fd", "lsqr", "tr"])
 def test_initial_geometry_fp64(Lattice, model):
     fill, obst = I.droplet(32, 8.0, noise=1e-6, seed=0)
     g, o = pair(Lattice, fill, obst, model, sigma=1e-3, tau=1.0)
@@ -81,7 +81,7 @@ def test_initial_geometry_fp64(Lattice, model):
     np.testing.assert_array_equal(g.fill(), o.fill())
 
 
-@pytest.mark.parametrize("model", ["fd", "lsqr"])
+@pytest.mark.parametrize("model", ["fd", "lsqr", "tr"])
 def test_static_droplet_fp64_500_steps(Lattice, model):
     """Static droplet R = 8 in 32^3, tau = 1, sigma = 1e-3, 500 steps (FP64)."""
     fill, obst = I.droplet(32, 8.0, noise=1e-6, seed=0)
@@ -95,7 +95,7 @@ def test_static_droplet_fp64_500_steps(Lattice, model):
     assert abs(g.mass() - o.mass()) / o.mass() < 1e-13
 
 
-@pytest.mark.parametrize("model", ["fd", "lsqr"])
+@pytest.mark.parametrize("model", ["fd", "lsqr", "tr"])
 def test_moving_droplet_conversions_fp64(Lattice, model):
     """A droplet advected through the lattice: cells fill and empty every step."""
     fill, obst = I.droplet(20, 4.5, noise=1e-6, seed=1)
@@ -238,7 +238,7 @@ def test_advection_test_fp64(Lattice):
     assert abs(l1g[0] - l1o[0]) < 1e-12 and abs(l1g[1] - l1o[1]) < 1e-12
 
 
-@pytest.mark.parametrize("model", ["fd", "lsqr"])
+@pytest.mark.parametrize("model", ["fd", "lsqr", "tr"])
 def test_bubble_model_fp64(Lattice, model):
     """Equilibrium-bubble setup (walls at z = 0, 1) with the bubble model:
     the gas density follows the gas volume every step."""
@@ -274,3 +274,22 @@ def test_bubble_model_fp32(Lattice):
     o.step(100)
     compare(g, o, 1e-5, exact_flags=False, what="bubble f32", vscale=1e-3 / (0.3 / 3.0))
     assert abs(g.gas_density() - o.gas_density()) / o.gas_density() < 1e-5
+
+
+def test_tr_at_walls_fp64(Lattice):
+    """TR has no wetting model: at a wall its fans are open on the wall side."""
+    fill, obst = I.sessile_droplet(32, 32, 20, 9.0, noise=1e-6, seed=2)
+    g, o = pair(Lattice, fill, obst, "tr", sigma=1e-3, tau=0.8)
+    ifc = o.flags() == O.INTERFACE
+    np.testing.assert_allclose(g.curvature()[ifc], o.curvature()[ifc], rtol=0, atol=1e-11)
+    g.step(60)
+    o.step(60)
+    compare(g, o, 1e-10, what="tr walls", vscale=1e-3 / (0.3 / 3.0))
+
+
+def test_tr_curvature_fp32(Lattice):
+    fill, obst = I.droplet(32, 8.0, noise=1e-6, seed=0)
+    g, o = pair(Lattice, fill, obst, "tr", precision="f32", sigma=1e-3, tau=1.0)
+    g.step(50)
+    o.step(50)
+    compare(g, o, 1e-5, exact_flags=False, what="tr f32", vscale=1e-3 / (0.5 / 3.0))

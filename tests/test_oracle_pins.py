@@ -270,7 +270,7 @@ def test_mass_is_conserved_through_conversions(model):
 
 
 # ---------------------------------------------------- curvature (Sec. II.A-C)
-@pytest.mark.parametrize("model,tol", [(O.CURV_FD, 0.03), (O.CURV_LSQR, 0.03)])
+@pytest.mark.parametrize("model,tol", [(O.CURV_FD, 0.03), (O.CURV_LSQR, 0.03), (O.CURV_TR, 0.03)])
 @pytest.mark.parametrize("R", [8.0, 12.0])
 def test_sphere_curvature_is_two_over_R(model, tol, R):
     n = int(2 * R + 8)
@@ -284,7 +284,7 @@ def test_sphere_curvature_is_two_over_R(model, tol, R):
     assert Kb.mean() * R / 2 == pytest.approx(-1.0, abs=tol)
 
 
-@pytest.mark.parametrize("model", [O.CURV_FD, O.CURV_LSQR])
+@pytest.mark.parametrize("model", [O.CURV_FD, O.CURV_LSQR, O.CURV_TR])
 def test_cylinder_curvature_is_one_over_R(model):
     R = 10.0
     fill = I.cylinder_fraction((4, 32, 32), (16.2, 15.9), R)
@@ -307,7 +307,7 @@ def _diagonal_slab(n, c1, c2):
     return np.broadcast_to(np.clip(area, 0, 1)[None], (4, n, n)).copy()
 
 
-@pytest.mark.parametrize("model", [O.CURV_FD, O.CURV_LSQR])
+@pytest.mark.parametrize("model", [O.CURV_FD, O.CURV_LSQR, O.CURV_TR])
 def test_planes_have_zero_curvature(model):
     fill, obst = I.flat_film(8, 8, 12, 5.3)
     orc = O.Oracle(fill, obst, curv_model=model)
