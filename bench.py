@@ -285,7 +285,7 @@ def gas_link_kappa_stdev(lat, n):
     return float(kap.std()), int(sel.sum()), int((fl == FSLBM_INTERFACE).sum())
 
 
-def laplace_table(dev, resolutions, steps, models=("fd", "lsqr"), precision="f64"):
+def laplace_table(dev, resolutions, steps, models=("fd", "lsqr"), precision="f64", eps_c=None):
     """Equilibrium bubble of Sec. III.A.1 with the bubble model: dx = 1/n,
     dt = 1e-4, no-slip walls at z = 0 and 1; spurious speeds at log-spaced
     times and the curvature error at the end, beside the printed values."""
@@ -300,7 +300,7 @@ def laplace_table(dev, resolutions, steps, models=("fd", "lsqr"), precision="f64
         tau, sig = I.renardy_units(n, dt)
         for model in models:
             lat = Lattice(fill, obst, precision=precision, curv_model=model, sigma=sig, tau=tau, bubble=True,
-                          device=dev)
+                          eps_c=eps_c, device=dev)
             hist, t = [], 0
             marks = [m for m in (1000, 2000, 5000, 10000, 20000, 50000, 100000, 200000, 500000, 1000000)
                      if m < steps] + [steps]
@@ -317,7 +317,7 @@ def laplace_table(dev, resolutions, steps, models=("fd", "lsqr"), precision="f64
             el = time.perf_counter() - t0
             paper = PAPER_LAPLACE.get((model, n))
             sd_gl, n_gl, n_if = gas_link_kappa_stdev(lat, n)
-            rows.append({"n": n, "model": model, "tau": round(tau, 4), "sigma_L": sig, "steps": steps,
+            rows.append({"n": n, "model": model, "tau": round(tau, 4), "sigma_L": sig, "steps": steps, "eps_c": eps_c,
                          "max_u": umax, "avg_u": uavg, "L2_kappa": l2, "stdev_kappa": sd,
                          "stdev_kappa_gas_link_cells": sd_gl, "gas_link_cells": n_gl, "interface_cells": n_if,
                          "rho_gas_t": lat.gas_density(), "history": hist,
@@ -329,7 +329,7 @@ def laplace_table(dev, resolutions, steps, models=("fd", "lsqr"), precision="f64
     return rows
 
 
-def moving_bubble_table(dev, resolutions, models=("fd", "lsqr"), precision="f64", samples=10):
+def moving_bubble_table(dev, resolutions, models=("fd", "lsqr"), precision="f64", samples=10, eps_c=None):
     """Moving frame of Sec. III.A.2: the equilibrium bubble with a uniform
     background velocity u0 = 1 along x, traversing the periodic unit cube
     once (T = n / u0_L steps, u0_L = dt/dx) under diffusive scaling
@@ -351,7 +351,7 @@ def moving_bubble_table(dev, resolutions, models=("fd", "lsqr"), precision="f64"
         T = int(round(n / u0))
         for model in models:
             lat = Lattice(fill, obst, precision=precision, curv_model=model, sigma=sig, tau=tau, bubble=True,
-                          device=dev)
+                          eps_c=eps_c, device=dev)
             u = np.zeros((3,) + shape)
             u[0] = u0
             lat.set_equilibrium(1.0, u)
@@ -369,7 +369,7 @@ def moving_bubble_table(dev, resolutions, models=("fd", "lsqr"), precision="f64"
             torch.cuda.synchronize()
             el = time.perf_counter() - t0
             l1, l2phi = I.advection_errors(fill, lat.fill(), 0)
-            rows.append({"n": n, "model": model, "tau": round(tau, 4), "sigma_L": sig, "u0_lattice": u0,
+            rows.append({"n": n, "model": model, "tau": round(tau, 4), "sigma_L": sig, "u0_lattice": u0, "eps_c": eps_c,
                          "steps": T, "history_t_frac_L2kappa_maxu_avgu": hist, "phi_L1_after_one_pass": l1,
                          "phi_L2_after_one_pass": l2phi, "ms_per_step_incl_readout": round(1e3 * el / T, 4)})
             lat.close()
@@ -406,6 +406,8 @@ def main():
     ap.add_argument("--moving", type=int, nargs="*", metavar="N",
                     help="moving-frame bubble at dx = 1/N (default 48 96) instead of the bench")
     ap.add_argument("--models", default="fd,lsqr")
+    ap.add_argument("--eps-c", type=float, default=None,
+                    help="conversion offset for the bubble studies (library default 1e-3)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
@@ -430,11 +432,11 @@ def main():
     models = tuple(args.models.split(","))
     if args.laplace is not None:
         res = args.laplace or [48, 96]
-        print(json.dumps({"laplace": laplace_table(dev, res, args.laplace_steps, models)}))
+        print(json.dumps({"laplace": laplace_table(dev, res, args.laplace_steps, models, eps_c=args.eps_c)}))
         return
     if args.moving is not None:
         res = args.moving or [48, 96]
-        print(json.dumps({"moving_bubble": moving_bubble_table(dev, res, models)}))
+        print(json.dumps({"moving_bubble": moving_bubble_table(dev, res, models, eps_c=args.eps_c)}))
         return
     if args.copy_calibration:
         # a plain elementwise copy: 1 GiB read and 1 GiB written per launch

@@ -167,6 +167,7 @@ struct fslbm_lattice {
     unsigned long long epoch;  // bumped whenever the state changes other than by stepping
     int frozen;        // 1 inside a frozen-topology window
     int icount0;       // interface cells at creation (sizes the list-kernel grids)
+    int ocount0;       // obstacle cells next to the fluid (sizes the reflection grid)
     int bubble;        // bubble model on (FSLBM_OPT_BUBBLE)
     double n_free;     // non-obstacle cells
     fslbm_batch self;
@@ -664,21 +665,20 @@ int enqueue_step_kernels(fslbm_batch *b, const void *fsrc = nullptr, void *fdst 
     for (auto *h : b->hs) frozen &= h->frozen != 0;
     mark(b, 2);
     if (!frozen) k_conv_mark_init<P><<<lg, 256, 0, st>>>(A);
-    if (!frozen) k_conv_close<P, 1><<<lg, 256, 0, st>>>(A);
-    if (!frozen) k_conv_close<P, 2><<<lg, 256, 0, st>>>(A);
-    if (!frozen) k_conv_share<P><<<lg, 256, 0, st>>>(A);
+    if (!frozen) k_conv_close<P><<<lg, 256, 0, st>>>(A);
+    if (!frozen) k_conv_share_keep<P><<<lg, 256, 0, st>>>(A);
     k_conv_gather<P><<<lg, 256, 0, st>>>(A);
     if (!frozen) k_conv_flags<P><<<lg, 256, 0, st>>>(A);
     mark(b, 3);
     HIP_OK(hipGetLastError());
-    if (!frozen) {
-        k_list_keep<P><<<lg, 256, 0, st>>>(A);
-        k_list_finish<P><<<lg, 256, 0, st>>>(A);
-    }
+    if (!frozen) k_list_finish<P><<<lg, 256, 0, st>>>(A);
     HIP_OK(hipGetLastError());
     int rc = 0;
     mark(b, 4);
-    k_obstacle_fill<P><<<dim3(list_blocks(maxN), n), 256, 0, st>>>(A, 1);
+    // grid-stride over the static obstacle list; block 0 also closes the step
+    int maxo = 0;
+    for (auto *h : b->hs) maxo = std::max(maxo, h->ocount0);
+    k_obstacle_fill<P><<<dim3(std::max(1, std::min(list_blocks(maxN), (maxo + 255) / 256)), n), 256, 0, st>>>(A, 1);
     bool any_bubble = false;
     for (auto *h : b->hs) any_bubble |= h->bubble != 0;
     if (any_bubble) {
@@ -1356,11 +1356,13 @@ int fslbm_create(int nx, int ny, int nz, int precision, int curv_model, const do
     h->self.hs.push_back(h);
     h->self.prec = precision;
     h->icount0 = 1 << 20;  // large until counted: the creation's own geometry launch
+    h->ocount0 = 1 << 20;
     int rc = dispatch<OpInit>(h, fill, obstacle);
     if (!rc) {
         int ic = 0, oc = 0;
         rc = read_counts(h, ic, oc);
         h->icount0 = ic;
+        h->ocount0 = oc;
     }
     if (rc) {
         delete h;

@@ -199,34 +199,52 @@ __device__ inline int layer_cell(const Fields<P> &F, int k, int n)
     return k < n ? F.ilist[k] : F.newlist[k - n];
 }
 
-// Rule 4. STAGE 1: a layer cell without a gas neighbour (types after rules
-// 1-3) becomes liquid. STAGE 2: a layer cell without a liquid neighbour
-// (those types with the STAGE-1 cells liquid) becomes gas. Each cell writes
-// only its own status, and no status a stage writes is read by that stage.
-template <class P, int STAGE>
+// Rule 4 for layer cell c (types after rules 1-3, CLOSE_* codes read as
+// interface): without a gas neighbour c becomes liquid; otherwise, without
+// a neighbour that is liquid after the first pass (liquid, or a layer cell
+// without a gas neighbour) c becomes gas.
+template <class P>
+__device__ inline bool lacks_gas_neighbour(const Fields<P> &F, int c, uint32_t tag)
+{
+    const Nbr nb(c, F.nx, F.ny, F.nz);
+    bool found = false;
+#pragma unroll
+    for (int q = 1; q < NQ; ++q) found |= type_after_conversion(F, nb.at(dir_x(q), dir_y(q), dir_z(q)), tag) == FL_GAS;
+    return !found;
+}
+
+// Rule 4, both passes in one launch: each cell writes only its own status,
+// and a neighbour's first-pass result is evaluated, not read, so no thread
+// depends on another's write. The second pass looks two cells out only for
+// a cell without a liquid neighbour after rules 1-3, which is rare.
+template <class P>
 __global__ __launch_bounds__(256) void k_conv_close(const Batch<P> B)
 {
     const Fields<P> &F = B.f[blockIdx.y];
     if (F.sc->nconv == 0) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {  // counters of the list rebuild in k_conv_share_keep
+        F.sc->nkeep = 0;
+        F.sc->bbox[0] = F.nx; F.sc->bbox[1] = F.ny; F.sc->bbox[2] = F.nz;
+        F.sc->bbox[3] = -1; F.sc->bbox[4] = -1; F.sc->bbox[5] = -1;
+    }
     const uint32_t tag = F.sc->step << 2;
     const int n = list_count(F.sc), nn = F.sc->nnew;
     for (int k = blockIdx.x * 256 + threadIdx.x; k < n + nn; k += gridDim.x * 256) {
         const int i = layer_cell(F, k, n);
-        const uint8_t st = F.conv[i];
-        if (st != CV_NONE) continue;
-        const Nbr nb(i, F.nx, F.ny, F.nz);
-        bool found = false;
-#pragma unroll
-        for (int q = 1; q < NQ; ++q) {
-            const int j = nb.at(dir_x(q), dir_y(q), dir_z(q));
-            const uint8_t t = type_after_conversion(F, j, tag);
-            if (STAGE == 1) {
-                found |= t == FL_GAS;
-            } else {
-                found |= t == FL_LIQ || (t == FL_IF && F.conv[j] == CV_CLOSE_LIQ);
-            }
+        if (F.conv[i] != CV_NONE) continue;
+        if (lacks_gas_neighbour(F, i, tag)) {
+            F.conv[i] = CV_CLOSE_LIQ;
+            continue;
         }
-        if (!found) F.conv[i] = STAGE == 1 ? CV_CLOSE_LIQ : CV_CLOSE_GAS;
+        const Nbr nb(i, F.nx, F.ny, F.nz);
+        bool liquid = false;
+#pragma unroll
+        for (int q = 1; q < NQ; ++q) liquid |= type_after_conversion(F, nb.at(dir_x(q), dir_y(q), dir_z(q)), tag) == FL_LIQ;
+        for (int q = 1; q < NQ && !liquid; ++q) {
+            const int j = nb.at(dir_x(q), dir_y(q), dir_z(q));
+            liquid = type_after_conversion(F, j, tag) == FL_IF && lacks_gas_neighbour(F, j, tag);
+        }
+        if (!liquid) F.conv[i] = CV_CLOSE_GAS;
     }
 }
 
@@ -236,30 +254,24 @@ __device__ inline bool is_receiver(const Fields<P> &F, int j, uint32_t tag)
     return in_layer(F, j, tag) && F.conv[j] == CV_NONE;
 }
 
-// Rule 5, first half: each cell that leaves the layer computes its share.
+// Rule 5, first half: a cell that leaves the layer computes its share
+// (run by k_conv_share_keep).
 template <class P>
-__global__ __launch_bounds__(256) void k_conv_share(const Batch<P> B)
+__device__ inline void conv_share_cell(const Fields<P> &F, int i, uint32_t tag)
 {
-    const Fields<P> &F = B.f[blockIdx.y];
     using R = typename P::R;
-    if (F.sc->nconv == 0) return;
-    const uint32_t tag = F.sc->step << 2;
-    const int n = list_count(F.sc), nn = F.sc->nnew;
-    for (int k = blockIdx.x * 256 + threadIdx.x; k < n + nn; k += gridDim.x * 256) {
-        const int i = layer_cell(F, k, n);
-        const uint8_t st = F.conv[i];
-        if (st == CV_NONE) continue;
-        const R mex = cv_to_liquid(st) ? F.m[i] - F.rho[i] : F.m[i];
-        const Nbr nb(i, F.nx, F.ny, F.nz);
-        int cnt = 0;
+    const uint8_t st = F.conv[i];
+    if (st == CV_NONE) return;
+    const R mex = cv_to_liquid(st) ? F.m[i] - F.rho[i] : F.m[i];
+    const Nbr nb(i, F.nx, F.ny, F.nz);
+    int cnt = 0;
 #pragma unroll
-        for (int q = 1; q < NQ; ++q) cnt += is_receiver(F, nb.at(dir_x(q), dir_y(q), dir_z(q)), tag);
-        if (cnt > 0) {
-            F.share[i] = mex / R(cnt);
-        } else {
-            F.share[i] = R(0);
-            atomicAdd(&F.sc->reservoir, (double)mex);
-        }
+    for (int q = 1; q < NQ; ++q) cnt += is_receiver(F, nb.at(dir_x(q), dir_y(q), dir_z(q)), tag);
+    if (cnt > 0) {
+        F.share[i] = mex / R(cnt);
+    } else {
+        F.share[i] = R(0);
+        atomicAdd(&F.sc->reservoir, (double)mex);
     }
 }
 
@@ -321,18 +333,12 @@ __global__ __launch_bounds__(256) void k_conv_gather(const Batch<P> B)
     }
 }
 
-// Rule 6: the new types of converting and new cells; block 0 also resets
-// the list rebuild counters for k_list_keep.
+// Rule 6: the new types of converting and new cells.
 template <class P>
 __global__ __launch_bounds__(256) void k_conv_flags(const Batch<P> B)
 {
     const Fields<P> &F = B.f[blockIdx.y];
     if (F.sc->nconv == 0) return;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        F.sc->nkeep = 0;
-        F.sc->bbox[0] = F.nx; F.sc->bbox[1] = F.ny; F.sc->bbox[2] = F.nz;
-        F.sc->bbox[3] = -1; F.sc->bbox[4] = -1; F.sc->bbox[5] = -1;
-    }
     const uint32_t tag = F.sc->step << 2;
     const int n = list_count(F.sc);
     for (int k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256) {
@@ -422,21 +428,25 @@ __device__ inline void box_add(const Fields<P> &F, int i, int (&lo)[3], int (&hi
     hi[0] = max(hi[0], x); hi[1] = max(hi[1], y); hi[2] = max(hi[2], z);
 }
 
-// Cells of the step's layer that are interface cells, written in layer
-// order within each block: a counting pass, one atomic for the block's
-// base, then the ordered write with a block prefix sum.
+// Shares of the cells that leave the layer (rule 5, first half), and the
+// cells of the step's layer that stay interface cells (status CV_NONE after
+// rule 4, old or new), written in layer order within each block: a counting
+// pass, one atomic for the block's base, then the ordered write with a
+// block prefix sum. Each block takes one contiguous range of the layer.
 template <class P>
-__global__ __launch_bounds__(256) void k_list_keep(const Batch<P> B)
+__global__ __launch_bounds__(256) void k_conv_share_keep(const Batch<P> B)
 {
     const Fields<P> &F = B.f[blockIdx.y];
     if (F.sc->nconv == 0) return;
+    const uint32_t tag = F.sc->step << 2;
     const int n = list_count(F.sc), nl = n + F.sc->nnew;
     int k0, k1;
     block_share(nl, k0, k1);
+    for (int k = k0 + threadIdx.x; k < k1; k += 256) conv_share_cell(F, layer_cell(F, k, n), tag);
     __shared__ int lw[4];
     __shared__ int base_s;
     int cnt = 0;
-    for (int k = k0 + threadIdx.x; k < k1; k += 256) cnt += (F.flags[layer_cell(F, k, n)] & FL_IF) != 0;
+    for (int k = k0 + threadIdx.x; k < k1; k += 256) cnt += F.conv[layer_cell(F, k, n)] == CV_NONE;
     int total;
     block_exclusive_scan(cnt, lw, total);
     if (threadIdx.x == 0) base_s = total > 0 ? atomicAdd(&F.sc->nkeep, total) : 0;
@@ -446,7 +456,7 @@ __global__ __launch_bounds__(256) void k_list_keep(const Batch<P> B)
     for (int kk = k0; kk < k1; kk += 256) {
         const int k = kk + threadIdx.x;
         const int i = k < k1 ? layer_cell(F, k, n) : 0;
-        const bool keep = k < k1 && (F.flags[i] & FL_IF);
+        const bool keep = k < k1 && F.conv[i] == CV_NONE;
         int tot;
         const int ex = block_exclusive_scan(keep ? 1 : 0, lw, tot);
         if (keep) {
@@ -460,7 +470,7 @@ __global__ __launch_bounds__(256) void k_list_keep(const Batch<P> B)
 
 // New list = the kept cells. The fluid box grows by every new cell (a new
 // cell from gas is fluid whether it stays in the layer or closes to
-// liquid); the interface box came from k_list_keep.
+// liquid); the interface box came from k_conv_share_keep.
 template <class P>
 __global__ __launch_bounds__(256) void k_list_finish(const Batch<P> B)
 {
