@@ -242,6 +242,10 @@ PAPER_LAPLACE = {
     ("lsqr", 96): (1.51490625e-10, 9.93127083e-12, 0.00421798, 3.1994304e-7),
     ("lsqr", 144): (1.98145139e-11, 7.88409722e-13, 0.00177479, 8.449776e-8),
     ("lsqr", 192): (7.79395833e-12, 4.72019271e-13, 0.000991554, 8.448192e-8),
+    ("tr", 48): (4.886375e-11, 4.29270833e-12, 0.00773397, 2.765856e-7),
+    ("tr", 96): (1.03624583e-10, 5.86341667e-12, 0.00617829, 1.71e-7),
+    ("tr", 144): (2.20902778e-11, 1.50839583e-12, 0.00519107, 1.19405232e-7),
+    ("tr", 192): (1.5055625e-11, 1.87496875e-12, 0.00517137, 1.69e-7),
 }
 
 
@@ -302,8 +306,9 @@ def laplace_table(dev, resolutions, steps, models=("fd", "lsqr"), precision="f64
             lat = Lattice(fill, obst, precision=precision, curv_model=model, sigma=sig, tau=tau, bubble=True,
                           eps_c=eps_c, device=dev)
             hist, t = [], 0
-            marks = [m for m in (1000, 2000, 5000, 10000, 20000, 50000, 100000, 200000, 500000, 1000000)
-                     if m < steps] + [steps]
+            # a progress line at least every 50k steps
+            marks = sorted(set([m for m in (1000, 2000, 5000, 10000, 20000) if m < steps]
+                               + list(range(50000, steps, 50000)) + [steps]))
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             for m in marks:

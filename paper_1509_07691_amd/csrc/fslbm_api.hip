@@ -594,24 +594,31 @@ int enqueue_compaction(const fslbm_batch *b, const Batch<P> &A, int maxN, int wh
     return 0;
 }
 
+// Curvature of every lattice of the batch. With eos = 1 the first launch
+// also closes the step's device bookkeeping (end_of_step).
 template <class P>
-int enqueue_geometry(const fslbm_batch *b, const Batch<P> &A, int maxN)
+int enqueue_geometry(const fslbm_batch *b, const Batch<P> &A, int maxN, int eos = 0)
 {
     const unsigned n = (unsigned)b->hs.size();
     const hipStream_t st = bstream(b);
     const dim3 tg(std::min(GEOM_GRID, std::max(1, maxN / 512)), n);
-    bool any_fd = false, any_lsqr = false, any_tr = false;
+    bool any_fd = false, any_fd_wall = false, any_lsqr = false, any_tr = false;
     for (auto *h : b->hs) {
         any_fd |= h->curv == FSLBM_CURV_FD;
+        any_fd_wall |= h->curv == FSLBM_CURV_FD && h->ocount0 > 0;
         any_lsqr |= h->curv == FSLBM_CURV_LSQR;
         any_tr |= h->curv == FSLBM_CURV_TR;
     }
     const bool any_plic = any_lsqr || any_tr;
     const dim3 cg4(batch_list_blocks(b, 64), n), cgt(batch_list_blocks(b, 256 / TR_LANES), n);
-    if (any_fd) k_fd_contact_normals<P><<<dim3(list_blocks(maxN), n), 256, 0, st>>>(A);
-    if (any_fd && any_plic) k_geometry_mixed<P><<<tg, 256, 0, st>>>(A);
-    else if (any_fd) k_geometry_fd<P><<<tg, 256, 0, st>>>(A);
-    else if (any_plic) k_normals_plic<P><<<dim3(batch_list_blocks(b, 256), n), 256, 0, st>>>(A);
+    // FD contact normals exist only next to walls
+    if (any_fd_wall) {
+        k_fd_contact_normals<P><<<dim3(list_blocks(maxN), n), 256, 0, st>>>(A, eos);
+        eos = 0;
+    }
+    if (any_fd && any_plic) k_geometry_mixed<P><<<tg, 256, 0, st>>>(A, eos);
+    else if (any_fd) k_geometry_fd<P><<<tg, 256, 0, st>>>(A, eos);
+    else k_normals_plic<P><<<dim3(batch_list_blocks(b, 256), n), 256, 0, st>>>(A, eos);
     if (any_lsqr) k_curv_lsqr4<P><<<cg4, 256, 0, st>>>(A);
     if (any_tr) k_curv_tr<P><<<cgt, 256, 0, st>>>(A);
     HIP_OK(hipGetLastError());
@@ -668,24 +675,23 @@ int enqueue_step_kernels(fslbm_batch *b, const void *fsrc = nullptr, void *fdst 
     if (!frozen) k_conv_close<P><<<lg, 256, 0, st>>>(A);
     if (!frozen) k_conv_share_keep<P><<<lg, 256, 0, st>>>(A);
     k_conv_gather<P><<<lg, 256, 0, st>>>(A);
-    if (!frozen) k_conv_flags<P><<<lg, 256, 0, st>>>(A);
     mark(b, 3);
     HIP_OK(hipGetLastError());
     if (!frozen) k_list_finish<P><<<lg, 256, 0, st>>>(A);
     HIP_OK(hipGetLastError());
     int rc = 0;
     mark(b, 4);
-    // grid-stride over the static obstacle list; block 0 also closes the step
+    // grid-stride over the static obstacle list (none without walls)
     int maxo = 0;
     for (auto *h : b->hs) maxo = std::max(maxo, h->ocount0);
-    k_obstacle_fill<P><<<dim3(std::max(1, std::min(list_blocks(maxN), (maxo + 255) / 256)), n), 256, 0, st>>>(A, 1);
+    if (maxo > 0) k_obstacle_fill<P><<<dim3(std::min(list_blocks(maxN), (maxo + 255) / 256), n), 256, 0, st>>>(A);
     bool any_bubble = false;
     for (auto *h : b->hs) any_bubble |= h->bubble != 0;
     if (any_bubble) {
         k_bubble_partial<P><<<dim3(VOL_BLOCKS, n), 256, 0, st>>>(A);
         k_bubble_final<P><<<dim3(1, n), 1024, 0, st>>>(A, VOL_BLOCKS);
     }
-    rc = enqueue_geometry<P>(b, A, maxN);
+    rc = enqueue_geometry<P>(b, A, maxN, 1);
     if (rc) return rc;
     mark(b, 5);
     return 0;
@@ -839,7 +845,7 @@ int enqueue_init(fslbm_lattice *h, const double *fill, const uint8_t *obstacle)
     k_fill_bytes<<<std::min(4096, cell_blocks(N)), 256, 0, h->stream>>>(F.conv, N, 0);
     rc = enqueue_compaction<P>(&h->self, A, maxN, 0, 1);
     if (rc) return rc;
-    k_obstacle_fill<P><<<dim3(list_blocks(N), 1), 256, 0, h->stream>>>(A, 0);
+    k_obstacle_fill<P><<<dim3(list_blocks(N), 1), 256, 0, h->stream>>>(A);
     HIP_OK(hipGetLastError());
     return enqueue_geometry<P>(&h->self, A, maxN);
 }
@@ -935,7 +941,7 @@ int do_set_interface_fill(fslbm_lattice *h, const double *fill, int is_device)
     int maxN;
     bool s_, t_;
     const Batch<P> A = make_batch<P>(&h->self, maxN, s_, t_);
-    k_obstacle_fill<P><<<dim3(list_blocks(N), 1), 256, 0, h->stream>>>(A, 0);
+    k_obstacle_fill<P><<<dim3(list_blocks(N), 1), 256, 0, h->stream>>>(A);
     HIP_OK(hipGetLastError());
     const int rc = enqueue_geometry<P>(&h->self, A, maxN);
     if (rc) return rc;
@@ -1672,6 +1678,11 @@ int fslbm_load_state(fslbm_t h, const void *src, size_t bytes)
     h->epoch += 1;
     h->version += 1;
     HIP_OK(hipStreamSynchronize(h->stream));
+    // the loaded state brings its own obstacle list (launch sizing only)
+    int ic = 0, oc = 0;
+    const int rc = read_counts(h, ic, oc);
+    if (rc) return rc;
+    h->ocount0 = oc;
     return 0;
 }
 

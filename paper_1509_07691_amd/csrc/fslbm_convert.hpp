@@ -46,11 +46,19 @@ __device__ inline bool in_layer(const Fields<P> &F, int j, uint32_t tag)
     return (F.flags[j] & FL_IF) || (F.mark[j] & ~3u) == tag;
 }
 
+// A cell that leaves the layer in this step. From k_conv_share_keep on,
+// every such cell carries the step's tag: new cells from their tagging,
+// and old-list cells that convert get tag | 3 there. The test reads no
+// flags, so k_conv_gather can rewrite flags while it runs.
 template <class P>
 __device__ inline bool is_converter(const Fields<P> &F, int j, uint32_t tag)
 {
-    return in_layer(F, j, tag) && F.conv[j] != CV_NONE;
+    return (F.mark[j] & ~3u) == tag && F.conv[j] != CV_NONE;
 }
+
+// A new cell of this step (tagged 1 from gas or 2 from liquid; 3 marks an
+// old-list cell that leaves the layer).
+__device__ inline bool is_new(uint32_t mk, uint32_t tag) { return (mk & ~3u) == tag && (mk & 3u) != 3u; }
 
 // Rule 2 for cell i: an emptying cell next to a filling cell does not
 // empty. Returns the cell's status after it. Readers of other cells' status
@@ -232,14 +240,19 @@ __global__ __launch_bounds__(256) void k_conv_close(const Batch<P> B)
     for (int k = blockIdx.x * 256 + threadIdx.x; k < n + nn; k += gridDim.x * 256) {
         const int i = layer_cell(F, k, n);
         if (F.conv[i] != CV_NONE) continue;
-        if (lacks_gas_neighbour(F, i, tag)) {
+        // most cells have both a gas and a liquid neighbour: stop at the
+        // first of each
+        const Nbr nb(i, F.nx, F.ny, F.nz);
+        bool gas = false, liquid = false;
+        for (int q = 1; q < NQ && !(gas && liquid); ++q) {
+            const uint8_t t = type_after_conversion(F, nb.at(dir_x(q), dir_y(q), dir_z(q)), tag);
+            gas |= t == FL_GAS;
+            liquid |= t == FL_LIQ;
+        }
+        if (!gas) {
             F.conv[i] = CV_CLOSE_LIQ;
             continue;
         }
-        const Nbr nb(i, F.nx, F.ny, F.nz);
-        bool liquid = false;
-#pragma unroll
-        for (int q = 1; q < NQ; ++q) liquid |= type_after_conversion(F, nb.at(dir_x(q), dir_y(q), dir_z(q)), tag) == FL_LIQ;
         for (int q = 1; q < NQ && !liquid; ++q) {
             const int j = nb.at(dir_x(q), dir_y(q), dir_z(q));
             liquid = type_after_conversion(F, j, tag) == FL_IF && lacks_gas_neighbour(F, j, tag);
@@ -255,13 +268,16 @@ __device__ inline bool is_receiver(const Fields<P> &F, int j, uint32_t tag)
 }
 
 // Rule 5, first half: a cell that leaves the layer computes its share
-// (run by k_conv_share_keep).
+// (run by k_conv_share_keep); an old-list cell is tagged tag | 3 (its own
+// thread writes it; the neighbours' receiver test reads flags or the tag,
+// both of which mark it as a layer cell).
 template <class P>
-__device__ inline void conv_share_cell(const Fields<P> &F, int i, uint32_t tag)
+__device__ inline void conv_share_cell(const Fields<P> &F, int i, uint32_t tag, bool old_list)
 {
     using R = typename P::R;
     const uint8_t st = F.conv[i];
     if (st == CV_NONE) return;
+    if (old_list) F.mark[i] = tag | 3u;
     const R mex = cv_to_liquid(st) ? F.m[i] - F.rho[i] : F.m[i];
     const Nbr nb(i, F.nx, F.ny, F.nz);
     int cnt = 0;
@@ -289,10 +305,12 @@ __device__ inline typename P::R gathered_excess(const Fields<P> &F, int j, uint3
     return acc;
 }
 
-// Rule 5, second half: receivers gather their neighbours' shares in fixed
-// direction order. This kernel also sets phi = m / rho of every interface
-// cell for the new time level, so it runs in every step. Every new cell is
-// next to a filling or emptying cell of the old list, whose thread sets it.
+// Rule 5, second half, and rule 6: receivers gather their neighbours'
+// shares in fixed direction order, and the cells that leave the layer and
+// the new cells take their types. This kernel also sets phi = m / rho of
+// every interface cell for the new time level, so it runs in every step.
+// Every new cell is next to a filling or emptying cell of the old list,
+// whose thread sets it (several threads may write the same values).
 template <class P>
 __global__ __launch_bounds__(256) void k_conv_gather(const Batch<P> B)
 {
@@ -312,6 +330,7 @@ __global__ __launch_bounds__(256) void k_conv_gather(const Batch<P> B)
             continue;
         }
         F.phi[i] = cv_to_liquid(st) ? R(1) : R(0);
+        F.flags[i] = (F.flags[i] & FL_NEAR_OBST) | (cv_to_liquid(st) ? FL_LIQ : FL_GAS);
         // a new neighbour of a closing cell is also next to the filling or
         // emptying cell that made it, whose thread sets it
         if (st == CV_CLOSE_LIQ || st == CV_CLOSE_GAS) continue;
@@ -319,8 +338,10 @@ __global__ __launch_bounds__(256) void k_conv_gather(const Batch<P> B)
         for (int q = 1; q < NQ; ++q) {
             const int j = nb.at(dir_x(q), dir_y(q), dir_z(q));
             const uint32_t mk = F.mark[j];
-            if ((mk & ~3u) != tag) continue;
+            if (!is_new(mk, tag)) continue;
             const uint8_t sj = F.conv[j];
+            const uint8_t tj = sj == CV_NONE ? FL_IF : (cv_to_liquid(sj) ? FL_LIQ : FL_GAS);
+            F.flags[j] = (F.flags[j] & FL_NEAR_OBST) | tj;
             if (sj != CV_NONE) {
                 F.phi[j] = cv_to_liquid(sj) ? R(1) : R(0);
                 continue;
@@ -329,32 +350,6 @@ __global__ __launch_bounds__(256) void k_conv_gather(const Batch<P> B)
             const R mn = base + gathered_excess(F, j, tag);
             F.m[j] = mn;
             F.phi[j] = mn / F.rho[j];
-        }
-    }
-}
-
-// Rule 6: the new types of converting and new cells.
-template <class P>
-__global__ __launch_bounds__(256) void k_conv_flags(const Batch<P> B)
-{
-    const Fields<P> &F = B.f[blockIdx.y];
-    if (F.sc->nconv == 0) return;
-    const uint32_t tag = F.sc->step << 2;
-    const int n = list_count(F.sc);
-    for (int k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256) {
-        const int i = F.ilist[k];
-        const uint8_t st = F.conv[i];
-        if (st == CV_NONE) continue;
-        const uint8_t stat = F.flags[i] & FL_NEAR_OBST;
-        F.flags[i] = stat | (cv_to_liquid(st) ? FL_LIQ : FL_GAS);
-        if (st == CV_CLOSE_LIQ || st == CV_CLOSE_GAS) continue;  // as in k_conv_gather
-        const Nbr nb(i, F.nx, F.ny, F.nz);
-        for (int q = 1; q < NQ; ++q) {
-            const int j = nb.at(dir_x(q), dir_y(q), dir_z(q));
-            if ((F.mark[j] & ~3u) != tag) continue;
-            const uint8_t sj = F.conv[j];
-            const uint8_t tj = sj == CV_NONE ? FL_IF : (cv_to_liquid(sj) ? FL_LIQ : FL_GAS);
-            F.flags[j] = (F.flags[j] & FL_NEAR_OBST) | tj;
         }
     }
 }
@@ -442,7 +437,7 @@ __global__ __launch_bounds__(256) void k_conv_share_keep(const Batch<P> B)
     const int n = list_count(F.sc), nl = n + F.sc->nnew;
     int k0, k1;
     block_share(nl, k0, k1);
-    for (int k = k0 + threadIdx.x; k < k1; k += 256) conv_share_cell(F, layer_cell(F, k, n), tag);
+    for (int k = k0 + threadIdx.x; k < k1; k += 256) conv_share_cell(F, layer_cell(F, k, n), tag, k < n);
     __shared__ int lw[4];
     __shared__ int base_s;
     int cnt = 0;
@@ -644,17 +639,12 @@ __global__ __launch_bounds__(256) void k_mark_wall_cells(const uint8_t *flags, u
 // phi(x_o) = sum |nw.c^_q| phi(x_o + c_q) / sum |nw.c^_q| over fluid
 // neighbours with aperture |nw.c^_q| > sqrt(2)/2 (strict; the 45-degree
 // links are excluded), nw the normalised sum of the directions from x_o to
-// its non-obstacle neighbours. Block 0 also closes the step's bookkeeping.
+// its non-obstacle neighbours.
 template <class P>
-__global__ __launch_bounds__(256) void k_obstacle_fill(const Batch<P> B, int end_of_step)
+__global__ __launch_bounds__(256) void k_obstacle_fill(const Batch<P> B)
 {
     const Fields<P> &F = B.f[blockIdx.y];
     using R = typename P::R;
-    if (end_of_step && blockIdx.x == 0 && threadIdx.x == 0) {
-        F.sc->nconv = 0;
-        F.sc->nnew = 0;
-        F.sc->step += 1;
-    }
     const int n = F.sc->ocount;
     const double alpha = 0.70710678118654752440 + 1e-12;
     for (int k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256) {

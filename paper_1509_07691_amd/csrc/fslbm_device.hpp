@@ -163,6 +163,19 @@ __device__ inline void block_share(int n, int &k0, int &k1)
     k1 = min(n, k0 + per * 256);
 }
 
+// Closes a time step's device bookkeeping (conversion counters, the step
+// number that tags new cells). The first geometry launch of a step does it,
+// by thread 0 of block (0, lattice), when asked; no kernel of that launch
+// reads these counters.
+__device__ inline void end_of_step(DevScalars *sc, int eos)
+{
+    if (eos && blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->nconv = 0;
+        sc->nnew = 0;
+        sc->step += 1;
+    }
+}
+
 // Model parameters (Sec. II): rho_b = 3 (p_g + sigma K), p_g = rho_gas / 3.
 struct Params {
     double sigma;

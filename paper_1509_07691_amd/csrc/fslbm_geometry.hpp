@@ -411,9 +411,10 @@ __device__ inline bool fd_contact_normal(const G (&w)[3], const G (&nb)[3], G ct
 
 // Contact normals of the obstacle-list cells of FD lattices (0 where none).
 template <class P>
-__global__ __launch_bounds__(256) void k_fd_contact_normals(const Batch<P> B)
+__global__ __launch_bounds__(256) void k_fd_contact_normals(const Batch<P> B, int eos)
 {
     const Params &prm = B.p[blockIdx.y];
+    end_of_step(B.f[blockIdx.y].sc, eos);
     if (prm.curv != 0) return;
     const Fields<P> &F = B.f[blockIdx.y];
     using G = typename P::G;
@@ -529,8 +530,9 @@ __device__ inline void geometry_fd_tiles(const Fields<P> &F)
 }
 
 template <class P>
-__global__ __launch_bounds__(256) void k_geometry_fd(const Batch<P> B)
+__global__ __launch_bounds__(256) void k_geometry_fd(const Batch<P> B, int eos)
 {
+    end_of_step(B.f[blockIdx.y].sc, eos);
     if (B.p[blockIdx.y].curv != 0) return;
     geometry_fd_tiles(B.f[blockIdx.y]);
 }
@@ -864,8 +866,9 @@ __device__ inline void normals_plic_list(const Fields<P> &F)
 }
 
 template <class P>
-__global__ __launch_bounds__(256) void k_normals_plic(const Batch<P> B)
+__global__ __launch_bounds__(256) void k_normals_plic(const Batch<P> B, int eos)
 {
+    end_of_step(B.f[blockIdx.y].sc, eos);
     if (B.p[blockIdx.y].curv == 0) return;  // LSQR and TR
     normals_plic_list(B.f[blockIdx.y]);
 }
@@ -874,8 +877,9 @@ __global__ __launch_bounds__(256) void k_normals_plic(const Batch<P> B)
 // their whole tiled curvature, LSQR lattices their normals and PLIC points
 // (the LSQR fit follows in k_curv_lsqr4), so the two overlap on the device.
 template <class P>
-__global__ __launch_bounds__(256) void k_geometry_mixed(const Batch<P> B)
+__global__ __launch_bounds__(256) void k_geometry_mixed(const Batch<P> B, int eos)
 {
+    end_of_step(B.f[blockIdx.y].sc, eos);
     if (B.p[blockIdx.y].curv == 0) geometry_fd_tiles(B.f[blockIdx.y]);
     else normals_plic_list(B.f[blockIdx.y]);
 }
@@ -900,9 +904,11 @@ __global__ __launch_bounds__(256) void k_curv_lsqr(const Batch<P> B)
 // lane l of a group scans the block cells s = l, l + 4, ... (s = 0..26,
 // x fastest) for obstacles and adds their data and contact rows; the sums
 // are reduced over the 4 lanes by an xor butterfly (a fixed order, the same
-// result on every lane) and every lane solves the same system.
+// result on every lane) and every lane solves the same system. Limited to
+// 168 VGPRs for 3 waves per SIMD (a 20-byte spill): this latency-bound
+// gather runs faster than at 2 waves with no spill.
 template <class P>
-__global__ __launch_bounds__(256) void k_curv_lsqr4(const Batch<P> B)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_curv_lsqr4(const Batch<P> B)
 {
     const Params &prm = B.p[blockIdx.y];
     if (prm.curv != 1) return;
