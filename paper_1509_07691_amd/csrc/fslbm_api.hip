@@ -55,7 +55,7 @@ size_t fbytes(int prec)
 size_t rbytes(int prec) { return prec == P_F64 ? 8 : 4; }
 
 struct Layout {
-    size_t fA, fB, flags, conv, mark, m, rho, phi, K, nrm, plic, share, phis, nmol, cnrm, ilist, olist, wlist, newlist,
+    size_t fA, fB, flags, conv, near, mark, m, rho, phi, K, nrm, plic, share, phis, nmol, cnrm, ilist, olist, wlist, newlist,
         ilist_tmp,
         staging,
         counts, part, sc, total;
@@ -63,8 +63,9 @@ struct Layout {
 
 constexpr int MASS_BLOCKS = 1024;
 
-Layout make_layout(long long N, int prec)
+Layout make_layout(int nx, int ny, int nz, int prec)
 {
+    const long long N = (long long)nx * ny * nz;
     Layout L;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -76,6 +77,7 @@ Layout make_layout(long long N, int prec)
     L.fA = take(19 * N * fb);
     L.fB = take(19 * N * fb);
     L.flags = take(N);
+    L.near = take(N);
     L.conv = take(N);
     L.mark = take(4 * N);
     L.m = take(N * rb);
@@ -213,6 +215,7 @@ Fields<P> make_fields(const fslbm_lattice *h)
     F.fdst = (S *)(w + (h->cur == 0 ? L.fB : L.fA));
     F.flags = (uint8_t *)(w + L.flags);
     F.conv = (uint8_t *)(w + L.conv);
+    F.near = (uint8_t *)(w + L.near);
     F.mark = (uint32_t *)(w + L.mark);
     F.m = (R *)(w + L.m);
     F.rho = (R *)(w + L.rho);
@@ -343,6 +346,7 @@ __global__ void k_init_fields(Fields<P> F, const double *fill, const uint8_t *ty
         F.cnrm[c * N + i] = 0;
     }
     F.mark[i] = 0;
+    F.near[i] = 0;
     typename P::S *dst = F.fdst;
     typename P::S *src = const_cast<typename P::S *>(F.fsrc);
 #pragma unroll
@@ -1313,7 +1317,7 @@ int fslbm_required_bytes(int nx, int ny, int nz, int precision, size_t *bytes)
     if (!bytes) return fail(FSLBM_E_ARG, "bytes is NULL");
     if (precision < 0 || precision > 3) return fail(FSLBM_E_ARG, "unknown precision %d", precision);
     if (!shape_ok(nx, ny, nz)) return fail(FSLBM_E_SHAPE, "lattice %dx%dx%d out of range", nx, ny, nz);
-    *bytes = make_layout((long long)nx * ny * nz, precision).total;
+    *bytes = make_layout(nx, ny, nz, precision).total;
     return 0;
 }
 
@@ -1331,7 +1335,7 @@ int fslbm_create(int nx, int ny, int nz, int precision, int curv_model, const do
         return fail(FSLBM_E_ARG, "unknown curvature model %d", curv_model);
     if (!shape_ok(nx, ny, nz)) return fail(FSLBM_E_SHAPE, "lattice %dx%dx%d out of range", nx, ny, nz);
     const long long N = (long long)nx * ny * nz;
-    const Layout L = make_layout(N, precision);
+    const Layout L = make_layout(nx, ny, nz, precision);
     if (workspace_bytes < L.total)
         return fail(FSLBM_E_SHAPE, "workspace has %zu bytes, %zu needed", workspace_bytes, L.total);
     fslbm_lattice *h = new (std::nothrow) fslbm_lattice();

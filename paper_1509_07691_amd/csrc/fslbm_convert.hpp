@@ -82,10 +82,21 @@ __device__ inline uint8_t prune_own(const Fields<P> &F, int i)
     return st;
 }
 
+__device__ inline int wrap_any(int v, int n)
+{
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
 // Rules 2 and 3: prune the cell's own emptying (it reads only its
 // neighbours' filling, which pruning never changes), then tag the new
 // interface cells and initialise them. Cells reached from several
-// converting neighbours are written identically by each.
+// converting neighbours are written identically by each. A filling or
+// emptying cell also stamps the 7x7x7 box around it in `near` with the low
+// byte of the step number: the closure of rule 4 can only change a cell
+// within two cells of one (the layer was closed before the step), and
+// the excess of rule 5 moves one cell further. A stale stamp that happens
+// to match only makes a cell be checked.
 template <class P>
 __global__ __launch_bounds__(256) void k_conv_mark_init(const Batch<P> B)
 {
@@ -102,6 +113,15 @@ __global__ __launch_bounds__(256) void k_conv_mark_init(const Batch<P> B)
         int nfresh = 0;
         const int i = k < n ? F.ilist[k] : 0;
         const uint8_t st = k < n ? prune_own(F, i) : CV_NONE;
+        if (st != CV_NONE) {
+            const uint8_t s8 = uint8_t(tag >> 2);
+            const int yz = i / F.nx, x = i - yz * F.nx, z = yz / F.ny, y = yz - z * F.ny;
+            for (int dz = -3; dz <= 3; ++dz)
+                for (int dy = -3; dy <= 3; ++dy) {
+                    const int row = F.nx * (wrap_any(y + dy, F.ny) + F.ny * wrap_any(z + dz, F.nz));
+                    for (int dx = -3; dx <= 3; ++dx) F.near[row + wrap_any(x + dx, F.nx)] = s8;
+                }
+        }
         const Nbr nb(i, F.nx, F.ny, F.nz);
         for (int q = 1; q < NQ && st != CV_NONE; ++q) {
             const int j = nb.at(dir_x(q), dir_y(q), dir_z(q));
@@ -236,10 +256,11 @@ __global__ __launch_bounds__(256) void k_conv_close(const Batch<P> B)
         F.sc->bbox[3] = -1; F.sc->bbox[4] = -1; F.sc->bbox[5] = -1;
     }
     const uint32_t tag = F.sc->step << 2;
+    const uint8_t s8 = uint8_t(tag >> 2);
     const int n = list_count(F.sc), nn = F.sc->nnew;
     for (int k = blockIdx.x * 256 + threadIdx.x; k < n + nn; k += gridDim.x * 256) {
         const int i = layer_cell(F, k, n);
-        if (F.conv[i] != CV_NONE) continue;
+        if (F.near[i] != s8 || F.conv[i] != CV_NONE) continue;
         // most cells have both a gas and a liquid neighbour: stop at the
         // first of each
         const Nbr nb(i, F.nx, F.ny, F.nz);
@@ -318,12 +339,14 @@ __global__ __launch_bounds__(256) void k_conv_gather(const Batch<P> B)
     using R = typename P::R;
     const bool any = F.sc->nconv != 0;
     const uint32_t tag = F.sc->step << 2;
+    const uint8_t s8 = uint8_t(tag >> 2);
     const int n = list_count(F.sc);
     for (int k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256) {
         const int i = F.ilist[k];
         const uint8_t st = any ? F.conv[i] : CV_NONE;
         if (st == CV_NONE) {
-            const R acc = any ? gathered_excess(F, i, tag) : R(0);
+            // only a cell near a filling or emptying cell can receive
+            const R acc = any && F.near[i] == s8 ? gathered_excess(F, i, tag) : R(0);
             const R mn = F.m[i] + acc;
             F.m[i] = mn;
             F.phi[i] = mn / F.rho[i];

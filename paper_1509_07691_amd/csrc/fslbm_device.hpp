@@ -206,6 +206,7 @@ template <class P> struct Fields {
     S *fdst;           // f'(t+1)
     uint8_t *flags;
     uint8_t *conv;
+    uint8_t *near;  // low byte of the step number when within 2 cells of a filling or emptying cell
     uint32_t *mark;
     R *m, *rho, *phi, *K, *nrm, *plic, *share, *phis, *nmol;
     R *cnrm;           // FD wetting: contact normal of obstacle cells (3 planes, 0 = none)
