@@ -382,6 +382,42 @@ def moving_bubble_table(dev, resolutions, models=("fd", "lsqr"), precision="f64"
     return rows
 
 
+def hbm_storage_comparison(dev, stream, precisions, steps, warmup):
+    """The storage forms on the HBM-bound bubble probe (gas bubble R = 64 in
+    a liquid-filled periodic 512^3, LSQR): MLUPS and the stream-collide's
+    algorithmic GB/s per form, one lattice at a time."""
+    import torch
+    from paper_1509_07691_amd.fslbm import Lattice
+
+    (label, fill, obst, p), = workload_runs("probe")[0]
+    out = {}
+    for prec in precisions:
+        with torch.cuda.stream(stream):
+            lat = Lattice(fill, obst, precision=prec, device=dev, stream=stream, **p)
+        lat.step(warmup)
+        torch.cuda.synchronize()
+        lat.set_timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lat.step(steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        ph, _ = lat.timing()
+        bl, bi, _, _ = sc_bytes(lat.flags(), prec)
+        out[prec] = {"mlups": round(lat.n * steps / el / 1e6, 1), "ms_per_step": round(1e3 * el / steps, 4),
+                     "stream_collide_us": round(1e3 * ph[0] / steps, 3),
+                     "stream_collide_GBs": round((bl + bi) * steps / (ph[0] * 1e-3) / 1e9, 1)}
+        lat.close()
+        del lat
+        torch.cuda.empty_cache()
+        print(f"# hbm comparison {prec}: {out[prec]['mlups']} MLUPS", file=sys.stderr, flush=True)
+    base = precisions[0]
+    for prec in precisions[1:]:
+        out[prec]["speedup_vs_" + base] = round(out[prec]["mlups"] / out[base]["mlups"], 3)
+    out["workload"] = "gas bubble R=64 in liquid-filled periodic 512^3, LSQR (HBM-bound)"
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -413,6 +449,8 @@ def main():
     ap.add_argument("--models", default="fd,lsqr")
     ap.add_argument("--eps-c", type=float, default=None,
                     help="conversion offset for the bubble studies (library default 1e-3)")
+    ap.add_argument("--hbm-compare", default="f32,f16",
+                    help="storage forms timed on the HBM-bound bubble probe after the run (empty: skip)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
@@ -566,6 +604,11 @@ def main():
         del cb, clats
         torch.cuda.synchronize()
 
+    hbm_compare = None
+    hprec = [p for p in args.hbm_compare.split(",") if p]
+    if hprec and args.workload != "probe":
+        hbm_compare = hbm_storage_comparison(dev, stream, hprec, steps=10, warmup=3)
+
     adjoint = None
     if args.adjoint_steps > 0:
         adjoint = adjoint_cost(dev, stream, args.adjoint_steps, args.adjoint_k, args.precision)
@@ -611,6 +654,8 @@ def main():
         res["cpu_baseline"] = cpu_baseline(runs, args.cpu_seconds)
     if compare:
         res["storage_comparison"] = compare
+    if hbm_compare:
+        res["storage_comparison_hbm"] = hbm_compare
     if adjoint:
         res["adjoint"] = adjoint
     print(json.dumps(res), flush=True)
