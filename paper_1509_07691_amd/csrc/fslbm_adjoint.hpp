@@ -1125,11 +1125,33 @@ __global__ __launch_bounds__(256) void k_adj_lsqr_cell(const Fields<P> F, const 
     }
 }
 
+// PLIC implicit derivatives of every interface cell, one thread per cell
+// (the polygon of the plane section is the heavy part of the PLIC reverse):
+// dphi goes to ms (unused by the LSQR model), dn to the cell's own gb
+// entries, which k_adj_lsqr_plic reads back before it overwrites them.
+template <class P>
+__global__ __launch_bounds__(256) void k_adj_plic_derivs(const Fields<P> F, const Adj A)
+{
+    const int n = F.sc->icount;
+    const size_t N = F.N;
+    for (int k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256) {
+        const int j = F.ilist[k];
+        const double nj[3] = {double(F.nrm[j]), double(F.nrm[N + j]), double(F.nrm[2 * N + j])};
+        double dphi = 0.0, dn[3] = {0.0, 0.0, 0.0};
+        if (nj[0] != 0.0 || nj[1] != 0.0 || nj[2] != 0.0) plic_derivs(nj, double(F.phi[j]), double(F.plic[j]), dphi, dn);
+        A.ms[j] = dphi;
+        A.gb[j] = dn[0];
+        A.gb[N + j] = dn[1];
+        A.gb[2 * N + j] = dn[2];
+    }
+}
+
 // Per interface cell j, 8 lanes: gather dL/dn_j, dL/da_j over the blocks
 // containing j (lane l takes the block offsets s = l, l + 8, ...) and the
 // Parker-Youngs gradient g of phi at j (the same split); lane 0 then passes
 // dL/da_j through the PLIC offset (into phib and dL/dn_j) and dL/dn_j
-// through n = g/|g| into gb.
+// through n = g/|g| into gb (the PLIC derivatives come from
+// k_adj_plic_derivs).
 template <class P>
 __global__ __launch_bounds__(256) void k_adj_lsqr_plic(const Fields<P> F, const Adj A)
 {
@@ -1166,8 +1188,7 @@ __global__ __launch_bounds__(256) void k_adj_lsqr_plic(const Fields<P> F, const 
         const double nj[3] = {double(F.nrm[j]), double(F.nrm[N + j]), double(F.nrm[2 * N + j])};
         double o[3] = {0, 0, 0};
         if (nj[0] != 0.0 || nj[1] != 0.0 || nj[2] != 0.0) {
-            double dphi, dn[3];
-            plic_derivs(nj, double(F.phi[j]), double(F.plic[j]), dphi, dn);
+            const double dphi = A.ms[j], dn[3] = {A.gb[j], A.gb[N + j], A.gb[2 * N + j]};  // k_adj_plic_derivs
             A.phib[j] += abar * dphi;
             for (int d = 0; d < 3; ++d) nbar[d] += abar * dn[d];
             const double len = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);

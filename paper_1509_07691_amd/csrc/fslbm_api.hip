@@ -1143,6 +1143,7 @@ int enqueue_geometry_adjoint(fslbm_lattice *h, const Fields<P> &F, const Adj &A,
     } else {
         const int l8 = std::min(2048, std::max(1, (h->adj.icount + 31) / 32));  // 32 cells per block
         k_adj_lsqr_cell<P><<<l8, 256, 0, st>>>(F, A, prm);
+        k_adj_plic_derivs<P><<<lg, 256, 0, st>>>(F, A);
         k_adj_lsqr_plic<P><<<l8, 256, 0, st>>>(F, A);
         k_adj_lsqr_phib<P><<<lg, 256, 0, st>>>(F, A);
     }
