@@ -461,7 +461,7 @@ def main():
         print(json.dumps(rec))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
               "(use --gpus 1).", file=sys.stderr)
         sys.exit(2)
 

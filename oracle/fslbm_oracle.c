@@ -795,7 +795,7 @@ static void curvature(orc_lattice *L)
  * reclassified in two passes: first those without a gas neighbour become
  * liquid, then, on the updated types, those without a liquid neighbour
  * become gas. Neither pass can put a liquid cell next to a gas cell, and
- * neither undoes what the other established, so one round suffices.
+ * neither undoes what the other established, so one pass of each suffices.
  * out[i] = 1 (to liquid), 2 (to gas) or 0. */
 static int any_nbr_of(const orc_lattice *L, const unsigned char *t, long i, unsigned char want)
 {
