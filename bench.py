@@ -382,6 +382,77 @@ def moving_bubble_table(dev, resolutions, models=("fd", "lsqr"), precision="f64"
     return rows
 
 
+# L2(r) of the contact-line radius printed for the grid study of Sec. III.B.1
+# (Fig. DropletConvergence) at dx = 1/48, 1/96, 1/144.
+PAPER_SESSILE_L2R = {
+    ("fd", 60): (0.0610761, 0.0256658, 0.0207583),
+    ("fd", 90): (0.0426878, 0.0190497, 0.0134927),
+    ("fd", 120): (0.0973444, 0.0389345, 0.0387821),
+    ("lsqr", 60): (0.0594971, 0.0211923, 0.0134882),
+    ("lsqr", 90): (0.00559683, 0.00508519, 0.0029987),
+    ("lsqr", 120): (0.0597827, 0.0322758, 0.0248789),
+}
+
+
+def sessile_measures(lat, n, h, r):
+    """h*/h - 1, L2(r) and STDEV of r~ over the contact-line cells, and the
+    apparent angle 2 atan(h*/r*) (Sec. III.B.1): h* = max over interface
+    cells of z + phi - 0.5 (z the cell centre above the wall), r~ = |x - x_o|
+    + phi - 0.5 over the contact-line cells (interface cells with an
+    obstacle D3Q19 neighbour, here the first fluid layer), r* their mean."""
+    from paper_1509_07691_amd.fslbm import FSLBM_INTERFACE
+
+    fl = lat.flags()
+    ph = lat.fill()
+    k, j, i = np.nonzero(fl == FSLBM_INTERFACE)
+    hs = float(np.max((k + 0.5 - 1.0) + ph[k, j, i] - 0.5))
+    c = k == 1
+    kc, jc, ic = k[c], j[c], i[c]
+    rt = np.hypot(ic + 0.5 - n / 2, jc + 0.5 - n / 2) + ph[kc, jc, ic] - 0.5
+    l2 = float(np.sqrt(((r - rt) ** 2).sum() / (r * r * rt.size)))
+    rs = float(rt.mean())
+    return hs / h - 1.0, l2, float(rt.std()) / r, float(np.degrees(2 * np.arctan(hs / rs)))
+
+
+def sessile_table(dev, resolutions, models, thetas, eps_c=None, t_phys=2.0):
+    """Equilibrium sessile droplets of Sec. III.B.1: the ideal spherical cap
+    of each contact angle (hemisphere volume, R = 0.125) on the wall of the
+    unit cube, dx = 1/n with diffusive scaling dt = 1e-4 (96/n)^2 (tau = 1.1912,
+    the paper's dt = 1e-4 at dx = 1/96), run for t_phys in the units of the
+    problem; height error, L2(r), STDEV(r~)/r and the apparent angle."""
+    import torch
+    from paper_1509_07691_amd import inputs as I
+    from paper_1509_07691_amd.fslbm import Lattice
+
+    rows = []
+    for n in resolutions:
+        dt = 1e-4 * (96.0 / n) ** 2
+        tau, sig = I.renardy_units(n, dt)
+        steps = int(round(t_phys / dt))
+        for th in thetas:
+            fill, obst, h, r = I.sessile_cap(n, th)
+            for model in models:
+                lat = Lattice(fill, obst, precision="f64", curv_model=model, sigma=sig, tau=tau,
+                              theta=np.radians(th), eps_c=eps_c, device=dev)
+                t, hist = 0, []
+                for m in sorted(set(list(range(steps // 4, steps, steps // 4)) + [steps])):
+                    lat.step(m - t)
+                    t = m
+                    he, l2, sd, ang = sessile_measures(lat, n, h, r)
+                    hist.append([t, he, l2])
+                    print(f"# sessile n={n} theta={th} {model} t={t}/{steps}: h*/h-1 {he:+.4f} L2(r) {l2:.4f} "
+                          f"angle {ang:.1f}", file=sys.stderr, flush=True)
+                paper = PAPER_SESSILE_L2R.get((model, int(th)))
+                idx = {48: 0, 96: 1, 144: 2}.get(n)
+                rows.append({"n": n, "theta": th, "model": model, "tau": round(tau, 4), "sigma_L": sig,
+                             "steps": steps, "h_err": he, "L2_r": l2, "stdev_r_rel": sd, "apparent_angle": ang,
+                             "paper_L2_r": None if paper is None or idx is None else paper[idx],
+                             "history": hist})
+                lat.close()
+                torch.cuda.empty_cache()
+    return rows
+
+
 def hbm_storage_comparison(dev, stream, precisions, steps, warmup):
     """The storage forms on the HBM-bound bubble probe (gas bubble R = 64 in
     a liquid-filled periodic 512^3, LSQR): MLUPS and the stream-collide's
@@ -447,6 +518,8 @@ def main():
     ap.add_argument("--moving", type=int, nargs="*", metavar="N",
                     help="moving-frame bubble at dx = 1/N (default 48 96) instead of the bench")
     ap.add_argument("--models", default="fd,lsqr")
+    ap.add_argument("--sessile", type=int, nargs="*", metavar="N",
+                    help="equilibrium sessile droplets at dx = 1/N (default 48 96 144) instead of the bench")
     ap.add_argument("--eps-c", type=float, default=None,
                     help="conversion offset for the bubble studies (library default 1e-3)")
     ap.add_argument("--hbm-compare", default="f32,f16",
@@ -476,6 +549,10 @@ def main():
     if args.laplace is not None:
         res = args.laplace or [48, 96]
         print(json.dumps({"laplace": laplace_table(dev, res, args.laplace_steps, models, eps_c=args.eps_c)}))
+        return
+    if args.sessile is not None:
+        res = args.sessile or [48, 96, 144]
+        print(json.dumps({"sessile": sessile_table(dev, res, models, (60.0, 90.0, 120.0), eps_c=args.eps_c)}))
         return
     if args.moving is not None:
         res = args.moving or [48, 96]

@@ -499,7 +499,9 @@ static void normals_and_plic(orc_lattice *L)
  * to the fluid, w is the normalised sum of the directions to its
  * non-obstacle neighbours (out of the wall) and x_b = x_o + c_b the neighbour
  * along the lattice direction closest to w (the first one on ties). When x_b
- * is an interface cell with mollified unit normal n_b, the wall value
+ * (a cell of any type but obstacle: the interface normal that the paper
+ * projects is the mollified gradient, which exists wherever phi varies)
+ * has a mollified unit normal n_b, the wall value
  * m = n_w cos(theta) + n_t sin(theta), with n_w = -w (into the wall) and n_t
  * the normalised projection of n_b onto the wall, is extrapolated linearly
  * to the obstacle node, which lies half a cell beyond the wall on the line
@@ -527,7 +529,7 @@ static void fd_contact_normals(const orc_lattice *L, double *nm)
             if (a > best) { best = a; qb = q; }
         }
         const long j = nbr(L, i, CX[qb], CY[qb], CZ[qb]);
-        if (L->type[j] != ORC_INTERFACE) continue;
+        if (L->type[j] == ORC_OBSTACLE) continue;
         const double nb[3] = {nm[j], nm[n + j], nm[2 * n + j]};
         if (dot3(nb, nb) == 0.0) continue;
         const double nw[3] = {-w[0], -w[1], -w[2]};

@@ -421,8 +421,8 @@ __device__ inline bool fd_contact_normal_adj(const double (&w)[3], const double 
 
 // Base direction qb of obstacle cell o for FD wetting (0: no contact
 // normal): the lattice direction closest to the normalised sum w of the
-// directions to o's non-obstacle neighbours, when o + c_qb is an interface
-// cell (the forward rule, in FP64).
+// directions to o's non-obstacle neighbours, when o + c_qb is not an
+// obstacle cell (the forward rule, in FP64).
 template <class P>
 __device__ inline int fd_contact_base_d(const Fields<P> &F, const Nbr &no, double (&w)[3])
 {
@@ -441,7 +441,7 @@ __device__ inline int fd_contact_base_d(const Fields<P> &F, const Nbr &no, doubl
         const double a = (dir_x(q) * w[0] + dir_y(q) * w[1] + dir_z(q) * w[2]) / cl;
         if (a > best) { best = a; qb = q; }
     }
-    return (F.flags[no.at(dir_x(qb), dir_y(qb), dir_z(qb))] & FL_IF) ? qb : 0;
+    return (F.flags[no.at(dir_x(qb), dir_y(qb), dir_z(qb))] & FL_OBST) ? 0 : qb;
 }
 
 __device__ inline bool unit_of(const double g[3], double (&n)[3], double &len)
@@ -454,7 +454,7 @@ __device__ inline bool unit_of(const double g[3], double (&n)[3], double &len)
 
 // gb = (I - n n^T) nbar / |g| with nbar = PY(kbar)/32. With FD wetting an
 // obstacle cell whose normal is the contact normal gets gb = 0, and its nbar
-// goes through the contact normal to its base interface cell (gathered
+// goes through the contact normal to its base cell (gathered
 // there) and to theta (tacc of the base cell).
 template <class P>
 __global__ __launch_bounds__(256) void k_adj_fd_nbar(const Fields<P> F, const Adj A, const Params prm)
@@ -480,7 +480,7 @@ __global__ __launch_bounds__(256) void k_adj_fd_nbar(const Fields<P> F, const Ad
                 overridden = unit_of(g, n, len) && fd_contact_normal_adj(w, n, prm.cos_theta, prm.sin_theta, ob, nbb, thb);
             }
         }
-        if (!overridden && walls && (fl & FL_IF) && (fl & FL_NEAR_OBST)) {
+        if (!overridden && walls && !(fl & FL_OBST) && (fl & FL_NEAR_OBST)) {
             // obstacle neighbours o = i - c_q whose base cell is i
             double g[3], n[3], len;
             py_grad(A.ms, nb, g[0], g[1], g[2]);

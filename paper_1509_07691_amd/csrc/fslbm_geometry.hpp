@@ -361,8 +361,9 @@ __device__ inline void fd_mollified_normal(const Fields<P> &F, int j, typename P
 // FD wetting (Sec. II.A, eq. contactNormal) at obstacle cell o: w is the
 // normalised sum of the directions to its non-obstacle neighbours (out of
 // the wall) and x_b = o + c_qb the neighbour along the lattice direction
-// closest to w (the first on ties). Returns qb, or 0 when x_b is not an
-// interface cell.
+// closest to w (the first on ties). Returns qb, or 0 when x_b is an
+// obstacle cell (a base cell of any other type carries the wall value when
+// its mollified normal is nonzero).
 template <class P>
 __device__ inline int fd_contact_base(const Fields<P> &F, const Nbr &no, typename P::G (&w)[3])
 {
@@ -384,7 +385,7 @@ __device__ inline int fd_contact_base(const Fields<P> &F, const Nbr &no, typenam
         const G a = (G(dir_x(q)) * w[0] + G(dir_y(q)) * w[1] + G(dir_z(q)) * w[2]) / cl;
         if (a > best) { best = a; qb = q; }
     }
-    return (F.flags[no.at(dir_x(qb), dir_y(qb), dir_z(qb))] & FL_IF) ? qb : 0;
+    return (F.flags[no.at(dir_x(qb), dir_y(qb), dir_z(qb))] & FL_OBST) ? 0 : qb;
 }
 
 // The wall value m = n_w cos(theta) + n_t sin(theta) (n_w = -w into the wall,

@@ -36,6 +36,7 @@ __all__ = [
     "lattice_units",
     "laplace_bubble",
     "renardy_units",
+    "sessile_cap",
 ]
 
 _GL_X, _GL_W = np.polynomial.legendre.leggauss(12)
@@ -317,6 +318,30 @@ def laplace_bubble(n: int, noise: float = 0.0, seed: int = 0):
     if noise:
         fill = perturb_interface(fill, noise, seed)
     return fill, obst
+
+
+def sessile_cap(n: int, theta_deg: float):
+    """The equilibrium sessile droplet of Sec. III.B.1 at dx = 1/n: a
+    spherical cap on the wall z = 0 of the unit cube (walls at z = 0 and 1,
+    periodic in x and y) with the volume of a hemisphere of radius n/8 and
+    the ideal height h and contact radius r of the contact angle theta
+    (equations of that section). Obstacle layers fill k = 0 and k = n+1; the
+    wall plane is z = 1 in cell-corner coordinates and the contact line is
+    centred at (n/2, n/2). Returns fill, obstacle, h, r."""
+    t = np.radians(theta_deg)
+    R0 = n / 8.0
+    V = 2.0 / 3.0 * np.pi * R0 ** 3
+    h = (V / (np.pi * (1.0 / (1.0 - np.cos(t)) - 1.0 / 3.0))) ** (1.0 / 3.0)
+    r = np.sqrt((6.0 * V / (np.pi * h) - h * h) / 3.0)
+    Rs = h / (1.0 - np.cos(t))
+    shape = (n + 2, n, n)
+    fill = sphere_fraction(shape, (n / 2, n / 2, 1.0 + h - Rs), Rs)
+    obst = np.zeros(shape, dtype=np.uint8)
+    obst[0] = 1
+    obst[n + 1] = 1
+    fill[0] = 0.0
+    fill[n + 1] = 0.0
+    return fill, obst, float(h), float(r)
 
 
 def renardy_units(n: int, dt: float = 1e-4):

@@ -420,6 +420,16 @@ def test_lattice_units_reproduce_printed_table():
         assert s / 1e-3 == pytest.approx(sig, rel=2e-3)
 
 
+def test_sessile_cap_input_volume_and_height():
+    # the cap of Sec. III.B.1 holds the hemisphere's volume and reaches h
+    for th in (60.0, 90.0, 120.0):
+        fill, obst, h, r = I.sessile_cap(48, th)
+        assert fill[obst == 0].sum() == pytest.approx(2.0 / 3.0 * math.pi * 6.0 ** 3, rel=1e-9)
+        assert fill[:, 24, 24].sum() == pytest.approx(h, abs=0.1)  # a column next to the axis
+        base = fill[1].sum()  # the first fluid layer holds about the contact disc
+        assert base == pytest.approx(math.pi * r * r, rel=0.15)
+
+
 def test_sessile_cap_closed_form_fixture():
     rows = np.loadtxt(os.path.join(GOLDEN, "sessile_cap_closed_form.txt"))
     V = 2.0 / 3.0 * math.pi * 48 ** 3
