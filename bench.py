@@ -453,6 +453,62 @@ def sessile_table(dev, resolutions, models, thetas, eps_c=None, t_phys=2.0):
     return rows
 
 
+def oscillation_table(dev, precisions, steps, every=500):
+    """Oscillating droplet (the precision form's workload): the ellipsoid
+    96/80/80 in a periodic 512^3, LSQR, sigma = 1e-3, tau = 0.55, per storage
+    form. The x semi-axis a(t) = sqrt(5 <(x - <x>)^2>) (phi-weighted, exact
+    for a solid ellipsoid) is sampled every `every` steps; the period is
+    twice the mean spacing of its successive extrema (parabolic refinement),
+    compared with Lamb's l = 2 mode, omega^2 = 8 sigma / (rho R^3), R the
+    equal-volume radius, and its viscous decay rate 5 nu / R^2."""
+    import torch
+    from paper_1509_07691_amd.fslbm import Lattice
+
+    (label, fill, obst, p), = workload_runs("c3")[0]
+    nz, ny, nx = fill.shape
+    x = torch.arange(nx, dtype=torch.float64, device=dev) + 0.5
+    R = (96.0 * 80.0 * 80.0) ** (1.0 / 3.0)
+    nu = (p["tau"] - 0.5) / 3.0
+    w0 = math.sqrt(8.0 * p["sigma"] / R ** 3)
+    out = {"lamb_period_steps": round(2 * math.pi / w0, 1), "lamb_decay_per_step": 5.0 * nu / R ** 2}
+    for prec in precisions:
+        lat = Lattice(fill, obst, precision=prec, device=dev, **p)
+        m0 = lat.mass()
+        ts, a = [], []
+        t = 0
+        while True:
+            ph = lat.fill_tensor()
+            wsum = ph.sum()
+            px = ph.sum(dim=(0, 1))
+            mx = (px * x).sum() / wsum
+            a.append(math.sqrt(5.0 * float((px * (x - mx) ** 2).sum() / wsum)))
+            ts.append(t)
+            del ph, px
+            if t >= steps:
+                break
+            lat.step(every)
+            t += every
+            if t % (10 * every) == 0:
+                print(f"# oscillation {prec} t={t}: a={a[-1]:.3f}", file=sys.stderr, flush=True)
+        a = np.array(a)
+        ext = []
+        for k in range(1, len(a) - 1):
+            if (a[k] - a[k - 1]) * (a[k + 1] - a[k]) < 0:
+                den = a[k - 1] - 2 * a[k] + a[k + 1]
+                off = 0.5 * (a[k - 1] - a[k + 1]) / den if den != 0 else 0.0
+                ext.append(ts[k] + off * every)
+        period = 2.0 * float(np.mean(np.diff(ext))) if len(ext) >= 2 else None
+        out[prec] = {"period_steps": None if period is None else round(period, 1),
+                     "period_vs_lamb": None if period is None else round(period * w0 / (2 * math.pi), 4),
+                     "extrema_steps": [round(e, 1) for e in ext], "a_first_last": [round(a[0], 3), round(a[-1], 3)],
+                     "a_series": [round(v, 3) for v in a], "sample_every": every,
+                     "mass_drift": (lat.mass() - m0) / m0, "steps": steps}
+        lat.close()
+        del lat
+        torch.cuda.empty_cache()
+    return out
+
+
 def hbm_storage_comparison(dev, stream, precisions, steps, warmup):
     """The storage forms on the HBM-bound bubble probe (gas bubble R = 64 in
     a liquid-filled periodic 512^3, LSQR): MLUPS and the stream-collide's
@@ -518,6 +574,9 @@ def main():
     ap.add_argument("--moving", type=int, nargs="*", metavar="N",
                     help="moving-frame bubble at dx = 1/N (default 48 96) instead of the bench")
     ap.add_argument("--models", default="fd,lsqr")
+    ap.add_argument("--oscillation", type=int, default=0, metavar="STEPS",
+                    help="oscillating 512^3 droplet for STEPS steps per storage form instead of the bench")
+    ap.add_argument("--osc-precisions", default="f64,f32,f16,bf16")
     ap.add_argument("--sessile", type=int, nargs="*", metavar="N",
                     help="equilibrium sessile droplets at dx = 1/N (default 48 96 144) instead of the bench")
     ap.add_argument("--eps-c", type=float, default=None,
@@ -549,6 +608,9 @@ def main():
     if args.laplace is not None:
         res = args.laplace or [48, 96]
         print(json.dumps({"laplace": laplace_table(dev, res, args.laplace_steps, models, eps_c=args.eps_c)}))
+        return
+    if args.oscillation > 0:
+        print(json.dumps({"oscillation": oscillation_table(dev, args.osc_precisions.split(","), args.oscillation)}))
         return
     if args.sessile is not None:
         res = args.sessile or [48, 96, 144]
