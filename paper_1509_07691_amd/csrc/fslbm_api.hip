@@ -246,7 +246,10 @@ inline int cell_blocks(int N) { return (N + 255) / 256; }
 inline int list_blocks(int N) { return std::min(LIST_GRID, std::max(1, (N + 255) / 256)); }
 inline int cmp_blocks(int N) { return std::min(CMP_GRID, (N + CMP_CELLS - 1) / CMP_CELLS); }
 constexpr int GEOM_GRID = 1024;  // blocks per lattice of the tiled geometry kernels
-constexpr int SC_GRID = 1024;  // blocks per lattice of the bulk stream-collide
+#ifndef FSLBM_SC_GRID
+#define FSLBM_SC_GRID 1024
+#endif
+constexpr int SC_GRID = FSLBM_SC_GRID;  // blocks per lattice of the bulk stream-collide
 
 // ------------------------------------------------------ init kernels
 __global__ void k_fill_bytes(uint8_t *p, size_t n, uint8_t v)

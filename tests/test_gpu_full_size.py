@@ -6,6 +6,9 @@ times (batched lattices, one stream, merged stream-collide).
   each compared cell by cell with the FP64 oracle run on the whole lattice:
   identical cell types, fill level, pressure and velocity within the FP32
   bar (1e-5 relative).
+- Sessile droplet (hemisphere R = 48 on the wall of 256 x 256 x 128,
+  theta 60 / 90 / 120 deg): sampled cells, contact-line cells among them,
+  each against the oracle on the full-height 28 x 28 column around it.
 - 512^3 workloads (the ellipsoid of radii 96/80/80 and the gas bubble of
   radius 64): the state after 2 steps at sampled cells, each against the
   oracle run on the 28^3 block of the initial fill centred on the cell. One
@@ -67,7 +70,12 @@ def test_droplet_sweep_batch_fp32_vs_oracle(torch_dev):
 BLOCK = 28
 
 
-def sampled_parity(torch, fill, obst, prm, steps=2, n_if=16, n_liq=8, seed=0):
+def sampled_parity(torch, fill, obst, prm, steps=2, n_if=16, n_liq=8, seed=0, full_z=False, n_wall=0):
+    """Worst differences at sampled cells between the HIP path (FP32, whole
+    lattice) and the oracle on the block of the initial state around each
+    cell: BLOCK^3 with periodic wrap, or BLOCK x BLOCK columns over the
+    whole height when full_z (walls at k = 0 and k = nz - 1 then enter the
+    oracle as they are). n_wall of the interface picks touch a wall."""
     from paper_1509_07691_amd.fslbm import Lattice
 
     g = Lattice(fill, obst, precision="f32", **prm)
@@ -77,24 +85,33 @@ def sampled_parity(torch, fill, obst, prm, steps=2, n_if=16, n_liq=8, seed=0):
     g.close()
     torch.cuda.empty_cache()
     rng = np.random.default_rng(seed)
-    ifc = np.flatnonzero(flags0 == O.INTERFACE)
-    liq = np.flatnonzero(flags0 == O.LIQUID)
-    picks = list(rng.choice(ifc, n_if, replace=False)) + list(rng.choice(liq, n_liq, replace=False))
+    ifc = flags0 == O.INTERFACE
+    picks = []
+    if n_wall:
+        wall_ifc = ifc & (np.roll(flags0, 1, axis=0) == O.OBSTACLE)
+        picks += list(rng.choice(np.flatnonzero(wall_ifc), n_wall, replace=False))
+        ifc &= ~wall_ifc
+    picks += list(rng.choice(np.flatnonzero(ifc), n_if, replace=False))
+    picks += list(rng.choice(np.flatnonzero(flags0 == O.LIQUID), n_liq, replace=False))
     nz, ny, nx = fill.shape
     h = BLOCK // 2
+    model = O.CURV_FD if prm["curv_model"] == "fd" else O.CURV_LSQR
+    kw = {k: prm[k] for k in ("sigma", "tau", "theta") if k in prm}
     worst = {"fill": 0.0, "rho": 0.0, "u": 0.0}
     for c in picks:
         z, y, x = np.unravel_index(c, fill.shape)
-        zz = (np.arange(z - h, z + h) % nz)[:, None, None]
+        zz = (np.arange(nz) if full_z else np.arange(z - h, z + h) % nz)[:, None, None]
         yy = (np.arange(y - h, y + h) % ny)[None, :, None]
         xx = (np.arange(x - h, x + h) % nx)[None, None, :]
         sub = np.ascontiguousarray(fill[zz, yy, xx])
-        o = O.Oracle(sub, None, sigma=prm["sigma"], tau=prm["tau"],
-                     curv_model=O.CURV_FD if prm["curv_model"] == "fd" else O.CURV_LSQR)
+        sob = None if obst is None else np.ascontiguousarray(obst[zz, yy, xx])
+        o = O.Oracle(sub, sob, curv_model=model, **kw)
         o.step(steps)
-        worst["fill"] = max(worst["fill"], abs(o.fill()[h, h, h] - phi[z, y, x]))
-        worst["rho"] = max(worst["rho"], abs(o.density()[h, h, h] - rho[z, y, x]))
-        worst["u"] = max(worst["u"], np.abs(o.velocity()[:, h, h, h] - u[:, z, y, x]).max())
+        zc = z if full_z else h
+        worst["fill"] = max(worst["fill"], abs(o.fill()[zc, h, h] - phi[z, y, x]))
+        worst["rho"] = max(worst["rho"], abs(o.density()[zc, h, h] - rho[z, y, x]))
+        worst["u"] = max(worst["u"], np.abs(o.velocity()[:, zc, h, h] - u[:, z, y, x]).max())
+        del o
     return worst
 
 
@@ -108,4 +125,18 @@ def test_512_sampled_cells_vs_oracle_blocks(torch_dev, name):
         prm = dict(curv_model="lsqr", tau=0.8, sigma=1e-3)
     worst = sampled_parity(torch_dev, fill, obst, prm)
     print(name, worst)
+    assert worst["fill"] < 2e-6 and worst["rho"] < 2e-6 and worst["u"] < 1e-6, worst
+
+
+@pytest.mark.parametrize("theta_deg", [60.0, 90.0, 120.0])
+def test_sessile_256_sampled_columns_vs_oracle(torch_dev, theta_deg):
+    """Sessile droplet at its benchmark size: hemisphere R = 48 on the wall
+    of a 256 x 256 x 128 lattice, LSQR with the wetting condition, sigma
+    5e-4, tau 0.8. Sampled: 12 contact-line cells (interface cells on the
+    wall), 8 other interface cells and 4 liquid cells, each against the
+    oracle on its full-height 28 x 28 column."""
+    fill, obst = I.sessile_droplet(256, 256, 128, 48.0, noise=1e-6, seed=2)
+    prm = dict(curv_model="lsqr", tau=0.8, sigma=5e-4, theta=math.radians(theta_deg))
+    worst = sampled_parity(torch_dev, fill, obst, prm, n_if=8, n_liq=4, n_wall=12, full_z=True, seed=1)
+    print("sessile", theta_deg, worst)
     assert worst["fill"] < 2e-6 and worst["rho"] < 2e-6 and worst["u"] < 1e-6, worst
