@@ -269,7 +269,7 @@ __device__ inline void cell_adj(const Fields<P> &F, const Adj &A, const Params &
         const double s = double(cox * ww - cw * nwx) * cnx + double(coy * ww - cw * nwy) * cny +
                          double(coz * ww - cw * nwz) * cnz;
         rec[q] = (t == FL_GAS) || (t == FL_OBST && corner && s < 0.0);
-        const double vrec = feq<double>(q, rhob, ubx, uby, ubz, ubsq) + feq<double>(o, rhob, ubx, uby, ubz, ubsq) - fo[o];
+        const double vrec = feq_pair<double>(q, rhob, ubx, uby, ubz, ubsq) - fo[o];
         fin[q] = (t & FL_FLUID) ? pl[q] : (rec[q] ? vrec : fo[o]);
     }
     double fb[NQ], fob[NQ];

@@ -18,11 +18,33 @@
 
 namespace fslbm {
 
+// c_q . u over the non-zero components of c_q only (a product with a zero
+// component cannot be dropped by the compiler, and adding it would not
+// change the sum: the two forms agree bit for bit).
+template <class T>
+__device__ inline T cdot(int q, T ux, T uy, T uz)
+{
+    const int cx = dir_x(q), cy = dir_y(q), cz = dir_z(q);
+    T r = cx ? (cx > 0 ? ux : -ux) : T(0);
+    if (cy) r = cx ? (cy > 0 ? r + uy : r - uy) : (cy > 0 ? uy : -uy);
+    if (cz) r = (cx || cy) ? (cz > 0 ? r + uz : r - uz) : (cz > 0 ? uz : -uz);
+    return r;
+}
+
 template <class T>
 __device__ inline T feq(int q, T rho, T ux, T uy, T uz, T usq)
 {
-    const T cu = T(dir_x(q)) * ux + T(dir_y(q)) * uy + T(dir_z(q)) * uz;
+    const T cu = cdot<T>(q, ux, uy, uz);
     return weight<T>(q) * rho * (T(1) + T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq);
+}
+
+// f^eq_q + f^eq_qbar, the sum eq. reconstruct needs: the terms odd in c_q
+// cancel.
+template <class T>
+__device__ inline T feq_pair(int q, T rho, T ux, T uy, T uz, T usq)
+{
+    const T cu = cdot<T>(q, ux, uy, uz);
+    return T(2) * weight<T>(q) * rho * (T(1) + T(4.5) * cu * cu - T(1.5) * usq);
 }
 
 // Moments of 19 values: rho in fixed q order, momentum over the directions
@@ -189,11 +211,14 @@ __device__ inline void boundary_cell(const Fields<P> &F, const Params &prm, int 
     for (int q = 1; q < NQ; ++q) {
         const int o = opp(q);
         const uint8_t t = nt[q];
-        const int cox = -dir_x(q), coy = -dir_y(q), coz = -dir_z(q);
-        const int cw = cox * nwx + coy * nwy + coz * nwz;
-        const T s = T(cox * ww - cw * nwx) * cnx + T(coy * ww - cw * nwy) * cny + T(coz * ww - cw * nwz) * cnz;
-        const bool rec = (t == FL_GAS) || (t == FL_OBST && corner && s < T(0));
-        const T vrec = feq<T>(q, rhob, ubx, uby, ubz, ubsq) + feq<T>(o, rhob, ubx, uby, ubz, ubsq) - fo[o];
+        bool rec = t == FL_GAS;
+        if (corner && t == FL_OBST) {
+            const int cox = -dir_x(q), coy = -dir_y(q), coz = -dir_z(q);
+            const int cw = cox * nwx + coy * nwy + coz * nwz;
+            const T s = T(cox * ww - cw * nwx) * cnx + T(coy * ww - cw * nwy) * cny + T(coz * ww - cw * nwz) * cnz;
+            rec = s < T(0);
+        }
+        const T vrec = feq_pair<T>(q, rhob, ubx, uby, ubz, ubsq) - fo[o];
         fin[q] = (t & FL_FLUID) ? pl[q] : (rec ? vrec : fo[o]);
     }
     if constexpr (IS_IF) {
@@ -276,11 +301,14 @@ __device__ inline void fluid_cell(const Fields<P> &F, const Params &prm, int i, 
         for (int q = 1; q < NQ; ++q) {
             const int o = opp(q);
             const uint8_t t = nt[q];
-            const int cox = -dir_x(q), coy = -dir_y(q), coz = -dir_z(q);
-            const int cw = cox * nwx + coy * nwy + coz * nwz;
-            const T s = T(cox * ww - cw * nwx) * cnx + T(coy * ww - cw * nwy) * cny + T(coz * ww - cw * nwz) * cnz;
-            const bool rec = (t == FL_GAS) || (t == FL_OBST && corner && s < T(0));
-            const T vrec = feq<T>(q, rhob, ubx, uby, ubz, ubsq) + feq<T>(o, rhob, ubx, uby, ubz, ubsq) - fo[o];
+            bool rec = t == FL_GAS;
+            if (corner && t == FL_OBST) {
+                const int cox = -dir_x(q), coy = -dir_y(q), coz = -dir_z(q);
+                const int cw = cox * nwx + coy * nwy + coz * nwz;
+                const T s = T(cox * ww - cw * nwx) * cnx + T(coy * ww - cw * nwy) * cny + T(coz * ww - cw * nwz) * cnz;
+                rec = s < T(0);
+            }
+            const T vrec = feq_pair<T>(q, rhob, ubx, uby, ubz, ubsq) - fo[o];
             fin[q] = (t & FL_FLUID) ? fin[q] : (rec ? vrec : fo[o]);
         }
         if (is_if) {
