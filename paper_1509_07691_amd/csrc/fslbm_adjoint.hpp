@@ -253,7 +253,7 @@ __device__ inline void cell_adj(const Fields<P> &F, const Adj &A, const Params &
     double rb0, ubx, uby, ubz;
     moments(fo, rb0, ubx, uby, ubz);
     const double ubsq = ubx * ubx + uby * uby + ubz * ubz;
-    const double rhob = 3.0 * (prm.rho_gas / 3.0 + prm.sigma * Kc);
+    const double rhob = prm.rho_gas + 3.0 * prm.sigma * Kc;
     const bool corner = is_if && has_gas && (nwx | nwy | nwz) != 0;
     const int ww = nwx * nwx + nwy * nwy + nwz * nwz;
     double fin[NQ];

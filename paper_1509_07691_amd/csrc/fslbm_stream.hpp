@@ -48,7 +48,7 @@ __device__ inline T feq_pair(int q, T rho, T ux, T uy, T uz, T usq)
 }
 
 // Moments of 19 values: rho in fixed q order, momentum over the directions
-// with a non-zero component.
+// with a non-zero component, u = j (1 / rho).
 template <class T>
 __device__ inline void moments(const T (&f)[NQ], T &rho, T &ux, T &uy, T &uz)
 {
@@ -61,9 +61,10 @@ __device__ inline void moments(const T (&f)[NQ], T &rho, T &ux, T &uy, T &uz)
         if (dir_z(q)) jz += T(dir_z(q)) * f[q];
     }
     rho = r;
-    ux = jx / r;
-    uy = jy / r;
-    uz = jz / r;
+    const T ir = T(1) / r;
+    ux = jx * ir;
+    uy = jy * ir;
+    uz = jz * ir;
 }
 
 template <class T, int COLL>
@@ -74,8 +75,18 @@ __device__ inline void collide(T (&f)[NQ], const Params &p)
     const T usq = ux * ux + uy * uy + uz * uz;
     const T we = T(p.omega);
     if constexpr (COLL == 0) {
+        f[0] = f[0] - we * (f[0] - feq<T>(0, rho, ux, uy, uz, usq));
+        // each pair (q, qbar) shares the even part of f^eq: f^eq = a +- b
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) f[q] = f[q] - we * (f[q] - feq<T>(q, rho, ux, uy, uz, usq));
+        for (int q = 1; q < NQ; ++q) {
+            const int o = opp(q);
+            if (o < q) continue;
+            const T cu = cdot<T>(q, ux, uy, uz);
+            const T wr = weight<T>(q) * rho;
+            const T a = wr * (T(1) + T(4.5) * cu * cu - T(1.5) * usq), b = wr * (T(3) * cu);
+            f[q] = f[q] - we * (f[q] - (a + b));
+            f[o] = f[o] - we * (f[o] - (a - b));
+        }
     } else {
         const T wo = T(p.omega_odd);
         T g[NQ];
@@ -198,7 +209,7 @@ __device__ inline void boundary_cell(const Fields<P> &F, const Params &prm, int 
     T rb0, ubx, uby, ubz;
     moments(fo, rb0, ubx, uby, ubz);
     const T ubsq = ubx * ubx + uby * uby + ubz * ubz;
-    const T rhob = T(3) * (T(gas_density(prm, F.sc)) / T(3) + T(prm.sigma) * Kc);
+    const T rhob = T(gas_density(prm, F.sc)) + T(3) * T(prm.sigma) * Kc;
     // corner rule: the outgoing link c_o = -c_q takes the free-surface rule
     // when c_o . (P n) < 0, P the projection onto the wall plane; evaluated
     // as (P c_o) . n with P c_o |nw|^2 = c_o |nw|^2 - (c_o . nw) nw in exact
@@ -294,7 +305,7 @@ __device__ inline void fluid_cell(const Fields<P> &F, const Params &prm, int i, 
         T rb0, ubx, uby, ubz;
         moments(fo, rb0, ubx, uby, ubz);
         const T ubsq = ubx * ubx + uby * uby + ubz * ubz;
-        const T rhob = T(3) * (T(gas_density(prm, F.sc)) / T(3) + T(prm.sigma) * Kc);
+        const T rhob = T(gas_density(prm, F.sc)) + T(3) * T(prm.sigma) * Kc;
         const bool corner = is_if && has_gas && (nwx | nwy | nwz) != 0;
         const int ww = nwx * nwx + nwy * nwy + nwz * nwz;
 #pragma unroll
