@@ -39,7 +39,7 @@ def workload_runs(name):
     """List of (label, fill, obstacle, params) of one workload."""
     from paper_1509_07691_amd import inputs as I
 
-    if name == "c1":
+    if name == "droplet-sweep":
         fill, obst = I.droplet(128, 32.0, noise=1e-6, seed=0)
         runs = []
         for model in ("fd", "lsqr"):
@@ -50,11 +50,11 @@ def workload_runs(name):
         desc = ("static droplet R=32 in periodic 128^3, 8 runs (tau 0.6/1.0 x sigma 1e-4/1e-3 x FD/LSQR) "
                 "stepped together")
         return runs, desc
-    if name == "c3":
+    if name == "ellipsoid":
         fill, obst = I.ellipsoid_droplet(512, (96, 80, 80), noise=1e-6, seed=0)
         return [("ellipsoid", fill, obst, dict(curv_model="lsqr", tau=0.55, sigma=1e-3))], \
             "oscillating droplet, ellipsoid 96/80/80 in periodic 512^3, LSQR"
-    if name == "probe":
+    if name == "bubble-probe":
         fill, obst = I.bubble_probe(512, 64.0)
         return [("bubble", fill, obst, dict(curv_model="lsqr", tau=0.8, sigma=1e-3))], \
             "gas bubble R=64 in liquid-filled periodic 512^3, LSQR"
@@ -134,7 +134,7 @@ def cpu_baseline(runs, budget_s):
                       f"{el:.1f} s, FP64, single-threaded plain C"}
 
 
-def adjoint_cost(dev, stream, steps, K, precision):
+def adjoint_cost(dev, stream, steps, K, precision, fd_check=True):
     """Cost of the differentiation window (frozen cell types, checkpoints
     every K steps, hand-written adjoint) on a sessile drop: hemisphere R=24
     on the wall k=0 of a 128^3 lattice (walls k=0 and k=127, periodic x, y),
@@ -194,7 +194,7 @@ def adjoint_cost(dev, stream, steps, K, precision):
             "workspace_GB": round(ws_gb, 2),
             "note": "cost is valid; the 128^3 gradient values are not: interface fills leave (0, 1) in the frozen "
                     "window and the loss is not smooth there; fd_check verifies the gradients on the downscale",
-            "fd_check": adjoint_fd_check(dev, 64, 12.0, steps, K)}
+            "fd_check": adjoint_fd_check(dev, 64, 12.0, steps, K) if fd_check else None}
 
 
 def adjoint_fd_check(dev, n, R, steps, K):
@@ -512,7 +512,7 @@ def oscillation_table(dev, precisions, steps, every=500):
     import torch
     from paper_1509_07691_amd.fslbm import Lattice
 
-    (label, fill, obst, p), = workload_runs("c3")[0]
+    (label, fill, obst, p), = workload_runs("ellipsoid")[0]
     nz, ny, nx = fill.shape
     x = torch.arange(nx, dtype=torch.float64, device=dev) + 0.5
     R = (96.0 * 80.0 * 80.0) ** (1.0 / 3.0)
@@ -564,7 +564,7 @@ def hbm_storage_comparison(dev, stream, precisions, steps, warmup):
     import torch
     from paper_1509_07691_amd.fslbm import Lattice
 
-    (label, fill, obst, p), = workload_runs("probe")[0]
+    (label, fill, obst, p), = workload_runs("bubble-probe")[0]
     out = {}
     for prec in precisions:
         with torch.cuda.stream(stream):
@@ -598,7 +598,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="c1", choices=["c1", "c3", "probe"])
+    ap.add_argument("--workload", default="droplet-sweep", choices=["droplet-sweep", "ellipsoid", "bubble-probe"])
     ap.add_argument("--precision", default="f32", choices=["f64", "f32", "f16", "bf16"])
     ap.add_argument("--graph", type=int, default=1,
                     help="also time a graph-replay pass after the timed region")
@@ -614,6 +614,8 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=2000,
                     help="steps of the differentiation window timed for the adjoint cost (0: skip)")
     ap.add_argument("--adjoint-k", type=int, default=100, help="checkpoint interval of that window")
+    ap.add_argument("--adjoint-fd-check", type=int, default=1,
+                    help="0: skip the difference check of the adjoint on the 64^3 downscale")
     ap.add_argument("--advection", action="store_true",
                     help="only run the pure advection test table (d = 10..80) and print it")
     ap.add_argument("--laplace", type=int, nargs="*", metavar="N",
@@ -793,12 +795,13 @@ def main():
 
     hbm_compare = None
     hprec = [p for p in args.hbm_compare.split(",") if p]
-    if hprec and args.workload != "probe":
+    if hprec and args.workload != "bubble-probe":
         hbm_compare = hbm_storage_comparison(dev, stream, hprec, steps=10, warmup=3)
 
     adjoint = None
     if args.adjoint_steps > 0:
-        adjoint = adjoint_cost(dev, stream, args.adjoint_steps, args.adjoint_k, args.precision)
+        adjoint = adjoint_cost(dev, stream, args.adjoint_steps, args.adjoint_k, args.precision,
+                               fd_check=bool(args.adjoint_fd_check))
         print(f"# adjoint window done: {adjoint['cost_ratio']}x forward", file=sys.stderr, flush=True)
 
     res = {

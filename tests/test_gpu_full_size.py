@@ -42,7 +42,7 @@ def test_droplet_sweep_batch_fp32_vs_oracle(torch_dev):
     import bench
     from paper_1509_07691_amd.fslbm import Batch, Lattice
 
-    runs, _ = bench.workload_runs("c1")
+    runs, _ = bench.workload_runs("droplet-sweep")
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         lats = [Lattice(fill, obst, precision="f32", stream=stream, **p) for _, fill, obst, p in runs]
