@@ -73,14 +73,18 @@ def sc_bytes(flags, prec):
     return 38 * FBYTES[prec] * nl + n, ni * (38 * FBYTES[prec] + 5 * RBYTES[prec] + 1), nl, ni
 
 
-def stored_traffic():
+def stored_traffic(workload, precision):
+    """The counted traffic record if it was taken on this workload and
+    storage precision with the current stream-collide sources, else None."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     try:
         rec = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
-    return rec if rec.get("source_sha256") == stream_source_hash() else None
+    same = (rec.get("source_sha256") == stream_source_hash() and rec.get("workload") == workload
+            and rec.get("precision", "f32") == precision)
+    return rec if same else None
 
 
 def stream_source_hash():
@@ -90,7 +94,7 @@ def stream_source_hash():
     return h.hexdigest()
 
 
-def traffic_from_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, workload_note):
+def traffic_from_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, workload_note, precision):
     """HBM bytes per stream-collide launch from rocprofv3 FETCH_SIZE and
     WRITE_SIZE (KiB per dispatch), each scaled by what the same counter reads
     for a plain copy of 2^28 floats (1 GiB read, 1 GiB written)."""
@@ -106,7 +110,7 @@ def traffic_from_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, 
     cw_kib, _ = mean_kib(copy_write_csv, "AUnaryFunctor")
     gib_kib = (4 << 28) / 1024.0
     f_scale, w_scale = gib_kib / cf_kib, gib_kib / cw_kib
-    rec = {"source_sha256": stream_source_hash(), "workload": workload_note,
+    rec = {"source_sha256": stream_source_hash(), "workload": workload_note, "precision": precision,
            "fetch_kib_per_launch": f_kib, "write_kib_per_launch": w_kib, "dispatches": [nf, nw],
            "copy_fetch_kib": cf_kib, "copy_write_kib": cw_kib, "fetch_scale": f_scale, "write_scale": w_scale,
            "bytes_per_launch": int(1024 * (f_kib * f_scale + w_kib * w_scale))}
@@ -637,7 +641,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
     if args.traffic_from:
-        rec = traffic_from_counters(*args.traffic_from, workload_note=args.workload)
+        rec = traffic_from_counters(*args.traffic_from, workload_note=args.workload, precision=args.precision)
         with open(TRAFFIC_FILE, "w") as fh:
             json.dump(rec, fh, indent=1)
         print(json.dumps(rec))
@@ -739,7 +743,7 @@ def main():
     achieved = sc_bytes_launch * args.steps / (sc_ms * 1e-3) / 1e9
     if_achieved = bytes_if * args.steps / (phase[1] * 1e-3) / 1e9 if args.split else None
     mlups = ncell * args.steps / el / 1e6
-    traffic = stored_traffic()
+    traffic = stored_traffic(args.workload, args.precision)
 
     # the same number of steps replayed from HIP graphs, untimed per kernel
     graph_ms = None
