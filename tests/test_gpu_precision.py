@@ -19,9 +19,9 @@ pytestmark = pytest.mark.gpu
 
 STEPS = 100
 PRM = dict(sigma=1e-3, tau=0.55)
-# about ten times the errors measured on MI355X (FP32 fill 7.8e-6, velocity
-# 6.7e-6, mass drift 2.9e-6; F16 2.2e-5, 1.4e-5, 9.3e-6; BF16 5.3e-5,
-# 2.7e-5, 2.3e-5 with 5e-7 of the cells typed differently)
+# about ten times the errors measured on MI355X (FP32 fill 7.9e-6, velocity
+# 7.7e-6, mass drift 2.8e-6; F16 2.2e-5, 1.0e-5, 9.3e-6; BF16 5.4e-5,
+# 2.3e-5, 2.3e-5; up to 5e-7 of the cells typed differently in BF16)
 BARS = {"f32": dict(fill=1e-4, vel=1e-4, flags=1e-5, mass=3e-5),
         "f16": dict(fill=3e-4, vel=2e-4, flags=1e-5, mass=1e-4),
         "bf16": dict(fill=6e-4, vel=3e-4, flags=1e-5, mass=3e-4)}
