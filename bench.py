@@ -35,12 +35,15 @@ FBYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
 RBYTES = {"f64": 8, "f32": 4, "f16": 4, "bf16": 4}
 
 
+SWEEP_RADIUS = 32.0  # droplet of the droplet sweep
+
+
 def workload_runs(name):
     """List of (label, fill, obstacle, params) of one workload."""
     from paper_1509_07691_amd import inputs as I
 
     if name == "droplet-sweep":
-        fill, obst = I.droplet(128, 32.0, noise=1e-6, seed=0)
+        fill, obst = I.droplet(128, SWEEP_RADIUS, noise=1e-6, seed=0)
         runs = []
         for model in ("fd", "lsqr"):
             for tau in (0.6, 1.0):
@@ -618,6 +621,8 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=2000,
                     help="steps of the differentiation window timed for the adjoint cost (0: skip)")
     ap.add_argument("--adjoint-k", type=int, default=100, help="checkpoint interval of that window")
+    ap.add_argument("--diag-steps", type=int, default=5000,
+                    help="droplet sweep: spurious currents and Laplace law of each run after this many steps (0: skip)")
     ap.add_argument("--adjoint-fd-check", type=int, default=1,
                     help="0: skip the difference check of the adjoint on the 64^3 downscale")
     ap.add_argument("--advection", action="store_true",
@@ -756,6 +761,21 @@ def main():
         torch.cuda.synchronize()
         graph_ms = 1e3 * (time.perf_counter() - t0) / args.steps
         batch.set_graph(False)
+    # spurious currents and the Laplace law of each run after diag_steps
+    # steps in all (device reductions, outside every timed region)
+    sweep_diag = None
+    if args.workload == "droplet-sweep" and args.diag_steps > 0:
+        more = args.diag_steps - lats[0].steps_taken()
+        if more > 0:
+            batch.step(more)
+        torch.cuda.synchronize()
+        sweep_diag = []
+        for (label, _, _, p), lat in zip(runs, lats):
+            d = lat.diagnostics()
+            dpl = 2.0 * p["sigma"] / SWEEP_RADIUS
+            sweep_diag.append({"run": label, "steps": lat.steps_taken(), "max_u": d["max_u"],
+                               "mean_u": d["mean_u"], "dp": d["dp"], "dp_laplace": dpl,
+                               "dp_rel_err": round((d["dp"] - dpl) / dpl, 5), "n_inner": d["n_inner"]})
     nlat = len(lats)
     batch.close()
     for lat in lats:
@@ -844,6 +864,8 @@ def main():
     if graph_ms is not None:
         res["graph_replay"] = {"ms_per_step": round(graph_ms, 4),
                                "mlups": round(ncell / graph_ms / 1e3, 1)}
+    if sweep_diag is not None:
+        res["sweep_diagnostics"] = sweep_diag
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(runs, args.cpu_seconds)
     if compare:

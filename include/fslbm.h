@@ -167,6 +167,23 @@ int fslbm_gas_density(fslbm_t h, double *rho_gas);
 /* Total mass: sum of rho over liquid cells + sum of m over interface cells +
  * excess mass that found no receiving cell; FP64, fixed summation order. */
 int fslbm_mass(fslbm_t h, double *total);
+/* Diagnostics of the current state: the measures of the paper's
+ * equilibrium tests (spurious currents, Laplace law; Sec. III.A.1). FP64
+ * device reductions over a fixed partition of the cells in a fixed order, so
+ * that calls on the same state agree bit for bit. out is a host array of 4
+ * doubles:
+ *   out[0]  max |u| over the fluid (liquid and interface) cells,
+ *   out[1]  mean |u| over the fluid cells (0 if there are none),
+ *   out[2]  the pressure jump (rho_in - rho_gas(t)) / 3, rho_in the mean
+ *           density of the inner liquid cells: liquid cells with no gas or
+ *           interface cell within a Euclidean distance of 2.5 cells
+ *           (periodic). 2 sigma / R for a droplet at equilibrium, minus
+ *           that for a bubble; 0 if there are no inner cells,
+ *   out[3]  the number of inner liquid cells.
+ * u = j / rho as in fslbm_read_velocity. Uses the lattice's reduction
+ * scratch (inside its workspace) and synchronises the stream. FSLBM_E_ARG
+ * if out is NULL. */
+int fslbm_diagnostics(fslbm_t h, double *out);
 /* FSLBM_E_NUMERIC if any fluid cell has a non-finite or non-positive
  * density, else 0. Synchronises. */
 int fslbm_check_numeric(fslbm_t h);

@@ -62,6 +62,7 @@ struct Layout {
 };
 
 constexpr int MASS_BLOCKS = 1024;
+constexpr int DIAG_VALUES = 5;  // partial sums per block of the diagnostics
 
 Layout make_layout(int nx, int ny, int nz, int prec)
 {
@@ -97,7 +98,7 @@ Layout make_layout(int nx, int ny, int nz, int prec)
     L.ilist_tmp = take(4 * N);
     L.staging = take(8 * N);
     L.counts = take(4 * (size_t)CMP_GRID);  // one count per compaction block (fixed grid)
-    L.part = take(8 * MASS_BLOCKS);
+    L.part = take(8 * (DIAG_VALUES * MASS_BLOCKS + 8));  // mass, bubble volume and diagnostics partials
     L.sc = take(sizeof(DevScalars));
     L.total = off;
     return L;
@@ -541,6 +542,88 @@ __global__ __launch_bounds__(1024) void k_mass_final(const double *part, DevScal
     if (threadIdx.x == 0) sc->mass = s[0] + sc->reservoir;
 }
 
+// Diagnostics (the measures of Sec. III.A.1: spurious currents and the
+// pressure jump), over the same fixed partition and with fixed trees like
+// the mass. Per block: max |u| and sum |u| over the fluid cells, their
+// count, and the density sum and count of the inner liquid cells, those with
+// no gas or interface cell within a Euclidean distance of 2.5 cells
+// (periodic). part holds DIAG_VALUES rows of MASS_BLOCKS entries.
+template <class P>
+__device__ inline bool near_surface(const Fields<P> &F, int i)
+{
+    const int yz = i / F.nx, x = i - yz * F.nx, z = yz / F.ny, y = yz - z * F.ny;
+    for (int dz = -2; dz <= 2; ++dz)
+        for (int dy = -2; dy <= 2; ++dy) {
+            const int row = F.nx * (wrap_any(y + dy, F.ny) + F.ny * wrap_any(z + dz, F.nz));
+            for (int dx = -2; dx <= 2; ++dx) {
+                if (dx * dx + dy * dy + dz * dz > 6) continue;
+                const uint8_t t = F.flags[row + wrap_any(x + dx, F.nx)] & FL_TYPE;
+                if (t == FL_GAS || t == FL_IF) return true;
+            }
+        }
+    return false;
+}
+
+template <class P>
+__global__ __launch_bounds__(256) void k_diag_partial(Fields<P> F, double *part)
+{
+    using T = typename P::T;
+    __shared__ double s[DIAG_VALUES][256];
+    const int chunk = (F.N + MASS_BLOCKS - 1) / MASS_BLOCKS;
+    const int b0 = blockIdx.x * chunk, b1 = min(F.N, b0 + chunk);
+    double umax = 0.0, usum = 0.0, nfl = 0.0, rsum = 0.0, nin = 0.0;
+    for (int i = b0 + threadIdx.x; i < b1; i += 256) {
+        const uint8_t fl = F.flags[i];
+        if (!(fl & FL_FLUID)) continue;
+        T f[NQ];
+        load_all(F, i, f);
+        T r, ux, uy, uz;
+        moments(f, r, ux, uy, uz);
+        const double a = double(ux), b = double(uy), c = double(uz);
+        const double sp = sqrt(a * a + b * b + c * c);
+        umax = fmax(umax, sp);
+        usum += sp;
+        nfl += 1.0;
+        if ((fl & FL_TYPE) == FL_LIQ && !near_surface(F, i)) {
+            rsum += double(r);
+            nin += 1.0;
+        }
+    }
+    s[0][threadIdx.x] = umax;
+    s[1][threadIdx.x] = usum;
+    s[2][threadIdx.x] = nfl;
+    s[3][threadIdx.x] = rsum;
+    s[4][threadIdx.x] = nin;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            s[0][threadIdx.x] = fmax(s[0][threadIdx.x], s[0][threadIdx.x + w]);
+            for (int v = 1; v < DIAG_VALUES; ++v) s[v][threadIdx.x] += s[v][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < DIAG_VALUES) part[threadIdx.x * MASS_BLOCKS + blockIdx.x] = s[threadIdx.x][0];
+}
+
+// One block: the block values in a fixed tree, then the results and the
+// current gas density after the partial rows.
+__global__ __launch_bounds__(1024) void k_diag_final(double *part, const DevScalars *sc)
+{
+    __shared__ double s[DIAG_VALUES][1024];
+    for (int v = 0; v < DIAG_VALUES; ++v)
+        s[v][threadIdx.x] = threadIdx.x < MASS_BLOCKS ? part[v * MASS_BLOCKS + threadIdx.x] : 0.0;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            s[0][threadIdx.x] = fmax(s[0][threadIdx.x], s[0][threadIdx.x + w]);
+            for (int v = 1; v < DIAG_VALUES; ++v) s[v][threadIdx.x] += s[v][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < DIAG_VALUES) part[DIAG_VALUES * MASS_BLOCKS + threadIdx.x] = s[threadIdx.x][0];
+    if (threadIdx.x == 0) part[DIAG_VALUES * MASS_BLOCKS + DIAG_VALUES] = sc->rho_gas_t;
+}
+
 template <class P>
 __global__ void k_check_numeric(Fields<P> F)
 {
@@ -885,6 +968,25 @@ int do_mass(fslbm_lattice *h, double *total)
     HIP_OK(hipGetLastError());
     HIP_OK(hipMemcpyAsync(total, &F.sc->mass, sizeof(double), hipMemcpyDeviceToHost, h->stream));
     HIP_OK(hipStreamSynchronize(h->stream));
+    return 0;
+}
+
+template <class P>
+int do_diagnostics(fslbm_lattice *h, double *out)
+{
+    const Fields<P> F = make_fields<P>(h);
+    double *part = (double *)(h->ws + h->L.part);
+    k_diag_partial<P><<<MASS_BLOCKS, 256, 0, h->stream>>>(F, part);
+    k_diag_final<<<1, 1024, 0, h->stream>>>(part, F.sc);
+    HIP_OK(hipGetLastError());
+    double v[DIAG_VALUES + 1];
+    HIP_OK(hipMemcpyAsync(v, part + DIAG_VALUES * MASS_BLOCKS, sizeof(v), hipMemcpyDeviceToHost, h->stream));
+    HIP_OK(hipStreamSynchronize(h->stream));
+    const double rho_gas = h->bubble ? v[DIAG_VALUES] : h->rho_gas;
+    out[0] = v[0];
+    out[1] = v[2] > 0.0 ? v[1] / v[2] : 0.0;
+    out[2] = v[4] > 0.0 ? (v[3] / v[4] - rho_gas) / 3.0 : 0.0;
+    out[3] = v[4];
     return 0;
 }
 
@@ -1281,6 +1383,7 @@ int batch_step(fslbm_batch *b, int64_t nsteps)
 template <class P> struct OpRead { static int run(fslbm_lattice *h, int w, double *o, int d) { return do_read<P>(h, w, o, d); } };
 template <class P> struct OpMass { static int run(fslbm_lattice *h, double *t) { return do_mass<P>(h, t); } };
 template <class P> struct OpCheck { static int run(fslbm_lattice *h) { return do_check<P>(h); } };
+template <class P> struct OpDiag { static int run(fslbm_lattice *h, double *o) { return do_diagnostics<P>(h, o); } };
 template <class P> struct OpEq { static int run(fslbm_lattice *h, const double *r, const double *u) { return do_set_equilibrium<P>(h, r, u); } };
 
 __global__ void k_bubble_arm(DevScalars *sc) { sc->bubble_init = 1; }
@@ -1604,6 +1707,13 @@ int fslbm_mass(fslbm_t h, double *total)
     if (!h) return fail(FSLBM_E_STATE, "null handle");
     if (!total) return fail(FSLBM_E_ARG, "total is NULL");
     return dispatch<OpMass>(h, total);
+}
+
+int fslbm_diagnostics(fslbm_t h, double *out)
+{
+    if (!h) return fail(FSLBM_E_STATE, "null handle");
+    if (!out) return fail(FSLBM_E_ARG, "out is NULL");
+    return dispatch<OpDiag>(h, out);
 }
 
 int fslbm_check_numeric(fslbm_t h)

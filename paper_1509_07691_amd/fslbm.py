@@ -71,6 +71,7 @@ def load_library(path: str = LIB_PATH):
         "fslbm_mass": [vp, dp],
         "fslbm_gas_density": [vp, dp],
         "fslbm_check_numeric": [vp],
+        "fslbm_diagnostics": [vp, dp],
         "fslbm_steps_taken": [vp, ctypes.POINTER(i64)],
         "fslbm_read_timing": [vp, dp, ctypes.POINTER(i64)],
         "fslbm_reset_timing": [vp],
@@ -218,6 +219,13 @@ def fslbm_mass(h):
 
 def fslbm_check_numeric(h):
     _check(load_library().fslbm_check_numeric(h))
+
+
+def fslbm_diagnostics(h):
+    """(max |u|, mean |u| over fluid cells, pressure jump, inner liquid cells)."""
+    out = (ctypes.c_double * 4)()
+    _check(load_library().fslbm_diagnostics(h, out))
+    return out[0], out[1], out[2], int(out[3])
 
 
 def fslbm_steps_taken(h):
@@ -431,6 +439,12 @@ class Lattice:
 
     def check_numeric(self):
         fslbm_check_numeric(self._h)
+
+    def diagnostics(self):
+        """max_u, mean_u (fluid cells), dp (inner liquid minus gas pressure)
+        and n_inner, from device reductions."""
+        u_max, u_mean, dp, n_inner = fslbm_diagnostics(self._h)
+        return {"max_u": u_max, "mean_u": u_mean, "dp": dp, "n_inner": n_inner}
 
     def steps_taken(self):
         return fslbm_steps_taken(self._h)

@@ -293,3 +293,60 @@ def test_tr_curvature_fp32(Lattice):
     g.step(50)
     o.step(50)
     compare(g, o, 1e-5, exact_flags=False, what="tr f32", vscale=1e-3 / (0.5 / 3.0))
+
+
+def _diagnostics_reference(o, rho_gas):
+    """The diagnostics written out on the oracle's fields: |u| over the fluid
+    cells, and the pressure jump over the liquid cells with no gas or
+    interface cell within a Euclidean distance of 2.5 cells (periodic)."""
+    fl, u, rho = o.flags(), o.velocity(), o.density()
+    fluid = (fl == O.LIQUID) | (fl == O.INTERFACE)
+    speed = np.sqrt((u ** 2).sum(0))[fluid]
+    surface = (fl == O.GAS) | (fl == O.INTERFACE)
+    near = np.zeros_like(surface)
+    for dz in range(-2, 3):
+        for dy in range(-2, 3):
+            for dx in range(-2, 3):
+                if dx * dx + dy * dy + dz * dz <= 6:
+                    near |= np.roll(surface, (dz, dy, dx), axis=(0, 1, 2))
+    inner = (fl == O.LIQUID) & ~near
+    dp = (rho[inner].mean() - rho_gas) / 3.0 if inner.any() else 0.0
+    return speed.max(), speed.mean(), dp, int(inner.sum())
+
+
+@pytest.mark.parametrize("case", ["droplet_fd_f64", "bubble_lsqr_f64", "droplet_lsqr_f32"])
+def test_diagnostics_vs_oracle(Lattice, case):
+    """fslbm_diagnostics (device FP64 reductions) against the same measures
+    taken on the oracle's fields: the static droplet of the Laplace test
+    (a positive jump near 2 sigma / R), and the wall-bounded bubble with the
+    bubble model (a negative jump against the current gas density)."""
+    if case.startswith("bubble"):
+        fill, obst = I.laplace_bubble(32)
+        kw = dict(sigma=1e-3, tau=0.8, bubble=True)
+        steps, uscale = 150, 1e-3 / (0.3 / 3.0)
+    else:
+        fill, obst = I.droplet(32, 8.0, noise=1e-6, seed=0)
+        kw = dict(sigma=1e-3, tau=1.0)
+        steps, uscale = 150, 1e-3 / (0.5 / 3.0)
+    model = case.split("_")[1]
+    precision = case.split("_")[2]
+    tol = 1e-10 if precision == "f64" else 1e-5
+    g, o = pair(Lattice, fill, obst, model, precision=precision, **kw)
+    g.step(steps)
+    o.step(steps)
+    d = g.diagnostics()
+    u_max, u_mean, dp, n_inner = _diagnostics_reference(o, o.gas_density())
+    print(case, d, (u_max, u_mean, dp, n_inner))
+    assert d["n_inner"] == n_inner > 0
+    assert abs(d["max_u"] - u_max) <= tol * max(u_max, uscale)
+    assert abs(d["mean_u"] - u_mean) <= tol * max(u_mean, uscale)
+    # the jump is a difference of two pressures near 1/3: its bar is the
+    # pressure bar
+    assert abs(d["dp"] - dp) <= tol * max(abs(dp), o.gas_density() / 3.0)
+    assert (dp > 0) == case.startswith("droplet")
+    if precision == "f64":
+        # the reduction's max is the max over the library's own read-out
+        ug = g.velocity()
+        fl = g.flags()
+        fluid = (fl == O.LIQUID) | (fl == O.INTERFACE)
+        assert d["max_u"] == np.sqrt((ug ** 2).sum(0))[fluid].max()
