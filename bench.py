@@ -469,6 +469,32 @@ def sessile_measures(lat, n, h, r):
     return hs / h - 1.0, l2, float(rt.std()) / r, float(np.degrees(2 * np.arctan(hs / rs)))
 
 
+def sessile_contact_angles(dev, steps, thetas=(60.0, 90.0, 120.0)):
+    """Sessile droplet on a no-slip wall: hemisphere R = 48 on the wall of a
+    256 x 256 x 128 lattice (walls k = 0 and 127), LSQR with the wetting
+    condition, sigma 5e-4, tau 0.8, FP32, per prescribed angle theta:
+    the apparent angle 2 atan(h*/r*) after `steps` steps, and the height
+    against the spherical cap of angle theta with the hemisphere's volume."""
+    from paper_1509_07691_amd import inputs as I
+    from paper_1509_07691_amd.fslbm import Lattice
+
+    R = 48.0
+    fill, obst = I.sessile_droplet(256, 256, 128, R, noise=1e-6, seed=2)
+    rows = []
+    for th in thetas:
+        c = math.cos(math.radians(th))
+        rc = R * (2.0 / (2.0 - 3.0 * c + c ** 3)) ** (1.0 / 3.0)  # equal-volume cap
+        h, r = rc * (1.0 - c), rc * math.sin(math.radians(th))
+        lat = Lattice(fill, obst, precision="f32", device=dev, curv_model="lsqr", sigma=5e-4, tau=0.8,
+                      theta=math.radians(th))
+        lat.step(steps)
+        dh, l2r, _, ang = sessile_measures(lat, 256, h, r)
+        rows.append({"theta": th, "steps": steps, "measured_deg": round(ang, 2),
+                     "error_deg": round(ang - th, 2), "h_rel_err": round(dh, 4), "L2_r": round(l2r, 4)})
+        lat.close()
+    return rows
+
+
 def sessile_table(dev, resolutions, models, thetas, eps_c=None, t_phys=2.0):
     """Equilibrium sessile droplets of Sec. III.B.1: the ideal spherical cap
     of each contact angle (hemisphere volume, R = 0.125) on the wall of the
@@ -621,6 +647,8 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=2000,
                     help="steps of the differentiation window timed for the adjoint cost (0: skip)")
     ap.add_argument("--adjoint-k", type=int, default=100, help="checkpoint interval of that window")
+    ap.add_argument("--sessile-steps", type=int, default=20000,
+                    help="sessile droplet 256x256x128 at 60/90/120 deg: apparent angle after this many steps (0: skip)")
     ap.add_argument("--diag-steps", type=int, default=5000,
                     help="droplet sweep: spurious currents and Laplace law of each run after this many steps (0: skip)")
     ap.add_argument("--adjoint-fd-check", type=int, default=1,
@@ -866,6 +894,9 @@ def main():
                                "mlups": round(ncell / graph_ms / 1e3, 1)}
     if sweep_diag is not None:
         res["sweep_diagnostics"] = sweep_diag
+    if args.workload == "droplet-sweep" and args.sessile_steps > 0:
+        res["sessile_contact_angles"] = sessile_contact_angles(dev, args.sessile_steps)
+        print("# sessile contact angles done", file=sys.stderr, flush=True)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(runs, args.cpu_seconds)
     if compare:
