@@ -26,6 +26,7 @@ FSLBM_GAS, FSLBM_LIQUID, FSLBM_INTERFACE, FSLBM_OBSTACLE = 0, 1, 2, 3
 FSLBM_OPT_EPS_C, FSLBM_OPT_COLLISION, FSLBM_OPT_TRT_MAGIC, FSLBM_OPT_TIMING, FSLBM_OPT_GRAPH = 0, 1, 2, 3, 4
 FSLBM_OPT_SPLIT_INTERFACE = 5
 FSLBM_OPT_BUBBLE = 6
+FSLBM_OK, FSLBM_E_ARG, FSLBM_E_SHAPE, FSLBM_E_HIP, FSLBM_E_STATE, FSLBM_E_NUMERIC = 0, -1, -2, -3, -4, -5
 
 PRECISIONS = {"f64": FSLBM_F64, "f32": FSLBM_F32, "f16": FSLBM_F16_STORE, "bf16": FSLBM_BF16_STORE}
 MODELS = {"fd": FSLBM_CURV_FD, "lsqr": FSLBM_CURV_LSQR, "tr": FSLBM_CURV_TR}
