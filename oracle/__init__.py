@@ -15,6 +15,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle_fslbm.so")
 _SRC = os.path.join(_HERE, "fslbm_oracle.c")
+TL_LIB_PATH = os.path.join(_HERE, "liboracle_fslbm_tl.so")
+_TL_SRCS = [os.path.join(_HERE, f) for f in ("fslbm_oracle_tl.cpp", "fslbm_dual.hpp", "fslbm_oracle.c")]
 
 GAS, LIQUID, INTERFACE, OBSTACLE = 0, 1, 2, 3
 CURV_FD, CURV_LSQR, CURV_TR = 0, 1, 2
@@ -28,7 +30,18 @@ def build(verbose: bool = False) -> str:
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
+    build_tl(verbose)
     return LIB_PATH
+
+
+def build_tl(verbose: bool = False) -> str:
+    """Compile the tangent-linear build (the same source with dual numbers)."""
+    cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off", "-Wall", "-Wno-unused-function",
+           "-I", _HERE, _TL_SRCS[0], "-o", TL_LIB_PATH]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    return TL_LIB_PATH
 
 
 class _Params(ctypes.Structure):
@@ -219,3 +232,68 @@ class Oracle:
         out = np.zeros(max(c, 1), dtype=np.int32)
         lib().orc_interface_list(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
         return out[:c]
+
+
+_tl = None
+
+
+def tl_lib():
+    global _tl
+    if _tl is None:
+        if not os.path.exists(TL_LIB_PATH) or os.path.getmtime(TL_LIB_PATH) < max(map(os.path.getmtime, _TL_SRCS)):
+            build_tl()
+        L = ctypes.CDLL(TL_LIB_PATH)
+        dp = ctypes.POINTER(ctypes.c_double)
+        vp = ctypes.c_void_p
+        d, i = ctypes.c_double, ctypes.c_int
+        L.orc_tl_create.restype = vp
+        L.orc_tl_create.argtypes = [i, i, i, dp, dp, ctypes.POINTER(ctypes.c_ubyte), d, d, d, d, d, d, d, i, i, d]
+        L.orc_tl_set_equilibrium.argtypes = [vp, dp, dp]
+        L.orc_tl_step.argtypes = [vp, ctypes.c_long]
+        L.orc_tl_get_fill.argtypes = [vp, dp, dp]
+        L.orc_tl_destroy.argtypes = [vp]
+        _tl = L
+    return _tl
+
+
+class TangentLinear:
+    """The frozen-type oracle (FD curvature) in tangent-linear mode: the
+    value of phi and its derivative along one direction of (sigma, theta,
+    phi_0), given by the seeds dsigma, dtheta and fill_dot (the last on the
+    initial fill levels). Arrays are (nz, ny, nx), x fastest."""
+
+    def __init__(self, fill, obstacle=None, *, fill_dot=None, dsigma=0.0, dtheta=0.0, sigma=0.0, tau=1.0,
+                 theta=np.pi / 2, rho_gas=1.0, eps_c=1e-3, collision=SRT, trt_magic=3.0 / 16.0):
+        fill = np.ascontiguousarray(fill, dtype=np.float64)
+        self.shape = fill.shape
+        nz, ny, nx = fill.shape
+        self.n = fill.size
+        if obstacle is None:
+            obstacle = np.zeros(fill.shape, dtype=np.uint8)
+        obstacle = np.ascontiguousarray(obstacle, dtype=np.uint8)
+        dot = None if fill_dot is None else np.ascontiguousarray(fill_dot, dtype=np.float64)
+        h = tl_lib().orc_tl_create(nx, ny, nz, _dptr(fill), None if dot is None else _dptr(dot),
+                                   obstacle.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte)), sigma, dsigma, tau,
+                                   theta, dtheta, rho_gas, eps_c, CURV_FD, collision, trt_magic)
+        if not h:
+            raise ValueError("tangent-linear oracle rejected the lattice arguments")
+        self._h = h
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            tl_lib().orc_tl_destroy(self._h)
+            self._h = None
+
+    def set_equilibrium(self, rho, u):
+        rho = np.ascontiguousarray(np.broadcast_to(np.asarray(rho, dtype=np.float64), self.shape))
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        tl_lib().orc_tl_set_equilibrium(self._h, _dptr(rho), _dptr(u))
+
+    def step(self, nsteps=1):
+        tl_lib().orc_tl_step(self._h, int(nsteps))
+
+    def fill_and_derivative(self):
+        v = np.zeros(self.n)
+        d = np.zeros(self.n)
+        tl_lib().orc_tl_get_fill(self._h, _dptr(v), _dptr(d))
+        return v.reshape(self.shape), d.reshape(self.shape)
