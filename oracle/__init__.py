@@ -257,13 +257,14 @@ def tl_lib():
 
 
 class TangentLinear:
-    """The frozen-type oracle (FD curvature) in tangent-linear mode: the
-    value of phi and its derivative along one direction of (sigma, theta,
-    phi_0), given by the seeds dsigma, dtheta and fill_dot (the last on the
-    initial fill levels). Arrays are (nz, ny, nx), x fastest."""
+    """The frozen-type oracle in tangent-linear mode: the value of phi and
+    its derivative along one direction of (sigma, theta, phi_0), given by the
+    seeds dsigma, dtheta and fill_dot (the last on the initial fill levels).
+    Arrays are (nz, ny, nx), x fastest."""
 
     def __init__(self, fill, obstacle=None, *, fill_dot=None, dsigma=0.0, dtheta=0.0, sigma=0.0, tau=1.0,
-                 theta=np.pi / 2, rho_gas=1.0, eps_c=1e-3, collision=SRT, trt_magic=3.0 / 16.0):
+                 theta=np.pi / 2, rho_gas=1.0, eps_c=1e-3, curv_model=CURV_FD, collision=SRT,
+                 trt_magic=3.0 / 16.0):
         fill = np.ascontiguousarray(fill, dtype=np.float64)
         self.shape = fill.shape
         nz, ny, nx = fill.shape
@@ -274,7 +275,7 @@ class TangentLinear:
         dot = None if fill_dot is None else np.ascontiguousarray(fill_dot, dtype=np.float64)
         h = tl_lib().orc_tl_create(nx, ny, nz, _dptr(fill), None if dot is None else _dptr(dot),
                                    obstacle.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte)), sigma, dsigma, tau,
-                                   theta, dtheta, rho_gas, eps_c, CURV_FD, collision, trt_magic)
+                                   theta, dtheta, rho_gas, eps_c, curv_model, collision, trt_magic)
         if not h:
             raise ValueError("tangent-linear oracle rejected the lattice arguments")
         self._h = h

@@ -188,7 +188,13 @@ double orc_cut_volume(const double nhat[3], double a)
 
 /* Plane offset a with cut volume phi (clamped to [0,1]), by bisection on
  * [-Ls/2, Ls/2]; 42 halvings bring the bracket below 4e-13, the error bound
- * the paper quotes for its bisection (Sec. II.B). */
+ * the paper quotes for its bisection (Sec. II.B). The result passes through
+ * ORC_PLIC_RESULT, the identity here; the tangent-linear build replaces it
+ * to give the offset the derivative of V(n, a) = phi, which a bisection
+ * bracket does not carry. */
+#ifndef ORC_PLIC_RESULT
+#define ORC_PLIC_RESULT(nhat, phi, a) (a)
+#endif
 double orc_plic_offset(const double nhat[3], double phi)
 {
     double Ls = fabs(nhat[0]) + fabs(nhat[1]) + fabs(nhat[2]);
@@ -201,7 +207,7 @@ double orc_plic_offset(const double nhat[3], double phi)
         if (orc_cut_volume(nhat, mid) > phi) lo = mid;
         else hi = mid;
     }
-    return 0.5 * (lo + hi);
+    return ORC_PLIC_RESULT(nhat, phi, 0.5 * (lo + hi));
 }
 
 /* ---- least squares by Householder QR (LSQR solve, Sec. II.C) ----------- */

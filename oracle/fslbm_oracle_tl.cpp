@@ -1,15 +1,15 @@
 /*
  * fslbm_oracle_tl.cpp -- tangent-linear (forward-mode) build of the CPU
- * reference: the unchanged source of fslbm_oracle.c compiled with every
+ * reference: the source of fslbm_oracle.c compiled with every
  * double carried as a dual number (fslbm_dual.hpp), so that one directional
  * derivative of the whole step -- with respect to sigma, theta and the
  * initial fill level, in any combination -- is propagated through the same
  * operations in the same order as the values.
  *
  * TEST INFRASTRUCTURE ONLY: the reference gradient of the frozen-topology
- * window for the finite-difference curvature model. The PLIC offset of the
- * other models is found by bisection, whose bracket carries no derivative,
- * so orc_tl_create refuses them.
+ * window, for every curvature model. The one replaced step is the PLIC
+ * offset's derivative (below): the bisection that finds the offset carries
+ * none, so it is taken from the implicit function of the cut volume.
  *
  * Entry points take and return plain doubles:
  *   orc_tl_create   fill and its seed direction (or NULL), obstacle mask,
@@ -25,9 +25,27 @@
 
 #include "fslbm_dual.hpp"
 
+// The PLIC offset found by bisection carries no derivative. Inside (0, 1)
+// it gets the one of the implicit function V(n, a) = phi:
+// da = (dphi - dV/dn . dn) / (dV/da), both partials from dual evaluations
+// of the cut volume. At phi = 0 or 1 (clamped) the plane sits on a corner of
+// the cell, a = +-Ls/2, and the bracket's own derivative is that of +-Ls/2.
+static Dual plic_result_tl(const Dual nhat[3], Dual phi, Dual a);
+#define ORC_PLIC_RESULT(nhat, phi, a) plic_result_tl(nhat, phi, a)
+
 #define double Dual
 #include "fslbm_oracle.c"
 #undef double
+
+static Dual plic_result_tl(const Dual nhat[3], Dual phi, Dual a)
+{
+    if (!(phi.v > 0.0 && phi.v < 1.0)) return a;
+    const Dual nv[3] = {Dual(nhat[0].v, 0.0), Dual(nhat[1].v, 0.0), Dual(nhat[2].v, 0.0)};
+    const Dual vn = orc_cut_volume(nhat, Dual(a.v, 0.0));  // dV/dn . dn
+    const Dual va = orc_cut_volume(nv, Dual(a.v, 1.0));    // dV/da
+    if (va.d == 0.0) return a;
+    return Dual(a.v, (phi.d - vn.d) / va.d);
+}
 
 extern "C" {
 
@@ -36,7 +54,6 @@ orc_lattice *orc_tl_create(int nx, int ny, int nz, const double *fill, const dou
                            double dtheta, double rho_gas, double eps_c, int curv_model, int collision,
                            double trt_magic)
 {
-    if (curv_model != ORC_CURV_FD) return NULL;
     const long n = (long)nx * ny * nz;
     Dual *f = (Dual *)malloc(sizeof(Dual) * n);
     for (long i = 0; i < n; ++i) f[i] = Dual(fill[i], fill_dot ? fill_dot[i] : 0.0);

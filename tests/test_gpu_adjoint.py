@@ -1,6 +1,6 @@
 """Discrete adjoint of the frozen-topology window (HIP path, through the C
 ABI) against central differences of the FP64 oracle run with frozen cell
-types, and, for the FD model, against the oracle's tangent-linear build.
+types, and against the oracle's tangent-linear build.
 
 Loss L = sum over non-obstacle cells of (phi_T - phi*)^2 (the fill level of
 liquid and gas cells is constant, so only interface cells contribute), with
@@ -180,17 +180,19 @@ def test_adjoint_fp32_vs_oracle_fd(Lattice, name):
     check(name, Lattice, "f32", 2e-3)
 
 
-@pytest.mark.parametrize("name", ["fd_droplet_moving", "fd_droplet_trt", "fd_sessile"])
+@pytest.mark.parametrize("name", ["fd_droplet_moving", "fd_droplet_trt", "fd_sessile", "lsqr_droplet", "lsqr_sessile"])
 def test_adjoint_fp64_vs_oracle_tangent_linear(Lattice, name):
-    """The FD-model gradients against the oracle's own tangent-linear
-    derivatives (the reference source run in forward mode with dual numbers,
-    frozen types): dL/dsigma, dL/dtheta (walls) and <dL/dphi_0, v>, with
-    dL = sum 2 (phi_T - phi*) dphi_T over non-obstacle cells. Both sides are
-    exact derivatives of the same FP64 map, so they agree to rounding."""
+    """The gradients against the oracle's own tangent-linear derivatives
+    (the reference source run in forward mode with dual numbers, frozen
+    types): dL/dsigma, dL/dtheta (walls: the FD contact normal or the LSQR
+    contact condition) and <dL/dphi_0, v>, with dL = sum 2 (phi_T - phi*)
+    dphi_T over non-obstacle cells. Both sides are exact derivatives of the
+    same FP64 map, so they agree to rounding."""
     fill, obst, model, prm, u, target, keep, v, inner = setup(name)
     _, d0, ds, dt, _ = gpu_gradients(Lattice, fill, obst, model, prm, u, target, keep, "f64")
     kw = dict(prm)
     kw["collision"] = O.TRT if kw.pop("collision", "srt") == "trt" else O.SRT
+    kw["curv_model"] = MODELS[model]
 
     def dL(**seed):
         t = O.TangentLinear(fill, obst, **kw, **seed)

@@ -1,11 +1,13 @@
 """Pins of the tangent-linear oracle (the reference source built with dual
-numbers, FD curvature, frozen cell types): its values are the plain
-oracle's bit for bit, and its directional derivatives of a linear functional
-of phi_T agree with central differences of the plain oracle,
-Richardson-extrapolated over the step and twice the step, for sigma (a
-moving droplet, SRT and TRT), theta (a sessile drop with the FD contact
-normal) and the initial fill level (a seeded direction on the interface
-cells)."""
+numbers, frozen cell types): its values are the plain oracle's bit for bit,
+and its directional derivatives of a linear functional of phi_T agree with
+central differences of the plain oracle, Richardson-extrapolated over the
+step and twice the step, for sigma (droplets, SRT and TRT, moving or at
+rest), theta (sessile drops: the FD contact normal, the LSQR contact
+condition) and the initial fill level (a seeded direction on the interface
+cells), with the FD, LSQR and TR curvature models. The LSQR and TR cases
+also pin the implicit derivative of the PLIC offset that replaces the
+bisection's."""
 import math
 
 import numpy as np
@@ -18,6 +20,16 @@ T = 24
 
 
 def _case(name):
+    model = {"lsqr": O.CURV_LSQR, "tr": O.CURV_TR}.get(name.split("_")[0], O.CURV_FD)
+    fill, obst, prm, u = _case_fd(name.split("_", 1)[1] if model != O.CURV_FD else name)
+    prm["curv_model"] = model
+    return fill, obst, prm, u
+
+
+def _case_fd(name):
+    if name == "droplet":
+        fill, obst = I.droplet(20, 5.0, noise=1e-6, seed=6)
+        return fill, obst, dict(sigma=5e-3, tau=0.8, theta=math.pi / 2), None
     if name == "droplet_moving":
         fill, obst = I.droplet(20, 5.0, noise=1e-6, seed=3)
         u = np.zeros((3,) + fill.shape)
@@ -31,7 +43,7 @@ def _case(name):
 
 
 def _plain(fill, obst, prm, u):
-    o = O.Oracle(fill, obst, curv_model=O.CURV_FD, frozen=True, **prm)
+    o = O.Oracle(fill, obst, frozen=True, **prm)
     if u is not None:
         o.set_equilibrium(np.ones(fill.shape), u)
     o.step(T)
@@ -52,7 +64,11 @@ def _richardson(f, x, e):
     return (4 * d1 - d2) / 3
 
 
-@pytest.mark.parametrize("name", ["droplet_moving", "droplet_trt", "sessile"])
+# The PLIC models are pinned at rest: in a moving droplet some cells pass
+# close to phi = 0 within the window, where the offset goes like phi^(1/3)
+# and a difference step of 1e-5 is no longer in the smooth regime.
+@pytest.mark.parametrize("name", ["droplet_moving", "droplet_trt", "sessile", "lsqr_droplet", "lsqr_sessile",
+                                  "tr_droplet"])
 def test_tangent_linear_values_and_derivatives(name):
     fill, obst, prm, u = _case(name)
     ifc = O.Oracle(fill, obst, frozen=True).flags() == O.INTERFACE
