@@ -317,3 +317,34 @@ def test_benchmark_window_downscale_fp64_matches_its_forward(Lattice):
     print("window", {k: f"{adj[k]:.6e} fd {fd[k]:.6e} rel {errs[k]:.1e}" for k in fd})
     for k, e in errs.items():
         assert e < 1e-6, f"{k}: relative error {e:.3e}"
+
+
+def test_long_window_fp64_vs_tangent_linear(Lattice):
+    """The 800-step window above (8 segments of 100; sessile drop, LSQR with
+    walls) against the tangent-linear oracle for sigma, theta and a seeded
+    direction of phi_0. Over a window this long differences fail in theta
+    (the loss is only piecewise smooth there), while the tangent-linear
+    oracle differentiates the same piece of the map as the adjoint."""
+    fill, obst = I.sessile_droplet(40, 40, 24, 8.0, noise=1e-6, seed=1)
+    prm = dict(sigma=1e-3, tau=0.8, theta=math.pi / 2)
+    T = 800
+    rng = np.random.default_rng(0)
+    w = rng.uniform(-1.0, 1.0, fill.shape)
+    g = Lattice(fill, obst, precision="f64", curv_model="lsqr", **prm)
+    ifc = g.flags() == O.INTERFACE
+    phi0 = g.fill()
+    v = rng.uniform(-1.0, 1.0, fill.shape) * ifc * (phi0 > 1e-3) * (phi0 < 1 - 1e-3)
+    g.adjoint_forward(T, 100)
+    d0, ds, dt = g.adjoint_backward(w * ifc)
+
+    def tl(**seed):
+        t = O.TangentLinear(fill, obst, curv_model=O.CURV_LSQR, **prm, **seed)
+        t.step(T)
+        _, der = t.fill_and_derivative()
+        return float((w * ifc * der).sum())
+
+    pairs = {"sigma": (ds, tl(dsigma=1.0)), "theta": (dt, tl(dtheta=1.0)),
+             "dir": (float((d0.cpu().numpy() * v).sum()), tl(fill_dot=v))}
+    print("long window", {k: f"{a:.12e} tl {b:.12e}" for k, (a, b) in pairs.items()})
+    for k, (a, b) in pairs.items():
+        assert abs(a - b) <= 1e-8 * abs(b), f"{k}: adjoint {a} vs tangent-linear {b}"
