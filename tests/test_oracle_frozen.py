@@ -9,7 +9,8 @@ the fill / empty conversion).
   cell receives f_in,q = feq_q(rho_b, 0) + feq_qbar(rho_b, 0) - f'_qbar =
   2 w_q rho_b - w_q with rho_b = rho_gas + 3 sigma K_0 (eq. reconstruct).
   Hence d phi_1/d sigma = -(m_1 / rho_1^2) * 6 K_0 * sum_{gas links} w_q
-  in closed form; central differences of the oracle must reproduce it.
+  in closed form; central differences of the oracle and its tangent-linear
+  build must reproduce it.
 """
 import numpy as np
 
@@ -68,3 +69,9 @@ def test_one_step_sigma_derivative_closed_form():
     assert np.abs(closed[ifc]).max() > 1e-4
     np.testing.assert_allclose(fd[ifc], closed[ifc], rtol=1e-6, atol=1e-12)
     assert np.abs(fd[~ifc]).max() == 0.0
+    # the tangent-linear oracle gives the same derivative to rounding
+    tl = O.TangentLinear(fill, obst, dsigma=1.0, sigma=sigma, tau=0.8)
+    tl.step(1)
+    _, dphi = tl.fill_and_derivative()
+    np.testing.assert_allclose(dphi[ifc], closed[ifc], rtol=1e-10, atol=1e-15)
+    assert np.abs(dphi[~ifc]).max() == 0.0
