@@ -124,18 +124,27 @@ int fslbm_create(int nx, int ny, int nz, int precision, int curv_model, const do
 
 /* sigma >= 0 (surface tension, lattice units), tau > 1/2 (relaxation time,
  * nu = (tau - 1/2)/3), 0 < theta < pi (equilibrium contact angle, radians),
- * rho_gas > 0 (gas pressure p_g = rho_gas/3). Recomputes the curvature field
- * (it depends on theta at walls). */
+ * rho_gas > 0 (gas pressure p_g = rho_gas/3) (Sec. II). Recomputes the
+ * curvature field (it depends on theta at walls). FSLBM_E_ARG for a value
+ * out of range or not finite. */
 int fslbm_set_params(fslbm_t h, double sigma, double tau, double theta_rad, double rho_gas);
+/* One option (enum fslbm_option). FSLBM_E_ARG for an unknown key or a value
+ * out of its range (eps_c in [0, 0.5), collision SRT or TRT, TRT Lambda > 0). */
 int fslbm_set_option(fslbm_t h, int key, double value);
+/* Later work of this lattice goes to hip_stream (a hipStream_t; NULL = the
+ * null stream). */
 int fslbm_set_stream(fslbm_t h, void *hip_stream);
 
-/* Overwrite the distributions of all fluid cells with feq(rho, u) (host
- * arrays: rho n doubles, u 3n component-major); interface masses become
- * m = fill * rho. Used to start flows with a prescribed velocity. */
+/* Overwrite the distributions of all fluid cells with feq(rho, u) (eq.
+ * lbe2's equilibrium; host arrays: rho n doubles, u 3n component-major);
+ * interface masses become m = fill * rho. Used to start flows with a
+ * prescribed velocity. The values are not checked (fslbm_check_numeric
+ * reports a non-positive or non-finite density). FSLBM_E_ARG if rho or u3
+ * is NULL. */
 int fslbm_set_equilibrium(fslbm_t h, const double *rho, const double *u3);
 
-/* Advance nsteps >= 0 time steps; enqueued, no synchronisation. */
+/* Advance nsteps >= 0 time steps (Sec. II); enqueued, no synchronisation.
+ * FSLBM_E_ARG if nsteps < 0. */
 int fslbm_step(fslbm_t h, int64_t nsteps);
 
 /* Read-outs (n doubles; 3n for velocity and normal). out_is_device = 1 if
@@ -148,6 +157,7 @@ int fslbm_step(fslbm_t h, int64_t nsteps);
  *  PLIC plane offset (point p = cell centre + a n) at interface cells,
  *  0 elsewhere;
  *  mass_field: interface mass m (0 at other cells). */
+/* FSLBM_E_ARG if out is NULL. */
 int fslbm_read_fill(fslbm_t h, double *out, int out_is_device);
 int fslbm_read_pressure(fslbm_t h, double *out, int out_is_device);
 int fslbm_read_curvature(fslbm_t h, double *out, int out_is_device);
@@ -155,17 +165,19 @@ int fslbm_read_velocity(fslbm_t h, double *out3, int out_is_device);
 int fslbm_read_normal(fslbm_t h, double *out3, int out_is_device);
 int fslbm_read_plic(fslbm_t h, double *out, int out_is_device);
 int fslbm_read_mass_field(fslbm_t h, double *out, int out_is_device);
-/* Cell types (enum fslbm_cell), n bytes. */
+/* Cell types (enum fslbm_cell), n bytes; FSLBM_E_ARG if out is NULL. */
 int fslbm_read_flags(fslbm_t h, uint8_t *out, int out_is_device);
 /* Interface cells as ascending linear indices into host out[capacity];
  * *count receives the number of interface cells (FSLBM_E_SHAPE if it
  * exceeds capacity; out may be NULL to query the count). */
 int fslbm_read_interface_list(fslbm_t h, int32_t *out, int64_t capacity, int64_t *count);
 /* Gas density used by the step (rho_gas, or rho_gas(t) of the bubble
- * model); synchronises. */
+ * model); synchronises. FSLBM_E_ARG if rho_gas is NULL. */
 int fslbm_gas_density(fslbm_t h, double *rho_gas);
 /* Total mass: sum of rho over liquid cells + sum of m over interface cells +
- * excess mass that found no receiving cell; FP64, fixed summation order. */
+ * excess mass that found no receiving cell; FP64, fixed summation order
+ * (the invariant of eqs. advection1/2). Synchronises. FSLBM_E_ARG if total
+ * is NULL. */
 int fslbm_mass(fslbm_t h, double *total);
 /* Diagnostics of the current state: the measures of the paper's
  * equilibrium tests (spurious currents, Laplace law; Sec. III.A.1). FP64
