@@ -446,6 +446,16 @@ def test_sessile_cap_closed_form_fixture():
 def test_input_volumes_and_noise():
     f = I.sphere_fraction((32, 32, 32), (16.3, 15.8, 16.1), 8.0)
     assert f.sum() == pytest.approx(4 / 3 * math.pi * 512, rel=1e-10)
+    # the ellipsoid of the oscillating-droplet workload (scaled) and a cylinder
+    e = I.ellipsoid_fraction((48, 48, 48), (24.2, 23.9, 24.1), (12.0, 10.0, 8.0))
+    assert e.sum() == pytest.approx(4 / 3 * math.pi * 12.0 * 10.0 * 8.0, rel=1e-10)
+    assert e.min() >= 0.0 and e.max() <= 1.0
+    c = I.cylinder_fraction((4, 32, 32), (16.2, 15.9), 7.5)
+    assert c.sum() == pytest.approx(math.pi * 7.5 ** 2 * 4, rel=1e-10)
+    # SplitMix64 with seed 0: the generator's published first outputs
+    # 0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F (top 53 bits)
+    ref = np.array([0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F], dtype=np.uint64)
+    assert np.array_equal(I.splitmix_uniform(0, 3), (ref >> np.uint64(11)).astype(np.float64) / 2.0 ** 53)
     f, o = I.sessile_droplet(40, 40, 20, 9.0)
     assert f.sum() == pytest.approx(2 / 3 * math.pi * 729, rel=1e-10)
     assert o[0].all() and o[-1].all() and not o[1:-1].any()
