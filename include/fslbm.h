@@ -116,7 +116,12 @@ int fslbm_required_bytes(int nx, int ny, int nz, int precision, size_t *bytes);
  * The distributions start at equilibrium with rho = 1, u = 0, the interface
  * mass at m = fill. Parameters start at sigma = 0, tau = 1, theta = pi/2,
  * rho_gas = 1 until fslbm_set_params. Copies fill and obstacle; returns with
- * the initialisation enqueued on the stream.
+ * the initialisation enqueued on the stream. FSLBM_E_ARG for a NULL fill,
+ * workspace or out, a misaligned workspace, or an unknown precision or
+ * model; FSLBM_E_SHAPE for an extent out of range (as fslbm_required_bytes),
+ * a workspace below fslbm_required_bytes(), or, with the FD model, any
+ * extent below 10 (its 8^3 tiles read a periodic halo of 3 + 10 cells).
+ * All of these are checked before any device call.
  */
 int fslbm_create(int nx, int ny, int nz, int precision, int curv_model, const double *fill,
                  const uint8_t *obstacle, void *workspace, size_t workspace_bytes,

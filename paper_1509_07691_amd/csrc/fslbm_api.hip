@@ -1441,6 +1441,10 @@ int fslbm_create(int nx, int ny, int nz, int precision, int curv_model, const do
     if (curv_model != FSLBM_CURV_FD && curv_model != FSLBM_CURV_LSQR && curv_model != FSLBM_CURV_TR)
         return fail(FSLBM_E_ARG, "unknown curvature model %d", curv_model);
     if (!shape_ok(nx, ny, nz)) return fail(FSLBM_E_SHAPE, "lattice %dx%dx%d out of range", nx, ny, nz);
+    // the FD model's 8^3 tiles read from 3 cells below to 10 cells above a
+    // tile origin; one periodic wrap covers that only for extents >= 10
+    if (curv_model == FSLBM_CURV_FD && (nx < 10 || ny < 10 || nz < 10))
+        return fail(FSLBM_E_SHAPE, "the FD curvature model needs every extent >= 10 (lattice %dx%dx%d)", nx, ny, nz);
     const long long N = (long long)nx * ny * nz;
     const Layout L = make_layout(nx, ny, nz, precision);
     if (workspace_bytes < L.total)

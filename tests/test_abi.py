@@ -74,6 +74,13 @@ def test_create_rejects_bad_arguments_before_touching_the_device(lib):
     assert lib.fslbm_create(8, 8, 8, 1, 0, dp, None, ctypes.c_void_p(16), 1 << 30, None, ctypes.byref(h)) == -1
     # workspace too small
     assert lib.fslbm_create(8, 8, 8, 1, 0, dp, None, ctypes.c_void_p(1 << 20), 64, None, ctypes.byref(h)) == -2
+    # the FD model needs every extent >= 10; LSQR gets past that check
+    f9 = np.zeros(9 * 32 * 32)
+    d9 = f9.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    assert lib.fslbm_create(9, 32, 32, 1, 0, d9, None, ctypes.c_void_p(1 << 20), 64, None, ctypes.byref(h)) == -2
+    assert b"FD" in lib.fslbm_last_error()
+    assert lib.fslbm_create(9, 32, 32, 1, 1, d9, None, ctypes.c_void_p(1 << 20), 64, None, ctypes.byref(h)) == -2
+    assert b"workspace" in lib.fslbm_last_error()
     # unknown curvature model
     assert lib.fslbm_create(8, 8, 8, 1, 5, dp, None, ctypes.c_void_p(1 << 20), 1 << 30, None, ctypes.byref(h)) == -1
     assert b"curvature" in lib.fslbm_last_error()
