@@ -55,47 +55,52 @@ class _Params(ctypes.Structure):
 _lib = None
 
 
+def load(path):
+    """A ctypes handle of an oracle build at `path` with the signatures set."""
+    L = ctypes.CDLL(path)
+    dp = ctypes.POINTER(ctypes.c_double)
+    up = ctypes.POINTER(ctypes.c_ubyte)
+    ip = ctypes.POINTER(ctypes.c_int)
+    vp = ctypes.c_void_p
+    L.orc_create.restype = vp
+    L.orc_create.argtypes = [ctypes.c_int] * 3 + [dp, up, ctypes.POINTER(_Params)]
+    L.orc_destroy.argtypes = [vp]
+    L.orc_step.argtypes = [vp, ctypes.c_long]
+    for name in ("orc_get_fill", "orc_get_density", "orc_get_velocity", "orc_get_curvature",
+                 "orc_get_normal", "orc_get_plic", "orc_get_mass_field", "orc_get_pdf"):
+        getattr(L, name).argtypes = [vp, dp]
+    L.orc_set_pdf.argtypes = [vp, dp]
+    L.orc_set_equilibrium.argtypes = [vp, dp, dp]
+    L.orc_get_flags.argtypes = [vp, up]
+    L.orc_get_mass.restype = ctypes.c_double
+    L.orc_get_mass.argtypes = [vp]
+    L.orc_get_reservoir.restype = ctypes.c_double
+    L.orc_get_reservoir.argtypes = [vp]
+    L.orc_get_gas_density.restype = ctypes.c_double
+    L.orc_get_gas_density.argtypes = [vp]
+    L.orc_interface_list.restype = ctypes.c_long
+    L.orc_interface_list.argtypes = [vp, ip]
+    L.orc_cut_volume.restype = ctypes.c_double
+    L.orc_cut_volume.argtypes = [dp, ctypes.c_double]
+    L.orc_plic_offset.restype = ctypes.c_double
+    L.orc_plic_offset.argtypes = [dp, ctypes.c_double]
+    L.orc_lsq_solve.restype = ctypes.c_int
+    L.orc_lsq_solve.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp]
+    L.orc_quadric_curvature.restype = ctypes.c_double
+    L.orc_quadric_curvature.argtypes = [ctypes.c_double] * 5
+    L.orc_lsqr_fit_points.restype = ctypes.c_int
+    L.orc_lsqr_fit_points.argtypes = [ctypes.c_int, dp, dp, dp]
+    L.orc_tr_curvature_points.restype = ctypes.c_double
+    L.orc_tr_curvature_points.argtypes = [ctypes.c_int, dp, dp]
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(_SRC):
             build()
-        L = ctypes.CDLL(LIB_PATH)
-        dp = ctypes.POINTER(ctypes.c_double)
-        up = ctypes.POINTER(ctypes.c_ubyte)
-        ip = ctypes.POINTER(ctypes.c_int)
-        vp = ctypes.c_void_p
-        L.orc_create.restype = vp
-        L.orc_create.argtypes = [ctypes.c_int] * 3 + [dp, up, ctypes.POINTER(_Params)]
-        L.orc_destroy.argtypes = [vp]
-        L.orc_step.argtypes = [vp, ctypes.c_long]
-        for name in ("orc_get_fill", "orc_get_density", "orc_get_velocity", "orc_get_curvature",
-                     "orc_get_normal", "orc_get_plic", "orc_get_mass_field", "orc_get_pdf"):
-            getattr(L, name).argtypes = [vp, dp]
-        L.orc_set_pdf.argtypes = [vp, dp]
-        L.orc_set_equilibrium.argtypes = [vp, dp, dp]
-        L.orc_get_flags.argtypes = [vp, up]
-        L.orc_get_mass.restype = ctypes.c_double
-        L.orc_get_mass.argtypes = [vp]
-        L.orc_get_reservoir.restype = ctypes.c_double
-        L.orc_get_reservoir.argtypes = [vp]
-        L.orc_get_gas_density.restype = ctypes.c_double
-        L.orc_get_gas_density.argtypes = [vp]
-        L.orc_interface_list.restype = ctypes.c_long
-        L.orc_interface_list.argtypes = [vp, ip]
-        L.orc_cut_volume.restype = ctypes.c_double
-        L.orc_cut_volume.argtypes = [dp, ctypes.c_double]
-        L.orc_plic_offset.restype = ctypes.c_double
-        L.orc_plic_offset.argtypes = [dp, ctypes.c_double]
-        L.orc_lsq_solve.restype = ctypes.c_int
-        L.orc_lsq_solve.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp]
-        L.orc_quadric_curvature.restype = ctypes.c_double
-        L.orc_quadric_curvature.argtypes = [ctypes.c_double] * 5
-        L.orc_lsqr_fit_points.restype = ctypes.c_int
-        L.orc_lsqr_fit_points.argtypes = [ctypes.c_int, dp, dp, dp]
-        L.orc_tr_curvature_points.restype = ctypes.c_double
-        L.orc_tr_curvature_points.argtypes = [ctypes.c_int, dp, dp]
-        _lib = L
+        _lib = load(LIB_PATH)
     return _lib
 
 
@@ -155,7 +160,8 @@ class Oracle:
         obstacle = np.ascontiguousarray(obstacle, dtype=np.uint8)
         p = _Params(sigma, tau, theta, rho_gas, eps_c, trt_magic, curv_model, collision, 1 if frozen else 0,
                     1 if bubble else 0)
-        h = lib().orc_create(nx, ny, nz, _dptr(fill),
+        self._L = lib()  # the build this lattice was created with
+        h = self._L.orc_create(nx, ny, nz, _dptr(fill),
                              obstacle.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte)), ctypes.byref(p))
         if not h:
             raise ValueError("oracle rejected the lattice arguments")
@@ -163,15 +169,15 @@ class Oracle:
 
     def __del__(self):
         if getattr(self, "_h", None):
-            lib().orc_destroy(self._h)
+            self._L.orc_destroy(self._h)
             self._h = None
 
     def step(self, nsteps=1):
-        lib().orc_step(self._h, int(nsteps))
+        self._L.orc_step(self._h, int(nsteps))
 
     def _get(self, name, comps=1):
         out = np.zeros((comps * self.n,), dtype=np.float64)
-        getattr(lib(), name)(self._h, _dptr(out))
+        getattr(self._L, name)(self._h, _dptr(out))
         return out.reshape((comps,) + self.shape) if comps > 1 else out.reshape(self.shape)
 
     def fill(self):
@@ -204,33 +210,33 @@ class Oracle:
     def set_pdf(self, f):
         f = np.ascontiguousarray(f, dtype=np.float64).reshape(-1)
         assert f.size == 19 * self.n
-        lib().orc_set_pdf(self._h, _dptr(f))
+        self._L.orc_set_pdf(self._h, _dptr(f))
 
     def set_equilibrium(self, rho, u):
         """f' = feq(rho, u) at fluid cells; rho shape (nz,ny,nx), u (3,nz,ny,nx)."""
         rho = np.ascontiguousarray(np.broadcast_to(rho, self.shape), dtype=np.float64).reshape(-1)
         u = np.ascontiguousarray(u, dtype=np.float64).reshape(-1)
         assert u.size == 3 * self.n
-        lib().orc_set_equilibrium(self._h, _dptr(rho), _dptr(u))
+        self._L.orc_set_equilibrium(self._h, _dptr(rho), _dptr(u))
 
     def flags(self):
         out = np.zeros(self.n, dtype=np.uint8)
-        lib().orc_get_flags(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte)))
+        self._L.orc_get_flags(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte)))
         return out.reshape(self.shape)
 
     def mass(self):
-        return lib().orc_get_mass(self._h)
+        return self._L.orc_get_mass(self._h)
 
     def reservoir(self):
-        return lib().orc_get_reservoir(self._h)
+        return self._L.orc_get_reservoir(self._h)
 
     def gas_density(self):
-        return lib().orc_get_gas_density(self._h)
+        return self._L.orc_get_gas_density(self._h)
 
     def interface_list(self):
-        c = lib().orc_interface_list(self._h, None)
+        c = self._L.orc_interface_list(self._h, None)
         out = np.zeros(max(c, 1), dtype=np.int32)
-        lib().orc_interface_list(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
+        self._L.orc_interface_list(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
         return out[:c]
 
 
