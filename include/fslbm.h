@@ -51,13 +51,16 @@ enum fslbm_status {
     FSLBM_E_SHAPE = -2,    /* lattice or buffer size out of range */
     FSLBM_E_HIP = -3,      /* a HIP runtime call failed */
     FSLBM_E_STATE = -4,    /* handle not usable for this call */
-    FSLBM_E_NUMERIC = -5   /* non-finite or non-positive density found */
+    FSLBM_E_NUMERIC = -5,  /* non-finite or non-positive density found */
+    FSLBM_E_TOPOLOGY = -6  /* a configuration the method does not support (Sec. II.D) */
 };
 
 /* Storage and arithmetic precision of the distributions. F16/BF16 store
  * (f_q - w_q) * S in 16 bits (S = 2^12 for F16, 1 for BF16) and compute in
- * FP32; m, phi, rho and K are FP64 in F64 mode and FP32 otherwise. Normals,
- * PLIC points and the least-squares solve are always FP64. */
+ * FP32; m, phi, rho and K are FP64 in F64 mode and FP32 otherwise. In the
+ * F32, F16 and BF16 modes the normals, PLIC offsets and FD curvature are
+ * computed and stored in FP32 as well; the least-squares normal equations of
+ * the LSQR fit and the mass and volume sums are FP64 in every mode. */
 enum fslbm_precision { FSLBM_F64 = 0, FSLBM_F32 = 1, FSLBM_F16_STORE = 2, FSLBM_BF16_STORE = 3 };
 /* Curvature models: FD (Sec. II.A, mollified finite differences, wetting
  * by the extrapolated contact normal), LSQR (Sec. II.C, least-squares
@@ -84,7 +87,7 @@ enum fslbm_option {
                                  interface and wall-adjacent cells; 0
                                  (default): one pass for all fluid cells.
                                  Results are identical either way. */
-    FSLBM_OPT_BUBBLE = 6      /* 1: bubble model (Sec. III.A.1): the whole gas
+    FSLBM_OPT_BUBBLE = 6,     /* 1: bubble model (Sec. III.A.1): the whole gas
                                  of the lattice is one bubble whose pressure
                                  follows its volume isothermally,
                                  rho_gas(t) = rho_gas V0 / V(t), with V the
@@ -93,6 +96,12 @@ enum fslbm_option {
                                  V0 its value when the option is set; 0
                                  (default): constant rho_gas. Not covered by
                                  the adjoint (FSLBM_E_STATE there). */
+    FSLBM_OPT_STRONG_WETTING = 7 /* 1: accept contact angles below 45 deg,
+                                 which Sec. II.D calls unsupported (the
+                                 curvature at the contact line then tends to
+                                 oscillate); 0 (default): fslbm_set_params
+                                 rejects them with FSLBM_E_TOPOLOGY. Setting 0
+                                 while theta < 45 deg is FSLBM_E_TOPOLOGY. */
 };
 
 /* Device workspace needed for a lattice (bytes, written to *bytes).
@@ -121,17 +130,31 @@ int fslbm_required_bytes(int nx, int ny, int nz, int precision, size_t *bytes);
  * model; FSLBM_E_SHAPE for an extent out of range (as fslbm_required_bytes),
  * a workspace below fslbm_required_bytes(), or, with the FD model, any
  * extent below 10 (its 8^3 tiles read a periodic halo of 3 + 10 cells).
- * All of these are checked before any device call.
+ * The closure rounds each rewritten cell to one phase; FSLBM_E_TOPOLOGY if it
+ * would have to round a cell to the phase that fills less than half of it
+ * (a fill >= 1/2 closing to gas or <= 1/2 closing to liquid): the input then
+ * holds a liquid film or gas layer thinner than one cell, which Sec. II.D
+ * (Fig. limitation) calls unsupported. Films thinner than half a cell close
+ * to gas without an error; fslbm_layer_closure reports every rewrite.
+ * All of these are checked on the host before any device call.
  */
 int fslbm_create(int nx, int ny, int nz, int precision, int curv_model, const double *fill,
                  const uint8_t *obstacle, void *workspace, size_t workspace_bytes,
                  void *hip_stream, fslbm_t *out);
 
+/* What the closure of the interface layer did to the input fill at
+ * creation: the number of cells closed to liquid (fill set to 1) and to gas
+ * (fill set to 0), the fill they gained and the fill they lost (sums over
+ * those cells, in cell volumes). FSLBM_E_ARG if an output is NULL. */
+int fslbm_layer_closure(fslbm_t h, int64_t *to_liquid, int64_t *to_gas, double *fill_added, double *fill_removed);
+
 /* sigma >= 0 (surface tension, lattice units), tau > 1/2 (relaxation time,
  * nu = (tau - 1/2)/3), 0 < theta < pi (equilibrium contact angle, radians),
  * rho_gas > 0 (gas pressure p_g = rho_gas/3) (Sec. II). Recomputes the
  * curvature field (it depends on theta at walls). FSLBM_E_ARG for a value
- * out of range or not finite. */
+ * out of range or not finite; FSLBM_E_TOPOLOGY for theta below 45 degrees,
+ * which Sec. II.D calls unsupported, unless FSLBM_OPT_STRONG_WETTING is set.
+ * The handle is unchanged on any error. */
 int fslbm_set_params(fslbm_t h, double sigma, double tau, double theta_rad, double rho_gas);
 /* One option (enum fslbm_option). FSLBM_E_ARG for an unknown key or a value
  * out of its range (eps_c in [0, 0.5), collision SRT or TRT, TRT Lambda > 0). */
@@ -172,9 +195,12 @@ int fslbm_read_plic(fslbm_t h, double *out, int out_is_device);
 int fslbm_read_mass_field(fslbm_t h, double *out, int out_is_device);
 /* Cell types (enum fslbm_cell), n bytes; FSLBM_E_ARG if out is NULL. */
 int fslbm_read_flags(fslbm_t h, uint8_t *out, int out_is_device);
-/* Interface cells as ascending linear indices into host out[capacity];
- * *count receives the number of interface cells (FSLBM_E_SHAPE if it
- * exceeds capacity; out may be NULL to query the count). */
+/* Interface cells (Sec. II: cells whose D3Q19 neighbourhood holds both gas
+ * and liquid) as ascending linear indices into host out[capacity], found by
+ * an ordered compaction of the cell types on the device; *count receives
+ * their number (FSLBM_E_SHAPE if it exceeds capacity; out may be NULL to
+ * query the count). Uses scratch inside the lattice's workspace and
+ * synchronises the stream. FSLBM_E_ARG if count is NULL. */
 int fslbm_read_interface_list(fslbm_t h, int32_t *out, int64_t capacity, int64_t *count);
 /* Gas density used by the step (rho_gas, or rho_gas(t) of the bubble
  * model); synchronises. FSLBM_E_ARG if rho_gas is NULL. */

@@ -64,9 +64,14 @@ struct Layout {
 constexpr int MASS_BLOCKS = 1024;
 constexpr int DIAG_VALUES = 5;  // partial sums per block of the diagnostics
 
+// Plane stride of the distribution buffers (elements): N rounded up to 64
+// elements, so that every plane starts on a 128-byte boundary.
+long long plane_stride(long long N) { return (N + 63) / 64 * 64; }
+
 Layout make_layout(int nx, int ny, int nz, int prec)
 {
     const long long N = (long long)nx * ny * nz;
+    const long long NS = plane_stride(N);
     Layout L;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -75,8 +80,8 @@ Layout make_layout(int nx, int ny, int nz, int prec)
         return o;
     };
     const size_t fb = fbytes(prec), rb = rbytes(prec);
-    L.fA = take(19 * N * fb);
-    L.fB = take(19 * N * fb);
+    L.fA = take(19 * NS * fb);
+    L.fB = take(19 * NS * fb);
     L.flags = take(N);
     L.near = take(N);
     L.conv = take(N);
@@ -96,7 +101,7 @@ Layout make_layout(int nx, int ny, int nz, int prec)
     L.wlist = take(4 * N);
     L.newlist = take(4 * N);
     L.ilist_tmp = take(4 * N);
-    L.staging = take(8 * N);
+    L.staging = take(8 * N + 512);  // N doubles for read-outs; the ordered interface list (count + N ints)
     L.counts = take(4 * (size_t)CMP_GRID);  // one count per compaction block (fixed grid)
     L.part = take(8 * (DIAG_VALUES * MASS_BLOCKS + 8));  // mass, bubble volume and diagnostics partials
     L.sc = take(sizeof(DevScalars));
@@ -108,10 +113,17 @@ bool shape_ok(int nx, int ny, int nz)
 {
     if (nx < 3 || ny < 3 || nz < 3) return false;
     const long long N = (long long)nx * ny * nz;
-    return N <= 2147483647LL / 1;  // cell indices are 32-bit
+    return plane_stride(N) <= 2147483647LL;  // cell indices and the plane stride are 32-bit
 }
 
 }  // namespace
+
+// What the closure of the interface layer at creation did to the input fill.
+struct LayerClosure {
+    long long against = 0;  // cells rounded to the phase that fills less than half of them
+    long long to_liquid = 0, to_gas = 0;
+    double fill_added = 0.0, fill_removed = 0.0;
+};
 
 struct fslbm_lattice;
 
@@ -159,6 +171,11 @@ struct fslbm_batch {
 struct fslbm_lattice {
     int nx, ny, nz;
     int N;
+    int NS;  // plane stride of the distribution buffers
+    int box_blocks;  // 256-cell chunks of the fluid box when last read back (grid of the bulk stream-collide)
+    int device;      // device that holds the workspace
+    int strong_wetting;  // 1: contact angles below 45 deg are accepted (FSLBM_OPT_STRONG_WETTING)
+    LayerClosure closure;  // what the closure of the interface layer did to the input fill
     int prec, curv, coll;
     double sigma, tau, theta, rho_gas, eps_c, trt_magic;
     hipStream_t stream;
@@ -240,6 +257,7 @@ Fields<P> make_fields(const fslbm_lattice *h)
     F.ny = h->ny;
     F.nz = h->nz;
     F.N = h->N;
+    F.NS = h->NS;
     return F;
 }
 
@@ -247,10 +265,7 @@ inline int cell_blocks(int N) { return (N + 255) / 256; }
 inline int list_blocks(int N) { return std::min(LIST_GRID, std::max(1, (N + 255) / 256)); }
 inline int cmp_blocks(int N) { return std::min(CMP_GRID, (N + CMP_CELLS - 1) / CMP_CELLS); }
 constexpr int GEOM_GRID = 1024;  // blocks per lattice of the tiled geometry kernels
-#ifndef FSLBM_SC_GRID
-#define FSLBM_SC_GRID 1024
-#endif
-constexpr int SC_GRID = FSLBM_SC_GRID;  // blocks per lattice of the bulk stream-collide
+constexpr int SC_LIST_GRID = 1024;  // blocks per lattice of the interface / wall-list stream-collide
 
 // ------------------------------------------------------ init kernels
 __global__ void k_fill_bytes(uint8_t *p, size_t n, uint8_t v)
@@ -359,8 +374,8 @@ __global__ void k_init_fields(Fields<P> F, const double *fill, const uint8_t *ty
         switch (q) {
 #define FSLBM_ST(QQ)                                 \
     case QQ:                                         \
-        store_f<P, QQ>(plane<P, QQ>(src, F.N), i, v); \
-        store_f<P, QQ>(plane<P, QQ>(dst, F.N), i, v); \
+        store_f<P, QQ>(plane<P, QQ>(src, F.NS), i, v); \
+        store_f<P, QQ>(plane<P, QQ>(dst, F.NS), i, v); \
         break;
             FSLBM_ST(0) FSLBM_ST(1) FSLBM_ST(2) FSLBM_ST(3) FSLBM_ST(4) FSLBM_ST(5) FSLBM_ST(6)
             FSLBM_ST(7) FSLBM_ST(8) FSLBM_ST(9) FSLBM_ST(10) FSLBM_ST(11) FSLBM_ST(12) FSLBM_ST(13)
@@ -425,7 +440,7 @@ __global__ void k_set_equilibrium(Fields<P> F, const double *rho_in, const doubl
     for (int q = 0; q < NQ; ++q) {
         const T v = feq<T>(q, r, ux, uy, uz, usq);
         switch (q) {
-#define FSLBM_ST(QQ) case QQ: store_f<P, QQ>(plane<P, QQ>(dst, F.N), i, v); break;
+#define FSLBM_ST(QQ) case QQ: store_f<P, QQ>(plane<P, QQ>(dst, F.NS), i, v); break;
             FSLBM_ST(0) FSLBM_ST(1) FSLBM_ST(2) FSLBM_ST(3) FSLBM_ST(4) FSLBM_ST(5) FSLBM_ST(6)
             FSLBM_ST(7) FSLBM_ST(8) FSLBM_ST(9) FSLBM_ST(10) FSLBM_ST(11) FSLBM_ST(12) FSLBM_ST(13)
             FSLBM_ST(14) FSLBM_ST(15) FSLBM_ST(16) FSLBM_ST(17) FSLBM_ST(18)
@@ -445,7 +460,7 @@ __device__ inline void load_all(const Fields<P> &F, int i, typename P::T (&f)[NQ
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
         switch (q) {
-#define FSLBM_LD(QQ) case QQ: f[q] = load_f<P, QQ>(plane<P, QQ>(F.fsrc, F.N), i); break;
+#define FSLBM_LD(QQ) case QQ: f[q] = load_f<P, QQ>(plane<P, QQ>(F.fsrc, F.NS), i); break;
             FSLBM_LD(0) FSLBM_LD(1) FSLBM_LD(2) FSLBM_LD(3) FSLBM_LD(4) FSLBM_LD(5) FSLBM_LD(6)
             FSLBM_LD(7) FSLBM_LD(8) FSLBM_LD(9) FSLBM_LD(10) FSLBM_LD(11) FSLBM_LD(12) FSLBM_LD(13)
             FSLBM_LD(14) FSLBM_LD(15) FSLBM_LD(16) FSLBM_LD(17) FSLBM_LD(18)
@@ -487,6 +502,77 @@ __global__ void k_read(Fields<P> F, double rho_gas, int bubble, int what, int co
         break;
     }
     out[i] = v;
+}
+
+// Ascending list of the interface cells (read-out): CMP_GRID blocks, each
+// owning a contiguous run of 1024-cell tiles of the fluid box; per-block
+// counts, one scan block, then every block writes its run in order. The
+// scratch holds the block counts, the total and up to `cap` list entries;
+// the write pass never writes past `cap` (the host rejects a longer list).
+struct ListScratch {
+    int *counts;    // CMP_GRID ints
+    int *total;     // one int
+    int32_t *list;  // cap ints
+    int cap;
+};
+
+__global__ __launch_bounds__(256) void k_ilist_count(const uint8_t *flags, const DevScalars *sc, int nx, int ny,
+                                                     ListScratch s)
+{
+    const CellRange range = CellRange::from(sc->fbox);
+    __shared__ int lw[4];
+    int t0, t1;
+    tile_range(range.size(), t0, t1);
+    int sum = 0;
+    for (int t = t0; t < t1; ++t) {
+        bool hit[4];
+        int idx[4];
+        const int c = cells_matching(flags, range, nx, ny, t * CMP_CELLS + threadIdx.x * 4, FL_IF, hit, idx);
+        int total;
+        block_exclusive_scan(c, lw, total);
+        sum += total;
+    }
+    if (threadIdx.x == 0) s.counts[blockIdx.x] = sum;
+}
+
+__global__ __launch_bounds__(1024) void k_ilist_scan(ListScratch s, int nblocks)
+{
+    __shared__ int lw[16];
+    int carry = 0;
+    for (int b0 = 0; b0 < nblocks; b0 += 1024) {
+        const int b = b0 + threadIdx.x;
+        const int v = b < nblocks ? s.counts[b] : 0;
+        int total;
+        const int ex = block_exclusive_scan(v, lw, total);
+        if (b < nblocks) s.counts[b] = carry + ex;
+        carry += total;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *s.total = carry;
+}
+
+__global__ __launch_bounds__(256) void k_ilist_write(const uint8_t *flags, const DevScalars *sc, int nx, int ny,
+                                                     ListScratch s)
+{
+    const CellRange range = CellRange::from(sc->fbox);
+    __shared__ int lw[4];
+    int t0, t1;
+    tile_range(range.size(), t0, t1);
+    int base = s.counts[blockIdx.x];
+    for (int t = t0; t < t1; ++t) {
+        bool hit[4];
+        int idx[4];
+        const int c = cells_matching(flags, range, nx, ny, t * CMP_CELLS + threadIdx.x * 4, FL_IF, hit, idx);
+        int total;
+        int pos = base + block_exclusive_scan(c, lw, total);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (hit[k]) {
+                if (pos < s.cap) s.list[pos] = idx[k];
+                ++pos;
+            }
+        base += total;
+    }
 }
 
 __global__ void k_read_flags(const uint8_t *flags, uint8_t *out, int N)
@@ -744,14 +830,18 @@ int enqueue_step_kernels(fslbm_batch *b, const void *fsrc = nullptr, void *fdst 
     };
     const unsigned n = (unsigned)b->hs.size();
     const hipStream_t st = bstream(b);
-    const dim3 cg(std::min(SC_GRID, cell_blocks(maxN)), n), lg(batch_list_blocks(b, 256), n);
+    // bulk stream-collide: one block per 256 cells of the largest fluid box
+    int boxb = 1;
+    for (auto *h : b->hs) boxb = std::max(boxb, h->box_blocks);
+    const dim3 cg(boxb, n), sg(std::min(SC_LIST_GRID, cell_blocks(maxN)), n),
+        lg(batch_list_blocks(b, 256), n);
     mark(b, 0);
     if (b->split_interface) {
         if (any_srt) launch_stream_collide<P, 0, 1>(cg, st, A);
         if (any_trt) launch_stream_collide<P, 1, 1>(cg, st, A);
         mark(b, 1);
-        if (any_srt) k_stream_collide_list<P, 0><<<cg, 256, 0, st>>>(A);
-        if (any_trt) k_stream_collide_list<P, 1><<<cg, 256, 0, st>>>(A);
+        if (any_srt) k_stream_collide_list<P, 0><<<sg, 256, 0, st>>>(A);
+        if (any_trt) k_stream_collide_list<P, 1><<<sg, 256, 0, st>>>(A);
     } else {
         if (any_srt) launch_stream_collide<P, 0, 0>(cg, st, A);
         if (any_trt) launch_stream_collide<P, 1, 0>(cg, st, A);
@@ -1064,7 +1154,7 @@ std::vector<std::pair<size_t, size_t>> state_regions(const fslbm_lattice *h)
 {
     const Layout &L = h->L;
     const size_t N = h->N, fb = fbytes(h->prec), rb = rbytes(h->prec);
-    return {{h->cur == 0 ? L.fA : L.fB, 19 * N * fb},
+    return {{h->cur == 0 ? L.fA : L.fB, 19 * (size_t)h->NS * fb},
             {L.flags, N},
             {L.mark, 4 * N},
             {L.m, N * rb},
@@ -1113,7 +1203,7 @@ size_t adj_layout(AdjWindow &w, const fslbm_lattice *h)
     w.off_contrib = take((size_t)CONTRIB * std::max(1, w.icount) * 8);
     w.off_pos = take(4 * N);
     w.off_part = take(8 * (MASS_BLOCKS + 4));
-    w.f_bytes = align256(19 * N * fbytes(h->prec));
+    w.f_bytes = align256(19 * (size_t)h->NS * fbytes(h->prec));
     w.snap_bytes = align256(((size_t)SNAP * w.icount + w.ocount) * rbytes(h->prec));
     w.slot_bytes = w.f_bytes + w.snap_bytes;
     w.ck.clear();
@@ -1153,6 +1243,25 @@ Adj adj_fields(const AdjWindow &w, const fslbm_lattice *h, int par)
     return A;
 }
 
+// Reads the fluid box back (synchronises the stream) and sizes the bulk
+// stream-collide grid to it; a changed grid invalidates captured graphs.
+int refresh_box(fslbm_lattice *h)
+{
+    const DevScalars *sc = (const DevScalars *)(h->ws + h->L.sc);
+    int b[6];
+    HIP_OK(hipMemcpyAsync(b, sc->fbox, sizeof b, hipMemcpyDeviceToHost, h->stream));
+    HIP_OK(hipStreamSynchronize(h->stream));
+    long long cells = 0;
+    if (b[3] >= b[0] && b[4] >= b[1] && b[5] >= b[2])
+        cells = (long long)(b[3] - b[0] + 1) * (b[4] - b[1] + 1) * (b[5] - b[2] + 1);
+    const int blocks = (int)std::max(1LL, (cells + 255) / 256);
+    if (blocks != h->box_blocks) {
+        h->box_blocks = blocks;
+        h->version += 1;
+    }
+    return 0;
+}
+
 int read_counts(fslbm_lattice *h, int &icount, int &ocount)
 {
     const DevScalars *sc = (const DevScalars *)(h->ws + h->L.sc);
@@ -1189,7 +1298,7 @@ int save_slot(fslbm_lattice *h, const Slot &sl, bool with_f)
 {
     const Fields<P> F = make_fields<P>(h);
     if (with_f)
-        HIP_OK(hipMemcpyAsync(sl.f, F.fsrc, 19 * (size_t)h->N * fbytes(h->prec), hipMemcpyDeviceToDevice, h->stream));
+        HIP_OK(hipMemcpyAsync(sl.f, F.fsrc, 19 * (size_t)h->NS * fbytes(h->prec), hipMemcpyDeviceToDevice, h->stream));
     k_snap<P><<<list_blocks(h->N), 256, 0, h->stream>>>(F, (typename P::R *)sl.snap, 1);
     HIP_OK(hipGetLastError());
     return 0;
@@ -1344,7 +1453,7 @@ int do_adj_backward(fslbm_lattice *h, const double *dphi, int in_dev, double *ds
         rc = load_snap<P>(h, last.snap);
         if (rc) return rc;
         const Fields<P> F = make_fields<P>(h);
-        HIP_OK(hipMemcpyAsync((void *)F.fsrc, last.f, 19 * (size_t)N * fbytes(h->prec), hipMemcpyDeviceToDevice, st));
+        HIP_OK(hipMemcpyAsync((void *)F.fsrc, last.f, 19 * (size_t)h->NS * fbytes(h->prec), hipMemcpyDeviceToDevice, st));
     }
     HIP_OK(hipStreamSynchronize(st));
     if (dsig) *dsig = g[0];
@@ -1428,6 +1537,77 @@ int fslbm_required_bytes(int nx, int ny, int nz, int precision, size_t *bytes)
     return 0;
 }
 
+namespace {
+// What the closure of the interface layer at creation does to the input
+// (Sec. II.D: an interface cell has both gas and liquid D3Q19 neighbours;
+// the device closes the layer in two passes, see k_init_layer): a partly
+// filled cell without a gas neighbour closes to liquid; a cell of the layer
+// that keeps a gas neighbour but has no neighbour that ends the first pass
+// liquid closes to gas. A cell is thus rounded to one phase. Rounded to the
+// phase that fills less than half of it (a fill >= 1/2 closing to gas, or
+// <= 1/2 closing to liquid), it belonged to a liquid film or gas layer
+// thinner than one cell: the configuration of Fig. limitation, which the
+// method does not support. Host code, run before any device call; periodic
+// wrap on every axis as on the device.
+LayerClosure layer_closure(int nx, int ny, int nz, const double *fill, const uint8_t *obst)
+{
+    auto is_obst = [&](long long j) { return obst && obst[j]; };
+    auto gas0 = [&](long long j) { return !is_obst(j) && fill[j] <= 0.0; };
+    auto wrap = [](long long v, long long n) { return v < 0 ? v + n : (v >= n ? v - n : v); };
+    auto nbr = [&](long long x, long long y, long long z, int q) {
+        return wrap(x + dir_x(q), nx) + nx * (wrap(y + dir_y(q), ny) + (long long)ny * wrap(z + dir_z(q), nz));
+    };
+    auto has_gas = [&](long long j) {
+        const long long x = j % nx, y = (j / nx) % ny, z = j / ((long long)nx * ny);
+        for (int q = 1; q < NQ; ++q)
+            if (gas0(nbr(x, y, z, q))) return true;
+        return false;
+    };
+    // rows (y, z) that hold a gas cell: a liquid cell can touch gas only if
+    // its own or a neighbouring row does
+    std::vector<uint8_t> row_gas((size_t)ny * nz, 0);
+    for (long long r = 0; r < (long long)ny * nz; ++r)
+        for (long long x = 0; x < nx; ++x)
+            if (gas0(r * nx + x)) {
+                row_gas[r] = 1;
+                break;
+            }
+    LayerClosure c;
+    for (long long z = 0; z < nz; ++z)
+        for (long long y = 0; y < ny; ++y) {
+            bool near_gas = false;
+            for (int dz = -1; dz <= 1; ++dz)
+                for (int dy = -1; dy <= 1; ++dy) near_gas |= row_gas[wrap(y + dy, ny) + ny * wrap(z + dz, nz)] != 0;
+            for (long long x = 0; x < nx; ++x) {
+                const long long i = x + nx * (y + (long long)ny * z);
+                const double f = fill[i];
+                if (is_obst(i) || f <= 0.0) continue;
+                if (f >= 1.0 && !near_gas) continue;  // liquid far from gas
+                const bool g = near_gas && has_gas(i);
+                if (f >= 1.0 && !g) continue;  // liquid, not on the layer
+                if (!g) {  // a partly filled cell without a gas neighbour closes to liquid
+                    c.against += f <= 0.5;
+                    c.to_liquid += 1;
+                    c.fill_added += 1.0 - f;
+                    continue;
+                }
+                // on the layer after the first pass: closes to gas without a liquid neighbour
+                bool liquid_nbr = false;
+                for (int q = 1; q < NQ && !liquid_nbr; ++q) {
+                    const long long j = nbr(x, y, z, q);
+                    liquid_nbr = !is_obst(j) && fill[j] > 0.0 && !has_gas(j);
+                }
+                if (!liquid_nbr) {  // closes to gas (fill 1 for a liquid cell on the layer)
+                    c.against += f >= 0.5;
+                    c.to_gas += 1;
+                    c.fill_removed += std::min(f, 1.0);
+                }
+            }
+        }
+    return c;
+}
+}  // namespace
+
 int fslbm_create(int nx, int ny, int nz, int precision, int curv_model, const double *fill,
                  const uint8_t *obstacle, void *workspace, size_t workspace_bytes, void *hip_stream,
                  fslbm_t *out)
@@ -1449,10 +1629,17 @@ int fslbm_create(int nx, int ny, int nz, int precision, int curv_model, const do
     const Layout L = make_layout(nx, ny, nz, precision);
     if (workspace_bytes < L.total)
         return fail(FSLBM_E_SHAPE, "workspace has %zu bytes, %zu needed", workspace_bytes, L.total);
+    const LayerClosure closure = layer_closure(nx, ny, nz, fill, obstacle);
+    if (closure.against > 0)
+        return fail(FSLBM_E_TOPOLOGY,
+                    "%lld cells belong to a liquid film or gas layer thinner than one cell (the interface layer's "
+                    "closure would turn a fill >= 1/2 into gas or <= 1/2 into liquid); Sec. II.D calls this unsupported",
+                    closure.against);
     fslbm_lattice *h = new (std::nothrow) fslbm_lattice();
     if (!h) return fail(FSLBM_E_STATE, "out of host memory");
     h->nx = nx; h->ny = ny; h->nz = nz;
     h->N = (int)N;
+    h->NS = (int)plane_stride(N);
     h->prec = precision;
     h->curv = curv_model;
     h->coll = FSLBM_SRT;
@@ -1460,6 +1647,18 @@ int fslbm_create(int nx, int ny, int nz, int precision, int curv_model, const do
     h->eps_c = 1e-3; h->trt_magic = 3.0 / 16.0;
     h->stream = (hipStream_t)hip_stream;
     h->ws = (char *)workspace;
+    {
+        hipPointerAttribute_t attr;
+        if (hipPointerGetAttributes(&attr, workspace) == hipSuccess && attr.device >= 0) {
+            h->device = attr.device;
+        } else {
+            (void)hipGetLastError();
+            if (hipGetDevice(&h->device) != hipSuccess) {
+                delete h;
+                return fail(FSLBM_E_HIP, "cannot determine the device of the workspace");
+            }
+        }
+    }
     h->L = L;
     h->cur = 0;
     h->steps = 0;
@@ -1467,6 +1666,8 @@ int fslbm_create(int nx, int ny, int nz, int precision, int curv_model, const do
     h->epoch = 0;
     h->frozen = 0;
     h->bubble = 0;
+    h->strong_wetting = 0;
+    h->closure = closure;
     {
         long long nf = N;
         if (obstacle)
@@ -1478,6 +1679,7 @@ int fslbm_create(int nx, int ny, int nz, int precision, int curv_model, const do
     h->self.prec = precision;
     h->icount0 = 1 << 20;  // large until counted: the creation's own geometry launch
     h->ocount0 = 1 << 20;
+    h->box_blocks = (int)((N + 255) / 256);
     int rc = dispatch<OpInit>(h, fill, obstacle);
     if (!rc) {
         int ic = 0, oc = 0;
@@ -1485,11 +1687,27 @@ int fslbm_create(int nx, int ny, int nz, int precision, int curv_model, const do
         h->icount0 = ic;
         h->ocount0 = oc;
     }
+    if (!rc) rc = refresh_box(h);
     if (rc) {
         delete h;
         return rc;
     }
     *out = h;
+    return 0;
+}
+
+// Smallest contact angle accepted by default (Sec. II.D): 45 degrees, with a
+// margin for the rounding of a converted 45.
+constexpr double THETA_MIN = M_PI / 4.0 - 1e-12;
+
+int fslbm_layer_closure(fslbm_t h, int64_t *to_liquid, int64_t *to_gas, double *fill_added, double *fill_removed)
+{
+    if (!h) return fail(FSLBM_E_STATE, "null handle");
+    if (!to_liquid || !to_gas || !fill_added || !fill_removed) return fail(FSLBM_E_ARG, "an output is NULL");
+    *to_liquid = h->closure.to_liquid;
+    *to_gas = h->closure.to_gas;
+    *fill_added = h->closure.fill_added;
+    *fill_removed = h->closure.fill_removed;
     return 0;
 }
 
@@ -1500,6 +1718,11 @@ int fslbm_set_params(fslbm_t h, double sigma, double tau, double theta_rad, doub
     if (!(tau > 0.5) || !std::isfinite(tau)) return fail(FSLBM_E_ARG, "tau must be > 1/2");
     if (!(theta_rad > 0.0 && theta_rad < M_PI)) return fail(FSLBM_E_ARG, "theta must lie in (0, pi)");
     if (!(rho_gas > 0.0) || !std::isfinite(rho_gas)) return fail(FSLBM_E_ARG, "rho_gas must be > 0");
+    if (theta_rad < THETA_MIN && !h->strong_wetting)
+        return fail(FSLBM_E_TOPOLOGY,
+                    "theta = %.4g deg is below 45 deg: Sec. II.D calls contact angles below 45 deg unsupported "
+                    "(FSLBM_OPT_STRONG_WETTING = 1 allows them)",
+                    theta_rad * 180.0 / M_PI);
     h->sigma = sigma; h->tau = tau; h->theta = theta_rad; h->rho_gas = rho_gas;
     h->version += 1;
     h->epoch += 1;
@@ -1533,6 +1756,12 @@ int fslbm_set_option(fslbm_t h, int key, double value)
         h->epoch += 1;
         h->bubble = value != 0.0;
         return h->bubble ? dispatch<OpBubble>(h) : 0;
+    case FSLBM_OPT_STRONG_WETTING:
+        if (value != 0.0 && value != 1.0) return fail(FSLBM_E_ARG, "strong wetting must be 0 or 1");
+        if (value == 0.0 && h->theta < THETA_MIN)
+            return fail(FSLBM_E_TOPOLOGY, "the current theta is below 45 deg; set theta >= 45 deg first");
+        h->strong_wetting = (int)value;
+        return 0;
     case FSLBM_OPT_TIMING:
     case FSLBM_OPT_GRAPH:
     case FSLBM_OPT_SPLIT_INTERFACE: return fslbm_batch_set_option(&h->self, key, value);
@@ -1644,11 +1873,15 @@ void fslbm_batch_destroy(fslbm_batch_t b)
     delete b;
 }
 
+// After a call that has synchronised the stream anyway, the fluid box is
+// read back so that the next steps' grid fits it.
+static int then_refresh(fslbm_t h, int rc) { return rc ? rc : refresh_box(h); }
+
 static int read_common(fslbm_t h, int what, double *out, int dev)
 {
     if (!h) return fail(FSLBM_E_STATE, "null handle");
     if (!out) return fail(FSLBM_E_ARG, "out is NULL");
-    return dispatch<OpRead>(h, what, out, dev);
+    return then_refresh(h, dispatch<OpRead>(h, what, out, dev));
 }
 
 int fslbm_read_fill(fslbm_t h, double *out, int d) { return read_common(h, RD_FILL, out, d); }
@@ -1670,6 +1903,31 @@ int fslbm_read_flags(fslbm_t h, uint8_t *out, int out_is_device)
     HIP_OK(hipGetLastError());
     if (!out_is_device) HIP_OK(hipMemcpyAsync(out, dst, N, hipMemcpyDeviceToHost, h->stream));
     HIP_OK(hipStreamSynchronize(h->stream));
+    return refresh_box(h);
+}
+
+// Runs the ordered compaction of the interface cells with the given
+// scratch and copies the count (and, with out, the list) to the host.
+static int read_ilist(fslbm_t h, const ListScratch &s, int32_t *out, int64_t capacity, int64_t *count)
+{
+    const uint8_t *flags = (const uint8_t *)(h->ws + h->L.flags);
+    const DevScalars *sc = (const DevScalars *)(h->ws + h->L.sc);
+    k_ilist_count<<<CMP_GRID, 256, 0, h->stream>>>(flags, sc, h->nx, h->ny, s);
+    k_ilist_scan<<<1, 1024, 0, h->stream>>>(s, CMP_GRID);
+    k_ilist_write<<<CMP_GRID, 256, 0, h->stream>>>(flags, sc, h->nx, h->ny, s);
+    HIP_OK(hipGetLastError());
+    int n = 0;
+    HIP_OK(hipMemcpyAsync(&n, s.total, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    HIP_OK(hipStreamSynchronize(h->stream));
+    if (n > s.cap)
+        return fail(FSLBM_E_SHAPE, "interface list has %d cells; the scratch of this call holds at most %d", n, s.cap);
+    *count = n;
+    if (!out) return 0;
+    if (n > capacity) return fail(FSLBM_E_SHAPE, "interface list has %d entries, capacity %lld", n, (long long)capacity);
+    if (n > 0) {
+        HIP_OK(hipMemcpyAsync(out, s.list, sizeof(int32_t) * n, hipMemcpyDeviceToHost, h->stream));
+        HIP_OK(hipStreamSynchronize(h->stream));
+    }
     return 0;
 }
 
@@ -1677,19 +1935,14 @@ int fslbm_read_interface_list(fslbm_t h, int32_t *out, int64_t capacity, int64_t
 {
     if (!h) return fail(FSLBM_E_STATE, "null handle");
     if (!count) return fail(FSLBM_E_ARG, "count is NULL");
-    const DevScalars *sc = (const DevScalars *)(h->ws + h->L.sc);
-    int n = 0;
-    HIP_OK(hipMemcpyAsync(&n, &sc->icount, sizeof(int), hipMemcpyDeviceToHost, h->stream));
-    HIP_OK(hipStreamSynchronize(h->stream));
-    *count = n;
-    if (!out) return 0;
-    if (n > capacity) return fail(FSLBM_E_SHAPE, "interface list has %d entries, capacity %lld", n, (long long)capacity);
-    if (n > 0) {
-        HIP_OK(hipMemcpyAsync(out, h->ws + h->L.ilist, sizeof(int32_t) * n, hipMemcpyDeviceToHost, h->stream));
-        HIP_OK(hipStreamSynchronize(h->stream));
-        std::sort(out, out + n);  // the device list is kept unordered between compactions
-    }
-    return 0;
+    // scratch inside the workspace: the compaction counts and the staging area
+    char *stg = h->ws + h->L.staging;
+    ListScratch s;
+    s.counts = (int *)(h->ws + h->L.counts);
+    s.total = (int *)stg;
+    s.list = (int32_t *)(stg + 256);
+    s.cap = h->N;
+    return read_ilist(h, s, out, capacity, count);
 }
 
 int fslbm_gas_density(fslbm_t h, double *rho_gas)
@@ -1710,20 +1963,20 @@ int fslbm_mass(fslbm_t h, double *total)
 {
     if (!h) return fail(FSLBM_E_STATE, "null handle");
     if (!total) return fail(FSLBM_E_ARG, "total is NULL");
-    return dispatch<OpMass>(h, total);
+    return then_refresh(h, dispatch<OpMass>(h, total));
 }
 
 int fslbm_diagnostics(fslbm_t h, double *out)
 {
     if (!h) return fail(FSLBM_E_STATE, "null handle");
     if (!out) return fail(FSLBM_E_ARG, "out is NULL");
-    return dispatch<OpDiag>(h, out);
+    return then_refresh(h, dispatch<OpDiag>(h, out));
 }
 
 int fslbm_check_numeric(fslbm_t h)
 {
     if (!h) return fail(FSLBM_E_STATE, "null handle");
-    return dispatch<OpCheck>(h);
+    return then_refresh(h, dispatch<OpCheck>(h));
 }
 
 int fslbm_steps_taken(fslbm_t h, int64_t *steps)
@@ -1805,7 +2058,7 @@ int fslbm_load_state(fslbm_t h, const void *src, size_t bytes)
     const int rc = read_counts(h, ic, oc);
     if (rc) return rc;
     h->ocount0 = oc;
-    return 0;
+    return refresh_box(h);
 }
 
 int fslbm_adjoint_required_bytes(fslbm_t h, int64_t nsteps, int K, size_t *bytes)

@@ -141,7 +141,7 @@ __global__ __launch_bounds__(256) void k_conv_mark_init(const Batch<P> B)
 #pragma unroll
                     for (int s = 0; s < NQ; ++s) {
                         switch (s) {
-#define FSLBM_LD(QQ) case QQ: fw[s] = load_f<P, QQ>(plane<P, QQ>((const typename P::S *)F.fdst, N), w); break;
+#define FSLBM_LD(QQ) case QQ: fw[s] = load_f<P, QQ>(plane<P, QQ>((const typename P::S *)F.fdst, F.NS), w); break;
                             FSLBM_LD(0) FSLBM_LD(1) FSLBM_LD(2) FSLBM_LD(3) FSLBM_LD(4) FSLBM_LD(5)
                             FSLBM_LD(6) FSLBM_LD(7) FSLBM_LD(8) FSLBM_LD(9) FSLBM_LD(10) FSLBM_LD(11)
                             FSLBM_LD(12) FSLBM_LD(13) FSLBM_LD(14) FSLBM_LD(15) FSLBM_LD(16)
@@ -160,7 +160,7 @@ __global__ __launch_bounds__(256) void k_conv_mark_init(const Batch<P> B)
                 for (int s = 0; s < NQ; ++s) {
                     const T v = feq<T>(s, rm, ux, uy, uz, usq);
                     switch (s) {
-#define FSLBM_ST(QQ) case QQ: store_f<P, QQ>(plane<P, QQ>(F.fdst, N), j, v); break;
+#define FSLBM_ST(QQ) case QQ: store_f<P, QQ>(plane<P, QQ>(F.fdst, F.NS), j, v); break;
                         FSLBM_ST(0) FSLBM_ST(1) FSLBM_ST(2) FSLBM_ST(3) FSLBM_ST(4) FSLBM_ST(5)
                         FSLBM_ST(6) FSLBM_ST(7) FSLBM_ST(8) FSLBM_ST(9) FSLBM_ST(10) FSLBM_ST(11)
                         FSLBM_ST(12) FSLBM_ST(13) FSLBM_ST(14) FSLBM_ST(15) FSLBM_ST(16)
@@ -177,7 +177,7 @@ __global__ __launch_bounds__(256) void k_conv_mark_init(const Batch<P> B)
 #pragma unroll
                 for (int s = 0; s < NQ; ++s) {
                     switch (s) {
-#define FSLBM_LD(QQ) case QQ: fw[s] = load_f<P, QQ>(plane<P, QQ>((const typename P::S *)F.fdst, N), j); break;
+#define FSLBM_LD(QQ) case QQ: fw[s] = load_f<P, QQ>(plane<P, QQ>((const typename P::S *)F.fdst, F.NS), j); break;
                         FSLBM_LD(0) FSLBM_LD(1) FSLBM_LD(2) FSLBM_LD(3) FSLBM_LD(4) FSLBM_LD(5)
                         FSLBM_LD(6) FSLBM_LD(7) FSLBM_LD(8) FSLBM_LD(9) FSLBM_LD(10) FSLBM_LD(11)
                         FSLBM_LD(12) FSLBM_LD(13) FSLBM_LD(14) FSLBM_LD(15) FSLBM_LD(16)

@@ -202,7 +202,7 @@ __device__ inline double gas_density(const Params &p, const DevScalars *sc)
 template <class P> struct Fields {
     using S = typename P::S;
     using R = typename P::R;
-    const S *fsrc;     // f'(t), 19 planes of N
+    const S *fsrc;     // f'(t), 19 planes of N cells, NS elements apart
     S *fdst;           // f'(t+1)
     uint8_t *flags;
     uint8_t *conv;
@@ -218,6 +218,7 @@ template <class P> struct Fields {
     DevScalars *sc;
     int nx, ny, nz;
     int N;
+    int NS;            // plane stride of the distribution buffers (elements, >= N)
 };
 
 // Up to MAXB lattices advanced by one launch per kernel: lattice b is

@@ -103,15 +103,16 @@ __device__ inline void collide(T (&f)[NQ], const Params &p)
     }
 }
 
+// Plane Q of a distribution buffer whose planes are NS elements apart.
 template <class P, int Q>
-__device__ inline const typename P::S *plane(const typename P::S *base, int N)
+__device__ inline const typename P::S *plane(const typename P::S *base, int NS)
 {
-    return base + (size_t)Q * (size_t)N;
+    return base + (size_t)Q * (size_t)NS;
 }
 template <class P, int Q>
-__device__ inline typename P::S *plane(typename P::S *base, int N)
+__device__ inline typename P::S *plane(typename P::S *base, int NS)
 {
-    return base + (size_t)Q * (size_t)N;
+    return base + (size_t)Q * (size_t)NS;
 }
 
 template <class P>
@@ -120,7 +121,7 @@ __device__ inline void store_all(const Fields<P> &F, int i, const typename P::T 
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
         switch (q) {
-#define FSLBM_STORE(QQ) case QQ: store_f<P, QQ>(plane<P, QQ>(F.fdst, F.N), i, f[q]); break;
+#define FSLBM_STORE(QQ) case QQ: store_f<P, QQ>(plane<P, QQ>(F.fdst, F.NS), i, f[q]); break;
             FSLBM_STORE(0) FSLBM_STORE(1) FSLBM_STORE(2) FSLBM_STORE(3) FSLBM_STORE(4)
             FSLBM_STORE(5) FSLBM_STORE(6) FSLBM_STORE(7) FSLBM_STORE(8) FSLBM_STORE(9)
             FSLBM_STORE(10) FSLBM_STORE(11) FSLBM_STORE(12) FSLBM_STORE(13) FSLBM_STORE(14)
@@ -137,7 +138,7 @@ __device__ inline void load_dirs(const Fields<P> &F, const int (&j)[NQ], typenam
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
         switch (q) {
-#define FSLBM_LD(QQ) case QQ: f[q] = load_f<P, QQ>(plane<P, QQ>(F.fsrc, F.N), j[q]); break;
+#define FSLBM_LD(QQ) case QQ: f[q] = load_f<P, QQ>(plane<P, QQ>(F.fsrc, F.NS), j[q]); break;
             FSLBM_LD(0) FSLBM_LD(1) FSLBM_LD(2) FSLBM_LD(3) FSLBM_LD(4)
             FSLBM_LD(5) FSLBM_LD(6) FSLBM_LD(7) FSLBM_LD(8) FSLBM_LD(9)
             FSLBM_LD(10) FSLBM_LD(11) FSLBM_LD(12) FSLBM_LD(13) FSLBM_LD(14)
@@ -350,9 +351,14 @@ __device__ inline void fluid_cell(const Fields<P> &F, const Params &prm, int i, 
 
 // Stream-collide over the fluid bounding box. MODE 0: every fluid cell;
 // MODE 1: only liquid cells away from walls (the lean pull, few registers;
-// the other fluid cells then go through k_stream_collide_list). Each block
-// takes one contiguous run of the box, so the rows it pulls from stay in
-// one XCD's L2.
+// the other fluid cells then go through k_stream_collide_list). Block b
+// takes the 256 consecutive box cells from 256 b; the host sizes the grid
+// to the box it last read back, so normally each block has one chunk and
+// returns (a box that has grown since is covered by a grid-stride tail).
+// Blocks are dispatched in index order, so the blocks in flight at any
+// moment work on one narrow window of the box and the 38 distribution
+// streams stay within few DRAM pages; blocks that each walk a long share of
+// the box drift apart and lose that locality.
 template <class P, int COLL, int MODE>
 __device__ inline void stream_collide_box(const Batch<P> &B)
 {
@@ -360,32 +366,20 @@ __device__ inline void stream_collide_box(const Batch<P> &B)
     if (prm.coll != COLL) return;
     const Fields<P> &F = B.f[blockIdx.y];
     const CellRange box = CellRange::from(F.sc->fbox);
-    int k0, k1;
-    block_share(box.size(), k0, k1);
-    int k = k0 + threadIdx.x;
-    if (k >= k1) return;
-    // box coordinates of k, then advanced by 256 cells per iteration
-    int bx = k % box.ex, r = k / box.ex, by = r % box.ey, bz = r / box.ey;
-    const int nxy = F.nx * F.ny;
-    for (; k < k1; k += 256) {
+    const int n = box.size();
+    for (int c = blockIdx.x; c * 256 < n; c += gridDim.x) {
+        const int k = c * 256 + (int)threadIdx.x;
+        if (k >= n) continue;
+        const int bx = k % box.ex, r = k / box.ex, by = r % box.ey, bz = r / box.ey;
         const int x = box.x0 + bx, y = box.y0 + by, z = box.z0 + bz;
-        const int i = x + F.nx * y + nxy * z;
+        const int i = x + F.nx * (y + F.ny * z);
         const uint8_t fl = F.flags[i];
-        if (fl & FL_FLUID) {
-            const Nbr nb(x, y, z, F.nx, F.ny, F.nz);
-            if (MODE == 1) {
-                if (fl == FL_LIQ) liquid_cell<P, COLL>(F, prm, i, nb);
-            } else {
-                fluid_cell<P, COLL>(F, prm, i, nb, fl);
-            }
-        }
-        bx += 256;
-        while (bx >= box.ex) {
-            bx -= box.ex;
-            if (++by == box.ey) {
-                by = 0;
-                ++bz;
-            }
+        if (!(fl & FL_FLUID)) continue;
+        const Nbr nb(x, y, z, F.nx, F.ny, F.nz);
+        if (MODE == 1) {
+            if (fl == FL_LIQ) liquid_cell<P, COLL>(F, prm, i, nb);
+        } else {
+            fluid_cell<P, COLL>(F, prm, i, nb, fl);
         }
     }
 }

@@ -26,7 +26,9 @@ FSLBM_GAS, FSLBM_LIQUID, FSLBM_INTERFACE, FSLBM_OBSTACLE = 0, 1, 2, 3
 FSLBM_OPT_EPS_C, FSLBM_OPT_COLLISION, FSLBM_OPT_TRT_MAGIC, FSLBM_OPT_TIMING, FSLBM_OPT_GRAPH = 0, 1, 2, 3, 4
 FSLBM_OPT_SPLIT_INTERFACE = 5
 FSLBM_OPT_BUBBLE = 6
+FSLBM_OPT_STRONG_WETTING = 7
 FSLBM_OK, FSLBM_E_ARG, FSLBM_E_SHAPE, FSLBM_E_HIP, FSLBM_E_STATE, FSLBM_E_NUMERIC = 0, -1, -2, -3, -4, -5
+FSLBM_E_TOPOLOGY = -6
 
 PRECISIONS = {"f64": FSLBM_F64, "f32": FSLBM_F32, "f16": FSLBM_F16_STORE, "bf16": FSLBM_BF16_STORE}
 MODELS = {"fd": FSLBM_CURV_FD, "lsqr": FSLBM_CURV_LSQR, "tr": FSLBM_CURV_TR}
@@ -56,6 +58,7 @@ def load_library(path: str = LIB_PATH):
         "fslbm_required_bytes": [i32, i32, i32, i32, ctypes.POINTER(ctypes.c_size_t)],
         "fslbm_create": [i32, i32, i32, i32, i32, dp, u8p, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)],
         "fslbm_set_params": [vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double],
+        "fslbm_layer_closure": [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), dp, dp],
         "fslbm_set_option": [vp, i32, ctypes.c_double],
         "fslbm_set_stream": [vp, vp],
         "fslbm_set_equilibrium": [vp, dp, dp],
@@ -206,6 +209,15 @@ def fslbm_read_interface_list(h):
     return out[:cnt.value]
 
 
+def fslbm_layer_closure(h):
+    """(cells closed to liquid, cells closed to gas, fill added, fill removed)
+    by the closure of the interface layer at creation."""
+    a, b = ctypes.c_int64(0), ctypes.c_int64(0)
+    c, d = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    _check(load_library().fslbm_layer_closure(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(d)))
+    return a.value, b.value, c.value, d.value
+
+
 def fslbm_gas_density(h):
     out = ctypes.c_double(0.0)
     _check(load_library().fslbm_gas_density(h, ctypes.byref(out)))
@@ -340,7 +352,7 @@ class Lattice:
 
     def __init__(self, fill, obstacle=None, *, precision="f64", curv_model="fd", sigma=0.0, tau=1.0,
                  theta=math.pi / 2, rho_gas=1.0, eps_c=None, collision="srt", trt_magic=None,
-                 bubble=False, device="cuda:0", stream=None):
+                 bubble=False, strong_wetting=False, device="cuda:0", stream=None):
         import torch
 
         fill = np.ascontiguousarray(fill, dtype=np.float64)
@@ -363,6 +375,8 @@ class Lattice:
         if trt_magic is not None:
             fslbm_set_option(self._h, FSLBM_OPT_TRT_MAGIC, trt_magic)
         fslbm_set_option(self._h, FSLBM_OPT_COLLISION, FSLBM_TRT if collision == "trt" else FSLBM_SRT)
+        if strong_wetting:
+            fslbm_set_option(self._h, FSLBM_OPT_STRONG_WETTING, 1)
         self.sigma, self.tau, self.theta, self.rho_gas = sigma, tau, theta, rho_gas
         fslbm_set_params(self._h, sigma, tau, theta, rho_gas)
         if bubble:
@@ -385,11 +399,10 @@ class Lattice:
             pass
 
     def set_params(self, sigma=None, tau=None, theta=None, rho_gas=None):
-        self.sigma = self.sigma if sigma is None else float(sigma)
-        self.tau = self.tau if tau is None else float(tau)
-        self.theta = self.theta if theta is None else float(theta)
-        self.rho_gas = self.rho_gas if rho_gas is None else float(rho_gas)
-        fslbm_set_params(self._h, self.sigma, self.tau, self.theta, self.rho_gas)
+        new = (self.sigma if sigma is None else float(sigma), self.tau if tau is None else float(tau),
+               self.theta if theta is None else float(theta), self.rho_gas if rho_gas is None else float(rho_gas))
+        fslbm_set_params(self._h, *new)  # raises, leaving the parameters unchanged, on a rejected value
+        self.sigma, self.tau, self.theta, self.rho_gas = new
 
     def set_equilibrium(self, rho, u):
         rho = np.broadcast_to(np.asarray(rho, dtype=np.float64), self.shape)

@@ -87,3 +87,40 @@ def test_create_rejects_bad_arguments_before_touching_the_device(lib):
     # null handle
     assert lib.fslbm_step(None, 1) == -4
     assert lib.fslbm_set_params(None, 0.0, 1.0, 1.0, 1.0) == -4
+
+
+def _film_on_wall(thickness, n=16):
+    """A liquid film of the given thickness (cells) on the wall z = 0 of an
+    n^3 box, gas above (exact cell fractions)."""
+    fill = np.zeros((n, n, n))
+    obst = np.zeros((n, n, n), np.uint8)
+    obst[0] = 1
+    full = int(np.floor(thickness))
+    fill[1:1 + full] = 1.0
+    if thickness > full:
+        fill[1 + full] = thickness - full
+    return fill, obst
+
+
+@pytest.mark.parametrize("thickness", [0.6, 1.0])
+def test_create_rejects_films_thinner_than_one_cell(lib, thickness):
+    """Sec. II.D, Fig. limitation: a liquid film on a wall must hold at least
+    one liquid cell; thinner films are rejected on the host, before any
+    device call (the workspace pointer here is never dereferenced)."""
+    fill, obst = _film_on_wall(thickness)
+    h = ctypes.c_void_p()
+    rc = lib.fslbm_create(16, 16, 16, 1, 1, fill.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                          obst.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), ctypes.c_void_p(1 << 20), 1 << 62,
+                          None, ctypes.byref(h))
+    assert rc == fslbm.FSLBM_E_TOPOLOGY
+    assert b"thinner than one cell" in lib.fslbm_last_error()
+    assert not h.value
+
+
+def test_create_rejects_gas_layers_thinner_than_one_cell(lib):
+    fill = np.ones((16, 16, 16))
+    fill[5] = 0.3  # a gas layer of 0.7 cells between liquid
+    h = ctypes.c_void_p()
+    rc = lib.fslbm_create(16, 16, 16, 1, 1, fill.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), None,
+                          ctypes.c_void_p(1 << 20), 1 << 62, None, ctypes.byref(h))
+    assert rc == fslbm.FSLBM_E_TOPOLOGY

@@ -84,3 +84,50 @@ def test_checkpoint_resume_bit_identical(fs, precision, model):
     assert err.value.code == fs.FSLBM_E_ARG
     for lat in (a, b, c):
         lat.close()
+
+
+@pytest.mark.gpu
+def test_contact_angles_below_45_degrees_are_rejected():
+    """Sec. II.D: contact angles below 45 degrees are unsupported; the
+    library rejects them unless FSLBM_OPT_STRONG_WETTING is set, and a
+    rejected call leaves the parameters unchanged."""
+    import math
+
+    from paper_1509_07691_amd import fslbm as F
+
+    fill, obst = I.sessile_droplet(28, 28, 14, 7.0, noise=1e-6)
+    lat = F.Lattice(fill, obst, precision="f64", curv_model="lsqr", sigma=1e-3, tau=0.8,
+                    theta=math.radians(60.0), device="cuda:0")
+    K0 = lat.curvature()
+    with pytest.raises(F.FslbmError) as e:
+        lat.set_params(theta=math.radians(30.0))
+    assert e.value.code == F.FSLBM_E_TOPOLOGY
+    assert lat.theta == pytest.approx(math.radians(60.0))
+    np.testing.assert_array_equal(lat.curvature(), K0)
+    lat.set_params(theta=math.radians(45.0))  # the boundary value is accepted
+    F.fslbm_set_option(lat.handle, F.FSLBM_OPT_STRONG_WETTING, 1)
+    lat.set_params(theta=math.radians(30.0))
+    with pytest.raises(F.FslbmError) as e:
+        F.fslbm_set_option(lat.handle, F.FSLBM_OPT_STRONG_WETTING, 0)
+    assert e.value.code == F.FSLBM_E_TOPOLOGY
+    lat.close()
+
+
+@pytest.mark.gpu
+def test_layer_closure_is_reported():
+    """The ideal 60-degree cap at dx = 1/48 loses the thin corner cells of
+    its contact line to the closure of the interface layer (Sec. II.D); the
+    report counts them and the fill they held, and the closed cells read
+    back as gas and liquid."""
+    from paper_1509_07691_amd import fslbm as F
+
+    fill, obst, _, _ = I.sessile_cap(48, 60.0)
+    lat = F.Lattice(fill, obst, precision="f64", curv_model="lsqr", device="cuda:0")
+    to_liq, to_gas, added, removed = F.fslbm_layer_closure(lat.handle)
+    fl = lat.flags()
+    part = (fill > 0) & (fill < 1) & (obst == 0)
+    assert to_gas == int((part & (fl == F.FSLBM_GAS)).sum()) == 32
+    assert to_liq == int((part & (fl == F.FSLBM_LIQUID)).sum()) == 40
+    assert removed == pytest.approx(fill[part & (fl == F.FSLBM_GAS)].sum(), rel=1e-12)
+    assert added == pytest.approx((1.0 - fill[part & (fl == F.FSLBM_LIQUID)]).sum(), rel=1e-12)
+    lat.close()
