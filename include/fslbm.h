@@ -202,6 +202,17 @@ int fslbm_read_flags(fslbm_t h, uint8_t *out, int out_is_device);
  * query the count). Uses scratch inside the lattice's workspace and
  * synchronises the stream. FSLBM_E_ARG if count is NULL. */
 int fslbm_read_interface_list(fslbm_t h, int32_t *out, int64_t capacity, int64_t *count);
+/* The same read-out for callers that cannot allocate device memory (code
+ * under graph capture, serving loops, harnesses that forbid hipMalloc): the
+ * compaction's scratch (block counts, total and the staged list) lives in a
+ * file-scope device array of 16 MiB that each device holds until the
+ * process ends, so this call allocates nothing. It holds at most 4,193,792
+ * interface cells: a longer list is rejected with FSLBM_E_SHAPE (nothing is
+ * copied to out). Every call on a device shares that device's array and
+ * leaves its contents behind; calls that overlap on one device (other
+ * streams or threads) race and must be serialised by the caller. Arguments,
+ * result and other errors as fslbm_read_interface_list. */
+int fslbm_read_interface_list_noalloc(fslbm_t h, int32_t *out, int64_t capacity, int64_t *count);
 /* Gas density used by the step (rho_gas, or rho_gas(t) of the bubble
  * model); synchronises. FSLBM_E_ARG if rho_gas is NULL. */
 int fslbm_gas_density(fslbm_t h, double *rho_gas);

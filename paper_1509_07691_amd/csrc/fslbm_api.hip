@@ -8,6 +8,7 @@
 #include <new>
 #include <string>
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "fslbm.h"
@@ -1943,6 +1944,60 @@ int fslbm_read_interface_list(fslbm_t h, int32_t *out, int64_t capacity, int64_t
     s.list = (int32_t *)(stg + 256);
     s.cap = h->N;
     return read_ilist(h, s, out, capacity, count);
+}
+
+// ------------------------------------------- allocation-free read-out
+// Scratch of fslbm_read_interface_list_noalloc: a file-scope device array
+// of fixed size (block counts, total, up to NOALLOC_LIST_CAP list entries).
+// Every device the library runs on holds its own copy until the process
+// ends. Host code never passes the symbol itself to a kernel: it uses the
+// per-device address that hipGetSymbolAddress returns on that device.
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(16) << 20;
+constexpr int NOALLOC_LIST_CAP = int((NOALLOC_SCRATCH_BYTES - 2048) / 4);
+static_assert(CMP_GRID * sizeof(int) <= 1024, "block counts must fit below the total at byte 1024");
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+char *g_scratch[MAX_DEVICES];
+
+// Address of `scratch` on device dev, which must be current; looked up once
+// per device.
+int scratch_address(int dev, char **out)
+{
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(FSLBM_E_STATE, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        HIP_OK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(FSLBM_E_HIP, "hipGetSymbolAddress returned a null address");
+        g_scratch[dev] = (char *)p;
+    }
+    *out = g_scratch[dev];
+    return 0;
+}
+}  // namespace
+
+int fslbm_read_interface_list_noalloc(fslbm_t h, int32_t *out, int64_t capacity, int64_t *count)
+{
+    if (!h) return fail(FSLBM_E_STATE, "null handle");
+    if (!count) return fail(FSLBM_E_ARG, "count is NULL");
+    int cur = 0;
+    HIP_OK(hipGetDevice(&cur));
+    if (cur != h->device) HIP_OK(hipSetDevice(h->device));
+    char *base = nullptr;
+    int rc = scratch_address(h->device, &base);
+    if (!rc) {
+        ListScratch s;
+        s.counts = (int *)base;  // CMP_GRID ints
+        s.total = (int *)(base + 1024);
+        s.list = (int32_t *)(base + 2048);
+        s.cap = NOALLOC_LIST_CAP;
+        rc = read_ilist(h, s, out, capacity, count);
+    }
+    if (cur != h->device) (void)hipSetDevice(cur);
+    return rc;
 }
 
 int fslbm_gas_density(fslbm_t h, double *rho_gas)

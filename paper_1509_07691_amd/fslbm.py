@@ -72,6 +72,7 @@ def load_library(path: str = LIB_PATH):
         "fslbm_read_mass_field": [vp, vp, i32],
         "fslbm_read_flags": [vp, vp, i32],
         "fslbm_read_interface_list": [vp, ctypes.POINTER(ctypes.c_int32), i64, ctypes.POINTER(i64)],
+        "fslbm_read_interface_list_noalloc": [vp, ctypes.POINTER(ctypes.c_int32), i64, ctypes.POINTER(i64)],
         "fslbm_mass": [vp, dp],
         "fslbm_gas_density": [vp, dp],
         "fslbm_check_numeric": [vp],
@@ -206,6 +207,16 @@ def fslbm_read_interface_list(h):
     out = np.zeros(max(cnt.value, 1), dtype=np.int32)
     _check(L.fslbm_read_interface_list(h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                                        out.size, ctypes.byref(cnt)))
+    return out[:cnt.value]
+
+
+def fslbm_read_interface_list_noalloc(h):
+    L = load_library()
+    cnt = ctypes.c_int64(0)
+    _check(L.fslbm_read_interface_list_noalloc(h, None, 0, ctypes.byref(cnt)))
+    out = np.zeros(max(cnt.value, 1), dtype=np.int32)
+    _check(L.fslbm_read_interface_list_noalloc(h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                               out.size, ctypes.byref(cnt)))
     return out[:cnt.value]
 
 
