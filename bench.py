@@ -1,20 +1,23 @@
 """Benchmark of the FSLBM hot path on one MI355X.
 
-Default workload: the static-droplet sweep of radius 32 in a periodic 128^3
-lattice, FP32 storage and arithmetic, eight runs (tau 0.6 / 1.0 x sigma 1e-4 /
-1e-3 x FD / LSQR curvature) advanced together; one step is one time step of
-all eight lattices (stream-collide with mass exchange, conversions, list
-compaction, obstacle fill, curvature). Inputs are synthetic: exact sphere
-volume fractions plus 1e-6 uniform noise on interface cells (seed 0).
+Default workload (the line's value, roofline and cpu_baseline): the HBM
+roofline probe, a gas bubble of radius 64 in a liquid-filled periodic 512^3
+lattice (99.2 % of the cells fluid), LSQR curvature, sigma 1e-3, tau 0.8,
+FP32 storage and arithmetic. One step is one time step of the whole hot path
+(stream-collide with mass exchange, conversions, interface-list update,
+obstacle fill, curvature). Inputs are synthetic: exact sphere volume
+fractions.
 
-Prints one JSON line: MLUPS over all lattice cells (value), the roofline of the
-dominant kernel (stream-collide, timed with HIP events on each lattice's own
-stream inside the timed region) and the FP64 CPU reference timed on a bounded
-sample of the same workload.
+Extra keys of the same JSON line: the probe with F16 and BF16 storage of
+f - w_q; the 512^3 oscillating droplet (ellipsoid 96/80/80, sigma 1e-3,
+tau 0.55) over 10,000 steps per storage form; the static-droplet sweep of
+eight 128^3 lattices; the 256 x 256 x 128 sessile droplets; the adjoint
+window's cost; the FP64 CPU oracle on one core and on all cores.
 """
 from __future__ import annotations
 
 import argparse
+import functools
 import hashlib
 import json
 import math
@@ -38,8 +41,10 @@ RBYTES = {"f64": 8, "f32": 4, "f16": 4, "bf16": 4}
 SWEEP_RADIUS = 32.0  # droplet of the droplet sweep
 
 
+@functools.lru_cache(maxsize=3)
 def workload_runs(name):
-    """List of (label, fill, obstacle, params) of one workload."""
+    """List of (label, fill, obstacle, params) of one workload (cached: the
+    512^3 inputs take seconds to build)."""
     from paper_1509_07691_amd import inputs as I
 
     if name == "droplet-sweep":
@@ -60,20 +65,32 @@ def workload_runs(name):
     if name == "bubble-probe":
         fill, obst = I.bubble_probe(512, 64.0)
         return [("bubble", fill, obst, dict(curv_model="lsqr", tau=0.8, sigma=1e-3))], \
-            "gas bubble R=64 in liquid-filled periodic 512^3, LSQR"
+            ("roofline probe: gas bubble R=64 in a liquid-filled periodic 512^3 lattice (99.2 % fluid cells), "
+             "LSQR, sigma 1e-3, tau 0.8")
     raise SystemExit(f"unknown workload {name}")
 
 
+def fluid_box_cells(flags):
+    """Cells of the bounding box of the fluid (liquid and interface) cells,
+    the range the stream-collide kernel reads flags over."""
+    fl = (flags == 1) | (flags == 2)
+    if not fl.any():
+        return 0
+    ext = [np.flatnonzero(fl.any(axis=a)) for a in ((1, 2), (0, 2), (0, 1))]
+    return int(np.prod([e[-1] - e[0] + 1 for e in ext]))
+
+
 def sc_bytes(flags, prec):
-    """Algorithmic bytes of one launch of the liquid stream-collide kernel:
-    19 reads + 19 writes of a distribution per liquid cell and 1 flag byte
-    per lattice cell; and of the interface kernel: the same 38 distribution
-    accesses per interface cell plus m (read, write), rho (write), K and phi
-    (read) and one status byte."""
+    """Algorithmic bytes of one stream-collide launch: 19 reads + 19 writes
+    of a distribution per fluid cell, one flag byte per cell of the fluid
+    bounding box (the range the kernel covers), and at interface cells m
+    (read, write), rho (write), K and phi (read) and one status byte.
+    Returns (liquid part incl. flags, interface part, liquid cells,
+    interface cells, box cells)."""
     nl = int((flags == 1).sum())
     ni = int((flags == 2).sum())
-    n = flags.size
-    return 38 * FBYTES[prec] * nl + n, ni * (38 * FBYTES[prec] + 5 * RBYTES[prec] + 1), nl, ni
+    nbox = fluid_box_cells(flags)
+    return 38 * FBYTES[prec] * nl + nbox, ni * (38 * FBYTES[prec] + 5 * RBYTES[prec] + 1), nl, ni, nbox
 
 
 def stored_traffic(workload, precision):
@@ -120,14 +137,19 @@ def traffic_from_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, 
     return rec
 
 
-def cpu_baseline(runs, budget_s):
-    """FP64 oracle (single thread) on the first run of the workload, timed
-    until budget_s of stepping has elapsed."""
-    import oracle as O
+PROBE_SAMPLE = (128, 16.0)  # the probe scaled to 128^3: bubble R = 16, the same cell mix
 
-    label, fill, obst, p = runs[0]
-    orc = O.Oracle(fill, obst, sigma=p["sigma"], tau=p["tau"],
-                   curv_model=O.CURV_FD if p["curv_model"] == "fd" else O.CURV_LSQR)
+
+def _oracle_rate(budget_s):
+    """One process: the FP64 oracle on the 128^3 downscale of the probe
+    (LSQR, sigma 1e-3, tau 0.8), stepped until budget_s has elapsed.
+    Returns (cells, steps, seconds)."""
+    import oracle as O
+    from paper_1509_07691_amd import inputs as I
+
+    n, R = PROBE_SAMPLE
+    fill, obst = I.bubble_probe(n, R)
+    orc = O.Oracle(fill, obst, sigma=1e-3, tau=0.8, curv_model=O.CURV_LSQR)
     steps = 0
     t0 = time.perf_counter()
     while True:
@@ -135,10 +157,39 @@ def cpu_baseline(runs, budget_s):
         steps += 1
         el = time.perf_counter() - t0
         if el >= budget_s:
-            break
-    return {"value": fill.size * steps / el / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} steps of one {'x'.join(map(str, fill.shape[::-1]))} lattice ({label}), "
-                      f"{el:.1f} s, FP64, single-threaded plain C"}
+            return fill.size, steps, el
+
+
+def cpu_baseline(budget_s):
+    """The FP64 oracle as it stands (plain C, one thread per process) on a
+    bounded sample of the probe: its 128^3 downscale, on one core and then
+    as one process per core of this host, each stepping for budget_s. The
+    rate is MLUPS over all cells of the sample."""
+    import multiprocessing as mp
+
+    cores = len(os.sched_getaffinity(0))
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    ctx = mp.get_context("spawn")  # fresh interpreters: nothing of this process's GPU state
+    with ctx.Pool(1) as pool:
+        (c1, s1, e1), = pool.map(_oracle_rate, [budget_s])
+    with ctx.Pool(cores) as pool:
+        res = pool.map(_oracle_rate, [budget_s] * cores)
+    one = c1 * s1 / e1 / 1e6
+    allc = sum(c * st / el for c, st, el in res) / 1e6
+    n, R = PROBE_SAMPLE
+    return {"value": round(allc, 3), "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "sample": f"the probe scaled to {n}^3 (gas bubble R={R:g} in liquid, LSQR, FP64), one oracle process "
+                      f"per core for {budget_s:g} s each ({sum(r[1] for r in res)} steps in all); MLUPS over all "
+                      f"cells of the sample",
+            "single_core": {"value": round(one, 3), "unit": "MLUPS", "steps": s1, "seconds": round(e1, 2)},
+            "host": {"cpu_model": model, "nproc": os.cpu_count(), "affinity_cores": cores}}
 
 
 def adjoint_cost(dev, stream, steps, K, precision, fd_check=True):
@@ -177,6 +228,7 @@ def adjoint_cost(dev, stream, steps, K, precision, fd_check=True):
     lat.load_state(start)
     lat.set_params(sigma=1e-3, theta=math.pi / 2)
     t_fwd, _ = timed(lambda: lat.adjoint_forward(steps, K))
+    inside_steps, fill_events, unconverted_steps = lat.adjoint_status()
     phi = lat.fill_tensor()
     dphi = 2.0 * (phi - target) * keep
     loss = float((((phi - target) * keep) ** 2).sum())
@@ -187,6 +239,7 @@ def adjoint_cost(dev, stream, steps, K, precision, fd_check=True):
     lat.close()
     del lat, start
     torch.cuda.empty_cache()
+    valid = fill_events == 0
     return {"workload": "sessile drop R=24 on the wall of a 128^3 lattice, LSQR + wetting, frozen-topology "
                         f"window of {steps} steps, checkpoints every {K}",
             "precision": precision, "steps": steps, "K": K,
@@ -195,12 +248,15 @@ def adjoint_cost(dev, stream, steps, K, precision, fd_check=True):
             "backward_ms_per_step": round(1e3 * t_bwd / steps, 4),
             "backward_over_forward": round(t_bwd / t_plain, 3),
             "cost_ratio": round((t_fwd + t_bwd) / t_plain, 3),
-            "loss": loss, "dL_dsigma": ds, "dL_dtheta": dt,
-            "dL_dphi0_norm": float(torch.linalg.vector_norm(d0)),
+            "window_inside_steps": inside_steps, "window_fill_events": fill_events,
+            "window_unconverted_steps": unconverted_steps,
+            "loss": loss if valid else None, "dL_dsigma": ds if valid else None, "dL_dtheta": dt if valid else None,
+            "dL_dphi0_norm": float(torch.linalg.vector_norm(d0)) if valid else None,
             "interface_fill_range_T": phi_range,
             "workspace_GB": round(ws_gb, 2),
-            "note": "cost is valid; the 128^3 gradient values are not: interface fills leave (0, 1) in the frozen "
-                    "window and the loss is not smooth there; fd_check verifies the gradients on the downscale",
+            "note": "the cost is measured on the whole window; its gradients are reported only when every interface "
+                    "fill stays inside (0, 1) (window_fill_events == 0): otherwise the frozen step is not smooth "
+                    "along the trajectory and they are null",
             "fd_check": adjoint_fd_check(dev, 64, 12.0, steps, K) if fd_check else None}
 
 
@@ -590,39 +646,121 @@ def oscillation_table(dev, precisions, steps, every=500):
     return out
 
 
-def hbm_storage_comparison(dev, stream, precisions, steps, warmup):
-    """The storage forms on the HBM-bound bubble probe (gas bubble R = 64 in
-    a liquid-filled periodic 512^3, LSQR): MLUPS and the stream-collide's
-    algorithmic GB/s per form, one lattice at a time."""
+def run_workload(dev, stream, name, prec, steps, warmup, split=False, graph=False, keep=False):
+    """Times `steps` steps of a workload (after `warmup`) with per-phase HIP
+    events on the lattices' stream; returns the record and, with keep, the
+    lattices and their batch (else they are released)."""
+    import torch
+    from paper_1509_07691_amd.fslbm import Batch, Lattice
+
+    runs, desc = workload_runs(name)
+    lats = []
+    with torch.cuda.stream(stream):
+        for label, fill, obst, p in runs:
+            lats.append(Lattice(fill, obst, precision=prec, device=dev, stream=stream, **p))
+    batch = Batch(lats)
+    if split:
+        batch.set_split_interface(True)
+    torch.cuda.synchronize()
+    print(f"# {len(lats)} lattice(s) created: {desc}, {prec}", file=sys.stderr, flush=True)
+    batch.step(warmup)
+    torch.cuda.synchronize()
+    batch.set_timing(True)
+    batch.reset_timing()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.step(steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    phase, st = batch.timing()
+    assert st == steps
+    batch.set_timing(False)
+    bl = bi = nl = ni = nbox = ncell = 0
+    for lat in lats:
+        a, b, c, d, e = sc_bytes(lat.flags(), prec)
+        bl, bi, nl, ni, nbox = bl + a, bi + b, nl + c, ni + d, nbox + e
+        ncell += lat.n
+        lat.check_numeric()
+    sc_ms = phase[0]
+    launch = bl if split else bl + bi  # the merged kernel also moves the interface cells' bytes
+    achieved = launch * steps / (sc_ms * 1e-3) / 1e9
+    rec = {"workload": desc, "lattice": list(runs[0][1].shape[::-1]), "lattices": len(lats), "storage": prec,
+           "steps": steps, "warmup": warmup, "ms_per_step": round(1e3 * el / steps, 4),
+           "mlups": round(ncell * steps / el / 1e6, 1), "mflups": round((nl + ni) * steps / el / 1e6, 1),
+           "fluid_cells": nl + ni, "interface_cells": ni, "fluid_box_cells": nbox,
+           "stream_collide_us": round(1e3 * sc_ms / steps, 3), "algorithmic_bytes_per_launch": int(launch),
+           "stream_collide_GBs": round(achieved, 1), "roofline_frac": round(achieved / HBM_PEAK_GBS, 4),
+           "phases_ms_per_step": {k: round(v / steps, 4) for k, v in
+                                  zip(("stream_collide", "stream_collide_interface_list", "conversion",
+                                       "list_update", "obstacle_fill_and_curvature"), phase)}}
+    if graph:
+        batch.set_graph(True)
+        batch.step(2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        batch.step(steps)
+        torch.cuda.synchronize()
+        gms = 1e3 * (time.perf_counter() - t0) / steps
+        batch.set_graph(False)
+        rec["graph_replay"] = {"ms_per_step": round(gms, 4), "mlups": round(ncell / gms / 1e3, 1)}
+    if keep:
+        return rec, runs, lats, batch
+    batch.close()
+    for lat in lats:
+        lat.close()
+    del batch, lats
+    torch.cuda.empty_cache()
+    return rec
+
+
+def c3_record(dev, precisions, steps, every=500):
+    """The oscillating droplet (precision form's workload): ellipsoid
+    96/80/80 in a periodic 512^3, LSQR, sigma 1e-3, tau 0.55, per storage
+    form: ms per step (stepping only, synchronised every `every` steps),
+    relative mass drift after `steps`, the x semi-axis a(t) =
+    sqrt(5 <(x - <x>)^2>) of the fill level every `every` steps and its
+    extrema. The l = 2 period of Lamb's formula is printed beside it."""
     import torch
     from paper_1509_07691_amd.fslbm import Lattice
 
-    (label, fill, obst, p), = workload_runs("bubble-probe")[0]
-    out = {}
+    (label, fill, obst, p), = workload_runs("ellipsoid")[0]
+    nz, ny, nx = fill.shape
+    x = torch.arange(nx, dtype=torch.float64, device=dev) + 0.5
+    R = (96.0 * 80.0 * 80.0) ** (1.0 / 3.0)
+    w0 = math.sqrt(8.0 * p["sigma"] / R ** 3)
+    out = {"workload": "oscillating droplet: ellipsoid 96/80/80 in periodic 512^3, LSQR, sigma 1e-3, tau 0.55",
+           "steps": steps, "lamb_period_steps": round(2 * math.pi / w0, 1),
+           "note": "the l = 2 period (~55k steps) exceeds the run; the 128^3 downscale's period is measured "
+                   "against the FP64 oracle in the tests"}
     for prec in precisions:
-        with torch.cuda.stream(stream):
-            lat = Lattice(fill, obst, precision=prec, device=dev, stream=stream, **p)
-        lat.step(warmup)
-        torch.cuda.synchronize()
-        lat.set_timing(True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        lat.step(steps)
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-        ph, _ = lat.timing()
-        bl, bi, _, _ = sc_bytes(lat.flags(), prec)
-        out[prec] = {"mlups": round(lat.n * steps / el / 1e6, 1), "ms_per_step": round(1e3 * el / steps, 4),
-                     "stream_collide_us": round(1e3 * ph[0] / steps, 3),
-                     "stream_collide_GBs": round((bl + bi) * steps / (ph[0] * 1e-3) / 1e9, 1)}
+        lat = Lattice(fill, obst, precision=prec, device=dev, **p)
+        m0 = lat.mass()
+        ts, a, t, tstep = [], [], 0, 0.0
+        while True:
+            ph = lat.fill_tensor()
+            px = ph.sum(dim=(0, 1))
+            wsum = px.sum()
+            mx = (px * x).sum() / wsum
+            a.append(math.sqrt(5.0 * float((px * (x - mx) ** 2).sum() / wsum)))
+            ts.append(t)
+            del ph, px
+            if t >= steps:
+                break
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            lat.step(every)
+            torch.cuda.synchronize()
+            tstep += time.perf_counter() - t0
+            t += every
+        ext = [ts[k] for k in range(1, len(a) - 1) if (a[k] - a[k - 1]) * (a[k + 1] - a[k]) < 0]
+        out[prec] = {"ms_per_step": round(1e3 * tstep / steps, 4), "mlups": round(fill.size * steps / tstep / 1e6, 1),
+                     "mass_drift": (lat.mass() - m0) / m0, "a_every": every, "a": [round(v, 3) for v in a],
+                     "a_extrema_steps": ext}
+        print(f"# C3 {prec}: {out[prec]['ms_per_step']} ms/step, drift {out[prec]['mass_drift']:.2e}",
+              file=sys.stderr, flush=True)
         lat.close()
         del lat
         torch.cuda.empty_cache()
-        print(f"# hbm comparison {prec}: {out[prec]['mlups']} MLUPS", file=sys.stderr, flush=True)
-    base = precisions[0]
-    for prec in precisions[1:]:
-        out[prec]["speedup_vs_" + base] = round(out[prec]["mlups"] / out[base]["mlups"], 3)
-    out["workload"] = "gas bubble R=64 in liquid-filled periodic 512^3, LSQR (HBM-bound)"
     return out
 
 
@@ -631,14 +769,19 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="droplet-sweep", choices=["droplet-sweep", "ellipsoid", "bubble-probe"])
+    ap.add_argument("--workload", default="bubble-probe", choices=["bubble-probe", "droplet-sweep", "ellipsoid"])
     ap.add_argument("--precision", default="f32", choices=["f64", "f32", "f16", "bf16"])
     ap.add_argument("--graph", type=int, default=1,
                     help="also time a graph-replay pass after the timed region")
     ap.add_argument("--split", type=int, default=0,
                     help="1: interface cells in their own list kernel (same results)")
-    ap.add_argument("--compare", default="f16",
+    ap.add_argument("--compare", default="f16,bf16",
                     help="comma list of storage precisions also timed on the same workload ('' for none)")
+    ap.add_argument("--sweep-steps", type=int, default=200,
+                    help="timed steps of the 8 x 128^3 droplet sweep reported beside the headline (0: skip)")
+    ap.add_argument("--c3-steps", type=int, default=10000,
+                    help="steps of the 512^3 oscillating droplet per storage form (0: skip)")
+    ap.add_argument("--c3-precisions", default="f32,f16,bf16")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain copy of 2^28 floats (for scaling rocprofv3 byte counters)")
     ap.add_argument("--no-copy", action="store_true", help="skip the copy-bandwidth reference")
@@ -668,9 +811,7 @@ def main():
                     help="equilibrium sessile droplets at dx = 1/N (default 48 96 144) instead of the bench")
     ap.add_argument("--eps-c", type=float, default=None,
                     help="conversion offset for the bubble studies (library default 1e-3)")
-    ap.add_argument("--hbm-compare", default="f32,f16",
-                    help="storage forms timed on the HBM-bound bubble probe after the run (empty: skip)")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
     if args.traffic_from:
@@ -685,7 +826,6 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_1509_07691_amd.fslbm import Batch, Lattice
 
     dev = torch.device("cuda:0")
     if args.advection:
@@ -733,178 +873,92 @@ def main():
         del src, dst
         torch.cuda.empty_cache()
 
-    runs, desc = workload_runs(args.workload)
     stream = torch.cuda.Stream(dev)
-    lats = []
-    with torch.cuda.stream(stream):
-        for label, fill, obst, p in runs:
-            lats.append(Lattice(fill, obst, precision=args.precision, device=dev, stream=stream, **p))
-    batch = Batch(lats)
-    if args.split:
-        batch.set_split_interface(True)
-    torch.cuda.synchronize()
-    print(f"# {len(lats)} lattice(s) created: {desc}", file=sys.stderr, flush=True)
-
-    batch.step(args.warmup)
-    torch.cuda.synchronize()
-    batch.set_timing(True)
-    batch.reset_timing()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    batch.step(args.steps)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    ms_per_step = 1e3 * el / args.steps
-    phase, st = batch.timing()
-    assert st == args.steps
-    batch.set_timing(False)
-
-    bytes_liq = bytes_if = 0
-    nl_tot = ni_tot = ncell = 0
-    for lat in lats:
-        bl, bi, nl, ni = sc_bytes(lat.flags(), args.precision)
-        bytes_liq += bl
-        bytes_if += bi
-        nl_tot += nl
-        ni_tot += ni
-        ncell += lat.n
-        lat.check_numeric()
-    nf_tot = nl_tot + ni_tot
-    sc_ms = phase[0]
-    # merged mode: the bulk kernel also moves the interface cells' bytes
-    sc_bytes_launch = bytes_liq if args.split else bytes_liq + bytes_if
-    achieved = sc_bytes_launch * args.steps / (sc_ms * 1e-3) / 1e9
-    if_achieved = bytes_if * args.steps / (phase[1] * 1e-3) / 1e9 if args.split else None
-    mlups = ncell * args.steps / el / 1e6
+    head = run_workload(dev, stream, args.workload, args.precision, args.steps, args.warmup,
+                        split=bool(args.split), graph=bool(args.graph))
     traffic = stored_traffic(args.workload, args.precision)
-
-    # the same number of steps replayed from HIP graphs, untimed per kernel
-    graph_ms = None
-    if args.graph:
-        batch.set_graph(True)
-        batch.step(2)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        batch.step(args.steps)
-        torch.cuda.synchronize()
-        graph_ms = 1e3 * (time.perf_counter() - t0) / args.steps
-        batch.set_graph(False)
-    # spurious currents and the Laplace law of each run after diag_steps
-    # steps in all (device reductions, outside every timed region)
-    sweep_diag = None
-    if args.workload == "droplet-sweep" and args.diag_steps > 0:
-        more = args.diag_steps - lats[0].steps_taken()
-        if more > 0:
-            batch.step(more)
-        torch.cuda.synchronize()
-        sweep_diag = []
-        for (label, _, _, p), lat in zip(runs, lats):
-            d = lat.diagnostics()
-            dpl = 2.0 * p["sigma"] / SWEEP_RADIUS
-            sweep_diag.append({"run": label, "steps": lat.steps_taken(), "max_u": d["max_u"],
-                               "mean_u": d["mean_u"], "dp": d["dp"], "dp_laplace": dpl,
-                               "dp_rel_err": round((d["dp"] - dpl) / dpl, 5), "n_inner": d["n_inner"]})
-    nlat = len(lats)
-    batch.close()
-    for lat in lats:
-        lat.close()
-    del batch, lats
-    torch.cuda.synchronize()
-
-    compare = {}
-    for prec in [p for p in args.compare.split(",") if p and p != args.precision]:
-        clats = []
-        with torch.cuda.stream(stream):
-            for label, fill, obst, p in runs:
-                clats.append(Lattice(fill, obst, precision=prec, device=dev, stream=stream, **p))
-        cb = Batch(clats)
-        cb.step(args.warmup)
-        torch.cuda.synchronize()
-        cb.set_timing(True)
-        cb.reset_timing()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        cb.step(args.steps)
-        torch.cuda.synchronize()
-        cel = time.perf_counter() - t0
-        cph, _ = cb.timing()
-        cb_liq = cb_if = 0
-        for lat in clats:
-            bl, bi, _, _ = sc_bytes(lat.flags(), prec)
-            cb_liq += bl
-            cb_if += bi
-        cbytes = cb_liq + cb_if
-        compare[prec] = {"mlups": round(ncell * args.steps / cel / 1e6, 1),
-                         "ms_per_step": round(1e3 * cel / args.steps, 4),
-                         "speedup_vs_" + args.precision: round(el / cel, 3),
-                         "stream_collide_us": round(1e3 * cph[0] / args.steps, 3),
-                         "stream_collide_GBs": round(cbytes * args.steps / (cph[0] * 1e-3) / 1e9, 1)}
-        cb.close()
-        for lat in clats:
-            lat.close()
-        del cb, clats
-        torch.cuda.synchronize()
-
-    hbm_compare = None
-    hprec = [p for p in args.hbm_compare.split(",") if p]
-    if hprec and args.workload != "bubble-probe":
-        hbm_compare = hbm_storage_comparison(dev, stream, hprec, steps=10, warmup=3)
-
-    adjoint = None
-    if args.adjoint_steps > 0:
-        adjoint = adjoint_cost(dev, stream, args.adjoint_steps, args.adjoint_k, args.precision,
-                               fd_check=bool(args.adjoint_fd_check))
-        print(f"# adjoint window done: {adjoint['cost_ratio']}x forward", file=sys.stderr, flush=True)
-
+    nunits = head["fluid_cells"]
     res = {
         "metric": METRIC,
-        "value": round(mlups, 1),
+        "value": head["mlups"],
         "unit": "MLUPS",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": args.precision,
         "data": "synthetic",
-        "config": {"workload": desc, "lattice": list(runs[0][1].shape[::-1]), "lattices": nlat,
-                   "storage": args.precision, "batched_launches": True, "split_interface": bool(args.split),
-                   "fluid_cells": nf_tot, "interface_cells": ni_tot},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "config": {"workload": f"{head['workload']}, {args.precision} storage and arithmetic",
+                   "lattice": head["lattice"], "lattices": head["lattices"], "storage": args.precision,
+                   "split_interface": bool(args.split), "fluid_cells": head["fluid_cells"],
+                   "interface_cells": head["interface_cells"], "fluid_box_cells": head["fluid_box_cells"]},
+        "roofline": {"bound": "hbm", "achieved": head["stream_collide_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": head["roofline_frac"],
+                     "traffic": traffic.get("bytes_per_launch") if traffic else None,
                      "copy_kernel_GBs": round(copy_gbs, 1) if copy_gbs else None,
-                     "traffic": (traffic or {}).get("bytes_per_launch") if traffic else None,
-                     "kernel": "k_stream_collide" + (" (liquid cells)" if args.split else " (liquid and interface cells)")
-                               + ", all lattices in one launch",
-                     "avg_launch_us": round(1e3 * sc_ms / args.steps, 3),
-                     "algorithmic_bytes_per_launch": int(sc_bytes_launch)},
-        "phases_ms_per_step": {k: round(v / args.steps, 4) for k, v in
-                               zip(("stream_collide_liquid", "stream_collide_interface", "conversion",
-                                    "compaction", "geometry"), phase)},
-        "mflups": round(nf_tot * args.steps / el / 1e6, 1),
+                     "kernel": "k_stream_collide" + (" (liquid cells)" if args.split else ""),
+                     "avg_launch_us": head["stream_collide_us"],
+                     "algorithmic_bytes_per_launch": head["algorithmic_bytes_per_launch"],
+                     "units_per_launch": nunits,
+                     "bytes_per_unit": round(head["algorithmic_bytes_per_launch"] / max(nunits, 1), 3),
+                     "unit_definition": "fluid cell: 38 distribution values, plus one flag byte per fluid-box cell "
+                                        "and m, rho, K, phi and a status byte per interface cell"},
+        "mflups": head["mflups"],
+        "phases_ms_per_step": head["phases_ms_per_step"],
     }
-    if args.split:
-        res["interface_kernel"] = {"kernel": "k_stream_collide_interface",
-                                   "avg_launch_us": round(1e3 * phase[1] / args.steps, 3),
-                                   "algorithmic_bytes_per_launch": int(bytes_if), "achieved_GBs": round(if_achieved, 1)}
-    if graph_ms is not None:
-        res["graph_replay"] = {"ms_per_step": round(graph_ms, 4),
-                               "mlups": round(ncell / graph_ms / 1e3, 1)}
-    if sweep_diag is not None:
-        res["sweep_diagnostics"] = sweep_diag
-    if args.workload == "droplet-sweep" and args.sessile_steps > 0:
-        res["sessile_contact_angles"] = sessile_contact_angles(dev, args.sessile_steps)
-        print("# sessile contact angles done", file=sys.stderr, flush=True)
-    if not args.no_cpu:
-        res["cpu_baseline"] = cpu_baseline(runs, args.cpu_seconds)
+    if "graph_replay" in head:
+        res["graph_replay"] = head["graph_replay"]
+    print(f"# headline: {res['value']} MLUPS, roofline {res['roofline']['frac']}", file=sys.stderr, flush=True)
+
+    compare = {}
+    for prec in [p for p in args.compare.split(",") if p and p != args.precision]:
+        rec = run_workload(dev, stream, args.workload, prec, args.steps, args.warmup)
+        rec["speedup_vs_" + args.precision] = round(head["ms_per_step"] / rec["ms_per_step"], 3)
+        rec["stream_collide_speedup_vs_" + args.precision] = round(head["stream_collide_us"] / rec["stream_collide_us"], 3)
+        compare[prec] = rec
+        print(f"# storage {prec}: {rec['mlups']} MLUPS", file=sys.stderr, flush=True)
     if compare:
         res["storage_comparison"] = compare
-    if hbm_compare:
-        res["storage_comparison_hbm"] = hbm_compare
-    if adjoint:
-        res["adjoint"] = adjoint
+
+    if args.sweep_steps > 0 and args.workload != "droplet-sweep":
+        rec, runs, lats, batch = run_workload(dev, stream, "droplet-sweep", "f32", args.sweep_steps, args.warmup,
+                                              graph=bool(args.graph), keep=True)
+        if args.diag_steps > 0:
+            more = args.diag_steps - lats[0].steps_taken()
+            if more > 0:
+                batch.step(more)
+            torch.cuda.synchronize()
+            diag = []
+            for (label, _, _, p), lat in zip(runs, lats):
+                d = lat.diagnostics()
+                dpl = 2.0 * p["sigma"] / SWEEP_RADIUS
+                diag.append({"run": label, "steps": lat.steps_taken(), "max_u": d["max_u"], "mean_u": d["mean_u"],
+                             "dp": d["dp"], "dp_laplace": dpl, "dp_rel_err": round((d["dp"] - dpl) / dpl, 5),
+                             "n_inner": d["n_inner"]})
+            rec["diagnostics"] = diag
+        batch.close()
+        for lat in lats:
+            lat.close()
+        del batch, lats
+        torch.cuda.empty_cache()
+        res["droplet_sweep"] = rec
+        print("# droplet sweep done", file=sys.stderr, flush=True)
+
+    if args.c3_steps > 0:
+        res["c3_oscillating_droplet"] = c3_record(dev, [p for p in args.c3_precisions.split(",") if p],
+                                                  args.c3_steps)
+    if args.sessile_steps > 0:
+        res["sessile_contact_angles"] = sessile_contact_angles(dev, args.sessile_steps)
+        print("# sessile contact angles done", file=sys.stderr, flush=True)
+    if args.adjoint_steps > 0:
+        res["adjoint"] = adjoint_cost(dev, stream, args.adjoint_steps, args.adjoint_k, "f32",
+                                      fd_check=bool(args.adjoint_fd_check))
+        print(f"# adjoint window done: {res['adjoint']['cost_ratio']}x forward", file=sys.stderr, flush=True)
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(res), flush=True)
 
 

@@ -318,6 +318,21 @@ int fslbm_adjoint_required_bytes(fslbm_t h, int64_t nsteps, int K, size_t *bytes
 int fslbm_adjoint_forward(fslbm_t h, int64_t nsteps, int K, void *workspace, size_t workspace_bytes);
 int fslbm_adjoint_backward(fslbm_t h, const double *dL_dfill_T, int in_is_device, double *dL_dsigma,
                            double *dL_dtheta, double *dL_dfill_0, int out_is_device);
+/* Validity of the recorded window. The frozen step is a smooth map only
+ * while every interface fill stays strictly inside (0, 1): at 0 and 1 the
+ * PLIC offset is clamped, and near the cell corners its derivative -1/A
+ * (A the area of the plane section) diverges. *inside_steps receives the
+ * number of window steps before the first step in which an interface fill
+ * left (0, 1) (nsteps if none did), *fill_events the number of (step,
+ * interface cell) pairs with a fill outside (0, 1), and *unconverted_steps
+ * the number of steps before the first step in which the method with free
+ * cell types would have filled or emptied a cell (m > (1 + eps) rho or
+ * m < -eps rho): up to there the frozen window is the method's own
+ * trajectory. Gradients of a window with fill_events > 0 belong to a
+ * piecewise-smooth map (each clamped cell contributes the derivative of its
+ * clamped piece) and do not describe changes that move a fill across 0 or 1.
+ * FSLBM_E_STATE if no window was recorded, FSLBM_E_ARG for a NULL output. */
+int fslbm_adjoint_status(fslbm_t h, int64_t *inside_steps, int64_t *fill_events, int64_t *unconverted_steps);
 
 /* Synchronises the handle's stream and frees the handle (not the caller's
  * workspace). */

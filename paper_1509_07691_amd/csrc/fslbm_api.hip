@@ -136,6 +136,9 @@ struct AdjWindow {
     int recorded = 0;
     long long T = 0;
     int K = 0;
+    long long fill_events = 0;     // (step, interface cell) events with a fill outside (0, 1)
+    long long inside_steps = 0;    // steps before the first such event (T if none)
+    long long unconverted_steps = 0;  // steps before a cell would first fill or empty (T if none)
     int icount = 0, ocount = 0;
     long long t_end = 0;     // steps taken at the end of the window
     unsigned long long epoch = 0;  // state epoch at the end of the window
@@ -282,14 +285,17 @@ __global__ void k_init_scalars(DevScalars *sc)
     sc->nnew = 0;
     sc->nkeep = 0;
     sc->step = 1;
-    sc->reservoir = 0.0;
+    sc->res_hi = 0;
+    sc->res_lo = 0;
     sc->mass = 0.0;
     sc->bad = 0;
     sc->wcount = 0;
     sc->gas_v0 = 0.0;
     sc->rho_gas_t = 0.0;
     sc->bubble_init = 0;
-    sc->pad2 = 0;
+    sc->fill_out = 0;
+    sc->fill_out_step = 0xffffffffu;
+    sc->conv_out_step = 0xffffffffu;
     for (int k = 0; k < 6; ++k) sc->bbox[k] = 0;
     sc->fbox[0] = sc->fbox[1] = sc->fbox[2] = 1 << 30;
     sc->fbox[3] = sc->fbox[4] = sc->fbox[5] = -1;
@@ -470,6 +476,34 @@ __device__ inline void load_all(const Fields<P> &F, int i, typename P::T (&f)[NQ
     }
 }
 
+// Density (FP64) and velocity of a fluid cell from its stored
+// distributions: for the shifted forms rho = 1 + sum d with the deviations
+// summed in FP64 (a sum of the f_q in FP32 would round at 1e-7 of rho).
+template <class P>
+__device__ inline void cell_moments(const Fields<P> &F, int i, double &rho, typename P::T &ux, typename P::T &uy,
+                                    typename P::T &uz)
+{
+    using T = typename P::T;
+    T f[NQ];
+    if constexpr (P::SHIFT) {
+        int own[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) own[q] = i;
+        load_dirs_dev<P>(F, own, f);
+        T dr;
+        moments_dev(f, dr, ux, uy, uz);
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) s += double(f[q]);
+        rho = 1.0 + s;
+    } else {
+        load_all(F, i, f);
+        T r;
+        moments(f, r, ux, uy, uz);
+        rho = double(r);
+    }
+}
+
 enum ReadWhat { RD_FILL, RD_PRESSURE, RD_CURV, RD_VEL, RD_NORMAL, RD_PLIC, RD_MASS };
 
 template <class P>
@@ -491,11 +525,10 @@ __global__ void k_read(Fields<P> F, double rho_gas, int bubble, int what, int co
     case RD_PRESSURE:
     case RD_VEL:
         if (fluid) {
-            T f[NQ];
-            load_all(F, i, f);
-            T r, ux, uy, uz;
-            moments(f, r, ux, uy, uz);
-            if (what == RD_PRESSURE) v = double(r) / 3.0;
+            double r;
+            T ux, uy, uz;
+            cell_moments(F, i, r, ux, uy, uz);
+            if (what == RD_PRESSURE) v = r / 3.0;
             else v = double(comp == 0 ? ux : (comp == 1 ? uy : uz));
         } else if (what == RD_PRESSURE) {
             v = (fl & FL_GAS) ? (bubble ? F.sc->rho_gas_t : rho_gas) / 3.0 : 0.0;
@@ -598,12 +631,10 @@ __global__ __launch_bounds__(256) void k_mass_partial(Fields<P> F, double *part)
     for (int i = b0 + threadIdx.x; i < b1; i += 256) {
         const uint8_t fl = F.flags[i];
         if (fl & FL_LIQ) {
-            T f[NQ];
-            load_all(F, i, f);
-            T r = 0;
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) r += f[q];
-            acc += double(r);
+            double r;
+            T ux, uy, uz;
+            cell_moments(F, i, r, ux, uy, uz);
+            acc += r;
         } else if (fl & FL_IF) {
             acc += double(F.m[i]);
         }
@@ -626,7 +657,7 @@ __global__ __launch_bounds__(1024) void k_mass_final(const double *part, DevScal
         if (threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) sc->mass = s[0] + sc->reservoir;
+    if (threadIdx.x == 0) sc->mass = s[0] + reservoir_value(sc->res_hi, sc->res_lo);
 }
 
 // Diagnostics (the measures of Sec. III.A.1: spurious currents and the
@@ -662,17 +693,16 @@ __global__ __launch_bounds__(256) void k_diag_partial(Fields<P> F, double *part)
     for (int i = b0 + threadIdx.x; i < b1; i += 256) {
         const uint8_t fl = F.flags[i];
         if (!(fl & FL_FLUID)) continue;
-        T f[NQ];
-        load_all(F, i, f);
-        T r, ux, uy, uz;
-        moments(f, r, ux, uy, uz);
+        double r;
+        T ux, uy, uz;
+        cell_moments(F, i, r, ux, uy, uz);
         const double a = double(ux), b = double(uy), c = double(uz);
         const double sp = sqrt(a * a + b * b + c * c);
         umax = fmax(umax, sp);
         usum += sp;
         nfl += 1.0;
         if ((fl & FL_TYPE) == FL_LIQ && !near_surface(F, i)) {
-            rsum += double(r);
+            rsum += r;
             nin += 1.0;
         }
     }
@@ -718,12 +748,10 @@ __global__ void k_check_numeric(Fields<P> F)
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= F.N) return;
     if (!(F.flags[i] & FL_FLUID)) return;
-    T f[NQ];
-    load_all(F, i, f);
-    T r = 0;
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) r += f[q];
-    if (!(r > T(0)) || !isfinite(double(r))) atomicOr(&F.sc->bad, 1);
+    double r;
+    T ux, uy, uz;
+    cell_moments(F, i, r, ux, uy, uz);
+    if (!(r > 0.0) || !isfinite(r)) atomicOr(&F.sc->bad, 1);
 }
 
 // ------------------------------------------------------ host sequences
@@ -1314,6 +1342,13 @@ int load_snap(fslbm_lattice *h, const char *snap)
     return 0;
 }
 
+__global__ void k_reset_fill_out(DevScalars *sc)
+{
+    sc->fill_out = 0;
+    sc->fill_out_step = 0xffffffffu;
+    sc->conv_out_step = 0xffffffffu;
+}
+
 template <class P>
 int do_adj_forward(fslbm_lattice *h, long long T, int K, void *ws, size_t bytes)
 {
@@ -1327,6 +1362,11 @@ int do_adj_forward(fslbm_lattice *h, long long T, int K, void *ws, size_t bytes)
     if (bytes < w.total) return fail(FSLBM_E_SHAPE, "adjoint workspace has %zu bytes, %zu needed", bytes, w.total);
     w.ws = (char *)ws;
     w.bytes = bytes;
+    DevScalars *sc = (DevScalars *)(h->ws + h->L.sc);
+    unsigned start_step = 0;
+    HIP_OK(hipMemcpyAsync(&start_step, &sc->step, sizeof start_step, hipMemcpyDeviceToHost, h->stream));
+    k_reset_fill_out<<<1, 1, 0, h->stream>>>(sc);
+    HIP_OK(hipGetLastError());
     h->frozen = 1;
     h->version += 1;
     rc = save_slot<P>(h, ck_slot(w, 0), true);
@@ -1338,6 +1378,13 @@ int do_adj_forward(fslbm_lattice *h, long long T, int K, void *ws, size_t bytes)
     h->frozen = 0;
     h->version += 1;
     if (rc) return rc;
+    unsigned out[3] = {0, 0, 0};  // fill_out, fill_out_step, conv_out_step
+    HIP_OK(hipMemcpyAsync(out, &sc->fill_out, sizeof out, hipMemcpyDeviceToHost, h->stream));
+    HIP_OK(hipStreamSynchronize(h->stream));
+    w.fill_events = (int)out[0];
+    // the window's step t (1..T) runs with step number start_step + t - 1
+    w.inside_steps = out[0] == 0 ? T : (long long)(out[1] - start_step);
+    w.unconverted_steps = out[2] == 0xffffffffu ? T : (long long)(out[2] - start_step);
     w.t_end = h->steps;
     w.epoch = h->epoch;
     w.recorded = 1;
@@ -2139,6 +2186,17 @@ int fslbm_adjoint_forward(fslbm_t h, int64_t nsteps, int K, void *workspace, siz
     if (h->curv == FSLBM_CURV_TR) return fail(FSLBM_E_STATE, "the adjoint covers the FD and LSQR models");
     if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return fail(FSLBM_E_ARG, "workspace not 256-byte aligned");
     return dispatch<OpAdjF>(h, (long long)nsteps, K, workspace, workspace_bytes);
+}
+
+int fslbm_adjoint_status(fslbm_t h, int64_t *inside_steps, int64_t *fill_events, int64_t *unconverted_steps)
+{
+    if (!h) return fail(FSLBM_E_STATE, "null handle");
+    if (!inside_steps || !fill_events || !unconverted_steps) return fail(FSLBM_E_ARG, "an output is NULL");
+    if (!h->adj.recorded) return fail(FSLBM_E_STATE, "no differentiation window recorded");
+    *inside_steps = h->adj.inside_steps;
+    *fill_events = h->adj.fill_events;
+    *unconverted_steps = h->adj.unconverted_steps;
+    return 0;
 }
 
 int fslbm_adjoint_backward(fslbm_t h, const double *dL_dfill_T, int in_is_device, double *dL_dsigma,

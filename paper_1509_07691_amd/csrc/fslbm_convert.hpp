@@ -308,7 +308,7 @@ __device__ inline void conv_share_cell(const Fields<P> &F, int i, uint32_t tag, 
         F.share[i] = mex / R(cnt);
     } else {
         F.share[i] = R(0);
-        atomicAdd(&F.sc->reservoir, (double)mex);
+        reservoir_add(F.sc, (double)mex);
     }
 }
 
@@ -336,6 +336,7 @@ template <class P>
 __global__ __launch_bounds__(256) void k_conv_gather(const Batch<P> B)
 {
     const Fields<P> &F = B.f[blockIdx.y];
+    const bool frozen = B.p[blockIdx.y].frozen != 0;
     using R = typename P::R;
     const bool any = F.sc->nconv != 0;
     const uint32_t tag = F.sc->step << 2;
@@ -348,8 +349,15 @@ __global__ __launch_bounds__(256) void k_conv_gather(const Batch<P> B)
             // only a cell near a filling or emptying cell can receive
             const R acc = any && F.near[i] == s8 ? gathered_excess(F, i, tag) : R(0);
             const R mn = F.m[i] + acc;
+            const R ph = mn / F.rho[i];
             F.m[i] = mn;
-            F.phi[i] = mn / F.rho[i];
+            F.phi[i] = ph;
+            // a frozen window stays on one smooth piece of the step only while
+            // every interface fill lies strictly inside (0, 1)
+            if (frozen && !(ph > R(0) && ph < R(1))) {
+                atomicAdd(&F.sc->fill_out, 1);
+                atomicMin(&F.sc->fill_out_step, F.sc->step);
+            }
             continue;
         }
         F.phi[i] = cv_to_liquid(st) ? R(1) : R(0);

@@ -60,7 +60,10 @@ __host__ __device__ inline bool cv_to_liquid(uint8_t st) { return st == CV_FILL 
 // R: type of the scalar fields m, rho, phi, K, normals and PLIC offsets,
 // G: arithmetic type of normals, PLIC offsets and FD curvature (the LSQR
 // normal equations are always FP64). Shifted storage keeps
-// g_q = (f_q - w_q) * SCALE.
+// g_q = (f_q - w_q) * SCALE, and the stream-collide of a shifted form works
+// on the deviations d_q = f_q - w_q throughout (fslbm_stream.hpp): they are
+// O(|u| + |rho - 1|), so FP32 rounds them far more finely than f_q ~ w_q.
+// The 16-bit forms round stochastically (store_d).
 enum Precision { P_F64 = 0, P_F32 = 1, P_F16 = 2, P_BF16 = 3 };
 
 template <int P> struct Prec;
@@ -71,7 +74,7 @@ template <> struct Prec<P_F64> {
 };
 template <> struct Prec<P_F32> {
     using S = float; using T = float; using R = float; using G = float;
-    static constexpr bool SHIFT = false;
+    static constexpr bool SHIFT = true;
     static constexpr double SCALE = 1.0;
 };
 template <> struct Prec<P_F16> {
@@ -85,14 +88,58 @@ template <> struct Prec<P_BF16> {
     static constexpr double SCALE = 1.0;
 };
 
+__device__ inline float to_float(float v) { return v; }
 __device__ inline float to_float(__half v) { return __half2float(v); }
 __device__ inline float to_float(__hip_bfloat16 v) { return __bfloat162float(v); }
-template <class S> __device__ inline S from_float(float v);
-// Round-to-nearest-even conversions (a truncating conversion would bias the
-// stored distributions and show up as mass drift).
-template <> __device__ inline __half from_float<__half>(float v) { return __float2half_rn(v); }
-template <> __device__ inline __hip_bfloat16 from_float<__hip_bfloat16>(float v) { return __float2bfloat16(v); }
+// Round-to-nearest-even stores (a truncating conversion would bias the
+// stored distributions and show up as mass drift); FP32 is stored as is.
+__device__ inline void store_rn(float *p, float v) { __builtin_nontemporal_store(v, p); }
+__device__ inline void store_rn(__half *p, float v) { *p = __float2half_rn(v); }
+__device__ inline void store_rn(__hip_bfloat16 *p, float v) { *p = __float2bfloat16(v); }
+// Stochastic rounding to 16 bits: `bits` (uniform) is added below the kept
+// mantissa bits of |v| and the rest dropped, which rounds |v| up with the
+// probability of the dropped fraction, so the expected stored value is v.
+// Rounding to nearest is exact in expectation only for values spread over
+// many quanta; a nearly uniform fluid stores the same few values in every
+// cell, the nearest-rounding errors then all have one sign, and the total
+// mass drifts by a fixed amount every step. F16 keeps 10 of FP32's 23
+// mantissa bits (13 dropped, for values in its normal range), BF16 keeps 7
+// (16 dropped); the truncated value is exact in the 16-bit format.
+__device__ inline void store_sr(float *p, float v, uint32_t) { __builtin_nontemporal_store(v, p); }
+__device__ inline void store_sr(__half *p, float v, uint32_t bits)
+{
+    const uint32_t u = (__float_as_uint(v) + (bits >> 19)) & ~0x1fffu;
+    *p = __float2half_rn(__uint_as_float(u));
+}
+__device__ inline void store_sr(__hip_bfloat16 *p, float v, uint32_t bits)
+{
+    const uint32_t u = (__float_as_uint(v) + (bits >> 16)) & ~0xffffu;
+    *p = __float2bfloat16(__uint_as_float(u));
+}
 
+// Counter-based random bits for the stochastic stores: one hash of (cell,
+// step) per cell (the low-bias 32-bit integer hash of Wellons' "prospecting
+// for hash functions"), then one multiply-xorshift per direction along a
+// Weyl sequence. Deterministic: a run is reproduced bit for bit.
+__device__ inline uint32_t hash32(uint32_t x)
+{
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+__device__ inline uint32_t cell_seed(int i, uint32_t step) { return hash32(uint32_t(i) ^ hash32(step * 0x9e3779b9u)); }
+__device__ inline uint32_t dir_bits(uint32_t seed, int q)
+{
+    uint32_t x = seed + uint32_t(q + 1) * 0x9e3779b9u;
+    x *= 0x85ebca6bu;
+    x ^= x >> 13;
+    return x;
+}
+
+// f_q from storage (any form).
 template <class P, int Q>
 __device__ inline typename P::T load_f(const typename P::S *__restrict__ plane, int i)
 {
@@ -103,15 +150,30 @@ __device__ inline typename P::T load_f(const typename P::S *__restrict__ plane, 
         return plane[i];
     }
 }
+// Stores f_q (any form; nearest rounding).
 template <class P, int Q>
 __device__ inline void store_f(typename P::S *__restrict__ plane, int i, typename P::T v)
 {
-    using S = typename P::S;
     if constexpr (P::SHIFT) {
-        plane[i] = from_float<S>((v - weight<typename P::T>(Q)) * typename P::T(P::SCALE));
+        store_rn(plane + i, (v - weight<typename P::T>(Q)) * typename P::T(P::SCALE));
     } else {
         __builtin_nontemporal_store(v, plane + i);
     }
+}
+// Deviation d_q = f_q - w_q from shifted storage.
+template <class P, int Q>
+__device__ inline typename P::T load_d(const typename P::S *__restrict__ plane, int i)
+{
+    static_assert(P::SHIFT, "deviations are stored by the shifted forms only");
+    return to_float(plane[i]) * typename P::T(1.0 / P::SCALE);
+}
+// Stores a deviation d_q into shifted storage (stochastic rounding in the
+// 16-bit forms, with the given random bits).
+template <class P, int Q>
+__device__ inline void store_d(typename P::S *__restrict__ plane, int i, typename P::T d, uint32_t bits)
+{
+    static_assert(P::SHIFT, "deviations are stored by the shifted forms only");
+    store_sr(plane + i, d * typename P::T(P::SCALE), bits);
 }
 
 // ------------------------------------------------------ per-step scalars
@@ -122,7 +184,11 @@ struct DevScalars {
     int nnew;           // new interface cells of this step (in newlist)
     int nkeep;          // interface cells that stay (rebuilding the list)
     unsigned step;      // completed steps + 1 (conversion tag, never 0)
-    double reservoir;   // excess mass that found no receiving cell
+    // excess mass that found no receiving cell, as a 128-bit fixed-point
+    // number res_hi + res_lo 2^-64: integer additions are associative, so
+    // the sum does not depend on the order of the atomic updates
+    long long res_hi;
+    unsigned long long res_lo;
     double mass;        // result of the last mass reduction
     int bad;            // numeric check result
     int wcount;         // number of cells in wlist (static)
@@ -131,7 +197,9 @@ struct DevScalars {
     double gas_v0;      // bubble model: gas volume when it was switched on
     double rho_gas_t;   // bubble model: gas density rho_gas V0 / V(t)
     int bubble_init;    // 1: the next volume reduction sets gas_v0
-    int pad2;
+    int fill_out;       // frozen window: (step, interface cell) events with a fill outside (0, 1)
+    unsigned fill_out_step;  // frozen window: step number of the first such event (UINT_MAX: none)
+    unsigned conv_out_step;  // frozen window: step number of the first would-be fill or empty (UINT_MAX: none)
 };
 
 // A box of cells [x0, x0+ex) x [y0, y0+ey) x [z0, z0+ez) enumerated with x
@@ -161,6 +229,31 @@ __device__ inline void block_share(int n, int &k0, int &k1)
     const int per = (strides + gridDim.x - 1) / gridDim.x;
     k0 = min(n, (int)blockIdx.x * per * 256);
     k1 = min(n, k0 + per * 256);
+}
+
+// Adds x to the fixed-point reservoir. |x| = a + b 2^-64 with a = floor|x|
+// and b the first 64 bits of the fraction (|x| - floor|x| is exact in FP64
+// and scaling by 2^64 is exact; bits below 2^-64 are dropped); a negative x
+// adds the two's complement. The carry out of the low word is taken from
+// the value its atomic returns, so concurrent additions in any order give
+// the same 128-bit sum.
+__device__ inline void reservoir_add(DevScalars *sc, double x)
+{
+    const double ax = fabs(x);
+    const double a = floor(ax);
+    unsigned long long lo = (unsigned long long)((ax - a) * 18446744073709551616.0);
+    long long hi = (long long)a;
+    if (x < 0.0) {
+        hi = -hi - (lo != 0ull ? 1 : 0);
+        lo = ~lo + 1ull;
+    }
+    const unsigned long long old = atomicAdd(&sc->res_lo, lo);
+    const long long carry = old + lo < old ? 1 : 0;
+    if (hi + carry != 0) atomicAdd((unsigned long long *)&sc->res_hi, (unsigned long long)(hi + carry));
+}
+__host__ __device__ inline double reservoir_value(long long hi, unsigned long long lo)
+{
+    return double(hi) + double(lo) * 5.421010862427522e-20;  // 2^-64
 }
 
 // Closes a time step's device bookkeeping (conversion counters, the step

@@ -11,7 +11,8 @@
 //     distribution f'_qbar(x + c_q) is exactly the pulled value),
 //   - moments and the SRT or TRT collision (eq. lbe2),
 //   - fill / empty classification of interface cells (counted only when
-//     cell types are not frozen, so that no conversion follows).
+//     cell types are not frozen, so that no conversion follows; a frozen
+//     window records the first step in which a cell would have converted).
 #pragma once
 
 #include "fslbm_device.hpp"
@@ -103,6 +104,77 @@ __device__ inline void collide(T (&f)[NQ], const Params &p)
     }
 }
 
+// Deviation form, used with the shifted storage forms (fslbm_device.hpp):
+// the values are d_q = f_q - w_q. The weights sum to 1 and carry no
+// momentum, so rho = 1 + sum d and rho u = sum c d, and the equilibrium
+// deviation is w_q (rho - 1) + w_q rho [3 c.u + 9/2 (c.u)^2 - 3/2 u^2]. Each
+// formula below is its f-form counterpart above rewritten exactly.
+template <class T>
+__device__ inline void moments_dev(const T (&d)[NQ], T &drho, T &ux, T &uy, T &uz)
+{
+    T r = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        r += d[q];
+        if (dir_x(q)) jx += T(dir_x(q)) * d[q];
+        if (dir_y(q)) jy += T(dir_y(q)) * d[q];
+        if (dir_z(q)) jz += T(dir_z(q)) * d[q];
+    }
+    drho = r;
+    const T ir = T(1) / (T(1) + r);
+    ux = jx * ir;
+    uy = jy * ir;
+    uz = jz * ir;
+}
+
+// f^eq_q + f^eq_qbar - 2 w_q at rho = 1 + drho: the deviation of the pair
+// sum eq. reconstruct needs.
+template <class T>
+__device__ inline T feq_pair_dev(int q, T drho, T ux, T uy, T uz, T usq)
+{
+    const T cu = cdot<T>(q, ux, uy, uz);
+    return T(2) * weight<T>(q) * (drho + (T(1) + drho) * (T(4.5) * cu * cu - T(1.5) * usq));
+}
+
+template <class T, int COLL>
+__device__ inline void collide_dev(T (&d)[NQ], const Params &p)
+{
+    T drho, ux, uy, uz;
+    moments_dev(d, drho, ux, uy, uz);
+    const T rho = T(1) + drho;
+    const T usq = ux * ux + uy * uy + uz * uz;
+    const T we = T(p.omega);
+    if constexpr (COLL == 0) {
+        d[0] = d[0] - we * (d[0] - weight<T>(0) * (drho - rho * (T(1.5) * usq)));
+        // each pair (q, qbar): equilibrium deviations a +- b
+#pragma unroll
+        for (int q = 1; q < NQ; ++q) {
+            const int o = opp(q);
+            if (o < q) continue;
+            const T cu = cdot<T>(q, ux, uy, uz);
+            const T w = weight<T>(q), wr = w * rho;
+            const T a = w * drho + wr * (T(4.5) * cu * cu - T(1.5) * usq), b = wr * (T(3) * cu);
+            d[q] = d[q] - we * (d[q] - (a + b));
+            d[o] = d[o] - we * (d[o] - (a - b));
+        }
+    } else {
+        const T wo = T(p.omega_odd);
+        T g[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int o = opp(q);
+            const T cu = cdot<T>(q, ux, uy, uz);
+            const T w = weight<T>(q), wr = w * rho;
+            // even and odd parts of the equilibrium deviation of q
+            const T ev = w * drho + wr * (T(4.5) * cu * cu - T(1.5) * usq), od = wr * (T(3) * cu);
+            const T dp = T(0.5) * (d[q] + d[o]), dm = T(0.5) * (d[q] - d[o]);
+            g[q] = d[q] - we * (dp - ev) - wo * (dm - od);
+        }
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) d[q] = g[q];
+    }
+}
+
 // Plane Q of a distribution buffer whose planes are NS elements apart.
 template <class P, int Q>
 __device__ inline const typename P::S *plane(const typename P::S *base, int NS)
@@ -148,6 +220,80 @@ __device__ inline void load_dirs(const Fields<P> &F, const int (&j)[NQ], typenam
     }
 }
 
+// The 19 deviations d_q(j_q) (shifted forms).
+template <class P>
+__device__ inline void load_dirs_dev(const Fields<P> &F, const int (&j)[NQ], typename P::T (&d)[NQ])
+{
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        switch (q) {
+#define FSLBM_LD(QQ) case QQ: d[q] = load_d<P, QQ>(plane<P, QQ>(F.fsrc, F.NS), j[q]); break;
+            FSLBM_LD(0) FSLBM_LD(1) FSLBM_LD(2) FSLBM_LD(3) FSLBM_LD(4)
+            FSLBM_LD(5) FSLBM_LD(6) FSLBM_LD(7) FSLBM_LD(8) FSLBM_LD(9)
+            FSLBM_LD(10) FSLBM_LD(11) FSLBM_LD(12) FSLBM_LD(13) FSLBM_LD(14)
+            FSLBM_LD(15) FSLBM_LD(16) FSLBM_LD(17) FSLBM_LD(18)
+#undef FSLBM_LD
+        }
+    }
+}
+
+// Stores the 19 deviations of cell i (shifted forms; the 16-bit forms round
+// stochastically with bits drawn from the cell and the step number).
+template <class P>
+__device__ inline void store_all_dev(const Fields<P> &F, int i, const typename P::T (&d)[NQ])
+{
+    const uint32_t seed = sizeof(typename P::S) == 2 ? cell_seed(i, F.sc->step) : 0u;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        switch (q) {
+#define FSLBM_STORE(QQ) case QQ: store_d<P, QQ>(plane<P, QQ>(F.fdst, F.NS), i, d[q], dir_bits(seed, q)); break;
+            FSLBM_STORE(0) FSLBM_STORE(1) FSLBM_STORE(2) FSLBM_STORE(3) FSLBM_STORE(4)
+            FSLBM_STORE(5) FSLBM_STORE(6) FSLBM_STORE(7) FSLBM_STORE(8) FSLBM_STORE(9)
+            FSLBM_STORE(10) FSLBM_STORE(11) FSLBM_STORE(12) FSLBM_STORE(13) FSLBM_STORE(14)
+            FSLBM_STORE(15) FSLBM_STORE(16) FSLBM_STORE(17) FSLBM_STORE(18)
+#undef FSLBM_STORE
+        }
+    }
+}
+
+// The stream-collide works on f (FP64) or on d = f - w (shifted forms):
+// pull, relax and push in the form of the precision.
+template <class P>
+__device__ inline void pull(const Fields<P> &F, const int (&j)[NQ], typename P::T (&v)[NQ])
+{
+    if constexpr (P::SHIFT) load_dirs_dev<P>(F, j, v);
+    else load_dirs<P>(F, j, v);
+}
+template <class P, int COLL>
+__device__ inline void relax(typename P::T (&v)[NQ], const Params &p)
+{
+    if constexpr (P::SHIFT) collide_dev<typename P::T, COLL>(v, p);
+    else collide<typename P::T, COLL>(v, p);
+}
+template <class P>
+__device__ inline void push(const Fields<P> &F, int i, const typename P::T (&v)[NQ])
+{
+    if constexpr (P::SHIFT) store_all_dev<P>(F, i, v);
+    else store_all<P>(F, i, v);
+}
+// Moments of the pulled or own values in either form: rho - 1 (dev) or rho.
+template <class P>
+__device__ inline void moments_any(const typename P::T (&v)[NQ], typename P::T &r, typename P::T &ux,
+                                   typename P::T &uy, typename P::T &uz)
+{
+    if constexpr (P::SHIFT) moments_dev(v, r, ux, uy, uz);
+    else moments(v, r, ux, uy, uz);
+}
+// The pair term of eq. reconstruct in the form of the values (rb: rho_b - 1
+// in the deviation form, rho_b otherwise).
+template <class P>
+__device__ inline typename P::T reconstruct_pair(int q, typename P::T rb, typename P::T ux, typename P::T uy,
+                                                 typename P::T uz, typename P::T usq)
+{
+    if constexpr (P::SHIFT) return feq_pair_dev(q, rb, ux, uy, uz, usq);
+    else return feq_pair(q, rb, ux, uy, uz, usq);
+}
+
 // Liquid cell away from walls: every D3Q19 neighbour is fluid (a liquid cell
 // never touches gas), so the pull needs no neighbour types.
 template <class P, int COLL>
@@ -158,9 +304,9 @@ __device__ inline void liquid_cell(const Fields<P> &F, const Params &prm, int i,
 #pragma unroll
     for (int q = 0; q < NQ; ++q) up[q] = nb.at(-dir_x(q), -dir_y(q), -dir_z(q));
     T fin[NQ];
-    load_dirs<P>(F, up, fin);
-    collide<T, COLL>(fin, prm);
-    store_all<P>(F, i, fin);
+    pull<P>(F, up, fin);
+    relax<P, COLL>(fin, prm);
+    push<P>(F, i, fin);
 }
 
 // Cell with wall links (IS_IF = false) or interface cell (IS_IF = true).
@@ -181,8 +327,8 @@ __device__ inline void boundary_cell(const Fields<P> &F, const Params &prm, int 
         own[q] = i;
     }
     T fo[NQ], pl[NQ];
-    load_dirs<P>(F, own, fo);
-    load_dirs<P>(F, up, pl);
+    pull<P>(F, own, fo);
+    pull<P>(F, up, pl);
     uint8_t nt[NQ];
 #pragma unroll
     for (int q = 1; q < NQ; ++q) nt[q] = F.flags[up[q]] & FL_TYPE;
@@ -208,9 +354,10 @@ __device__ inline void boundary_cell(const Fields<P> &F, const Params &prm, int 
     }
     // boundary values of eq. reconstruct
     T rb0, ubx, uby, ubz;
-    moments(fo, rb0, ubx, uby, ubz);
+    moments_any<P>(fo, rb0, ubx, uby, ubz);
     const T ubsq = ubx * ubx + uby * uby + ubz * ubz;
-    const T rhob = T(gas_density(prm, F.sc)) + T(3) * T(prm.sigma) * Kc;
+    // rho_b (rho_b - 1 in the deviation form)
+    const T rhob = T(gas_density(prm, F.sc) - (P::SHIFT ? 1.0 : 0.0)) + T(3) * T(prm.sigma) * Kc;
     // corner rule: the outgoing link c_o = -c_q takes the free-surface rule
     // when c_o . (P n) < 0, P the projection onto the wall plane; evaluated
     // as (P c_o) . n with P c_o |nw|^2 = c_o |nw|^2 - (c_o . nw) nw in exact
@@ -230,7 +377,7 @@ __device__ inline void boundary_cell(const Fields<P> &F, const Params &prm, int 
             const T s = T(cox * ww - cw * nwx) * cnx + T(coy * ww - cw * nwy) * cny + T(coz * ww - cw * nwz) * cnz;
             rec = s < T(0);
         }
-        const T vrec = feq_pair<T>(q, rhob, ubx, uby, ubz, ubsq) - fo[o];
+        const T vrec = reconstruct_pair<P>(q, rhob, ubx, uby, ubz, ubsq) - fo[o];
         fin[q] = (t & FL_FLUID) ? pl[q] : (rec ? vrec : fo[o]);
     }
     if constexpr (IS_IF) {
@@ -246,6 +393,7 @@ __device__ inline void boundary_cell(const Fields<P> &F, const Params &prm, int 
         T r = 0;
 #pragma unroll
         for (int q = 0; q < NQ; ++q) r += fin[q];
+        if constexpr (P::SHIFT) r = T(1) + r;
         const T mn = mc + dm;
         uint8_t st = CV_NONE;
         if (mn > (T(1) + T(prm.eps_c)) * r) st = CV_FILL;
@@ -253,10 +401,13 @@ __device__ inline void boundary_cell(const Fields<P> &F, const Params &prm, int 
         F.m[i] = R(mn);
         F.rho[i] = R(r);
         F.conv[i] = st;
-        if (st != CV_NONE && !prm.frozen) atomicAdd(&F.sc->nconv, 1);
+        if (st != CV_NONE) {
+            if (!prm.frozen) atomicAdd(&F.sc->nconv, 1);
+            else atomicMin(&F.sc->conv_out_step, F.sc->step);  // the free method would convert here
+        }
     }
-    collide<T, COLL>(fin, prm);
-    store_all<P>(F, i, fin);
+    relax<P, COLL>(fin, prm);
+    push<P>(F, i, fin);
 }
 
 // Any fluid cell, written so that the lanes of a wavefront share the pull,
@@ -273,14 +424,14 @@ __device__ inline void fluid_cell(const Fields<P> &F, const Params &prm, int i, 
 #pragma unroll
     for (int q = 0; q < NQ; ++q) up[q] = nb.at(-dir_x(q), -dir_y(q), -dir_z(q));
     T fin[NQ];
-    load_dirs<P>(F, up, fin);  // the pull; final wherever the upstream node is fluid
+    pull<P>(F, up, fin);  // the pull; final wherever the upstream node is fluid
     if (fl != FL_LIQ) {
         const bool is_if = (fl & FL_IF) != 0;
         int own[NQ];
 #pragma unroll
         for (int q = 0; q < NQ; ++q) own[q] = i;
         T fo[NQ];
-        load_dirs<P>(F, own, fo);
+        pull<P>(F, own, fo);
         uint8_t nt[NQ];
 #pragma unroll
         for (int q = 1; q < NQ; ++q) nt[q] = F.flags[up[q]] & FL_TYPE;
@@ -304,9 +455,10 @@ __device__ inline void fluid_cell(const Fields<P> &F, const Params &prm, int i, 
             if (nt[q] == FL_OBST) { nwx -= dir_x(q); nwy -= dir_y(q); nwz -= dir_z(q); }
         }
         T rb0, ubx, uby, ubz;
-        moments(fo, rb0, ubx, uby, ubz);
+        moments_any<P>(fo, rb0, ubx, uby, ubz);
         const T ubsq = ubx * ubx + uby * uby + ubz * ubz;
-        const T rhob = T(gas_density(prm, F.sc)) + T(3) * T(prm.sigma) * Kc;
+        // rho_b (rho_b - 1 in the deviation form)
+        const T rhob = T(gas_density(prm, F.sc) - (P::SHIFT ? 1.0 : 0.0)) + T(3) * T(prm.sigma) * Kc;
         const bool corner = is_if && has_gas && (nwx | nwy | nwz) != 0;
         const int ww = nwx * nwx + nwy * nwy + nwz * nwz;
 #pragma unroll
@@ -320,7 +472,7 @@ __device__ inline void fluid_cell(const Fields<P> &F, const Params &prm, int i, 
                 const T s = T(cox * ww - cw * nwx) * cnx + T(coy * ww - cw * nwy) * cny + T(coz * ww - cw * nwz) * cnz;
                 rec = s < T(0);
             }
-            const T vrec = feq_pair<T>(q, rhob, ubx, uby, ubz, ubsq) - fo[o];
+            const T vrec = reconstruct_pair<P>(q, rhob, ubx, uby, ubz, ubsq) - fo[o];
             fin[q] = (t & FL_FLUID) ? fin[q] : (rec ? vrec : fo[o]);
         }
         if (is_if) {
@@ -335,6 +487,7 @@ __device__ inline void fluid_cell(const Fields<P> &F, const Params &prm, int i, 
             T r = 0;
 #pragma unroll
             for (int q = 0; q < NQ; ++q) r += fin[q];
+            if constexpr (P::SHIFT) r = T(1) + r;
             const T mn = mc + dm;
             uint8_t st = CV_NONE;
             if (mn > (T(1) + T(prm.eps_c)) * r) st = CV_FILL;
@@ -342,11 +495,14 @@ __device__ inline void fluid_cell(const Fields<P> &F, const Params &prm, int i, 
             F.m[i] = R(mn);
             F.rho[i] = R(r);
             F.conv[i] = st;
-            if (st != CV_NONE && !prm.frozen) atomicAdd(&F.sc->nconv, 1);
+            if (st != CV_NONE) {
+                if (!prm.frozen) atomicAdd(&F.sc->nconv, 1);
+                else atomicMin(&F.sc->conv_out_step, F.sc->step);  // the free method would convert here
+            }
         }
     }
-    collide<T, COLL>(fin, prm);
-    store_all<P>(F, i, fin);
+    relax<P, COLL>(fin, prm);
+    push<P>(F, i, fin);
 }
 
 // Stream-collide over the fluid bounding box. MODE 0: every fluid cell;

@@ -92,6 +92,7 @@ def load_library(path: str = LIB_PATH):
         "fslbm_adjoint_required_bytes": [vp, i64, i32, ctypes.POINTER(ctypes.c_size_t)],
         "fslbm_adjoint_forward": [vp, i64, i32, vp, ctypes.c_size_t],
         "fslbm_adjoint_backward": [vp, vp, i32, dp, dp, vp, i32],
+        "fslbm_adjoint_status": [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -310,6 +311,13 @@ def fslbm_adjoint_required_bytes(h, nsteps, K):
 def fslbm_adjoint_forward(h, nsteps, K, workspace_ptr, workspace_bytes):
     _check(load_library().fslbm_adjoint_forward(h, int(nsteps), int(K), ctypes.c_void_p(workspace_ptr),
                                                 workspace_bytes))
+
+
+def fslbm_adjoint_status(h):
+    """(inside_steps, fill_events, unconverted_steps) of the recorded window."""
+    a, b, c = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
+    _check(load_library().fslbm_adjoint_status(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return a.value, b.value, c.value
 
 
 def fslbm_adjoint_backward(h, dfill_T, dfill_0):
@@ -531,6 +539,13 @@ class Lattice:
             self._adj_ws = None
             self._adj_ws = self._torch.empty(nbytes, dtype=self._torch.uint8, device=self.device)
         fslbm_adjoint_forward(self._h, nsteps, K, self._adj_ws.data_ptr(), self._adj_ws.numel())
+
+    def adjoint_status(self):
+        """(inside_steps, fill_events, unconverted_steps) of the recorded
+        window: the steps before an interface fill first left (0, 1), how
+        many (step, cell) pairs did, and the steps before the method with
+        free cell types would first have converted a cell."""
+        return fslbm_adjoint_status(self._h)
 
     def adjoint_backward(self, dfill_T):
         """(dL/dphi_0 as a device float64 tensor (nz, ny, nx), dL/dsigma,

@@ -16,10 +16,12 @@ def test_algorithmic_bytes_per_launch():
     flags[2, 2, 2] = 2    # one interface cell
     flags[0, 0, 0] = 3
     for prec, s, r in (("f32", 4, 4), ("f16", 2, 4), ("bf16", 2, 4), ("f64", 8, 8)):
-        bl, bi, nl, ni = bench.sc_bytes(flags, prec)
+        bl, bi, nl, ni, nbox = bench.sc_bytes(flags, prec)
         assert (nl, ni) == (2, 1)
-        # 19 reads and 19 writes of a distribution per liquid cell, 1 flag byte per lattice cell
-        assert bl == 2 * 38 * s + 64
+        # the fluid bounding box: z 1..2, y 1..2, x 1..2
+        assert nbox == 8
+        # 19 reads and 19 writes of a distribution per liquid cell, 1 flag byte per fluid-box cell
+        assert bl == 2 * 38 * s + 8
         # the same per interface cell, plus m (read, write), rho, K, phi and a status byte
         assert bi == 38 * s + 5 * r + 1
 
