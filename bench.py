@@ -646,7 +646,7 @@ def oscillation_table(dev, precisions, steps, every=500):
     return out
 
 
-def run_workload(dev, stream, name, prec, steps, warmup, split=False, graph=False, keep=False):
+def run_workload(dev, stream, name, prec, steps, warmup, split=None, graph=False, keep=False):
     """Times `steps` steps of a workload (after `warmup`) with per-phase HIP
     events on the lattices' stream; returns the record and, with keep, the
     lattices and their batch (else they are released)."""
@@ -659,8 +659,7 @@ def run_workload(dev, stream, name, prec, steps, warmup, split=False, graph=Fals
         for label, fill, obst, p in runs:
             lats.append(Lattice(fill, obst, precision=prec, device=dev, stream=stream, **p))
     batch = Batch(lats)
-    if split:
-        batch.set_split_interface(True)
+    batch.set_split_interface(split)
     torch.cuda.synchronize()
     print(f"# {len(lats)} lattice(s) created: {desc}, {prec}", file=sys.stderr, flush=True)
     batch.step(warmup)
@@ -681,6 +680,7 @@ def run_workload(dev, stream, name, prec, steps, warmup, split=False, graph=Fals
         bl, bi, nl, ni, nbox = bl + a, bi + b, nl + c, ni + d, nbox + e
         ncell += lat.n
         lat.check_numeric()
+    split = batch.split_active()
     sc_ms = phase[0]
     launch = bl if split else bl + bi  # the merged kernel also moves the interface cells' bytes
     achieved = launch * steps / (sc_ms * 1e-3) / 1e9
@@ -688,6 +688,7 @@ def run_workload(dev, stream, name, prec, steps, warmup, split=False, graph=Fals
            "steps": steps, "warmup": warmup, "ms_per_step": round(1e3 * el / steps, 4),
            "mlups": round(ncell * steps / el / 1e6, 1), "mflups": round((nl + ni) * steps / el / 1e6, 1),
            "fluid_cells": nl + ni, "interface_cells": ni, "fluid_box_cells": nbox,
+           "split_passes": split,
            "stream_collide_us": round(1e3 * sc_ms / steps, 3), "algorithmic_bytes_per_launch": int(launch),
            "stream_collide_GBs": round(achieved, 1), "roofline_frac": round(achieved / HBM_PEAK_GBS, 4),
            "phases_ms_per_step": {k: round(v / steps, 4) for k, v in
@@ -773,8 +774,8 @@ def main():
     ap.add_argument("--precision", default="f32", choices=["f64", "f32", "f16", "bf16"])
     ap.add_argument("--graph", type=int, default=1,
                     help="also time a graph-replay pass after the timed region")
-    ap.add_argument("--split", type=int, default=0,
-                    help="1: interface cells in their own list kernel (same results)")
+    ap.add_argument("--split", type=int, default=-1,
+                    help="1: interface cells in their own list kernel, 0: one pass, -1: the library's choice")
     ap.add_argument("--compare", default="f16,bf16",
                     help="comma list of storage precisions also timed on the same workload ('' for none)")
     ap.add_argument("--sweep-steps", type=int, default=200,
@@ -875,7 +876,7 @@ def main():
 
     stream = torch.cuda.Stream(dev)
     head = run_workload(dev, stream, args.workload, args.precision, args.steps, args.warmup,
-                        split=bool(args.split), graph=bool(args.graph))
+                        split=None if args.split < 0 else bool(args.split), graph=bool(args.graph))
     traffic = stored_traffic(args.workload, args.precision)
     nunits = head["fluid_cells"]
     res = {
@@ -893,13 +894,13 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{head['workload']}, {args.precision} storage and arithmetic",
                    "lattice": head["lattice"], "lattices": head["lattices"], "storage": args.precision,
-                   "split_interface": bool(args.split), "fluid_cells": head["fluid_cells"],
+                   "split_passes": head["split_passes"], "fluid_cells": head["fluid_cells"],
                    "interface_cells": head["interface_cells"], "fluid_box_cells": head["fluid_box_cells"]},
         "roofline": {"bound": "hbm", "achieved": head["stream_collide_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": head["roofline_frac"],
                      "traffic": traffic.get("bytes_per_launch") if traffic else None,
                      "copy_kernel_GBs": round(copy_gbs, 1) if copy_gbs else None,
-                     "kernel": "k_stream_collide" + (" (liquid cells)" if args.split else ""),
+                     "kernel": "k_stream_collide" + (" (lean liquid pass)" if head["split_passes"] else ""),
                      "avg_launch_us": head["stream_collide_us"],
                      "algorithmic_bytes_per_launch": head["algorithmic_bytes_per_launch"],
                      "units_per_launch": nunits,

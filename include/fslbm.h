@@ -84,8 +84,10 @@ enum fslbm_option {
                                  stream), 0: plain launches (default) */
     FSLBM_OPT_SPLIT_INTERFACE = 5, /* 1: two stream-collide passes, a lean one
                                  for liquid cells away from walls and one for
-                                 interface and wall-adjacent cells; 0
-                                 (default): one pass for all fluid cells.
+                                 interface and wall-adjacent cells; 0: one pass for all fluid cells; -1
+                                 (default): the two passes for the 16-bit
+                                 storage forms when interface and wall cells
+                                 are under 1/64 of the fluid box, else one.
                                  Results are identical either way. */
     FSLBM_OPT_BUBBLE = 6,     /* 1: bubble model (Sec. III.A.1): the whole gas
                                  of the lattice is one bubble whose pressure
@@ -256,6 +258,10 @@ int fslbm_batch_create(const fslbm_t *handles, int count, fslbm_batch_t *out);
 int fslbm_batch_step(fslbm_batch_t b, int64_t nsteps);
 int fslbm_batch_set_option(fslbm_batch_t b, int key, double value);
 int fslbm_batch_read_timing(fslbm_batch_t b, double *phase_ms, int64_t *steps);
+/* *active = 1 if the last step of the batch (of the lattice) ran the two
+ * stream-collide passes of FSLBM_OPT_SPLIT_INTERFACE, else 0. */
+int fslbm_batch_split_active(fslbm_batch_t b, int *active);
+int fslbm_split_active(fslbm_t h, int *active);
 int fslbm_batch_reset_timing(fslbm_batch_t b);
 void fslbm_batch_destroy(fslbm_batch_t b);
 

@@ -96,31 +96,64 @@ __device__ inline float to_float(__hip_bfloat16 v) { return __bfloat162float(v);
 __device__ inline void store_rn(float *p, float v) { __builtin_nontemporal_store(v, p); }
 __device__ inline void store_rn(__half *p, float v) { *p = __float2half_rn(v); }
 __device__ inline void store_rn(__hip_bfloat16 *p, float v) { *p = __float2bfloat16(v); }
-// Stochastic rounding to 16 bits: `bits` (uniform) is added below the kept
-// mantissa bits of |v| and the rest dropped, which rounds |v| up with the
-// probability of the dropped fraction, so the expected stored value is v.
-// Rounding to nearest is exact in expectation only for values spread over
-// many quanta; a nearly uniform fluid stores the same few values in every
-// cell, the nearest-rounding errors then all have one sign, and the total
-// mass drifts by a fixed amount every step. F16 keeps 10 of FP32's 23
-// mantissa bits (13 dropped, for values in its normal range), BF16 keeps 7
-// (16 dropped); the truncated value is exact in the 16-bit format.
+// Stochastic rounding to 16 bits with gfx950's conversion instructions: the
+// top bits of the uniform word `bits` are added below the kept mantissa
+// bits and the rest is dropped (13 bits for F16 in its normal range, 16 for
+// BF16), so |v| is rounded up with the probability of the dropped fraction
+// and the expected stored value is v. Rounding to nearest is exact in
+// expectation only for values spread over many quanta; a nearly uniform
+// fluid stores the same few values in every cell, the nearest-rounding
+// errors then all have one sign, and the total mass drifts by a fixed amount
+// every step.
+typedef _Float16 fslbm_h2 __attribute__((ext_vector_type(2)));
+typedef __bf16 fslbm_bf2 __attribute__((ext_vector_type(2)));
+// The 16-bit code of v in the low half of the result.
+// The conversion keeps the other half of its destination; callers of
+// sr_code store only the low half, so it starts as v's own bits (any value
+// would do; this one needs no extra register).
+__device__ inline uint32_t sr_code(__half, float v, uint32_t bits)
+{
+    return __builtin_bit_cast(uint32_t,
+                              __builtin_amdgcn_cvt_sr_f16_f32(__builtin_bit_cast(fslbm_h2, v), v, bits, false));
+}
+__device__ inline uint32_t sr_code(__hip_bfloat16, float v, uint32_t bits)
+{
+    return __builtin_bit_cast(uint32_t,
+                              __builtin_amdgcn_cvt_sr_bf16_f32(__builtin_bit_cast(fslbm_bf2, v), v, bits, false));
+}
+// Two codes in one word: a (low half) and b (high half).
+__device__ inline uint32_t sr_code2(__half, float a, uint32_t ba, float b, uint32_t bb)
+{
+    fslbm_h2 h = __builtin_bit_cast(fslbm_h2, a);
+    h = __builtin_amdgcn_cvt_sr_f16_f32(h, a, ba, false);
+    h = __builtin_amdgcn_cvt_sr_f16_f32(h, b, bb, true);
+    return __builtin_bit_cast(uint32_t, h);
+}
+__device__ inline uint32_t sr_code2(__hip_bfloat16, float a, uint32_t ba, float b, uint32_t bb)
+{
+    fslbm_bf2 h = __builtin_bit_cast(fslbm_bf2, a);
+    h = __builtin_amdgcn_cvt_sr_bf16_f32(h, a, ba, false);
+    h = __builtin_amdgcn_cvt_sr_bf16_f32(h, b, bb, true);
+    return __builtin_bit_cast(uint32_t, h);
+}
 __device__ inline void store_sr(float *p, float v, uint32_t) { __builtin_nontemporal_store(v, p); }
+// Streaming stores (non-temporal), as FP32: the written planes are not read
+// again in the step, and leaving them out of L2 keeps the pulled lines there.
 __device__ inline void store_sr(__half *p, float v, uint32_t bits)
 {
-    const uint32_t u = (__float_as_uint(v) + (bits >> 19)) & ~0x1fffu;
-    *p = __float2half_rn(__uint_as_float(u));
+    __builtin_nontemporal_store((unsigned short)sr_code(__half(), v, bits), (unsigned short *)p);
 }
 __device__ inline void store_sr(__hip_bfloat16 *p, float v, uint32_t bits)
 {
-    const uint32_t u = (__float_as_uint(v) + (bits >> 16)) & ~0xffffu;
-    *p = __float2bfloat16(__uint_as_float(u));
+    __builtin_nontemporal_store((unsigned short)sr_code(__hip_bfloat16(), v, bits), (unsigned short *)p);
 }
 
 // Counter-based random bits for the stochastic stores: one hash of (cell,
 // step) per cell (the low-bias 32-bit integer hash of Wellons' "prospecting
-// for hash functions"), then one multiply-xorshift per direction along a
-// Weyl sequence. Deterministic: a run is reproduced bit for bit.
+// for hash functions") seeds Marsaglia's xorshift32 generator (shifts 13,
+// 17, 5; "Xorshift RNGs", 2003). Each of its words serves two directions:
+// the word itself and its low half moved to the top, since the conversions
+// take the top bits. Deterministic: a run is reproduced bit for bit.
 __device__ inline uint32_t hash32(uint32_t x)
 {
     x ^= x >> 16;
@@ -131,13 +164,23 @@ __device__ inline uint32_t hash32(uint32_t x)
     return x;
 }
 __device__ inline uint32_t cell_seed(int i, uint32_t step) { return hash32(uint32_t(i) ^ hash32(step * 0x9e3779b9u)); }
-__device__ inline uint32_t dir_bits(uint32_t seed, int q)
-{
-    uint32_t x = seed + uint32_t(q + 1) * 0x9e3779b9u;
-    x *= 0x85ebca6bu;
-    x ^= x >> 13;
-    return x;
-}
+struct SrBits {
+    uint32_t x, w;
+    // xorshift32 never leaves the state 0, which the hash maps one cell to
+    __device__ inline explicit SrBits(uint32_t seed) : x(seed ? seed : 0x9e3779b9u), w(0) {}
+    // the word for direction q; called for q = 0, 1, ..., 18 in order
+    __device__ inline uint32_t at(int q)
+    {
+        if ((q & 1) == 0) {
+            x ^= x << 13;
+            x ^= x >> 17;
+            x ^= x << 5;
+            w = x;
+            return w;
+        }
+        return w << 16;
+    }
+};
 
 // f_q from storage (any form).
 template <class P, int Q>
@@ -159,6 +202,30 @@ __device__ inline void store_f(typename P::S *__restrict__ plane, int i, typenam
     } else {
         __builtin_nontemporal_store(v, plane + i);
     }
+}
+// Stored value of a shifted form in the units of the store (d_q SCALE) and
+// its inverse, with stochastic rounding in the 16-bit forms. The 16-bit
+// forms address a plane with a 32-bit byte offset (a plane of at most
+// 2^31 cells), which the loads and stores take as is.
+template <class P>
+__device__ inline constexpr int scale_log2()
+{
+    static_assert(P::SCALE == 1.0 || P::SCALE == 4096.0, "power-of-two scales only");
+    return P::SCALE == 4096.0 ? 12 : 0;
+}
+template <class P>
+__device__ inline typename P::T load_raw(const typename P::S *__restrict__ plane, int i)
+{
+    using S = typename P::S;
+    if constexpr (sizeof(S) == 2) return to_float(*(const S *)((const char *)plane + uint32_t(i) * 2u));
+    else return to_float(plane[i]);
+}
+template <class P>
+__device__ inline void store_raw(typename P::S *__restrict__ plane, int i, typename P::T v, uint32_t bits)
+{
+    using S = typename P::S;
+    if constexpr (sizeof(S) == 2) store_sr((S *)((char *)plane + uint32_t(i) * 2u), v, bits);
+    else store_sr(plane + i, v, bits);
 }
 // Deviation d_q = f_q - w_q from shifted storage.
 template <class P, int Q>
@@ -220,6 +287,39 @@ struct CellRange {
         return {b[0], b[1], b[2], b[3] - b[0] + 1, b[4] - b[1] + 1, b[5] - b[2] + 1};
     }
 };
+
+// XCD-aware order of the 256-cell chunks of a one-shot grid. The hardware
+// hands workgroups to the 8 XCDs in turn (workgroup b to XCD b mod 8), and
+// each XCD has its own L2. The x-shifted pulls of a chunk read one cache
+// line of every such plane that the neighbouring chunk also reads; with
+// chunk = b that neighbour runs on another XCD and the line is fetched from
+// HBM twice (about 1/8 more reads in FP32, 1/4 in the 16-bit forms, over
+// the 10 directions with c_x != 0). Here `run` consecutive chunks go to one
+// XCD, so only one chunk boundary in `run` crosses XCDs, and successive
+// runs go to successive XCDs, so the blocks in flight still cover one
+// narrow window of the box. Measured on the 512^3 probe: the 16-bit lean
+// pass gains 6 % with runs of 8 (2.02 -> 1.89 ms); FP32 does not gain and
+// runs of 4 or 8 slow it by 5-25 % (the access pattern across HBM channels
+// changes), so it keeps runs of 1. The host rounds such grids up to a
+// multiple of XCD_GRID (so that blockIdx.y does not shift the XCD of a
+// block); the map is a bijection of [0, gridDim.x).
+constexpr int XCDS = 8, XCD_GRID = 64;
+template <class P>
+__host__ __device__ constexpr int xcd_run()
+{
+    return sizeof(typename P::S) == 2 ? 8 : 1;
+}
+__host__ __device__ inline int xcd_chunk(int b, int grid, int run)
+{
+    const int period = XCDS * run;
+    if (b >= grid / period * period) return b;
+    return b / period * period + (b % XCDS) * run + (b / XCDS) % run;
+}
+__host__ inline int xcd_grid(long long chunks)
+{
+    const long long g = (chunks + XCD_GRID - 1) / XCD_GRID * XCD_GRID;
+    return (int)std::max<long long>(XCD_GRID, g);
+}
 
 // Contiguous share [k0, k1) of n items for block blockIdx.x of gridDim.x,
 // in whole 256-item strides.

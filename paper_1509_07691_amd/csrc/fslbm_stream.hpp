@@ -104,12 +104,24 @@ __device__ inline void collide(T (&f)[NQ], const Params &p)
     }
 }
 
+// a * b + c. The FP32 arithmetic of the shifted forms rounds once (fused);
+// FP64, compared value by value with the CPU reference, rounds twice.
+template <class T> __device__ inline T mla(T a, T b, T c);
+template <> __device__ inline float mla<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+template <> __device__ inline double mla<double>(double a, double b, double c) { return a * b + c; }
+
 // Deviation form, used with the shifted storage forms (fslbm_device.hpp):
 // the values are d_q = f_q - w_q. The weights sum to 1 and carry no
 // momentum, so rho = 1 + sum d and rho u = sum c d, and the equilibrium
 // deviation is w_q (rho - 1) + w_q rho [3 c.u + 9/2 (c.u)^2 - 3/2 u^2]. Each
 // formula below is its f-form counterpart above rewritten exactly.
-template <class T>
+//
+// LS: the values may be held as D_q = 2^LS d_q, the units of the F16 store
+// (its scale 2^12), so that loads and stores need no scaling. Every step is
+// then exactly 2^LS times its LS = 0 counterpart (sums, and products with
+// one scaled factor; scaling by a power of two does not change a rounding),
+// so both give the same stored bits.
+template <class T, int LS = 0>
 __device__ inline void moments_dev(const T (&d)[NQ], T &drho, T &ux, T &uy, T &uz)
 {
     T r = 0, jx = 0, jy = 0, jz = 0;
@@ -120,8 +132,9 @@ __device__ inline void moments_dev(const T (&d)[NQ], T &drho, T &ux, T &uy, T &u
         if (dir_y(q)) jy += T(dir_y(q)) * d[q];
         if (dir_z(q)) jz += T(dir_z(q)) * d[q];
     }
-    drho = r;
-    const T ir = T(1) / (T(1) + r);
+    drho = LS ? r * T(1.0 / (1 << LS)) : r;
+    T ir = T(1) / (T(1) + drho);
+    if (LS) ir = ir * T(1.0 / (1 << LS));
     ux = jx * ir;
     uy = jy * ir;
     uz = jz * ir;
@@ -136,26 +149,28 @@ __device__ inline T feq_pair_dev(int q, T drho, T ux, T uy, T uz, T usq)
     return T(2) * weight<T>(q) * (drho + (T(1) + drho) * (T(4.5) * cu * cu - T(1.5) * usq));
 }
 
-template <class T, int COLL>
+template <class T, int COLL, int LS = 0>
 __device__ inline void collide_dev(T (&d)[NQ], const Params &p)
 {
     T drho, ux, uy, uz;
-    moments_dev(d, drho, ux, uy, uz);
+    moments_dev<T, LS>(d, drho, ux, uy, uz);
     const T rho = T(1) + drho;
-    const T usq = ux * ux + uy * uy + uz * uz;
+    const T usq = mla(ux, ux, mla(uy, uy, uz * uz));
+    const T u15 = T(1.5) * usq;
     const T we = T(p.omega);
+    constexpr double SC = double(1 << LS);
     if constexpr (COLL == 0) {
-        d[0] = d[0] - we * (d[0] - weight<T>(0) * (drho - rho * (T(1.5) * usq)));
+        d[0] = mla(-we, d[0] - (weight<T>(0) * T(SC)) * mla(-rho, u15, drho), d[0]);
         // each pair (q, qbar): equilibrium deviations a +- b
 #pragma unroll
         for (int q = 1; q < NQ; ++q) {
             const int o = opp(q);
             if (o < q) continue;
             const T cu = cdot<T>(q, ux, uy, uz);
-            const T w = weight<T>(q), wr = w * rho;
-            const T a = w * drho + wr * (T(4.5) * cu * cu - T(1.5) * usq), b = wr * (T(3) * cu);
-            d[q] = d[q] - we * (d[q] - (a + b));
-            d[o] = d[o] - we * (d[o] - (a - b));
+            const T w = weight<T>(q) * T(SC), wr = w * rho;
+            const T a = mla(wr, mla(T(4.5) * cu, cu, -u15), w * drho), b = wr * (T(3) * cu);
+            d[q] = mla(-we, d[q] - (a + b), d[q]);
+            d[o] = mla(-we, d[o] - (a - b), d[o]);
         }
     } else {
         const T wo = T(p.omega_odd);
@@ -164,11 +179,11 @@ __device__ inline void collide_dev(T (&d)[NQ], const Params &p)
         for (int q = 0; q < NQ; ++q) {
             const int o = opp(q);
             const T cu = cdot<T>(q, ux, uy, uz);
-            const T w = weight<T>(q), wr = w * rho;
+            const T w = weight<T>(q) * T(SC), wr = w * rho;
             // even and odd parts of the equilibrium deviation of q
-            const T ev = w * drho + wr * (T(4.5) * cu * cu - T(1.5) * usq), od = wr * (T(3) * cu);
+            const T ev = mla(wr, mla(T(4.5) * cu, cu, -u15), w * drho), od = wr * (T(3) * cu);
             const T dp = T(0.5) * (d[q] + d[o]), dm = T(0.5) * (d[q] - d[o]);
-            g[q] = d[q] - we * (dp - ev) - wo * (dm - od);
+            g[q] = mla(-wo, dm - od, mla(-we, dp - ev, d[q]));
         }
 #pragma unroll
         for (int q = 0; q < NQ; ++q) d[q] = g[q];
@@ -242,11 +257,12 @@ __device__ inline void load_dirs_dev(const Fields<P> &F, const int (&j)[NQ], typ
 template <class P>
 __device__ inline void store_all_dev(const Fields<P> &F, int i, const typename P::T (&d)[NQ])
 {
-    const uint32_t seed = sizeof(typename P::S) == 2 ? cell_seed(i, F.sc->step) : 0u;
+    SrBits rb(sizeof(typename P::S) == 2 ? cell_seed(i, F.sc->step) : 0u);
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
+        const uint32_t bits = sizeof(typename P::S) == 2 ? rb.at(q) : 0u;
         switch (q) {
-#define FSLBM_STORE(QQ) case QQ: store_d<P, QQ>(plane<P, QQ>(F.fdst, F.NS), i, d[q], dir_bits(seed, q)); break;
+#define FSLBM_STORE(QQ) case QQ: store_d<P, QQ>(plane<P, QQ>(F.fdst, F.NS), i, d[q], bits); break;
             FSLBM_STORE(0) FSLBM_STORE(1) FSLBM_STORE(2) FSLBM_STORE(3) FSLBM_STORE(4)
             FSLBM_STORE(5) FSLBM_STORE(6) FSLBM_STORE(7) FSLBM_STORE(8) FSLBM_STORE(9)
             FSLBM_STORE(10) FSLBM_STORE(11) FSLBM_STORE(12) FSLBM_STORE(13) FSLBM_STORE(14)
@@ -296,6 +312,7 @@ __device__ inline typename P::T reconstruct_pair(int q, typename P::T rb, typena
 
 // Liquid cell away from walls: every D3Q19 neighbour is fluid (a liquid cell
 // never touches gas), so the pull needs no neighbour types.
+// The shifted forms work here in the units of the store (LS above).
 template <class P, int COLL>
 __device__ inline void liquid_cell(const Fields<P> &F, const Params &prm, int i, const Nbr &nb)
 {
@@ -304,9 +321,20 @@ __device__ inline void liquid_cell(const Fields<P> &F, const Params &prm, int i,
 #pragma unroll
     for (int q = 0; q < NQ; ++q) up[q] = nb.at(-dir_x(q), -dir_y(q), -dir_z(q));
     T fin[NQ];
-    pull<P>(F, up, fin);
-    relax<P, COLL>(fin, prm);
-    push<P>(F, i, fin);
+    if constexpr (P::SHIFT) {
+        constexpr int LS = scale_log2<P>();
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) fin[q] = load_raw<P>(F.fsrc + (size_t)q * (size_t)F.NS, up[q]);
+        collide_dev<T, COLL, LS>(fin, prm);
+        SrBits rb(sizeof(typename P::S) == 2 ? cell_seed(i, F.sc->step) : 0u);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+            store_raw<P>(F.fdst + (size_t)q * (size_t)F.NS, i, fin[q], sizeof(typename P::S) == 2 ? rb.at(q) : 0u);
+    } else {
+        pull<P>(F, up, fin);
+        relax<P, COLL>(fin, prm);
+        push<P>(F, i, fin);
+    }
 }
 
 // Cell with wall links (IS_IF = false) or interface cell (IS_IF = true).
@@ -523,7 +551,7 @@ __device__ inline void stream_collide_box(const Batch<P> &B)
     const Fields<P> &F = B.f[blockIdx.y];
     const CellRange box = CellRange::from(F.sc->fbox);
     const int n = box.size();
-    for (int c = blockIdx.x; c * 256 < n; c += gridDim.x) {
+    for (int c = xcd_chunk(blockIdx.x, gridDim.x, xcd_run<P>()); c * 256 < n; c += gridDim.x) {
         const int k = c * 256 + (int)threadIdx.x;
         if (k >= n) continue;
         const int bx = k % box.ex, r = k / box.ex, by = r % box.ey, bz = r / box.ey;

@@ -85,6 +85,8 @@ def load_library(path: str = LIB_PATH):
         "fslbm_batch_set_option": [vp, i32, ctypes.c_double],
         "fslbm_batch_read_timing": [vp, dp, ctypes.POINTER(i64)],
         "fslbm_batch_reset_timing": [vp],
+        "fslbm_batch_split_active": [vp, ctypes.POINTER(i32)],
+        "fslbm_split_active": [vp, ctypes.POINTER(i32)],
         "fslbm_set_interface_fill": [vp, vp, i32],
         "fslbm_state_bytes": [vp, ctypes.POINTER(ctypes.c_size_t)],
         "fslbm_save_state": [vp, vp, ctypes.c_size_t],
@@ -356,6 +358,18 @@ def fslbm_batch_reset_timing(b):
     _check(load_library().fslbm_batch_reset_timing(b))
 
 
+def fslbm_batch_split_active(b):
+    out = ctypes.c_int(0)
+    _check(load_library().fslbm_batch_split_active(b, ctypes.byref(out)))
+    return bool(out.value)
+
+
+def fslbm_split_active(h):
+    out = ctypes.c_int(0)
+    _check(load_library().fslbm_split_active(h, ctypes.byref(out)))
+    return bool(out.value)
+
+
 def fslbm_batch_destroy(b):
     load_library().fslbm_batch_destroy(b)
 
@@ -489,7 +503,11 @@ class Lattice:
         fslbm_set_option(self._h, FSLBM_OPT_GRAPH, 1 if on else 0)
 
     def set_split_interface(self, on=True):
-        fslbm_set_option(self._h, FSLBM_OPT_SPLIT_INTERFACE, 1 if on else 0)
+        """True: two passes, False: one pass, None: automatic (default)."""
+        fslbm_set_option(self._h, FSLBM_OPT_SPLIT_INTERFACE, -1 if on is None else (1 if on else 0))
+
+    def split_active(self):
+        return fslbm_split_active(self._h)
 
     def set_bubble(self, on=True):
         fslbm_set_option(self._h, FSLBM_OPT_BUBBLE, 1 if on else 0)
@@ -583,7 +601,11 @@ class Batch:
         fslbm_batch_set_option(self._b, FSLBM_OPT_GRAPH, 1 if on else 0)
 
     def set_split_interface(self, on=True):
-        fslbm_batch_set_option(self._b, FSLBM_OPT_SPLIT_INTERFACE, 1 if on else 0)
+        """True: two passes, False: one pass, None: automatic (default)."""
+        fslbm_batch_set_option(self._b, FSLBM_OPT_SPLIT_INTERFACE, -1 if on is None else (1 if on else 0))
+
+    def split_active(self):
+        return fslbm_batch_split_active(self._b)
 
     def timing(self):
         return fslbm_batch_read_timing(self._b)

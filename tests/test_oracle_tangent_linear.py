@@ -8,7 +8,9 @@ condition) and the initial fill level (a seeded direction on the interface
 cells), with the FD, LSQR and TR curvature models. The LSQR and TR cases
 also pin the implicit derivative of the PLIC offset that replaces the
 bisection's."""
+import json
 import math
+import os
 
 import numpy as np
 import pytest
@@ -95,3 +97,22 @@ def test_tangent_linear_values_and_derivatives(name):
     for k, (tl, fd) in checks.items():
         print(name, k, tl, fd)
         assert abs(tl - fd) <= 1e-6 * abs(fd), (k, tl, fd)
+
+
+def test_stored_benchmark_window_tangent_linear_matches_differences():
+    """The stored oracle values of the differentiation workload
+    (tests/golden/make_adjoint_c4_reference.py): over the window in which
+    every interface fill stays inside (0, 1) the tangent-linear derivatives
+    agree with the oracle's extrapolated central differences; over the
+    longer window, where fills cross 0, the loss is only piecewise smooth
+    and the two may differ by percents."""
+    ref = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "adjoint_c4_oracle.json")))
+    assert 1 <= ref["T_inside"] <= ref["T_unconverted"] <= ref["TMAX"]
+    inside = [w for w in ref["windows"] if w["T"] <= ref["T_inside"]]
+    assert inside
+    for w in inside:
+        lo, hi = w["interface_fill_range_T"]
+        assert 0.0 < lo and hi < 1.0
+        for k, tl in w["tangent_linear"].items():
+            cd = w["central_differences"][k]
+            assert abs(tl - cd) <= 1e-7 * abs(tl), (w["T"], k, tl, cd)
