@@ -124,17 +124,29 @@ __global__ void k_adj_finish(Fields<P> F, Adj A, const typename P::R *snap0, dou
 }
 
 // ------------------------------------------------ phi = m / rho (reverse)
+// phi = m / rho of step t+1 reversed (m and rho from its snapshot), and the
+// state of step t restored from its snapshot (as k_snap with save = 0):
+// both go entry by entry over the same lists, so they share one launch.
 template <class P>
-__global__ void k_adj_prepass(Fields<P> F, Adj A, const typename P::R *snap_next)
+__global__ __launch_bounds__(256) void k_adj_prepass(Fields<P> F, Adj A, const typename P::R *snap_next,
+                                                     const typename P::R *snap_cur)
 {
-    const int n = F.sc->icount;
-    for (int k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256) {
-        const int i = F.ilist[k];
-        const double m = double(snap_next[(size_t)SNAP * k]), r = double(snap_next[(size_t)SNAP * k + 1]);
-        const double pb = A.phib[i];
-        A.mbar[i] += pb / r;
-        A.rhob[i] = -pb * m / (r * r);
-        A.phib[i] = 0.0;
+    const int n = F.sc->icount, no = F.sc->ocount;
+    const size_t N = F.N;
+    for (int k = blockIdx.x * 256 + threadIdx.x; k < n + no; k += gridDim.x * 256) {
+        if (k < n) {
+            const int i = F.ilist[k];
+            const double m = double(snap_next[(size_t)SNAP * k]), r = double(snap_next[(size_t)SNAP * k + 1]);
+            const double pb = A.phib[i];
+            A.mbar[i] += pb / r;
+            A.rhob[i] = -pb * m / (r * r);
+            A.phib[i] = 0.0;
+            const typename P::R *s = snap_cur + (size_t)SNAP * k;
+            F.m[i] = s[0]; F.rho[i] = s[1]; F.phi[i] = s[2]; F.K[i] = s[3];
+            F.nrm[i] = s[4]; F.nrm[N + i] = s[5]; F.nrm[2 * N + i] = s[6]; F.plic[i] = s[7];
+        } else {
+            F.phi[F.olist[k - n]] = snap_cur[(size_t)SNAP * n + (k - n)];
+        }
     }
 }
 
@@ -1102,39 +1114,63 @@ __host__ __device__ inline void lsqr_curvature_adj(const View &V, const Params &
 constexpr int ADJ_LANES = 8;
 
 template <class P>
-__global__ __launch_bounds__(256) void k_adj_lsqr_cell(const Fields<P> F, const Adj A, const Params prm)
+__device__ inline void plic_derivs_blocks(const Fields<P> &F, const Adj &A, int b, int nb);
+
+// The launch also computes the PLIC derivatives (plic_derivs_blocks): blocks
+// from cell_blocks on take that independent work, which then runs in the
+// slots the long per-cell blocks leave free instead of after them.
+template <class P>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_adj_lsqr_cell(const Fields<P> F, const Adj A, const Params prm,
+                                                       int cell_blocks)
 {
-    const int n = F.sc->icount;
-    const int lane = threadIdx.x % ADJ_LANES;
+    if ((int)blockIdx.x >= cell_blocks) {
+        plic_derivs_blocks<P>(F, A, blockIdx.x - cell_blocks, gridDim.x - cell_blocks);
+        return;
+    }
     constexpr int per_block = 256 / ADJ_LANES;
-    for (int k = blockIdx.x * per_block + threadIdx.x / ADJ_LANES; k < n; k += gridDim.x * per_block) {
-        const int i = F.ilist[k];
-        double *cb = A.contrib + (size_t)CONTRIB * k;
-        // each slot is written only by the lane that owns it (slot 13, the
-        // centre, by lane 0), and cleared by that lane
-        for (int s = lane; s < 27; s += ADJ_LANES)
-            if (s != 13) cb[4 * s] = cb[4 * s + 1] = cb[4 * s + 2] = cb[4 * s + 3] = 0.0;
-        if (lane == 0) cb[52] = cb[53] = cb[54] = cb[55] = 0.0;
-        const double kb = A.kbar[i];
-        if (kb == 0.0) continue;  // the same for the whole group
+    __shared__ LsqrStage<typename P::R> stage[per_block];
+    const int n = F.sc->icount;
+    const int lane = threadIdx.x % ADJ_LANES, cl = threadIdx.x / ADJ_LANES;
+    // every thread of the block runs the same iterations (the stage is
+    // shared between its two barriers)
+    for (int k0 = blockIdx.x * per_block; k0 < n; k0 += cell_blocks * per_block) {
+        const int k = k0 + cl;
+        const bool on = k < n;
+        const int i = on ? F.ilist[k] : 0;
         const int yz = i / F.nx, x = i - yz * F.nx, z = yz / F.ny, y = yz - z * F.ny;
-        const LsqrView<P> V{F, x, y, z};
-        double thb = 0.0;
-        lsqr_curvature_adj<ADJ_LANES>(V, prm, kb, lane, cb, thb);
-        if (lane == 0) A.tacc[i] += thb;
+        double kb = 0.0;
+        if (on) {
+            double *cb = A.contrib + (size_t)CONTRIB * k;
+            // each slot is written only by the lane that owns it (slot 13,
+            // the centre, by lane 0), and cleared by that lane
+            for (int s = lane; s < 27; s += ADJ_LANES)
+                if (s != 13) cb[4 * s] = cb[4 * s + 1] = cb[4 * s + 2] = cb[4 * s + 3] = 0.0;
+            if (lane == 0) cb[52] = cb[53] = cb[54] = cb[55] = 0.0;
+            kb = A.kbar[i];  // the same for the whole group
+            if (kb != 0.0) lsqr_stage(F, x, y, z, lane, ADJ_LANES, stage[cl]);
+        }
+        __syncthreads();
+        if (on && kb != 0.0) {
+            const LsqrLdsView<typename P::R> V{stage[cl]};
+            double thb = 0.0;
+            lsqr_curvature_adj<ADJ_LANES>(V, prm, kb, lane, A.contrib + (size_t)CONTRIB * k, thb);
+            if (lane == 0) A.tacc[i] += thb;
+        }
+        __syncthreads();
     }
 }
 
 // PLIC implicit derivatives of every interface cell, one thread per cell
-// (the polygon of the plane section is the heavy part of the PLIC reverse):
-// dphi goes to ms (unused by the LSQR model), dn to the cell's own gb
-// entries, which k_adj_lsqr_plic reads back before it overwrites them.
+// (the polygon of the plane section is the heavy part of the PLIC reverse),
+// run by blocks b of nb in k_adj_lsqr_cell: dphi goes to ms (unused by the
+// LSQR model), dn to the cell's own gb entries, which k_adj_lsqr_plic reads
+// back before it overwrites them.
 template <class P>
-__global__ __launch_bounds__(256) void k_adj_plic_derivs(const Fields<P> F, const Adj A)
+__device__ inline void plic_derivs_blocks(const Fields<P> &F, const Adj &A, int b, int nb)
 {
     const int n = F.sc->icount;
     const size_t N = F.N;
-    for (int k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256) {
+    for (int k = b * 256 + threadIdx.x; k < n; k += nb * 256) {
         const int j = F.ilist[k];
         const double nj[3] = {double(F.nrm[j]), double(F.nrm[N + j]), double(F.nrm[2 * N + j])};
         double dphi = 0.0, dn[3] = {0.0, 0.0, 0.0};
@@ -1151,7 +1187,7 @@ __global__ __launch_bounds__(256) void k_adj_plic_derivs(const Fields<P> F, cons
 // Parker-Youngs gradient g of phi at j (the same split); lane 0 then passes
 // dL/da_j through the PLIC offset (into phib and dL/dn_j) and dL/dn_j
 // through n = g/|g| into gb (the PLIC derivatives come from
-// k_adj_plic_derivs).
+// plic_derivs_blocks).
 template <class P>
 __global__ __launch_bounds__(256) void k_adj_lsqr_plic(const Fields<P> F, const Adj A)
 {
@@ -1188,7 +1224,7 @@ __global__ __launch_bounds__(256) void k_adj_lsqr_plic(const Fields<P> F, const 
         const double nj[3] = {double(F.nrm[j]), double(F.nrm[N + j]), double(F.nrm[2 * N + j])};
         double o[3] = {0, 0, 0};
         if (nj[0] != 0.0 || nj[1] != 0.0 || nj[2] != 0.0) {
-            const double dphi = A.ms[j], dn[3] = {A.gb[j], A.gb[N + j], A.gb[2 * N + j]};  // k_adj_plic_derivs
+            const double dphi = A.ms[j], dn[3] = {A.gb[j], A.gb[N + j], A.gb[2 * N + j]};  // plic_derivs_blocks
             A.phib[j] += abar * dphi;
             for (int d = 0; d < 3; ++d) nbar[d] += abar * dn[d];
             const double len = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);

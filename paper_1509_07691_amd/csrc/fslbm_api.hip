@@ -1429,9 +1429,9 @@ int enqueue_geometry_adjoint(fslbm_lattice *h, const Fields<P> &F, const Adj &A,
         k_adj_fd_msb<P><<<cg, 256, 0, st>>>(F, A);
         k_adj_fd_phib<P><<<cg, 256, 0, st>>>(F, A);
     } else {
-        const int l8 = std::min(2048, std::max(1, (h->adj.icount + 31) / 32));  // 32 cells per block
-        k_adj_lsqr_cell<P><<<l8, 256, 0, st>>>(F, A, prm);
-        k_adj_plic_derivs<P><<<lg, 256, 0, st>>>(F, A);
+        const int cpb = 256 / ADJ_LANES;  // interface cells per block
+        const int l8 = std::min(2048, std::max(1, (h->adj.icount + cpb - 1) / cpb));
+        k_adj_lsqr_cell<P><<<l8 + lg, 256, 0, st>>>(F, A, prm, l8);
         k_adj_lsqr_plic<P><<<l8, 256, 0, st>>>(F, A);
         k_adj_lsqr_phib<P><<<lg, 256, 0, st>>>(F, A);
     }
@@ -1491,8 +1491,8 @@ int do_adj_backward(fslbm_lattice *h, const double *dphi, int in_dev, double *ds
         for (long long t = t1 - 1; t >= t0 && !rc; --t) {
             const Slot cur = seg_slot(w, s, t), nxt = seg_slot(w, s, t + 1);
             Fields<P> F = make_fields<P>(h);
-            k_adj_prepass<P><<<lg, 256, 0, st>>>(F, A, (const typename P::R *)nxt.snap);
-            k_snap<P><<<lg, 256, 0, st>>>(F, (typename P::R *)cur.snap, 0);
+            k_adj_prepass<P><<<lg, 256, 0, st>>>(F, A, (const typename P::R *)nxt.snap,
+                                                 (const typename P::R *)cur.snap);
             F.fsrc = (const typename P::S *)cur.f;
             A = adj_fields(w, h, par);
             if (h->coll == FSLBM_SRT) k_adj_stream<P, 0><<<cg, 256, 0, st>>>(F, A, prm);

@@ -559,6 +559,45 @@ template <class P> struct LsqrView {
     __device__ inline double plic(int dx, int dy, int dz) const { return double(F.plic[at(dx, dy, dz)]); }
 };
 
+// The same view served from LDS: the lanes that share a centre first copy
+// the flags of its 5 x 5 x 5 block and the normals and PLIC offsets of its
+// 3 x 3 x 3 block (all that the fit and the contact conditions read), as
+// independent loads, so the fit's scattered reads wait for memory once
+// instead of once per dependent access.
+template <class R> struct LsqrStage {
+    uint8_t fl[128];  // 125 used: (dz + 2) 25 + (dy + 2) 5 + dx + 2
+    R nrm[81];        // 3 per block cell (dz + 1) 9 + (dy + 1) 3 + dx + 1
+    R pl[27];
+};
+template <class R> struct LsqrLdsView {
+    const LsqrStage<R> &s;
+    __device__ inline uint8_t flag(int dx, int dy, int dz) const { return s.fl[(dz + 2) * 25 + (dy + 2) * 5 + dx + 2]; }
+    __device__ inline void normal(int dx, int dy, int dz, double (&n)[3]) const
+    {
+        const int j = 3 * ((dz + 1) * 9 + (dy + 1) * 3 + dx + 1);
+        n[0] = double(s.nrm[j]);
+        n[1] = double(s.nrm[j + 1]);
+        n[2] = double(s.nrm[j + 2]);
+    }
+    __device__ inline double plic(int dx, int dy, int dz) const { return double(s.pl[(dz + 1) * 9 + (dy + 1) * 3 + dx + 1]); }
+};
+// Lane `lane` of the L lanes of centre (x, y, z) copies its share.
+template <class P>
+__device__ inline void lsqr_stage(const Fields<P> &F, int x, int y, int z, int lane, int L,
+                                  LsqrStage<typename P::R> &s)
+{
+    for (int t = lane; t < 125; t += L)
+        s.fl[t] = F.flags[gidx(x + t % 5 - 2, y + (t / 5) % 5 - 2, z + t / 25 - 2, F.nx, F.ny, F.nz)];
+    const size_t N = F.N;
+    for (int t = lane; t < 27; t += L) {
+        const int j = gidx(x + t % 3 - 1, y + (t / 3) % 3 - 1, z + t / 9 - 1, F.nx, F.ny, F.nz);
+        s.nrm[3 * t] = F.nrm[j];
+        s.nrm[3 * t + 1] = F.nrm[N + j];
+        s.nrm[3 * t + 2] = F.nrm[2 * N + j];
+        s.pl[t] = F.plic[j];
+    }
+}
+
 // Contact point and contact normal of the contact-line cell at offset d from
 // the centre (eqs. contactNormal, contactConstraint; Fig. contactPoint): the
 // point of (PLIC plane) ∩ (wall plane) nearest to the PLIC point, reached

@@ -4,8 +4,9 @@ times (batched lattices, one stream, merged stream-collide).
 - Droplet sweep: the eight 128^3 lattices (radius 32; tau 0.6 / 1.0 x
   sigma 1e-4 / 1e-3 x FD / LSQR) advanced as one batch in FP32 for 3 steps,
   each compared cell by cell with the FP64 oracle run on the whole lattice:
-  identical cell types, fill level, pressure and velocity within the FP32
-  bar (1e-5 relative).
+  identical cell types, fill level and pressure within the FP32 bar (1e-5
+  relative), velocity within 1e-6 absolute and 1e-5 of max(|u|, sigma/mu)
+  (the plain relative error is printed).
 - Sessile droplet (hemisphere R = 48 on the wall of 256 x 256 x 128,
   theta 60 / 90 / 120 deg): sampled cells, contact-line cells among them,
   each against the oracle on the full-height 28 x 28 column around it.
@@ -59,8 +60,17 @@ def test_droplet_sweep_batch_fp32_vs_oracle(torch_dev):
         for name, a, r in (("fill", g.fill(), o.fill()), ("pressure", g.pressure(), o.pressure())):
             e = np.linalg.norm((a - r)[fluid]) / np.linalg.norm(r[fluid])
             assert e < 1e-5, f"{label} {name} {e:.2e}"
-        du = np.abs(g.velocity() - o.velocity())[:, fluid].max()
-        assert du < 1e-6, f"{label} velocity {du:.2e}"
+        # velocity: largest absolute difference, the relative L2 error, and
+        # the L2 error normalised by max(|u_ref|, (sigma / mu) sqrt(n)) with
+        # mu = rho nu, the parity measure of the droplet tests
+        dv = (g.velocity() - o.velocity())[:, fluid]
+        ur = o.velocity()[:, fluid]
+        du = np.abs(dv).max()
+        mu = (p["tau"] - 0.5) / 3.0
+        e_rel = np.linalg.norm(dv) / np.linalg.norm(ur)
+        e_norm = np.linalg.norm(dv) / max(np.linalg.norm(ur), p["sigma"] / mu * math.sqrt(fluid.sum()))
+        print(f"{label}: velocity max |du| {du:.2e}, relative {e_rel:.2e}, normalised {e_norm:.2e}")
+        assert du < 1e-6 and e_norm < 1e-5, f"{label} velocity {du:.2e} {e_norm:.2e}"
         del o
     b.close()
     for g in lats:
@@ -97,7 +107,8 @@ def sampled_parity(torch, fill, obst, prm, steps=2, n_if=16, n_liq=8, seed=0, fu
     h = BLOCK // 2
     model = O.CURV_FD if prm["curv_model"] == "fd" else O.CURV_LSQR
     kw = {k: prm[k] for k in ("sigma", "tau", "theta") if k in prm}
-    worst = {"fill": 0.0, "rho": 0.0, "u": 0.0}
+    mu = (prm["tau"] - 0.5) / 3.0
+    worst = {"fill": 0.0, "rho": 0.0, "u": 0.0, "u_rel": 0.0, "u_norm": 0.0}
     for c in picks:
         z, y, x = np.unravel_index(c, fill.shape)
         zz = (np.arange(nz) if full_z else np.arange(z - h, z + h) % nz)[:, None, None]
@@ -110,7 +121,13 @@ def sampled_parity(torch, fill, obst, prm, steps=2, n_if=16, n_liq=8, seed=0, fu
         zc = z if full_z else h
         worst["fill"] = max(worst["fill"], abs(o.fill()[zc, h, h] - phi[z, y, x]))
         worst["rho"] = max(worst["rho"], abs(o.density()[zc, h, h] - rho[z, y, x]))
-        worst["u"] = max(worst["u"], np.abs(o.velocity()[:, zc, h, h] - u[:, z, y, x]).max())
+        ur = o.velocity()[:, zc, h, h]
+        du = np.abs(ur - u[:, z, y, x])
+        worst["u"] = max(worst["u"], du.max())
+        # relative to |u_ref| and to max(|u_ref|, sigma / mu)
+        un = np.linalg.norm(ur)
+        worst["u_rel"] = max(worst["u_rel"], np.linalg.norm(du) / un if un > 0 else 0.0)
+        worst["u_norm"] = max(worst["u_norm"], np.linalg.norm(du) / max(un, prm["sigma"] / mu))
         del o
     return worst
 
@@ -125,7 +142,7 @@ def test_512_sampled_cells_vs_oracle_blocks(torch_dev, name):
         prm = dict(curv_model="lsqr", tau=0.8, sigma=1e-3)
     worst = sampled_parity(torch_dev, fill, obst, prm)
     print(name, worst)
-    assert worst["fill"] < 2e-6 and worst["rho"] < 2e-6 and worst["u"] < 1e-6, worst
+    assert worst["fill"] < 2e-6 and worst["rho"] < 2e-6 and worst["u"] < 1e-6 and worst["u_norm"] < 1e-5, worst
 
 
 @pytest.mark.parametrize("theta_deg", [60.0, 90.0, 120.0])
@@ -139,4 +156,4 @@ def test_sessile_256_sampled_columns_vs_oracle(torch_dev, theta_deg):
     prm = dict(curv_model="lsqr", tau=0.8, sigma=5e-4, theta=math.radians(theta_deg))
     worst = sampled_parity(torch_dev, fill, obst, prm, n_if=8, n_liq=4, n_wall=12, full_z=True, seed=1)
     print("sessile", theta_deg, worst)
-    assert worst["fill"] < 2e-6 and worst["rho"] < 2e-6 and worst["u"] < 1e-6, worst
+    assert worst["fill"] < 2e-6 and worst["rho"] < 2e-6 and worst["u"] < 1e-6 and worst["u_norm"] < 1e-5, worst
