@@ -13,7 +13,10 @@
 // The reverse step maps the adjoints (lam = dL/df', mbar, phib) at t+1 to
 // those at t. Every kernel is written as a gather (one writer per value) so
 // the results do not depend on scheduling:
-//   k_adj_prepass      phi_{t+1} = m_{t+1}/rho_{t+1} -> mbar, rhob
+//   k_adj_prepass      phi_{t+1} = m_{t+1}/rho_{t+1} -> mbar, rhob (phib
+//                      with the transposed obstacle fill reflection of
+//                      Sec. II.A left by the previous reverse step); the
+//                      restore of state t from its snapshot
 //   k_adj_stream       per fluid cell: gathers lam_q(x) = own_q(x) +
 //                      gin_q(x + c_q) of the previous reverse step, then the
 //                      transposed collision, mass exchange and boundary
@@ -29,7 +32,6 @@
 //                      implicit function theorem (da/dphi = -1/A, da/dn =
 //                      centroid of the plane section, A its area) and the
 //                      Parker-Youngs normals
-//   k_adj_reflect      transposed obstacle fill reflection (Sec. II.A)
 // All adjoint arithmetic is FP64 whatever the storage precision.
 #pragma once
 
@@ -65,7 +67,6 @@ __host__ __device__ constexpr int slot27(int a, int b, int c) { return (c + 1) *
 // and, per interface-list entry, m, rho, phi, K, n (3) and the PLIC offset,
 // followed by phi of the obstacle-list cells. Everything else is constant
 // while the cell types are frozen.
-constexpr int SNAP = 8;
 
 template <class P>
 __global__ __launch_bounds__(256) void k_snap(Fields<P> F, typename P::R *snap, int save)
@@ -111,6 +112,25 @@ __global__ void k_adj_begin(Fields<P> F, Adj A, const double *dphi)
     }
 }
 
+// Transposed obstacle fill reflection, deferred to the next reader of
+// phib: each reverse step leaves the adjoint of the obstacle fill levels in
+// phib at the obstacle cells (k_adj_fd_phib, k_adj_lsqr_phib), and the
+// interface cell i (list entry k) adds phib(o) w_oi / den_o over its
+// obstacle neighbours o (weights from k_adj_reflect_setup) where it reads
+// its own phib: in k_adj_prepass of the next step and in k_adj_finish.
+template <class P>
+__device__ inline double reflected_phib(const Fields<P> &F, const Adj &A, int k, int i)
+{
+    if (!(F.flags[i] & FL_NEAR_OBST)) return 0.0;
+    const Nbr ni(i, F.nx, F.ny, F.nz);
+    const double *c = A.refl + (size_t)(NQ - 1) * k;
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 1; q < NQ; ++q)
+        if (c[q - 1] != 0.0) acc += A.phib[ni.at(dir_x(q), dir_y(q), dir_z(q))] * c[q - 1];
+    return acc;
+}
+
 // dL/dphi_0 = phib + mbar rho_0 at interface cells (m_0 = phi_0 rho_0 with
 // the distributions of the window start held fixed).
 template <class P>
@@ -119,14 +139,15 @@ __global__ void k_adj_finish(Fields<P> F, Adj A, const typename P::R *snap0, dou
     const int n = F.sc->icount;
     for (int k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256) {
         const int i = F.ilist[k];
-        out[i] = A.phib[i] + A.mbar[i] * double(snap0[(size_t)SNAP * k + 1]);
+        out[i] = (A.phib[i] + reflected_phib(F, A, k, i)) + A.mbar[i] * double(snap0[(size_t)SNAP * k + 1]);
     }
 }
 
 // ------------------------------------------------ phi = m / rho (reverse)
-// phi = m / rho of step t+1 reversed (m and rho from its snapshot), and the
-// state of step t restored from its snapshot (as k_snap with save = 0):
-// both go entry by entry over the same lists, so they share one launch.
+// phi = m / rho of step t+1 reversed (m and rho from its snapshot, phib
+// with the deferred reflection added), and the state of step t restored
+// from its snapshot (as k_snap with save = 0): both go entry by entry over
+// the same lists, so they share one launch.
 template <class P>
 __global__ __launch_bounds__(256) void k_adj_prepass(Fields<P> F, Adj A, const typename P::R *snap_next,
                                                      const typename P::R *snap_cur)
@@ -137,7 +158,7 @@ __global__ __launch_bounds__(256) void k_adj_prepass(Fields<P> F, Adj A, const t
         if (k < n) {
             const int i = F.ilist[k];
             const double m = double(snap_next[(size_t)SNAP * k]), r = double(snap_next[(size_t)SNAP * k + 1]);
-            const double pb = A.phib[i];
+            const double pb = A.phib[i] + reflected_phib(F, A, k, i);
             A.mbar[i] += pb / r;
             A.rhob[i] = -pb * m / (r * r);
             A.phib[i] = 0.0;
@@ -214,7 +235,9 @@ __device__ inline void load_dirs_d(const Fields<P> &F, const int (&j)[NQ], doubl
 // Recomputes the forward pull of boundary_cell (same rules, in FP64) and
 // applies the transposed step. Writes gin and own of the cell; at interface
 // cells also kbar, phib (the part from the mass-exchange weights) and the
-// sigma accumulator.
+// sigma accumulator. A liquid cell away from walls has the plain pull and
+// writes gin only (its own outgoing values are never read: the cell is
+// liquid at every step of the window).
 template <class P, int COLL>
 __device__ inline void cell_adj(const Fields<P> &F, const Adj &A, const Params &prm, int i, const Nbr &nb, uint8_t fl)
 {
@@ -357,7 +380,11 @@ __device__ inline void cell_adj(const Fields<P> &F, const Adj &A, const Params &
 }
 
 // Reverse stream-collide over the fluid bounding box (same traversal as the
-// forward kernel).
+// forward kernel). Measured on the 128^3 sessile drop: one launch in which
+// liquid and boundary wavefronts overlap is faster than a lean liquid pass
+// followed by a list pass over the interface and wall cells (0.147 against
+// 0.169 ms per reverse step), and capping it at 2 waves per SIMD (spills)
+// is slower too.
 template <class P, int COLL>
 __global__ __launch_bounds__(256) void k_adj_stream(const Fields<P> F, const Adj A, const Params prm)
 {
@@ -615,23 +642,6 @@ __global__ __launch_bounds__(256) void k_adj_reflect_setup(const Fields<P> F, co
             }
             if (den > 0.0 && wi > 0.0) c[q - 1] = wi / den;
         }
-    }
-}
-
-template <class P>
-__global__ __launch_bounds__(256) void k_adj_reflect(const Fields<P> F, const Adj A)
-{
-    const int n = F.sc->icount;
-    for (int k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256) {
-        const int i = F.ilist[k];
-        if (!(F.flags[i] & FL_NEAR_OBST)) continue;
-        const Nbr ni(i, F.nx, F.ny, F.nz);
-        const double *c = A.refl + (size_t)(NQ - 1) * k;
-        double acc = 0.0;
-#pragma unroll
-        for (int q = 1; q < NQ; ++q)
-            if (c[q - 1] != 0.0) acc += A.phib[ni.at(dir_x(q), dir_y(q), dir_z(q))] * c[q - 1];
-        A.phib[i] += acc;
     }
 }
 

@@ -260,6 +260,7 @@ Fields<P> make_fields(const fslbm_lattice *h)
     F.counts = (int *)(w + L.counts);
     F.part = (double *)(w + L.part);
     F.sc = (DevScalars *)(w + L.sc);
+    F.snap = nullptr;
     F.nx = h->nx;
     F.ny = h->ny;
     F.nz = h->nz;
@@ -862,9 +863,11 @@ bool split_now(const fslbm_batch *b)
 
 // Kernels of one time step of every lattice of the batch.
 // With fsrc / fdst given (a single lattice), the step reads and writes those
-// distribution buffers instead of the lattice's pair, and records no timing.
+// distribution buffers instead of the lattice's pair, and records no timing;
+// with snap given too, the kernels that finish the interface-list and
+// obstacle-list values also write them there (Fields::snap; LSQR model).
 template <class P>
-int enqueue_step_kernels(fslbm_batch *b, const void *fsrc = nullptr, void *fdst = nullptr)
+int enqueue_step_kernels(fslbm_batch *b, const void *fsrc = nullptr, void *fdst = nullptr, void *snap = nullptr)
 {
     int maxN;
     bool any_srt, any_trt;
@@ -874,6 +877,7 @@ int enqueue_step_kernels(fslbm_batch *b, const void *fsrc = nullptr, void *fdst 
         for (int k = 0; k < MAXB; ++k) {
             A.f[k].fsrc = (const typename P::S *)fsrc;
             A.f[k].fdst = (typename P::S *)fdst;
+            A.f[k].snap = (typename P::R *)snap;
         }
     auto mark = [&](fslbm_batch *bb, int k) {
         if (!over && bb->timing) (void)hipEventRecord(bb->ev[(size_t)bb->ev_used * TIMING_EV + k], bstream(bb));
@@ -1435,7 +1439,6 @@ int enqueue_geometry_adjoint(fslbm_lattice *h, const Fields<P> &F, const Adj &A,
         k_adj_lsqr_plic<P><<<l8, 256, 0, st>>>(F, A);
         k_adj_lsqr_phib<P><<<lg, 256, 0, st>>>(F, A);
     }
-    k_adj_reflect<P><<<lg, 256, 0, st>>>(F, A);
     HIP_OK(hipGetLastError());
     return 0;
 }
@@ -1480,8 +1483,10 @@ int do_adj_backward(fslbm_lattice *h, const double *dphi, int in_dev, double *ds
         rc = load_snap<P>(h, ck_slot(w, s).snap);
         for (long long t = t0; t + 1 < t1 && !rc; ++t) {
             const Slot a = seg_slot(w, s, t), b = seg_slot(w, s, t + 1);
-            rc = enqueue_step_kernels<P>(&h->self, a.f, b.f);
-            if (!rc) {
+            // the LSQR step writes the snapshot itself; FD takes k_snap
+            const bool lsqr = h->curv == FSLBM_CURV_LSQR;
+            rc = enqueue_step_kernels<P>(&h->self, a.f, b.f, lsqr ? b.snap : nullptr);
+            if (!rc && !lsqr) {
                 const Fields<P> F = make_fields<P>(h);
                 k_snap<P><<<lg, 256, 0, st>>>(F, (typename P::R *)b.snap, 1);
                 HIP_OK(hipGetLastError());

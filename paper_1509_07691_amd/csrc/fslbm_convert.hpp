@@ -704,6 +704,7 @@ __global__ __launch_bounds__(256) void k_obstacle_fill(const Batch<P> B)
             }
         }
         F.phi[i] = R(den > 0 ? num / den : 0.0);
+        if (F.snap) F.snap[(size_t)SNAP * F.sc->icount + k] = R(den > 0 ? num / den : 0.0);
     }
 }
 

@@ -409,10 +409,16 @@ template <class P> struct Fields {
     int *counts;       // per-block counts of the list compaction
     double *part;      // per-block partial sums of reductions
     DevScalars *sc;
+    // when set (the recompute steps of the reverse sweep, LSQR model): the
+    // step's end state of the interface-list entries (SNAP values each: m,
+    // rho, phi, K, n, PLIC offset) and the obstacle-list fill levels after
+    // them, written by the kernels that finish those values
+    R *snap;
     int nx, ny, nz;
     int N;
     int NS;            // plane stride of the distribution buffers (elements, >= N)
 };
+constexpr int SNAP = 8;
 
 // Up to MAXB lattices advanced by one launch per kernel: lattice b is
 // handled by the blocks with blockIdx.y == b. Passed by value as the kernel

@@ -996,6 +996,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         }
         const double K = f.ok ? lsqr_solve_curvature(f, S) : 0.0;
         if (l == 0) F.K[i] = R(K);
+        if (l == 1 && F.snap && k < F.sc->icount) {
+            R *sn = F.snap + (size_t)SNAP * k;
+            const size_t N = F.N;
+            sn[0] = F.m[i]; sn[1] = F.rho[i]; sn[2] = F.phi[i]; sn[3] = R(K);
+            sn[4] = F.nrm[i]; sn[5] = F.nrm[N + i]; sn[6] = F.nrm[2 * N + i]; sn[7] = F.plic[i];
+        }
     }
 }
 
