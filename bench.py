@@ -257,7 +257,8 @@ def adjoint_cost(dev, stream, steps, K, precision, fd_check=True):
             "note": "the cost is measured on the whole window; its gradients are reported only when every interface "
                     "fill stays inside (0, 1) (window_fill_events == 0): otherwise the frozen step is not smooth "
                     "along the trajectory and they are null",
-            "fd_check": adjoint_fd_check(dev, 64, 12.0, steps, K) if fd_check else None}
+            "fd_check": adjoint_fd_check(dev, 64, 12.0, steps, K) if fd_check else None,
+            "oracle_check": adjoint_oracle_check(dev) if fd_check else None}
 
 
 def adjoint_fd_check(dev, n, R, steps, K):
@@ -303,6 +304,54 @@ def adjoint_fd_check(dev, n, R, steps, K):
     return {"workload": f"the same drop scaled to {n}^3 (R={R:g}), window of {steps} steps, checkpoints every {K}, FP64",
             "interface_fill_range_T": rng,
             **{k: {"adjoint": adj[k], "fd": fd[k], "rel": abs(adj[k] - fd[k]) / abs(fd[k])} for k in fd}}
+
+
+GOLDEN_ADJ = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden", "adjoint_c4_oracle.json")
+
+
+def adjoint_oracle_check(dev, precisions=("f64", "f32")):
+    """The differentiation workload at its configured size against the FP64
+    oracle's stored values (tests/golden/adjoint_c4_oracle.json, written by
+    tests/golden/make_adjoint_c4_reference.py from the oracle alone): the
+    window lengths T_inside (every interface fill inside (0, 1)) and
+    T_unconverted (no cell that the free method would convert), and for the
+    stored windows the relative errors of dL/dsigma, dL/dtheta and
+    <dL/dphi_0, v> against the tangent-linear oracle (same loss as the cost
+    measurement). Within T_inside the oracle's central differences agree
+    with its tangent-linear values; beyond it the loss is only piecewise
+    smooth along the trajectory."""
+    from paper_1509_07691_amd import inputs as I
+    from paper_1509_07691_amd.fslbm import Lattice
+
+    if not os.path.exists(GOLDEN_ADJ):
+        return None
+    ref = json.load(open(GOLDEN_ADJ))
+    fill, obst = I.sessile_droplet(128, 128, 128, 24.0, noise=1e-6, seed=1)
+    keep = (obst == 0).astype(float)
+    out = {"oracle_T_inside": ref["T_inside"], "oracle_T_unconverted": ref["T_unconverted"], "windows": []}
+    for win in ref["windows"]:
+        T = win["T"]
+        row = {"T": T, "tangent_linear": win["tangent_linear"], "oracle_central_differences": win["central_differences"]}
+        for prec in precisions:
+            g = Lattice(fill, obst, precision=prec, device=dev, curv_model="lsqr", sigma=1e-3, tau=0.8,
+                        theta=math.pi / 2)
+            start = g.save_state()
+            ifc = g.flags() == 2
+            v = np.random.default_rng(3).uniform(-1.0, 1.0, fill.shape) * (ifc & (fill > 1e-3) & (fill < 1 - 1e-3))
+            g.set_params(sigma=8e-4, theta=math.radians(70.0))
+            g.adjoint_forward(T, 100)
+            target = g.fill()
+            g.load_state(start)
+            g.set_params(sigma=1e-3, theta=math.pi / 2)
+            g.adjoint_forward(T, 100)
+            inside, events, unconverted = g.adjoint_status()
+            d0, ds, dt = g.adjoint_backward(2.0 * (g.fill() - target) * keep)
+            adj = {"sigma": ds, "theta": dt, "phi0_dir": float((d0.cpu().numpy() * v).sum())}
+            g.close()
+            row[prec] = {"window_inside_steps": inside, "window_unconverted_steps": unconverted,
+                         "rel_err_vs_tangent_linear": {k: abs(adj[k] - t) / abs(t) for k, t in win["tangent_linear"].items()}}
+        out["windows"].append(row)
+    return out
 
 
 def advection_table(dev, precision):
