@@ -178,7 +178,7 @@ struct fslbm_lattice {
     int nx, ny, nz;
     int N;
     int NS;  // plane stride of the distribution buffers
-    int box_blocks;  // 256-cell chunks of the fluid box when last read back (grid of the bulk stream-collide)
+    int box_blocks;  // SC_BLOCK-cell chunks of the fluid box when last read back (grid of the bulk stream-collide)
     long long box_cells, boundary_cells;  // fluid-box cells, interface + wall-list cells (last read back)
     int device;      // device that holds the workspace
     int strong_wetting;  // 1: contact angles below 45 deg are accepted (FSLBM_OPT_STRONG_WETTING)
@@ -1311,7 +1311,7 @@ int refresh_box(fslbm_lattice *h)
     long long cells = 0;
     if (b[3] >= b[0] && b[4] >= b[1] && b[5] >= b[2])
         cells = (long long)(b[3] - b[0] + 1) * (b[4] - b[1] + 1) * (b[5] - b[2] + 1);
-    const int blocks = xcd_grid((cells + 255) / 256);
+    const int blocks = xcd_grid((cells + SC_BLOCK - 1) / SC_BLOCK);
     h->boundary_cells = (long long)sc.icount + sc.wcount;
     h->box_cells = cells;
     if (blocks != h->box_blocks) {
@@ -1758,7 +1758,7 @@ int fslbm_create(int nx, int ny, int nz, int precision, int curv_model, const do
     h->self.prec = precision;
     h->icount0 = 1 << 20;  // large until counted: the creation's own geometry launch
     h->ocount0 = 1 << 20;
-    h->box_blocks = xcd_grid((N + 255) / 256);
+    h->box_blocks = xcd_grid(((long long)N + SC_BLOCK - 1) / SC_BLOCK);
     h->box_cells = N;
     h->boundary_cells = N;
     int rc = dispatch<OpInit>(h, fill, obstacle);

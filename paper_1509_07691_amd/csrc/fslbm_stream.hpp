@@ -536,7 +536,7 @@ __device__ inline void fluid_cell(const Fields<P> &F, const Params &prm, int i, 
 // Stream-collide over the fluid bounding box. MODE 0: every fluid cell;
 // MODE 1: only liquid cells away from walls (the lean pull, few registers;
 // the other fluid cells then go through k_stream_collide_list). Block b
-// takes the 256 consecutive box cells from 256 b; the host sizes the grid
+// takes the SC_BLOCK consecutive box cells from SC_BLOCK b; the host sizes the grid
 // to the box it last read back, so normally each block has one chunk and
 // returns (a box that has grown since is covered by a grid-stride tail).
 // Blocks are dispatched in index order, so the blocks in flight at any
@@ -551,8 +551,8 @@ __device__ inline void stream_collide_box(const Batch<P> &B)
     const Fields<P> &F = B.f[blockIdx.y];
     const CellRange box = CellRange::from(F.sc->fbox);
     const int n = box.size();
-    for (int c = xcd_chunk(blockIdx.x, gridDim.x, xcd_run<P>()); c * 256 < n; c += gridDim.x) {
-        const int k = c * 256 + (int)threadIdx.x;
+    for (int c = xcd_chunk(blockIdx.x, gridDim.x, xcd_run<P>()); c * SC_BLOCK < n; c += gridDim.x) {
+        const int k = c * SC_BLOCK + (int)threadIdx.x;
         if (k >= n) continue;
         const int bx = k % box.ex, r = k / box.ex, by = r % box.ey, bz = r / box.ey;
         const int x = box.x0 + bx, y = box.y0 + by, z = box.z0 + bz;
@@ -571,12 +571,12 @@ __device__ inline void stream_collide_box(const Batch<P> &B)
 // FP32 arithmetic: 4 waves per SIMD (the boundary path then fits in 128
 // VGPRs); FP64 keeps the compiler's register choice (it would spill).
 template <class P, int COLL, int MODE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_stream_collide(const Batch<P> B)
+__global__ __launch_bounds__(SC_BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_stream_collide(const Batch<P> B)
 {
     stream_collide_box<P, COLL, MODE>(B);
 }
 template <int COLL, int MODE>
-__global__ __launch_bounds__(256) void k_stream_collide_f64(const Batch<Prec<P_F64>> B)
+__global__ __launch_bounds__(SC_BLOCK) void k_stream_collide_f64(const Batch<Prec<P_F64>> B)
 {
     stream_collide_box<Prec<P_F64>, COLL, MODE>(B);
 }
@@ -584,9 +584,9 @@ template <class P, int COLL, int MODE>
 inline void launch_stream_collide(dim3 grid, hipStream_t st, const Batch<P> &A)
 {
     if constexpr (P::SHIFT == false && sizeof(typename P::T) == 8)
-        k_stream_collide_f64<COLL, MODE><<<grid, 256, 0, st>>>(A);
+        k_stream_collide_f64<COLL, MODE><<<grid, SC_BLOCK, 0, st>>>(A);
     else
-        k_stream_collide<P, COLL, MODE><<<grid, 256, 0, st>>>(A);
+        k_stream_collide<P, COLL, MODE><<<grid, SC_BLOCK, 0, st>>>(A);
 }
 
 // The fluid cells that the lean box pass (MODE 1) leaves out, one thread
