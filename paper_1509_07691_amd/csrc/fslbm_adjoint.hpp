@@ -733,16 +733,18 @@ __host__ __device__ inline void plic_derivs(const double (&n)[3], double phi, do
 }
 
 // ------------------------------------------------ LSQR curvature (reverse)
-// Reverse of contact_condition: given the adjoints of (u_c, v_c, -m_u/m_n,
-// -m_v/m_n), accumulates those of p_c, n_c, t_u, t_v, of the contact cell's
-// normal and PLIC offset (into its slot of cb) and of theta.
-template <class View>
+// contact_condition and its reverse in one pass: the forward values
+// (u_c, v_c, -m_u/m_n, -m_v/m_n) go to seeds(uc, vc, ru, rv, ucb, vcb, rub,
+// rvb), which returns their adjoints; from those the adjoints of p_c, n_c,
+// t_u, t_v, of the contact cell's normal and PLIC offset (into its slot of
+// cb) and of theta are accumulated. Nothing happens (seeds is not called)
+// where contact_condition skips the condition.
+template <class View, class Seeds>
 __host__ __device__ inline void contact_condition_adj(const View &V, int dx, int dy, int dz, const double (&pc)[3],
                                                       const double (&nc)[3], const double (&tu)[3],
-                                                      const double (&tv)[3], const Params &prm, double ucb,
-                                                      double vcb, double rub, double rvb, double (&pcb)[3],
-                                                      double (&ncb)[3], double (&tub)[3], double (&tvb)[3],
-                                                      double *cb, double &thb)
+                                                      const double (&tv)[3], const Params &prm, Seeds &&seeds,
+                                                      double (&pcb)[3], double (&ncb)[3], double (&tub)[3],
+                                                      double (&tvb)[3], double *cb, double &thb)
 {
     double nj[3];
     V.normal(dx, dy, dz, nj);
@@ -771,6 +773,8 @@ __host__ __device__ inline void contact_condition_adj(const View &V, int dx, int
     const double r[3] = {dx + pj[0] + t * g[0] - pc[0], dy + pj[1] + t * g[1] - pc[1], dz + pj[2] + t * g[2] - pc[2]};
     const double mu = dot(mh, tu), mv = dot(mh, tv), mn = dot(mh, nc);
     if (fabs(mn) < 1e-6) return;
+    double ucb, vcb, rub, rvb;
+    seeds(dot(r, tu), dot(r, tv), -mu / mn, -mv / mn, ucb, vcb, rub, rvb);
     // reverse
     const double mub = -rub / mn, mvb = -rvb / mn, mnb = (rub * mu + rvb * mv) / (mn * mn);
     double mhb[3], rb[3], pjb[3], gb[3], njb[3];
@@ -1067,16 +1071,18 @@ __host__ __device__ inline void lsqr_curvature_adj(const View &V, const Params &
             if (a == 0 && b == 0 && c == 0) continue;
             const uint8_t fj = V.flag(a, b, c);
             if (!((fj & FL_IF) && (fj & FL_NEAR_OBST))) continue;
-            double uc, vc, ru, rv;
-            if (!contact_condition(V, a, b, c, pc, nc, tu, tv, prm, uc, vc, ru, rv)) continue;
-            const double row1[5] = {2.0 * uc, 0.0, vc, 1.0, 0.0};
-            const double row2[5] = {0.0, 2.0 * vc, uc, 0.0, 1.0};
-            double p5[5], q5[5], pb, qb;
-            row_adj(row1, ru, p5, pb);
-            row_adj(row2, rv, q5, qb);
-            const double ucb = 2.0 * p5[0] + q5[2];
-            const double vcb = p5[2] + 2.0 * q5[1];
-            contact_condition_adj(V, a, b, c, pc, nc, tu, tv, prm, ucb, vcb, pb, qb, pcb, ncb, tub, tvb, cb, thl);
+            // the two gradient rows of the cell and their adjoints
+            auto seeds = [&](double uc, double vc, double ru, double rv, double &ucb, double &vcb, double &rub,
+                             double &rvb) {
+                const double row1[5] = {2.0 * uc, 0.0, vc, 1.0, 0.0};
+                const double row2[5] = {0.0, 2.0 * vc, uc, 0.0, 1.0};
+                double p5[5], q5[5];
+                row_adj(row1, ru, p5, rub);
+                row_adj(row2, rv, q5, rvb);
+                ucb = 2.0 * p5[0] + q5[2];
+                vcb = p5[2] + 2.0 * q5[1];
+            };
+            contact_condition_adj(V, a, b, c, pc, nc, tu, tv, prm, seeds, pcb, ncb, tub, tvb, cb, thl);
         }
     }
     // ---- shared adjoints summed over the lanes
@@ -1094,7 +1100,15 @@ __host__ __device__ inline void lsqr_curvature_adj(const View &V, const Params &
     if (lane != 0) return;
     thb = thl;
     // ---- hard constraint of the centre
-    if (hard) contact_condition_adj(V, 0, 0, 0, pc, nc, tu, tv, prm, hucb, hvcb, hub, hvb, pcb, ncb, tub, tvb, cb, thb);
+    if (hard) {
+        auto seeds = [&](double, double, double, double, double &ucb, double &vcb, double &rub, double &rvb) {
+            ucb = hucb;
+            vcb = hvcb;
+            rub = hub;
+            rvb = hvb;
+        };
+        contact_condition_adj(V, 0, 0, 0, pc, nc, tu, tv, prm, seeds, pcb, ncb, tub, tvb, cb, thb);
+    }
     // ---- frame: t_v = n x t_u, t_u = w/|w|, w = e_ax - n_ax n; p_c = a_c n
     ncb[0] += tu[1] * tvb[2] - tu[2] * tvb[1];
     ncb[1] += tu[2] * tvb[0] - tu[0] * tvb[2];
