@@ -1133,9 +1133,12 @@ __host__ __device__ inline void lsqr_curvature_adj(const View &V, const Params &
     c0[3] += acb;
 }
 
-// Per interface cell, 8 lanes: partials of K w.r.t. the normals and PLIC
-// offsets of its block, scaled by dL/dK, into contrib; dL/dtheta into tacc.
-constexpr int ADJ_LANES = 8;
+// Per interface cell, 16 lanes (measured faster than 8: the block cells'
+// rows and contact conditions spread over more lanes shorten the chain of
+// the wall cells, which sets the kernel's time): partials of K w.r.t. the
+// normals and PLIC offsets of its block, scaled by dL/dK, into contrib;
+// dL/dtheta into tacc.
+constexpr int ADJ_LANES = 16;
 
 template <class P>
 __device__ inline void plic_derivs_blocks(const Fields<P> &F, const Adj &A, int b, int nb);
@@ -1206,11 +1209,11 @@ __device__ inline void plic_derivs_blocks(const Fields<P> &F, const Adj &A, int 
     }
 }
 
-// Per interface cell j, 8 lanes: gather dL/dn_j, dL/da_j over the blocks
-// containing j (lane l takes the block offsets s = l, l + 8, ...) and the
-// Parker-Youngs gradient g of phi at j (the same split); lane 0 then passes
-// dL/da_j through the PLIC offset (into phib and dL/dn_j) and dL/dn_j
-// through n = g/|g| into gb (the PLIC derivatives come from
+// Per interface cell j, ADJ_LANES lanes: gather dL/dn_j, dL/da_j over the
+// blocks containing j (lane l takes the block offsets s = l, l + ADJ_LANES,
+// ...) and the Parker-Youngs gradient g of phi at j (the same split); lane
+// 0 then passes dL/da_j through the PLIC offset (into phib and dL/dn_j) and
+// dL/dn_j through n = g/|g| into gb (the PLIC derivatives come from
 // plic_derivs_blocks).
 template <class P>
 __global__ __launch_bounds__(256) void k_adj_lsqr_plic(const Fields<P> F, const Adj A)
