@@ -141,6 +141,7 @@ struct AdjWindow {
     long long unconverted_steps = 0;  // steps before a cell would first fill or empty (T if none)
     int icount = 0, ocount = 0;
     long long t_end = 0;     // steps taken at the end of the window
+    unsigned start_step = 0;  // the device step number of the window's first step
     unsigned long long epoch = 0;  // state epoch at the end of the window
     char *ws = nullptr;
     size_t bytes = 0;
@@ -1372,6 +1373,9 @@ int load_snap(fslbm_lattice *h, const char *snap)
     return 0;
 }
 
+// The device step number (it seeds the stochastic 16-bit stores).
+__global__ void k_set_step(DevScalars *sc, unsigned step) { sc->step = step; }
+
 __global__ void k_reset_fill_out(DevScalars *sc)
 {
     sc->fill_out = 0;
@@ -1395,6 +1399,8 @@ int do_adj_forward(fslbm_lattice *h, long long T, int K, void *ws, size_t bytes)
     DevScalars *sc = (DevScalars *)(h->ws + h->L.sc);
     unsigned start_step = 0;
     HIP_OK(hipMemcpyAsync(&start_step, &sc->step, sizeof start_step, hipMemcpyDeviceToHost, h->stream));
+    HIP_OK(hipStreamSynchronize(h->stream));
+    w.start_step = start_step;
     k_reset_fill_out<<<1, 1, 0, h->stream>>>(sc);
     HIP_OK(hipGetLastError());
     h->frozen = 1;
@@ -1479,8 +1485,11 @@ int do_adj_backward(fslbm_lattice *h, const double *dphi, int in_dev, double *ds
     int rc = 0;
     for (size_t s = nseg; s-- > 0 && !rc;) {
         const long long t0 = w.ck[s], t1 = w.ck[s + 1];
-        // recompute the states t0+1 .. t1-1 of the segment into the ring
+        // recompute the states t0+1 .. t1-1 of the segment into the ring,
+        // with the step numbers the window ran them with (the 16-bit forms
+        // draw their rounding bits from them)
         rc = load_snap<P>(h, ck_slot(w, s).snap);
+        k_set_step<<<1, 1, 0, st>>>((DevScalars *)(h->ws + h->L.sc), w.start_step + (unsigned)t0);
         for (long long t = t0; t + 1 < t1 && !rc; ++t) {
             const Slot a = seg_slot(w, s, t), b = seg_slot(w, s, t + 1);
             // the LSQR step writes the snapshot itself; FD takes k_snap
@@ -1533,6 +1542,8 @@ int do_adj_backward(fslbm_lattice *h, const double *dphi, int in_dev, double *ds
         if (rc) return rc;
         const Fields<P> F = make_fields<P>(h);
         HIP_OK(hipMemcpyAsync((void *)F.fsrc, last.f, 19 * (size_t)h->NS * fbytes(h->prec), hipMemcpyDeviceToDevice, st));
+        k_set_step<<<1, 1, 0, st>>>(F.sc, w.start_step + (unsigned)w.T);
+        HIP_OK(hipGetLastError());
     }
     HIP_OK(hipStreamSynchronize(st));
     if (dsig) *dsig = g[0];

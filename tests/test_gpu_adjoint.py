@@ -240,6 +240,28 @@ def test_autograd_function_matches_abi(Lattice):
     assert abs(float(grads[0][2]) - dt) <= 1e-12 * abs(dt)
 
 
+@pytest.mark.parametrize("precision", ["f32", "f16", "bf16"])
+def test_recomputed_segments_equal_stored_states(Lattice, precision):
+    """With checkpoints every K < T steps the reverse sweep recomputes the
+    states inside each segment; with K = 1 every state is stored by the
+    forward window. The recompute must reproduce the window's states bit
+    for bit, the stochastic 16-bit stores included (they draw their bits
+    from the step number), so the gradients of the two are identical. A
+    sessile drop with walls, LSQR with the contact condition, 12 steps."""
+    fill, obst, model, prm, u, target, keep, v, inner = setup("lsqr_sessile")
+    out = []
+    for K in (1, 5):
+        g = Lattice(fill, obst, precision=precision, curv_model=model, **prm)
+        g.adjoint_forward(12, K)
+        phi = g.fill()
+        d0, ds, dt = g.adjoint_backward(2.0 * (phi - target) * keep)
+        out.append((phi, d0.cpu().numpy(), ds, dt))
+        g.close()
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
+    assert out[0][2] == out[1][2] and out[0][3] == out[1][3], (out[0][2:], out[1][2:])
+
+
 def test_long_window_fp64(Lattice):
     """800 steps in 8 checkpoint segments of 100 (sessile drop, LSQR with
     walls): <w, dphi_T/dsigma> for a seeded linear functional w against the
