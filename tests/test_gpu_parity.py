@@ -352,15 +352,16 @@ def test_diagnostics_vs_oracle(Lattice, case):
         assert d["max_u"] == np.sqrt((ug ** 2).sum(0))[fluid].max()
 
 
-@pytest.mark.parametrize("precision", ["f16", "bf16"])
-def test_split_passes_equal_the_merged_pass_16bit(Lattice, precision):
-    """16-bit storage: the two-pass step (lean pass over the plain liquid
-    cells, which works in the units of the store, then the interface and
-    wall cells from their lists) equals the one-pass step bit for bit,
-    stochastic rounding included (its bits depend on cell and step only).
-    Cases: a moving gas bubble in liquid with even and odd nx, and a sessile
-    drop with walls. The automatic choice takes the two passes for a
-    lattice that is nearly all liquid and one pass for the small boxes."""
+@pytest.mark.parametrize("precision", ["f32", "f16", "bf16"])
+def test_split_passes_equal_the_merged_pass(Lattice, precision):
+    """The shifted storage forms: the two-pass step (lean pass over the
+    plain liquid cells, which works in the units of the store, and the
+    interface and wall cells from their lists; one launch in FP32, two in
+    the 16-bit forms) equals the one-pass step bit for bit, stochastic
+    rounding included (its bits depend on cell and step only). Cases: a
+    moving gas bubble in liquid with even and odd nx, and a sessile drop
+    with walls. The automatic choice takes the two passes for a lattice
+    that is nearly all liquid and one pass for the small boxes."""
     cases = []
     for nx in (24, 25):
         fill = np.clip(1.0 - I.sphere_fraction((24, 24, nx), (nx / 2, 12.0, 12.0), 5.0), 0.0, 1.0)

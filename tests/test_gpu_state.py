@@ -57,7 +57,7 @@ def _assert_same(a, b):
         assert np.array_equal(np.asarray(a[k]), np.asarray(b[k])), k
 
 
-@pytest.mark.parametrize("precision,model", [("f64", "lsqr"), ("f32", "fd")])
+@pytest.mark.parametrize("precision,model", [("f64", "lsqr"), ("f32", "fd"), ("f16", "lsqr"), ("bf16", "fd")])
 def test_checkpoint_resume_bit_identical(fs, precision, model):
     fill, obst = I.sessile_droplet(24, 24, 14, 6.0, noise=1e-6, seed=1)
     kw = dict(precision=precision, curv_model=model, sigma=2e-3, tau=0.8, theta=math.radians(60.0))
