@@ -107,10 +107,10 @@ __device__ inline void store_rn(__hip_bfloat16 *p, float v) { *p = __float2bfloa
 // every step.
 typedef _Float16 fslbm_h2 __attribute__((ext_vector_type(2)));
 typedef __bf16 fslbm_bf2 __attribute__((ext_vector_type(2)));
-// The 16-bit code of v in the low half of the result.
-// The conversion keeps the other half of its destination; callers of
-// sr_code store only the low half, so it starts as v's own bits (any value
-// would do; this one needs no extra register).
+// The 16-bit code of v in the low half of the result. The conversion keeps
+// the other half of its destination; only the low half is stored, so the
+// destination starts as v's own bits (any value would do; this one needs no
+// extra register).
 __device__ inline uint32_t sr_code(__half, float v, uint32_t bits)
 {
     return __builtin_bit_cast(uint32_t,
@@ -120,21 +120,6 @@ __device__ inline uint32_t sr_code(__hip_bfloat16, float v, uint32_t bits)
 {
     return __builtin_bit_cast(uint32_t,
                               __builtin_amdgcn_cvt_sr_bf16_f32(__builtin_bit_cast(fslbm_bf2, v), v, bits, false));
-}
-// Two codes in one word: a (low half) and b (high half).
-__device__ inline uint32_t sr_code2(__half, float a, uint32_t ba, float b, uint32_t bb)
-{
-    fslbm_h2 h = __builtin_bit_cast(fslbm_h2, a);
-    h = __builtin_amdgcn_cvt_sr_f16_f32(h, a, ba, false);
-    h = __builtin_amdgcn_cvt_sr_f16_f32(h, b, bb, true);
-    return __builtin_bit_cast(uint32_t, h);
-}
-__device__ inline uint32_t sr_code2(__hip_bfloat16, float a, uint32_t ba, float b, uint32_t bb)
-{
-    fslbm_bf2 h = __builtin_bit_cast(fslbm_bf2, a);
-    h = __builtin_amdgcn_cvt_sr_bf16_f32(h, a, ba, false);
-    h = __builtin_amdgcn_cvt_sr_bf16_f32(h, b, bb, true);
-    return __builtin_bit_cast(uint32_t, h);
 }
 __device__ inline void store_sr(float *p, float v, uint32_t) { __builtin_nontemporal_store(v, p); }
 // Streaming stores (non-temporal), as FP32: the written planes are not read
@@ -166,7 +151,8 @@ __device__ inline uint32_t hash32(uint32_t x)
 __device__ inline uint32_t cell_seed(int i, uint32_t step) { return hash32(uint32_t(i) ^ hash32(step * 0x9e3779b9u)); }
 struct SrBits {
     uint32_t x, w;
-    // xorshift32 never leaves the state 0, which the hash maps one cell to
+    // 0 is a fixed point of xorshift32; the hash maps one cell per step to
+    // it, which then starts from another state
     __device__ inline explicit SrBits(uint32_t seed) : x(seed ? seed : 0x9e3779b9u), w(0) {}
     // the word for direction q; called for q = 0, 1, ..., 18 in order
     __device__ inline uint32_t at(int q)
