@@ -360,8 +360,8 @@ def test_split_passes_equal_the_merged_pass(Lattice, precision):
     the 16-bit forms) equals the one-pass step bit for bit, stochastic
     rounding included (its bits depend on cell and step only). Cases: a
     moving gas bubble in liquid with even and odd nx, and a sessile drop
-    with walls. The automatic choice takes the two passes for a lattice
-    that is nearly all liquid and one pass for the small boxes."""
+    with walls. The automatic choice takes the two passes for a 16-bit
+    lattice that is nearly all liquid and one pass for the small boxes."""
     cases = []
     for nx in (24, 25):
         fill = np.clip(1.0 - I.sphere_fraction((24, 24, nx), (nx / 2, 12.0, 12.0), 5.0), 0.0, 1.0)
@@ -384,11 +384,12 @@ def test_split_passes_equal_the_merged_pass(Lattice, precision):
             np.testing.assert_array_equal(a, b)
         for lat in lats:
             lat.close()
-    # the automatic choice
+    # the automatic choice (FP32 always takes the merged pass, measured the
+    # faster on every workload)
     fill = np.clip(1.0 - I.sphere_fraction((64, 64, 64), (32.0, 32.0, 32.0), 4.0), 0.0, 1.0)
     big = Lattice(fill, None, precision=precision, curv_model="lsqr", sigma=1e-3, tau=0.8)
     big.step(2)
-    assert big.split_active()
+    assert big.split_active() == (precision != "f32")
     big.close()
     fill, obst = I.droplet(24, 6.0, noise=1e-6, seed=3)
     small = Lattice(fill, obst, precision=precision, curv_model="lsqr", sigma=1e-3, tau=0.8)
