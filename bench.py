@@ -579,7 +579,8 @@ def sessile_contact_angles(dev, steps, thetas=(60.0, 90.0, 120.0)):
     256 x 256 x 128 lattice (walls k = 0 and 127), LSQR with the wetting
     condition, sigma 5e-4, tau 0.8, FP32, per prescribed angle theta:
     the apparent angle 2 atan(h*/r*) after `steps` steps, and the height
-    against the spherical cap of angle theta with the hemisphere's volume."""
+    against the spherical cap of angle theta with the hemisphere's volume;
+    then the same from that ideal cap as the start."""
     from paper_1509_07691_amd import inputs as I
     from paper_1509_07691_amd.fslbm import Lattice
 
@@ -594,9 +595,22 @@ def sessile_contact_angles(dev, steps, thetas=(60.0, 90.0, 120.0)):
                       theta=math.radians(th))
         lat.step(steps)
         dh, l2r, _, ang = sessile_measures(lat, 256, h, r)
-        rows.append({"theta": th, "steps": steps, "measured_deg": round(ang, 2),
-                     "error_deg": round(ang - th, 2), "h_rel_err": round(dh, 4), "L2_r": round(l2r, 4)})
         lat.close()
+        # the same run started from the equal-volume cap of angle theta: the
+        # hemisphere start is still moving after `steps` steps at 60 and 120
+        # degrees, the cap start shows whether that angle is held
+        cap = np.zeros_like(fill)
+        cap[1:-1] = I.sphere_fraction(fill.shape, (128.0, 128.0, 1.0 + h - rc), rc)[1:-1]
+        cap = I.perturb_interface(cap, 1e-6, 2)
+        lat = Lattice(cap, obst, precision="f32", device=dev, curv_model="lsqr", sigma=5e-4, tau=0.8,
+                      theta=math.radians(th))
+        lat.step(steps)
+        cdh, cl2r, _, cang = sessile_measures(lat, 256, h, r)
+        lat.close()
+        rows.append({"theta": th, "steps": steps, "measured_deg": round(ang, 2),
+                     "error_deg": round(ang - th, 2), "h_rel_err": round(dh, 4), "L2_r": round(l2r, 4),
+                     "ideal_cap_start": {"measured_deg": round(cang, 2), "error_deg": round(cang - th, 2),
+                                         "h_rel_err": round(cdh, 4), "L2_r": round(cl2r, 4)}})
     return rows
 
 
