@@ -709,6 +709,29 @@ def oscillation_table(dev, precisions, steps, every=500):
     return out
 
 
+def pull_copy_rate(dev, stream, shape, prec, launches=10):
+    """The stream-collide's memory bound on this device: the library's
+    pull-only copy (19 planes in the lattice layout, D3Q19 upstream offsets,
+    the stream-collide's grid; no arithmetic) on an nx x ny x nz lattice,
+    timed by the library with HIP events on `stream`. Returns (us per
+    launch, GB/s over the 38 s N bytes it moves)."""
+    import torch
+    from paper_1509_07691_amd import fslbm as F
+
+    code = F.PRECISIONS[prec]
+    nx, ny, nz = shape
+    nbytes = F.fslbm_pull_copy_bytes(nx, ny, nz, code)
+    src = torch.zeros(nbytes, dtype=torch.uint8, device=dev)
+    dst = torch.zeros(nbytes, dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+    us = F.fslbm_pull_copy_time(nx, ny, nz, code, src.data_ptr(), dst.data_ptr(), nbytes, stream.cuda_stream,
+                                launches)
+    del src, dst
+    torch.cuda.empty_cache()
+    moved = 38 * {"f64": 8, "f32": 4}.get(prec, 2) * nx * ny * nz
+    return us, moved / (us * 1e-6) / 1e9
+
+
 def run_workload(dev, stream, name, prec, steps, warmup, split=None, graph=False, keep=False):
     """Times `steps` steps of a workload (after `warmup`) with per-phase HIP
     events on the lattices' stream; returns the record and, with keep, the
@@ -942,6 +965,13 @@ def main():
                         split=None if args.split < 0 else bool(args.split), graph=bool(args.graph))
     traffic = stored_traffic(args.workload, args.precision)
     nunits = head["fluid_cells"]
+    pull = None
+    if not args.no_copy and head["lattices"] == 1:
+        pus, pgbs = pull_copy_rate(dev, stream, head["lattice"], args.precision)
+        pull = {"us": round(pus, 3), "GBs": round(pgbs, 1),
+                "kernel_frac_of_pull_copy": round(head["stream_collide_GBs"] / pgbs, 4),
+                "what": "the library's pull-only copy (fslbm_pull_copy_time) on the same lattice shape and "
+                        "layout: the 38 distribution streams with no arithmetic, the memory bound of the pass"}
     res = {
         "metric": METRIC,
         "value": head["mlups"],
@@ -963,6 +993,7 @@ def main():
                      "frac": head["roofline_frac"],
                      "traffic": traffic.get("bytes_per_launch") if traffic else None,
                      "copy_kernel_GBs": round(copy_gbs, 1) if copy_gbs else None,
+                     "pull_copy": pull,
                      "kernel": "k_stream_collide" + (" (lean liquid pass)" if head["split_passes"] else ""),
                      "avg_launch_us": head["stream_collide_us"],
                      "algorithmic_bytes_per_launch": head["algorithmic_bytes_per_launch"],
@@ -982,6 +1013,10 @@ def main():
         rec = run_workload(dev, stream, args.workload, prec, args.steps, args.warmup)
         rec["speedup_vs_" + args.precision] = round(head["ms_per_step"] / rec["ms_per_step"], 3)
         rec["stream_collide_speedup_vs_" + args.precision] = round(head["stream_collide_us"] / rec["stream_collide_us"], 3)
+        if not args.no_copy and rec["lattices"] == 1:
+            pus, pgbs = pull_copy_rate(dev, stream, rec["lattice"], prec)
+            rec["pull_copy"] = {"us": round(pus, 3), "GBs": round(pgbs, 1),
+                                "kernel_frac_of_pull_copy": round(rec["stream_collide_GBs"] / pgbs, 4)}
         compare[prec] = rec
         print(f"# storage {prec}: {rec['mlups']} MLUPS", file=sys.stderr, flush=True)
     if compare:

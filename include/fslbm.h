@@ -340,6 +340,28 @@ int fslbm_adjoint_backward(fslbm_t h, const double *dL_dfill_T, int in_is_device
  * FSLBM_E_STATE if no window was recorded, FSLBM_E_ARG for a NULL output. */
 int fslbm_adjoint_status(fslbm_t h, int64_t *inside_steps, int64_t *fill_events, int64_t *unconverted_steps);
 
+/* Measurement aid: the bound that memory sets for the stream-collide. The
+ * streaming half of eq. lbe1 (Sec. II) alone, as a copy: on a periodic
+ * nx x ny x nz lattice every cell x writes dst_q(x) = src_q(x - c_q) for the
+ * 19 directions, with no collision and no cell types, in the library's
+ * distribution layout for `precision` (19 planes, q-major, the plane stride
+ * a lattice of that shape uses; elements of 8, 4 or 2 bytes copied as raw
+ * bits) and with the grid, chunk order and launch bounds of the bulk
+ * stream-collide. src and dst are caller-owned device buffers on the
+ * current device, of at least fslbm_pull_copy_bytes() bytes each (the
+ * padding between planes is neither read nor written). The call enqueues
+ * one untimed and then `launches` (1 .. 100000) timed launches on
+ * hip_stream (NULL: the null stream), waits for them, and writes their
+ * average duration from HIP events recorded on that stream to
+ * *us_per_launch; it moves 38 s N bytes per launch (s the element size,
+ * N = nx ny nz). FSLBM_E_ARG for an unknown precision, NULL pointers,
+ * src == dst or launches out of range, FSLBM_E_SHAPE for an extent < 3, a
+ * cell count above 2^31 - 1 or buffers that are too small, FSLBM_E_HIP if
+ * a HIP call fails. */
+int fslbm_pull_copy_bytes(int nx, int ny, int nz, int precision, size_t *bytes);
+int fslbm_pull_copy_time(int nx, int ny, int nz, int precision, const void *src, void *dst, size_t buffer_bytes,
+                         void *hip_stream, int launches, double *us_per_launch);
+
 /* Synchronises the handle's stream and frees the handle (not the caller's
  * workspace). */
 void fslbm_destroy(fslbm_t h);

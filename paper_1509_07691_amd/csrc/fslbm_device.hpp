@@ -135,10 +135,14 @@ __device__ inline void store_sr(__hip_bfloat16 *p, float v, uint32_t bits)
 
 // Counter-based random bits for the stochastic stores: one hash of (cell,
 // step) per cell (the low-bias 32-bit integer hash of Wellons' "prospecting
-// for hash functions") seeds Marsaglia's xorshift32 generator (shifts 13,
-// 17, 5; "Xorshift RNGs", 2003). Each of its words serves two directions:
-// the word itself and its low half moved to the top, since the conversions
-// take the top bits. Deterministic: a run is reproduced bit for bit.
+// for hash functions") gives a word s that is uniform over cells and steps,
+// and direction q takes s + q phi (phi = 0x9e3779b9, 2^32 times the
+// fractional part of the golden ratio: a Weyl sequence). Each direction's
+// word is then uniform on its own, which is what makes the stochastic
+// rounding unbiased; the 19 words of a cell are spread evenly instead of
+// being independent, which changes the spread of the cell's summed rounding
+// error but not its mean. One add per direction. Deterministic: a run is
+// reproduced bit for bit.
 __device__ inline uint32_t hash32(uint32_t x)
 {
     x ^= x >> 16;
@@ -150,22 +154,10 @@ __device__ inline uint32_t hash32(uint32_t x)
 }
 __device__ inline uint32_t cell_seed(int i, uint32_t step) { return hash32(uint32_t(i) ^ hash32(step * 0x9e3779b9u)); }
 struct SrBits {
-    uint32_t x, w;
-    // 0 is a fixed point of xorshift32; the hash maps one cell per step to
-    // it, which then starts from another state
-    __device__ inline explicit SrBits(uint32_t seed) : x(seed ? seed : 0x9e3779b9u), w(0) {}
-    // the word for direction q; called for q = 0, 1, ..., 18 in order
-    __device__ inline uint32_t at(int q)
-    {
-        if ((q & 1) == 0) {
-            x ^= x << 13;
-            x ^= x >> 17;
-            x ^= x << 5;
-            w = x;
-            return w;
-        }
-        return w << 16;
-    }
+    uint32_t s;
+    __device__ inline explicit SrBits(uint32_t seed) : s(seed) {}
+    // the word for direction q
+    __device__ inline uint32_t at(int q) const { return s + uint32_t(q) * 0x9e3779b9u; }
 };
 
 // f_q from storage (any form).
@@ -206,12 +198,22 @@ __device__ inline typename P::T load_raw(const typename P::S *__restrict__ plane
     if constexpr (sizeof(S) == 2) return to_float(*(const S *)((const char *)plane + uint32_t(i) * 2u));
     else return to_float(plane[i]);
 }
+// The 16-bit stores go through a buffer resource per plane (base and size
+// in scalar registers, the byte offset 2 i the only per-lane operand), so
+// the 19 stores need no 64-bit address arithmetic; a store past the plane's
+// `plane_cells` is dropped by the hardware.
 template <class P>
-__device__ inline void store_raw(typename P::S *__restrict__ plane, int i, typename P::T v, uint32_t bits)
+__device__ inline void store_raw(typename P::S *__restrict__ plane, int i, typename P::T v, uint32_t bits,
+                                 int plane_cells)
 {
     using S = typename P::S;
-    if constexpr (sizeof(S) == 2) store_sr((S *)((char *)plane + uint32_t(i) * 2u), v, bits);
-    else store_sr(plane + i, v, bits);
+    if constexpr (sizeof(S) == 2) {
+        const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(plane, 0, plane_cells * 2, 0x00020000);
+        // cache policy 2: non-temporal, as the global stores of store_sr
+        __builtin_amdgcn_raw_buffer_store_b16((unsigned short)sr_code(S(), v, bits), r, int(uint32_t(i) * 2u), 0, 2);
+    } else {
+        store_sr(plane + i, v, bits);
+    }
 }
 // Deviation d_q = f_q - w_q from shifted storage.
 template <class P, int Q>
@@ -438,10 +440,12 @@ struct Nbr {
         z = z_;
         const int nxy = nx * ny;
         ox[0] = x == 0 ? nx - 1 : x - 1; ox[1] = x; ox[2] = x == nx - 1 ? 0 : x + 1;
-        oy[0] = (y == 0 ? ny - 1 : y - 1) * nx; oy[1] = y * nx;
-        oy[2] = (y == ny - 1 ? 0 : y + 1) * nx;
-        oz[0] = (z == 0 ? nz - 1 : z - 1) * nxy; oz[1] = z * nxy;
-        oz[2] = (z == nz - 1 ? 0 : z + 1) * nxy;
+        // the wrapped row and plane offsets as sums around y nx and z nx ny
+        // (a product of a selected index would be multiplied out by the
+        // compiler for each of the nine (dy, dz) combinations)
+        const int ry = y * nx, wy = nxy - nx, rz = z * nxy, wz = nxy * (nz - 1);
+        oy[0] = y == 0 ? ry + wy : ry - nx; oy[1] = ry; oy[2] = y == ny - 1 ? ry - wy : ry + nx;
+        oz[0] = z == 0 ? rz + wz : rz - nxy; oz[1] = rz; oz[2] = z == nz - 1 ? rz - wz : rz + nxy;
     }
     __device__ inline int at(int dx, int dy, int dz) const
     {

@@ -329,7 +329,7 @@ __device__ inline void liquid_cell(const Fields<P> &F, const Params &prm, int i,
         SrBits rb(sizeof(typename P::S) == 2 ? cell_seed(i, F.sc->step) : 0u);
 #pragma unroll
         for (int q = 0; q < NQ; ++q)
-            store_raw<P>(F.fdst + (size_t)q * (size_t)F.NS, i, fin[q], sizeof(typename P::S) == 2 ? rb.at(q) : 0u);
+            store_raw<P>(F.fdst + (size_t)q * (size_t)F.NS, i, fin[q], sizeof(typename P::S) == 2 ? rb.at(q) : 0u, F.NS);
     } else {
         pull<P>(F, up, fin);
         relax<P, COLL>(fin, prm);
@@ -554,12 +554,14 @@ __device__ inline void stream_collide_box(const Batch<P> &B)
     for (int c = xcd_chunk(blockIdx.x, gridDim.x, xcd_run<P>()); c * SC_BLOCK < n; c += gridDim.x) {
         const int k = c * SC_BLOCK + (int)threadIdx.x;
         if (k >= n) continue;
-        const int bx = k % box.ex, r = k / box.ex, by = r % box.ey, bz = r / box.ey;
-        const int x = box.x0 + bx, y = box.y0 + by, z = box.z0 + bz;
-        const int i = x + F.nx * (y + F.ny * z);
+        // unsigned: the signed division costs twice the instructions
+        const unsigned uk = unsigned(k), uex = unsigned(box.ex), uey = unsigned(box.ey);
+        const unsigned r = uk / uex;
+        const int bx = int(uk - r * uex), by = int(r % uey), bz = int(r / uey);
+        const Nbr nb(box.x0 + bx, box.y0 + by, box.z0 + bz, F.nx, F.ny, F.nz);
+        const int i = nb.at(0, 0, 0);
         const uint8_t fl = F.flags[i];
         if (!(fl & FL_FLUID)) continue;
-        const Nbr nb(x, y, z, F.nx, F.ny, F.nz);
         if (MODE == 1) {
             if (fl == FL_LIQ) liquid_cell<P, COLL>(F, prm, i, nb);
         } else {

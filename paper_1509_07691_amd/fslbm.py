@@ -95,6 +95,8 @@ def load_library(path: str = LIB_PATH):
         "fslbm_adjoint_forward": [vp, i64, i32, vp, ctypes.c_size_t],
         "fslbm_adjoint_backward": [vp, vp, i32, dp, dp, vp, i32],
         "fslbm_adjoint_status": [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)],
+        "fslbm_pull_copy_bytes": [i32, i32, i32, i32, ctypes.POINTER(ctypes.c_size_t)],
+        "fslbm_pull_copy_time": [i32, i32, i32, i32, vp, vp, ctypes.c_size_t, vp, i32, dp],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -330,6 +332,21 @@ def fslbm_adjoint_backward(h, dfill_T, dfill_0):
     ds, dt = ctypes.c_double(0.0), ctypes.c_double(0.0)
     _check(load_library().fslbm_adjoint_backward(h, gp, gd, ctypes.byref(ds), ctypes.byref(dt), op, od))
     return ds.value, dt.value
+
+
+def fslbm_pull_copy_bytes(nx, ny, nz, precision):
+    out = ctypes.c_size_t(0)
+    _check(load_library().fslbm_pull_copy_bytes(nx, ny, nz, precision, ctypes.byref(out)))
+    return out.value
+
+
+def fslbm_pull_copy_time(nx, ny, nz, precision, src_ptr, dst_ptr, buffer_bytes, stream_ptr, launches):
+    """Average duration (us) of the pull-only copy over `launches` launches."""
+    us = ctypes.c_double(0.0)
+    _check(load_library().fslbm_pull_copy_time(nx, ny, nz, precision, ctypes.c_void_p(src_ptr),
+                                               ctypes.c_void_p(dst_ptr), buffer_bytes, ctypes.c_void_p(stream_ptr),
+                                               int(launches), ctypes.byref(us)))
+    return us.value
 
 
 def fslbm_batch_create(handles):

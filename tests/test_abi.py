@@ -64,6 +64,27 @@ def test_required_bytes_and_shape_errors(lib):
     assert e.value.code == -1
 
 
+def test_pull_copy_sizes_and_argument_errors(lib):
+    """The pull-copy measurement aid: 19 planes of the lattice's plane stride
+    (N rounded up to 64, plus a 1024-element gap); every argument error is
+    reported before any device call."""
+    n = 13 * 17 * 19
+    ns = (n + 63) // 64 * 64 + 1024
+    for prec, s in ((fslbm.FSLBM_F64, 8), (fslbm.FSLBM_F32, 4), (fslbm.FSLBM_F16_STORE, 2), (fslbm.FSLBM_BF16_STORE, 2)):
+        assert fslbm.fslbm_pull_copy_bytes(13, 17, 19, prec) == 19 * ns * s
+    need = 19 * ns * 4
+    cases = [((2, 17, 19, fslbm.FSLBM_F32, 1, 2, need, 0, 3), -2),   # extent below 3
+             ((13, 17, 19, 9, 1, 2, need, 0, 3), -1),                 # precision
+             ((13, 17, 19, fslbm.FSLBM_F32, 0, 2, need, 0, 3), -1),   # NULL source
+             ((13, 17, 19, fslbm.FSLBM_F32, 1, 1, need, 0, 3), -1),   # src == dst
+             ((13, 17, 19, fslbm.FSLBM_F32, 1, 2, need - 1, 0, 3), -2),  # buffers too small
+             ((13, 17, 19, fslbm.FSLBM_F32, 1, 2, need, 0, 0), -1)]   # no launch
+    for args, code in cases:
+        with pytest.raises(fslbm.FslbmError) as e:
+            fslbm.fslbm_pull_copy_time(*args)
+        assert e.value.code == code, args
+
+
 def test_create_rejects_bad_arguments_before_touching_the_device(lib):
     fill = np.zeros(8 * 8 * 8)
     h = ctypes.c_void_p()
