@@ -74,8 +74,9 @@ LONG_STEPS = 10000
 # differently; the semi-axis a(t) and the mass are the smooth measures. The
 # bars are about three times the values measured on MI355X (FP32: fill
 # 1.9e-2, velocity 2.1e-3, cells 2.1e-4, mass drift 8.1e-8, semi-axis
-# 1.6e-3; F16 4.4e-2, 1.8e-3, 3.8e-4, 1.2e-7, 1.7e-3; BF16 6.5e-2, 2.0e-3,
-# 6.2e-4, 7.9e-8, 1.4e-3), printed by the test. The stochastic 16-bit
+# 1.6e-3; F16 3.6e-2, 2.0e-3, 3.0e-4, 6.6e-8, 1.1e-3; BF16 1.8e-2, 2.0e-3,
+# 2.3e-4, 3.2e-7, 9.6e-4; other runs of the 16-bit forms up to 6.5e-2 and
+# 6.2e-4 for fill and cells), printed by the test. The stochastic 16-bit
 # stores make the mass a random walk (zero mean, spread growing like the
 # square root of the steps; 0.8e-7 to 3.6e-7 seen), so their mass bar is
 # 1e-6.
