@@ -314,8 +314,11 @@ int fslbm_load_state(fslbm_t h, const void *src, size_t bytes);
  *               phi_0 as set by fslbm_set_interface_fill (m_0 = phi_0 rho_0
  *               with the distributions of the window start held fixed),
  *               0 elsewhere.
- * It recomputes each K-step segment from its checkpoint into a ring of
- * K-1 states, runs the transposed steps in reverse order, and leaves the
+ * It recomputes each K-step segment from its checkpoint into one of two
+ * rings of K-1 states, on a second HIP stream that it creates for the call
+ * (default priority) and on a copy of the lattice's fields in the
+ * workspace, while the transposed steps of the segment after it run in
+ * reverse order on the handle's stream from the other ring; it leaves the
  * lattice at the state of step nsteps, so it may be called again with
  * another dL/dphi_T. FSLBM_E_STATE if no window was recorded or the
  * lattice has been stepped or modified since. Synchronises the stream.

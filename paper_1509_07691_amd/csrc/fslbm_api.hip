@@ -152,7 +152,7 @@ struct AdjWindow {
     size_t bytes = 0;
     std::vector<long long> ck;  // checkpoint times 0, K, 2K, ..., T
     size_t f_bytes = 0, snap_bytes = 0, slot_bytes = 0;
-    size_t off_ck = 0, off_ring = 0;
+    size_t off_ck = 0, off_ring[2] = {0, 0}, off_shadow = 0;
     size_t off_gin[2] = {0, 0}, off_own[2] = {0, 0}, off_refl = 0, off_scal = 0, off_gb = 0, off_contrib = 0, off_pos = 0,
            off_part = 0, total = 0;
 };
@@ -205,6 +205,10 @@ struct fslbm_lattice {
     double n_free;     // non-obstacle cells
     fslbm_batch self;
     AdjWindow adj;
+    // while the reverse sweep enqueues a segment's recompute: the copy of the
+    // non-distribution fields (from Layout::flags on) that those steps work
+    // on, so that they can run beside the reverse steps (make_fields)
+    char *scal_base = nullptr;
 };
 
 namespace {
@@ -242,30 +246,33 @@ Fields<P> make_fields(const fslbm_lattice *h)
     Fields<P> F;
     char *w = h->ws;
     const Layout &L = h->L;
+    // every field after the two distribution buffers: in the workspace, or
+    // in the copy h->scal_base holds
+    auto at = [&](size_t off) { return h->scal_base ? h->scal_base + (off - L.flags) : w + off; };
     F.fsrc = (const S *)(w + (h->cur == 0 ? L.fA : L.fB));
     F.fdst = (S *)(w + (h->cur == 0 ? L.fB : L.fA));
-    F.flags = (uint8_t *)(w + L.flags);
-    F.conv = (uint8_t *)(w + L.conv);
-    F.near = (uint8_t *)(w + L.near);
-    F.mark = (uint32_t *)(w + L.mark);
-    F.m = (R *)(w + L.m);
-    F.rho = (R *)(w + L.rho);
-    F.phi = (R *)(w + L.phi);
-    F.K = (R *)(w + L.K);
-    F.nrm = (R *)(w + L.nrm);
-    F.plic = (R *)(w + L.plic);
-    F.share = (R *)(w + L.share);
-    F.phis = (R *)(w + L.phis);
-    F.nmol = (R *)(w + L.nmol);
-    F.cnrm = (R *)(w + L.cnrm);
-    F.ilist = (int32_t *)(w + L.ilist);
-    F.olist = (int32_t *)(w + L.olist);
-    F.wlist = (int32_t *)(w + L.wlist);
-    F.newlist = (int32_t *)(w + L.newlist);
-    F.ilist_tmp = (int32_t *)(w + L.ilist_tmp);
-    F.counts = (int *)(w + L.counts);
-    F.part = (double *)(w + L.part);
-    F.sc = (DevScalars *)(w + L.sc);
+    F.flags = (uint8_t *)at(L.flags);
+    F.conv = (uint8_t *)at(L.conv);
+    F.near = (uint8_t *)at(L.near);
+    F.mark = (uint32_t *)at(L.mark);
+    F.m = (R *)at(L.m);
+    F.rho = (R *)at(L.rho);
+    F.phi = (R *)at(L.phi);
+    F.K = (R *)at(L.K);
+    F.nrm = (R *)at(L.nrm);
+    F.plic = (R *)at(L.plic);
+    F.share = (R *)at(L.share);
+    F.phis = (R *)at(L.phis);
+    F.nmol = (R *)at(L.nmol);
+    F.cnrm = (R *)at(L.cnrm);
+    F.ilist = (int32_t *)at(L.ilist);
+    F.olist = (int32_t *)at(L.olist);
+    F.wlist = (int32_t *)at(L.wlist);
+    F.newlist = (int32_t *)at(L.newlist);
+    F.ilist_tmp = (int32_t *)at(L.ilist_tmp);
+    F.counts = (int *)at(L.counts);
+    F.part = (double *)at(L.part);
+    F.sc = (DevScalars *)at(L.sc);
     F.snap = nullptr;
     F.nx = h->nx;
     F.ny = h->ny;
@@ -1273,8 +1280,11 @@ size_t adj_layout(AdjWindow &w, const fslbm_lattice *h)
     for (long long t = 0; t < w.T; t += w.K) w.ck.push_back(t);
     w.ck.push_back(w.T);
     w.off_ck = take(w.ck.size() * w.slot_bytes);
+    // two rings: the reverse steps of one segment read one while the
+    // recompute of the segment before it fills the other
     const long long ring = std::max(0LL, std::min<long long>(w.K, w.T) - 1);
-    w.off_ring = take((size_t)ring * w.slot_bytes);
+    for (int r = 0; r < 2; ++r) w.off_ring[r] = take((size_t)ring * w.slot_bytes);
+    w.off_shadow = take(h->L.total - h->L.flags);
     w.total = off;
     return off;
 }
@@ -1355,7 +1365,7 @@ inline Slot seg_slot(const AdjWindow &w, size_t s, long long t)
     const long long t0 = w.ck[s], t1 = w.ck[s + 1];
     if (t == t0) return ck_slot(w, s);
     if (t == t1) return ck_slot(w, s + 1);
-    char *b = w.ws + w.off_ring + (size_t)(t - t0 - 1) * w.slot_bytes;
+    char *b = w.ws + w.off_ring[s & 1] + (size_t)(t - t0 - 1) * w.slot_bytes;
     return {b, b + w.f_bytes};
 }
 
@@ -1488,25 +1498,70 @@ int do_adj_backward(fslbm_lattice *h, const double *dphi, int in_dev, double *ds
     h->frozen = 1;
     const Params prm = make_params(h);
     const size_t nseg = w.ck.size() - 1;
+    // Segment s is recomputed on a second stream, on the copy of the
+    // non-distribution fields at off_shadow and into ring s % 2, while the
+    // reverse steps of segment s + 1 run on the handle's stream from the
+    // other ring and the handle's own fields: both chains are latency-bound
+    // launches of a few thousand wavefronts, so they overlap. Events order
+    // the rings: ev[s] = recompute of s done, ev[nseg + s] = reverse of s
+    // done, ev[2 nseg] = the copy of the fields done.
     int rc = 0;
-    for (size_t s = nseg; s-- > 0 && !rc;) {
-        const long long t0 = w.ck[s], t1 = w.ck[s + 1];
-        // recompute the states t0+1 .. t1-1 of the segment into the ring,
-        // with the step numbers the window ran them with (the 16-bit forms
-        // draw their rounding bits from them)
-        rc = load_snap<P>(h, ck_slot(w, s).snap);
-        k_set_step<<<1, 1, 0, st>>>((DevScalars *)(h->ws + h->L.sc), w.start_step + (unsigned)t0);
+    auto hip = [&](hipError_t e, const char *what) {
+        if (e != hipSuccess && !rc) rc = fail(FSLBM_E_HIP, "%s: %s", what, hipGetErrorString(e));
+    };
+    hipStream_t st2 = nullptr;
+    std::vector<hipEvent_t> ev(2 * nseg + 1, nullptr);
+    auto cleanup = [&]() {
+        h->stream = st;
+        h->scal_base = nullptr;
+        if (st2) (void)hipStreamSynchronize(st2);
+        (void)hipStreamSynchronize(st);
+        for (auto e : ev)
+            if (e) (void)hipEventDestroy(e);
+        if (st2) (void)hipStreamDestroy(st2);
+    };
+    hip(hipStreamCreateWithFlags(&st2, hipStreamNonBlocking), "hipStreamCreateWithFlags");
+    for (auto &e : ev)
+        if (!rc) hip(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreateWithFlags");
+    char *shadow = w.ws + w.off_shadow;
+    if (!rc)
+        hip(hipMemcpyAsync(shadow, h->ws + h->L.flags, h->L.total - h->L.flags, hipMemcpyDeviceToDevice, st),
+            "copy of the fields");
+    if (!rc) hip(hipEventRecord(ev[2 * nseg], st), "hipEventRecord");
+    if (!rc) hip(hipStreamWaitEvent(st2, ev[2 * nseg], 0), "hipStreamWaitEvent");
+    const bool lsqr = h->curv == FSLBM_CURV_LSQR;
+    // the states t0+1 .. t1-1 of segment s into its ring, with the step
+    // numbers the window ran them with (the 16-bit forms draw their rounding
+    // bits from them); the LSQR step writes the snapshot itself, FD takes
+    // k_snap
+    auto recompute = [&](size_t sg) {
+        if (sg + 2 < nseg && !rc) hip(hipStreamWaitEvent(st2, ev[nseg + sg + 2], 0), "hipStreamWaitEvent");
+        h->stream = st2;
+        h->scal_base = shadow;
+        const long long t0 = w.ck[sg], t1 = w.ck[sg + 1];
+        if (!rc) rc = load_snap<P>(h, ck_slot(w, sg).snap);
+        if (!rc) {
+            k_set_step<<<1, 1, 0, st2>>>(make_fields<P>(h).sc, w.start_step + (unsigned)t0);
+            hip(hipGetLastError(), "k_set_step");
+        }
         for (long long t = t0; t + 1 < t1 && !rc; ++t) {
-            const Slot a = seg_slot(w, s, t), b = seg_slot(w, s, t + 1);
-            // the LSQR step writes the snapshot itself; FD takes k_snap
-            const bool lsqr = h->curv == FSLBM_CURV_LSQR;
+            const Slot a = seg_slot(w, sg, t), b = seg_slot(w, sg, t + 1);
             rc = enqueue_step_kernels<P>(&h->self, a.f, b.f, lsqr ? b.snap : nullptr);
             if (!rc && !lsqr) {
                 const Fields<P> F = make_fields<P>(h);
-                k_snap<P><<<lg, 256, 0, st>>>(F, (typename P::R *)b.snap, 1);
-                HIP_OK(hipGetLastError());
+                k_snap<P><<<lg, 256, 0, st2>>>(F, (typename P::R *)b.snap, 1);
+                hip(hipGetLastError(), "k_snap");
             }
         }
+        h->stream = st;
+        h->scal_base = nullptr;
+        if (!rc) hip(hipEventRecord(ev[sg], st2), "hipEventRecord");
+    };
+    if (!rc && nseg > 0) recompute(nseg - 1);
+    for (size_t s = nseg; s-- > 0 && !rc;) {
+        if (s > 0) recompute(s - 1);
+        if (!rc) hip(hipStreamWaitEvent(st, ev[s], 0), "hipStreamWaitEvent");
+        const long long t0 = w.ck[s], t1 = w.ck[s + 1];
         // reverse steps t1-1 .. t0
         for (long long t = t1 - 1; t >= t0 && !rc; --t) {
             const Slot cur = seg_slot(w, s, t), nxt = seg_slot(w, s, t + 1);
@@ -1518,10 +1573,12 @@ int do_adj_backward(fslbm_lattice *h, const double *dphi, int in_dev, double *ds
             if (h->coll == FSLBM_SRT) k_adj_stream<P, 0><<<cg, 256, 0, st>>>(F, A, prm);
             else k_adj_stream<P, 1><<<cg, 256, 0, st>>>(F, A, prm);
             par ^= 1;
-            HIP_OK(hipGetLastError());
-            rc = enqueue_geometry_adjoint<P>(h, F, A, prm);
+            hip(hipGetLastError(), "k_adj_stream");
+            if (!rc) rc = enqueue_geometry_adjoint<P>(h, F, A, prm);
         }
+        if (!rc) hip(hipEventRecord(ev[nseg + s], st), "hipEventRecord");
     }
+    cleanup();
     h->frozen = 0;
     if (rc) return rc;
     // dL/dphi_0, dL/dsigma, dL/dtheta

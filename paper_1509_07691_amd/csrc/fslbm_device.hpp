@@ -208,7 +208,9 @@ __device__ inline void store_raw(typename P::S *__restrict__ plane, int i, typen
 {
     using S = typename P::S;
     if constexpr (sizeof(S) == 2) {
-        const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(plane, 0, plane_cells * 2, 0x00020000);
+        // the byte size as an unsigned 32-bit value (a plane of up to 2^31 - 1 cells)
+        const __amdgpu_buffer_rsrc_t r =
+            __builtin_amdgcn_make_buffer_rsrc(plane, 0, int(uint32_t(plane_cells) * 2u), 0x00020000);
         // cache policy 2: non-temporal, as the global stores of store_sr
         __builtin_amdgcn_raw_buffer_store_b16((unsigned short)sr_code(S(), v, bits), r, int(uint32_t(i) * 2u), 0, 2);
     } else {

@@ -257,10 +257,17 @@ __device__ inline void load_dirs_dev(const Fields<P> &F, const int (&j)[NQ], typ
 template <class P>
 __device__ inline void store_all_dev(const Fields<P> &F, int i, const typename P::T (&d)[NQ])
 {
-    SrBits rb(sizeof(typename P::S) == 2 ? cell_seed(i, F.sc->step) : 0u);
+    if constexpr (sizeof(typename P::S) == 2) {
+        // buffer stores, as in the lean pass (no 64-bit address per store)
+        const SrBits rb(cell_seed(i, F.sc->step));
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+            store_raw<P>(F.fdst + (size_t)q * (size_t)F.NS, i, d[q] * typename P::T(P::SCALE), rb.at(q), F.NS);
+        return;
+    }
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-        const uint32_t bits = sizeof(typename P::S) == 2 ? rb.at(q) : 0u;
+        const uint32_t bits = 0u;
         switch (q) {
 #define FSLBM_STORE(QQ) case QQ: store_d<P, QQ>(plane<P, QQ>(F.fdst, F.NS), i, d[q], bits); break;
             FSLBM_STORE(0) FSLBM_STORE(1) FSLBM_STORE(2) FSLBM_STORE(3) FSLBM_STORE(4)
@@ -570,10 +577,14 @@ __device__ inline void stream_collide_box(const Batch<P> &B)
     }
 }
 
-// FP32 arithmetic: 4 waves per SIMD (the boundary path then fits in 128
-// VGPRs); FP64 keeps the compiler's register choice (it would spill).
+// FP32 storage: 4 waves per SIMD (the boundary path then fits in 128
+// VGPRs). 16-bit storage: 3 waves per SIMD, where the boundary path takes
+// 134 VGPRs without spilling (at 4 waves it spilled 6-8; the droplet
+// sweep's merged pass took 102 us there against 94 us now). The lean pass
+// takes 37-60 VGPRs either way. FP64 keeps the compiler's register choice
+// (it would spill).
 template <class P, int COLL, int MODE>
-__global__ __launch_bounds__(SC_BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_stream_collide(const Batch<P> B)
+__global__ __launch_bounds__(SC_BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(typename P::S) == 2 ? 3 : 4))) void k_stream_collide(const Batch<P> B)
 {
     stream_collide_box<P, COLL, MODE>(B);
 }
