@@ -1536,6 +1536,9 @@ int do_adj_backward(fslbm_lattice *h, const double *dphi, int in_dev, double *ds
     // k_snap
     auto recompute = [&](size_t sg) {
         if (sg + 2 < nseg && !rc) hip(hipStreamWaitEvent(st2, ev[nseg + sg + 2], 0), "hipStreamWaitEvent");
+        // the step functions enqueue on h->stream and take their fields from
+        // make_fields(h): both point at the second stream and the copy while
+        // this segment's steps are enqueued (host code, one thread per handle)
         h->stream = st2;
         h->scal_base = shadow;
         const long long t0 = w.ck[sg], t1 = w.ck[sg + 1];
