@@ -73,10 +73,13 @@ LONG_STEPS = 10000
 # the oracle, so the fill error is carried by a few hundred cells typed
 # differently; the semi-axis a(t) and the mass are the smooth measures. The
 # bars are about three times the values measured on MI355X (FP32: fill
-# 1.9e-2, velocity 2.1e-3, cells 2.1e-4, mass drift 8.1e-8, semi-axis
-# 1.6e-3; F16 3.6e-2, 2.0e-3, 3.0e-4, 6.6e-8, 1.1e-3; BF16 1.8e-2, 2.0e-3,
-# 2.3e-4, 3.2e-7, 9.6e-4; other runs of the 16-bit forms up to 6.5e-2 and
-# 6.2e-4 for fill and cells), printed by the test. The stochastic 16-bit
+# 1.9e-2 to 2.7e-2, velocity 1.5e-3 to 2.1e-3, cells 2.1e-4 to 2.7e-4, mass
+# drift 8.1e-8, semi-axis 1.6e-3 to 2.0e-3; F16 3.6e-2 to 5.6e-2, 2.0e-3,
+# 3.0e-4 to 5.0e-4, 7.6e-8, 1.2e-3; BF16 1.8e-2, 1.7e-3 to 2.0e-3, 1.6e-4 to
+# 2.3e-4, 1.5e-8 to 3.2e-7, 5.9e-4 to 9.6e-4; other runs of the 16-bit forms
+# up to 6.5e-2 and 6.2e-4 for fill and cells), printed by the test; the
+# spread between builds that differ only in rounding is the conversion
+# timing of single cells, not a trend. The stochastic 16-bit
 # stores make the mass a random walk (zero mean, spread growing like the
 # square root of the steps; 0.8e-7 to 3.6e-7 seen), so their mass bar is
 # 1e-6.
@@ -85,21 +88,24 @@ LONG_BARS = {"f32": dict(fill=6e-2, vel=7e-3, flags=7e-4, mass=3e-7, axis=5e-3),
              "bf16": dict(fill=0.2, vel=7e-3, flags=2e-3, mass=1e-6, axis=5e-3)}
 
 
-def _min_then_max(a, every):
-    """Steps of the smallest sample of a series and of the largest sample
-    after it, each refined by a parabola through it and its two
-    neighbours. (Arg-extrema rather than sign changes of the slope: the
-    oracle's a(t) has a near-flat stretch between them where a small error
-    could add a spurious turn.)"""
-    def refine(k):
-        if 0 < k < len(a) - 1:
-            den = a[k - 1] - 2 * a[k] + a[k + 1]
-            if den:
-                return (k + 0.5 * (a[k - 1] - a[k + 1]) / den) * every
-        return float(k * every)
-    k0 = int(np.argmin(a))
-    k1 = k0 + int(np.argmax(a[k0:]))
-    return refine(k0), refine(k1)
+def _refined_min(a, every):
+    """Step of the smallest sample of a series, refined by a parabola through
+    it and its two neighbours; and its index."""
+    k = int(np.argmin(a))
+    if 0 < k < len(a) - 1:
+        den = a[k - 1] - 2 * a[k] + a[k + 1]
+        if den:
+            return (k + 0.5 * (a[k - 1] - a[k + 1]) / den) * every, k
+    return float(k * every), k
+
+
+def _rising_crossing(a, every, k0, level):
+    """Step at which the series first rises through `level` after sample k0
+    (linear interpolation between samples), or None."""
+    for k in range(k0, len(a) - 1):
+        if a[k] < level <= a[k + 1]:
+            return (k + (level - a[k]) / (a[k + 1] - a[k])) * every
+    return None
 
 
 def _semi_axis_x(phi):
@@ -118,8 +124,8 @@ def test_ellipsoid_downscale_errors_after_10000_steps(precision):
     fill level, pressure and velocity errors over the oracle's fluid cells,
     cells typed differently, mass drift, the x semi-axis a(t) of the
     oscillation sampled every 250 steps against the oracle's (largest
-    difference relative to a(0)), and the steps of its first minimum and
-    maximum (the period's half)."""
+    difference relative to a(0)), and the timing of the oscillation (the step
+    of its first minimum and of the rise after it)."""
     import torch
 
     from paper_1509_07691_amd.fslbm import Lattice
@@ -149,13 +155,21 @@ def test_ellipsoid_downscale_errors_after_10000_steps(precision):
     e_u = np.linalg.norm(du) / max(np.linalg.norm(uref), PRM["sigma"] / mu * np.sqrt(idx.size))
     drift = abs(g.mass() - M0) / M0
     e_axis = np.abs(np.array(a) - ref["a"]).max() / ref["a"][0]
-    # the oscillation: the steps of its first minimum and of the maximum
-    # after it (the oracle's at about 3030 and 8320) within two sample
-    # spacings (500 steps, 5 % of the period) of the oracle's
-    ext, ext_ref = _min_then_max(np.array(a), 250), _min_then_max(ref["a"], 250)
-    print(f"{precision}: a(t) minimum and maximum at {ext[0]:.0f}, {ext[1]:.0f} steps; "
-          f"oracle {ext_ref[0]:.0f}, {ext_ref[1]:.0f}")
-    assert abs(ext[0] - ext_ref[0]) < 500 and abs(ext[1] - ext_ref[1]) < 500
+    # the oscillation's timing: the step of its first minimum (sharp: the
+    # oracle's near 3030) and the step at which a(t) rises back through the
+    # level halfway between the oracle's minimum and its following maximum
+    # (about 4190), both within one sample spacing of the oracle's. The
+    # maximum itself is too flat to time: between 8000 and 10000 steps the
+    # oracle's a(t) varies by 0.04 cells, as much as the GPU's a(t) error.
+    ra = np.asarray(ref["a"])
+    t_min_ref, k_ref = _refined_min(ra, 250)
+    level = 0.5 * (ra[k_ref] + ra[k_ref:].max())
+    t_up_ref = _rising_crossing(ra, 250, k_ref, level)
+    t_min, k_g = _refined_min(np.asarray(a), 250)
+    t_up = _rising_crossing(np.asarray(a), 250, k_g, level)
+    print(f"{precision}: a(t) minimum at {t_min:.0f} steps (oracle {t_min_ref:.0f}), rises through {level:.3f} "
+          f"at {t_up if t_up is None else round(t_up)} (oracle {t_up_ref:.0f})")
+    assert abs(t_min - t_min_ref) < 250 and t_up is not None and abs(t_up - t_up_ref) < 250
     print(f"{precision} after {LONG_STEPS} steps: fill {e_fill:.3e} pressure {e_p:.3e} velocity {e_u:.3e} "
           f"flags {e_flags:.2e} mass drift {drift:.2e} semi-axis {e_axis:.2e} "
           f"(oracle drift {abs(float(ref['mass']) - float(ref['mass0'])) / float(ref['mass0']):.1e})", flush=True)
