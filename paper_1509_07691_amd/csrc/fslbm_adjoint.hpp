@@ -267,9 +267,13 @@ __device__ inline void cell_adj(const Fields<P> &F, const Adj &A, const Params &
     nt[0] = FL_LIQ;
 #pragma unroll
     for (int q = 1; q < NQ; ++q) nt[q] = F.flags[up[q]] & FL_TYPE;
+    // the neighbour's value is loaded whatever its type (every up[] index is
+    // a cell of the lattice), so the loads do not wait for the flags
 #pragma unroll
-    for (int q = 0; q < NQ; ++q)
-        yb[q] = A.own_in[q * N + i] + ((nt[opp(q)] & FL_FLUID) ? A.gin_in[q * N + up[opp(q)]] : 0.0);
+    for (int q = 0; q < NQ; ++q) {
+        const double g = A.gin_in[q * N + up[opp(q)]];
+        yb[q] = A.own_in[q * N + i] + ((nt[opp(q)] & FL_FLUID) ? g : 0.0);
+    }
     double Kc = 0, phx = 0, cnx = 0, cny = 0, cnz = 0;
     if (is_if) {
         Kc = double(F.K[i]);
@@ -312,6 +316,15 @@ __device__ inline void cell_adj(const Fields<P> &F, const Adj &A, const Params &
 #pragma unroll
     for (int q = 0; q < NQ; ++q) fob[q] = 0.0;
     if (is_if) {
+        // the neighbours' phi and mbar, loaded whatever their type (used at
+        // interface neighbours), so that the loads do not wait for the flags
+        double phz[NQ], mbz[NQ];
+#pragma unroll
+        for (int q = 1; q < NQ; ++q) {
+            const int z = up[opp(q)];
+            phz[q] = double(F.phi[z]);
+            mbz[q] = A.mbar[z];
+        }
         // rho(t+1) = sum_q f_in,q
         const double rb = A.rhob[i];
 #pragma unroll
@@ -327,12 +340,11 @@ __device__ inline void cell_adj(const Fields<P> &F, const Adj &A, const Params &
                 fb[o] += Mb;
                 fob[q] -= Mb;
             } else if (tz == FL_IF) {
-                const int z = up[o];
-                const double k = 0.5 * (double(F.phi[z]) + phx);
+                const double k = 0.5 * (phz[q] + phx);
                 fb[o] += k * Mb;
                 fob[q] -= k * Mb;
                 // both ends of the link carry the weight (phi_x + phi_z)/2
-                phb += 0.5 * (fin[o] - fo[q]) * (Mb - A.mbar[z]);
+                phb += 0.5 * (fin[o] - fo[q]) * (Mb - mbz[q]);
             }
         }
         A.phib[i] = phb;
