@@ -1751,6 +1751,8 @@ int fslbm_pull_copy_time(int nx, int ny, int nz, int precision, const void *src,
     return 0;
 }
 
+}  // extern "C"
+
 namespace {
 // What the closure of the interface layer at creation does to the input
 // (Sec. II.D: an interface cell has both gas and liquid D3Q19 neighbours;
@@ -1821,6 +1823,8 @@ LayerClosure layer_closure(int nx, int ny, int nz, const double *fill, const uin
     return c;
 }
 }  // namespace
+
+extern "C" {
 
 int fslbm_create(int nx, int ny, int nz, int precision, int curv_model, const double *fill,
                  const uint8_t *obstacle, void *workspace, size_t workspace_bytes, void *hip_stream,
