@@ -1520,9 +1520,15 @@ int do_adj_backward(fslbm_lattice *h, const double *dphi, int in_dev, double *ds
             if (e) (void)hipEventDestroy(e);
         if (st2) (void)hipStreamDestroy(st2);
     };
-    hip(hipStreamCreateWithFlags(&st2, hipStreamNonBlocking), "hipStreamCreateWithFlags");
+    // the stream and events belong to the lattice's device, whichever device
+    // is current
+    int dev0 = 0;
+    hip(hipGetDevice(&dev0), "hipGetDevice");
+    if (!rc && dev0 != h->device) hip(hipSetDevice(h->device), "hipSetDevice");
+    if (!rc) hip(hipStreamCreateWithFlags(&st2, hipStreamNonBlocking), "hipStreamCreateWithFlags");
     for (auto &e : ev)
         if (!rc) hip(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreateWithFlags");
+    if (dev0 != h->device) (void)hipSetDevice(dev0);
     char *shadow = w.ws + w.off_shadow;
     if (!rc)
         hip(hipMemcpyAsync(shadow, h->ws + h->L.flags, h->L.total - h->L.flags, hipMemcpyDeviceToDevice, st),
