@@ -431,7 +431,7 @@ __global__ __launch_bounds__(256) void k_adj_fd_mol(const Fields<P> F, const Adj
             for (int b = -1; b <= 1; ++b)
 #pragma unroll
                 for (int a = -1; a <= 1; ++a) s += k8w(a * a + b * b + c * c) * double(F.phi[nb.at(a, b, c)]);
-        A.ms[i] = s / 942.0;
+        A.ms[i] = s * K8_INV;
     }
 }
 
@@ -606,7 +606,7 @@ __global__ __launch_bounds__(256) void k_adj_fd_phib(const Fields<P> F, const Ad
             for (int b = -1; b <= 1; ++b)
 #pragma unroll
                 for (int a = -1; a <= 1; ++a) s += k8w(a * a + b * b + c * c) * A.msb[nb.at(a, b, c)];
-        s /= 942.0;
+        s *= K8_INV;
         if (fl & FL_IF) A.phib[i] += s;
         else A.phib[i] = s;
     }

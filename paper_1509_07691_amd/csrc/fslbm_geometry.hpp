@@ -297,9 +297,10 @@ __host__ __device__ inline void unit_normal(G gx, G gy, G gz, G (&n)[3])
 {
     const G len = sqrt(gx * gx + gy * gy + gz * gz);
     const bool ok = len > G(1e-12);
-    n[0] = ok ? gx / len : G(0);
-    n[1] = ok ? gy / len : G(0);
-    n[2] = ok ? gz / len : G(0);
+    const G il = ok ? G(1) / len : G(0);  // one division for the three components
+    n[0] = gx * il;
+    n[1] = gy * il;
+    n[2] = gz * il;
 }
 
 template <class P, class G>
@@ -316,6 +317,9 @@ __device__ inline void store_normal(const Fields<P> &F, int i, const G (&n)[3], 
 // K8 kernel of support 2 on the 27-point block: (1 - r^2/4)^4 gives
 // 256, 81, 16, 1 (times 1/256) for r^2 = 0, 1, 2, 3; normalised by 942.
 __device__ inline double k8w(int r2) { return r2 == 0 ? 256.0 : (r2 == 1 ? 81.0 : (r2 == 2 ? 16.0 : 1.0)); }
+// 1 / (the sum of the K8 weights, 256 + 6 81 + 12 16 + 8 = 942): the
+// mollified value is the weighted sum times this factor
+constexpr double K8_INV = 1.0 / 942.0;
 
 
 // FD model, one 8^3 tile per iteration. LDS: the fill level on the tile
@@ -351,7 +355,7 @@ __device__ inline void fd_mollified_normal(const Fields<P> &F, int j, typename P
 #pragma unroll
                         for (int dx = -1; dx <= 1; ++dx)
                             s += G(k8w(dx * dx + dy * dy + dz * dz)) * G(F.phi[nk.at(dx, dy, dz)]);
-                m[(c + 1) * 9 + (b + 1) * 3 + (a + 1)] = s / G(942);
+                m[(c + 1) * 9 + (b + 1) * 3 + (a + 1)] = s * G(K8_INV);
             }
     auto at = [&](int dx, int dy, int dz) { return m[(dz + 1) * 9 + (dy + 1) * 3 + (dx + 1)]; };
     G gx = G(0), gy = G(0), gz = G(0);
@@ -464,9 +468,20 @@ __device__ inline void geometry_fd_tiles(const Fields<P> &F)
         T.origin(t, ox, oy, oz);
         __syncthreads();
         if (!tile_has_interface(F, T, ox, oy, oz)) continue;
-        for (int c = threadIdx.x; c < 14 * 14 * 14; c += 256) {
-            const int x = c % 14, y = (c / 14) % 14, z = c / 196;
-            L.buf[c] = G(F.phi[gidx(ox - 3 + x, oy - 3 + y, oz - 3 + z, F.nx, F.ny, F.nz)]);
+        // the fill level on the 14^3 block: thread c < 196 takes column
+        // (x, y) = (c % 14, c / 14) and walks it in z with a running plane
+        // offset (no index division or product per element)
+        if (threadIdx.x < 196) {
+            const int c = threadIdx.x, x = c % 14, y = c / 14;
+            const int col = wrapi(ox - 3 + x, F.nx) + F.nx * wrapi(oy - 3 + y, F.ny);
+            const int nxy = F.nx * F.ny;
+            int zoff = wrapi(oz - 3, F.nz) * nxy;
+#pragma unroll
+            for (int z = 0; z < 14; ++z) {
+                L.buf[z * 196 + c] = G(F.phi[col + zoff]);
+                zoff += nxy;
+                if (zoff >= F.N) zoff -= F.N;
+            }
         }
         __syncthreads();
         // raw-fill normals of the tile's interface cells
@@ -491,7 +506,7 @@ __device__ inline void geometry_fd_tiles(const Fields<P> &F)
 #pragma unroll
                     for (int dx = -1; dx <= 1; ++dx)
                         s += G(k8w(dx * dx + dy * dy + dz * dz)) * L.buf[((z + 1 + dz) * 14 + y + 1 + dy) * 14 + x + 1 + dx];
-            L.mol[c] = s / G(942);
+            L.mol[c] = s * G(K8_INV);
         }
         __syncthreads();
         // unit normals of the mollified field on 10^3; obstacle cells with a
